@@ -1,0 +1,204 @@
+/*
+ * mcrt.h -- C ABI of the MI355X Monte-Carlo dust continuum radiative transfer
+ * library (libmcrt.so).  The method is that of Robitaille (2011), HYPERION:
+ * photon packets emitted by point sources propagate through a 3-D Cartesian
+ * grid of constant-density cells; at each interaction they scatter
+ * (Henyey-Greenstein) or are absorbed and immediately re-emitted; the Lucy
+ * path-length estimator gives the specific energy absorption rate of every
+ * cell, from which the LTE temperature follows; the iteration repeats until
+ * the absorbed energy has converged, and a final pass bins escaping packets
+ * into SEDs and images.
+ *
+ * Conventions
+ *   - cgs units: cm, g, s, erg, Hz, K.
+ *   - Cell arrays are C-ordered with x fastest: j = i + nx*(jy + ny*k).
+ *   - Frequency bins are ordered by increasing frequency; a packet carries a
+ *     bin index (multigroup); dust properties are constant over a bin.
+ *   - Host input arrays are copied during the call; device input pointers
+ *     are read during the call only and never retained.
+ *   - Output buffers are owned by the caller; their element count n is
+ *     checked (MCRT_E_SIZE when it does not match).
+ *   - The library owns every device allocation it makes and frees it in
+ *     mcrt_destroy.  Nothing crosses the ABI as an exception, abort or print:
+ *     functions return a status and keep a per-model message.
+ *   - Threading: one model per host thread; models are independent.
+ *   - Every numerical step runs in HIP kernels on the model's device; the
+ *     host only validates, builds FP64 tables once and schedules launches.
+ */
+#ifndef MCRT_H
+#define MCRT_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct mcrt_model mcrt_model;
+
+typedef enum {
+    MCRT_OK = 0,
+    MCRT_E_ARG = -1,         /* invalid argument value                        */
+    MCRT_E_STATE = -2,       /* call out of order (e.g. iterate before setup) */
+    MCRT_E_NOMEM = -3,       /* device or host allocation failed              */
+    MCRT_E_DEVICE = -4,      /* a HIP call failed                             */
+    MCRT_E_UNSUPPORTED = -5, /* option not available                          */
+    MCRT_E_SIZE = -6         /* caller buffer size does not match             */
+} mcrt_status;
+
+typedef enum {
+    MCRT_FP64 = 0,           /* FP64 transport: same-stream parity path        */
+    MCRT_FP32_TRANSPORT = 1  /* FP32 packet transport, FP64 reductions/tables  */
+} mcrt_precision;
+
+/* Event types of the per-packet log. */
+enum { MCRT_EV_EMIT = 0, MCRT_EV_SCATTER = 1, MCRT_EV_ABSORB = 2, MCRT_EV_ESCAPE = 3,
+       MCRT_EV_KILLED = 4 };
+
+/* One event.  cell: the cell of the event (for ESCAPE the last cell inside the
+ * grid); nu: frequency bin after the event; incl: SED inclination bin of an
+ * ESCAPE, else -1. */
+typedef struct {
+    int64_t packet;
+    int32_t index;
+    int32_t type;
+    int32_t cell[3];
+    int32_t nu;
+    int32_t incl;
+    int32_t reserved;
+} mcrt_event;
+
+/* Run parameters (mcrt_run_cfg_default fills the defaults in brackets). */
+typedef struct {
+    int64_t n_packets;         /* source packets per Lucy iteration [1e5] (Sec. 2.2)      */
+    int64_t n_packets_final;   /* packets of the final binning pass [= n_packets]         */
+    int32_t n_iter;            /* maximum Lucy iterations of mcrt_run [5]                 */
+    int32_t precision;         /* mcrt_precision [MCRT_FP64]                              */
+    uint64_t seed;             /* Philox key word 0 = seed mod 2^32 [1]                   */
+    double t_init;             /* initial temperature, K [10]                             */
+    int64_t max_events;        /* interactions before a packet is killed [1e6]            */
+    double conv_p;             /* percentile p of Sec. 2.4 [0.999]                        */
+    double conv_q_thres;       /* Q_thres [2]                                             */
+    double conv_d_thres;       /* Delta_thres [1.1]                                       */
+    double conv_dT_thres;      /* max |dT/T| threshold [0.01]                             */
+    double conv_noise_thres;   /* noise mask: sigma_dT/T limit when want_noise [0.002]    */
+    int32_t stop_on_convergence; /* 0 none, 1 max dT/T, 2 Q/Delta [0]                     */
+    int32_t source_sampling;   /* 0 luminosity-proportional, 1 equal numbers [0]          */
+    int32_t want_noise;        /* also accumulate sum of squared weights [0]              */
+    int32_t event_log_packets; /* log events of packets [0, this) of each pass [0]        */
+    int32_t event_log_cap;     /* events kept per logged packet [256]                     */
+    int32_t bin_every_iteration; /* bin escapes into SED/images in Lucy iterations too [0]*/
+    int32_t block_size;        /* transport threads per block, multiple of 64 [256]       */
+    int32_t blocks_per_cu;     /* persistent blocks per compute unit [0 = occupancy]      */
+    int32_t defer_lanes;       /* lanes of a wave that wait before events run [16]        */
+    int32_t reserved0;
+} mcrt_run_cfg;
+
+/* Statistics of one pass (a Lucy iteration or the final pass). */
+typedef struct {
+    int32_t iteration;         /* index of the iteration just finished                    */
+    int32_t converged_q;       /* Q < Q_thres and Delta < Delta_thres (Eqs. 4-6)          */
+    int32_t converged_dT;      /* max over the mask of |dT/T| < conv_dT_thres             */
+    int32_t precision;
+    double q;                  /* p-th percentile of R_j (Eq. 5); +inf without history    */
+    double delta;              /* delta(Q^{i-1}, Q^i) (Eq. 6)                             */
+    double max_dT;             /* max over the mask of |T^i - T^{i-1}| / T^{i-1}          */
+    double p999_dT;            /* 99.9th percentile of the same                           */
+    int64_t n_mask;            /* cells in the dT mask                                    */
+    int64_t n_r;               /* cells entering the percentile of R                      */
+    int64_t n_unsampled;       /* dust cells with zero absorption (T set to 1 K)          */
+    int64_t n_t_clamped;       /* cells whose T was clamped to [1 K, 1e4 K]               */
+    int64_t n_row_clamped;     /* dust cells whose emission row was clamped               */
+    int64_t n_cross_dust;      /* walk segments in cells with rho > 0                     */
+    int64_t n_cross_empty;     /* walk segments in cells with rho = 0                     */
+    int64_t n_scatter;
+    int64_t n_absorb;
+    int64_t n_escape;
+    int64_t n_killed;
+    double e_escaped;          /* energy of escaped packets, erg (Delta t = 1 s)          */
+    double e_killed;           /* energy of killed packets, erg                           */
+    double ms_transport;       /* device time of the transport kernel(s)                  */
+    double ms_update;          /* device time of the temperature update and statistics    */
+    double ms_total;           /* host wall time of the call                              */
+} mcrt_iter_stats;
+
+typedef struct {
+    int32_t n_iterations;      /* Lucy iterations run                                     */
+    int32_t converged;         /* the stopping criterion was met                          */
+    int32_t first_converged;   /* first iteration meeting the criterion, -1 if none       */
+    int32_t reserved;
+    double ms_total;           /* wall time of mcrt_run                                   */
+    double ms_to_converged;    /* wall time until the end of first_converged              */
+    mcrt_iter_stats last;      /* statistics of the last Lucy iteration                   */
+    mcrt_iter_stats final_pass;
+} mcrt_run_stats;
+
+/* ---- lifetime ------------------------------------------------------------ */
+mcrt_status mcrt_create(mcrt_model** out, int hip_device);
+void mcrt_destroy(mcrt_model* m);                      /* NULL-safe                   */
+const char* mcrt_last_error(const mcrt_model* m);      /* valid until the next call  */
+/* Run all work of m on this HIP stream (e.g. a PyTorch stream handle); NULL =
+ * the library's own stream.  The stream must outlive the model's use of it. */
+mcrt_status mcrt_set_stream(mcrt_model* m, void* hip_stream);
+
+/* ---- problem (Sec. 2.1) -------------------------------------------------- */
+/* Cartesian grid of nx*ny*nz cells over [lo, hi] (Sec. 2.1.2). */
+mcrt_status mcrt_set_grid(mcrt_model* m, int nx, int ny, int nz, const double lo[3],
+                          const double hi[3]);
+/* Dust density per cell, g cm^-3, finite and >= 0 (host array, n = ncell). */
+mcrt_status mcrt_set_density(mcrt_model* m, const double* rho, size_t n);
+/* Same from device memory (FP64 if is_fp64 else FP32), read during the call. */
+mcrt_status mcrt_set_density_device(mcrt_model* m, const void* d_rho, int is_fp64, size_t n);
+/* n_nu+1 increasing frequency edges, Hz. */
+mcrt_status mcrt_set_frequencies(mcrt_model* m, const double* nu_edges, int n_nu);
+/* Mass extinction chi_nu (cm^2/g, >= 0), albedo in [0,1] and HG asymmetry g,
+ * |g| < 1, per bin (Sec. 2.1.3).  kappa = chi (1 - albedo). */
+mcrt_status mcrt_set_dust(mcrt_model* m, const double* chi, const double* albedo, const double* g,
+                          int n_nu);
+/* Isotropic point source with a blackbody spectrum of teff (Sec. 2.1.1); the
+ * spectrum is truncated to the bins and renormalised to lum (erg/s). */
+mcrt_status mcrt_add_point_source(mcrt_model* m, const double pos[3], double lum, double teff);
+/* Isotropic point source with a given relative luminosity per bin. */
+mcrt_status mcrt_add_point_source_spectrum(mcrt_model* m, const double pos[3], double lum,
+                                           const double* l_nu_bin, int n_nu);
+/* SED and image binning of escaping packets (Sec. 2.6.1): n_incl bins of
+ * |d_z|; images of img_npix^2 pixels over +-img_half_width (cm) for the listed
+ * frequency bins. */
+mcrt_status mcrt_set_observers(mcrt_model* m, int n_incl, int img_npix, double img_half_width,
+                               const int* img_nu_bins, int n_img_nu);
+mcrt_status mcrt_run_cfg_default(mcrt_run_cfg* cfg);
+mcrt_status mcrt_set_run(mcrt_model* m, const mcrt_run_cfg* cfg);
+/* Temperatures (K, > 0) that the next iteration re-emits from (warm start). */
+mcrt_status mcrt_set_temperature(mcrt_model* m, const double* T, size_t n);
+mcrt_status mcrt_set_temperature_device(mcrt_model* m, const void* d_T, int is_fp64, size_t n);
+
+/* ---- running ------------------------------------------------------------- */
+/* One Lucy iteration (Sec. 2.3-2.4): transport n_packets with the emission of
+ * the current temperatures, Ȧ by Eq. 2, T by Eq. 3, convergence statistics. */
+mcrt_status mcrt_iterate(mcrt_model* m, mcrt_iter_stats* st);
+/* Final binning pass at fixed temperatures (Sec. 2.6.1); Ȧ is not updated. */
+mcrt_status mcrt_final_pass(mcrt_model* m, mcrt_iter_stats* st);
+/* Iterations until n_iter or the stopping criterion, then the final pass. */
+mcrt_status mcrt_run(mcrt_model* m, mcrt_run_stats* st);
+
+/* ---- results ------------------------------------------------------------- */
+mcrt_status mcrt_get_specific_energy(mcrt_model* m, double* adot, double* adot_sigma, size_t n);
+mcrt_status mcrt_get_temperature(mcrt_model* m, double* T, size_t n);
+/* Device pointer to the FP64 temperature field (valid until the next call). */
+mcrt_status mcrt_get_temperature_device(mcrt_model* m, const double** d_T);
+/* SED [n_incl][n_nu]: sum of energies, sum of squares, packet counts. */
+mcrt_status mcrt_get_sed(mcrt_model* m, double* sum, double* sum2, int64_t* count, size_t n);
+/* Images [n_img_nu][n_incl][npix][npix]: sum of energies and of squares. */
+mcrt_status mcrt_get_images(mcrt_model* m, double* sum, double* sum2, size_t n);
+/* Event log of the last pass: ev[p*cap + i], counts[p] events of packet p
+ * (may exceed cap: later events were dropped).  Returns MCRT_OK. */
+mcrt_status mcrt_get_event_log(mcrt_model* m, mcrt_event* ev, size_t cap_total, int32_t* counts,
+                               size_t n_counts);
+/* Number of compute units of the model's device. */
+mcrt_status mcrt_device_info(mcrt_model* m, int* n_cu, int* wave_size);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* MCRT_H */

@@ -85,6 +85,8 @@ def lib():
         L.orc_iterate.argtypes = [vp, C.POINTER(IterStats)]
         L.orc_final_pass.argtypes = [vp, C.POINTER(IterStats)]
         L.orc_transport_sample.argtypes = [vp, C.c_int64, C.POINTER(IterStats)]
+        L.orc_transport_range.argtypes = [vp, C.c_int64, C.c_int64, C.c_int64, C.c_int,
+                                          C.POINTER(IterStats)]
         L.orc_get_specific_energy.argtypes = [vp, _dp, C.c_void_p, C.c_size_t]
         L.orc_get_temperature.argtypes = [vp, _dp, C.c_size_t]
         L.orc_get_absorbed_sum.argtypes = [vp, _dp, C.c_size_t]
@@ -262,6 +264,13 @@ class OracleModel:
     def transport_sample(self, n_packets: int) -> dict:
         st = IterStats()
         self._check(self.L.orc_transport_sample(self.h, int(n_packets), C.byref(st)))
+        return st.as_dict()
+
+    def transport_range(self, np_total: int, p_first: int, p_count: int, final_pass=False) -> dict:
+        st = IterStats()
+        self._check(self.L.orc_transport_range(self.h, int(np_total), int(p_first), int(p_count),
+                                               int(bool(final_pass)), C.byref(st)))
+        self._log_count = min(int(self.run.get("event_log_packets", 0)), int(p_count))
         return st.as_dict()
 
     def run_all(self):

@@ -277,6 +277,7 @@ struct orc_model {
     orc_event* evlog;
     int32_t* evcount;
     int ev_packets, ev_cap;
+    int64_t ev_first;
 };
 
 static int fail(orc_model* m, const char* msg)
@@ -697,10 +698,11 @@ typedef struct {
 
 static void log_event(const orc_model* m, int64_t p, int type, const int c[3], int k, int incl)
 {
-    if (p >= m->ev_packets) return;
-    int32_t i = m->evcount[p];
+    int64_t q = p - m->ev_first; /* slot of the packet in the log */
+    if (q < 0 || q >= m->ev_packets) return;
+    int32_t i = m->evcount[q];
     if (i < m->ev_cap) {
-        orc_event* e = m->evlog + (size_t)p * m->ev_cap + i;
+        orc_event* e = m->evlog + (size_t)q * m->ev_cap + i;
         e->packet = p;
         e->index = i;
         e->type = type;
@@ -709,7 +711,7 @@ static void log_event(const orc_model* m, int64_t p, int type, const int c[3], i
         e->incl = incl;
         e->reserved = 0;
     }
-    m->evcount[p] = i + 1;
+    m->evcount[q] = i + 1;
 }
 
 /*
@@ -902,14 +904,15 @@ static int64_t rows_from_T(orc_model* m)
  * afterwards (results are independent of the partition up to the order of
  * floating-point summation, Sec. 3).
  */
-static int transport(orc_model* m, int64_t np, uint32_t key1, int binning, orc_iter_stats* st)
+static int transport(orc_model* m, int64_t np, int64_t p_first, int64_t p_count, uint32_t key1,
+                     int binning, orc_iter_stats* st)
 {
     int nt = 1;
 #ifdef _OPENMP
     nt = m->cfg.n_threads > 0 ? m->cfg.n_threads : omp_get_max_threads();
 #endif
     int64_t chunk = m->cfg.chunk > 0 ? m->cfg.chunk : 1024;
-    int64_t nchunk = (np + chunk - 1) / chunk;
+    int64_t nchunk = (p_count + chunk - 1) / chunk;
     size_t nc = (size_t)m->ncell;
     size_t ns = (size_t)m->n_incl * m->nnu;
     size_t ni = (size_t)m->n_img * m->n_incl * m->npix * m->npix;
@@ -926,7 +929,8 @@ static int transport(orc_model* m, int64_t np, uint32_t key1, int binning, orc_i
     }
     /* event log */
     free(m->evlog); free(m->evcount);
-    m->ev_packets = (int)(m->cfg.event_log_packets < np ? m->cfg.event_log_packets : np);
+    m->ev_packets = (int)(m->cfg.event_log_packets < p_count ? m->cfg.event_log_packets : p_count);
+    m->ev_first = p_first;
     m->ev_cap = m->cfg.event_log_cap;
     m->evlog = (orc_event*)calloc((size_t)(m->ev_packets ? m->ev_packets : 1) * m->ev_cap, sizeof(orc_event));
     m->evcount = (int32_t*)calloc(m->ev_packets ? m->ev_packets : 1, sizeof(int32_t));
@@ -940,8 +944,9 @@ static int transport(orc_model* m, int64_t np, uint32_t key1, int binning, orc_i
 #ifdef _OPENMP
         tid = omp_get_thread_num();
 #endif
-        int64_t p1 = (ch + 1) * chunk < np ? (ch + 1) * chunk : np;
-        for (int64_t p = ch * chunk; p < p1; ++p) run_packet(m, key1, p, np, binning, &T[tid]);
+        int64_t p1 = (ch + 1) * chunk < p_count ? (ch + 1) * chunk : p_count;
+        for (int64_t p = ch * chunk; p < p1; ++p)
+            run_packet(m, key1, p_first + p, np, binning, &T[tid]);
     }
     double t1 = now_seconds();
 
@@ -1156,7 +1161,9 @@ int orc_iterate(orc_model* m, orc_iter_stats* st)
     memset(m->acc, 0, (size_t)m->ncell * sizeof(double));
     memset(m->acc2, 0, (size_t)m->ncell * sizeof(double));
     if (m->cfg.bin_every_iteration) clear_bins(m);
-    if (transport(m, m->cfg.n_packets, (uint32_t)m->iter, m->cfg.bin_every_iteration, st)) return -1;
+    if (transport(m, m->cfg.n_packets, 0, m->cfg.n_packets, (uint32_t)m->iter,
+                  m->cfg.bin_every_iteration, st))
+        return -1;
     finish_iteration(m, st);
     st->iteration = m->iter;
     m->iter++;
@@ -1172,7 +1179,7 @@ int orc_final_pass(orc_model* m, orc_iter_stats* st)
     memset(m->acc2, 0, (size_t)m->ncell * sizeof(double));
     clear_bins(m);
     int64_t np = m->cfg.n_packets_final > 0 ? m->cfg.n_packets_final : m->cfg.n_packets;
-    if (transport(m, np, 0x80000000u | (uint32_t)m->iter, 1, st)) return -1;
+    if (transport(m, np, 0, np, 0x80000000u | (uint32_t)m->iter, 1, st)) return -1;
     st->iteration = m->iter;
     return 0;
 }
@@ -1185,8 +1192,24 @@ int orc_transport_sample(orc_model* m, int64_t n_packets, orc_iter_stats* st)
     st->n_row_clamped = rows_from_T(m);
     memset(m->acc, 0, (size_t)m->ncell * sizeof(double));
     memset(m->acc2, 0, (size_t)m->ncell * sizeof(double));
-    /* energy per packet as in a full iteration of cfg.n_packets packets */
-    if (transport(m, n_packets, (uint32_t)m->iter, 0, st)) return -1;
+    if (transport(m, n_packets, 0, n_packets, (uint32_t)m->iter, 0, st)) return -1;
+    st->iteration = m->iter;
+    return 0;
+}
+
+int orc_transport_range(orc_model* m, int64_t np_total, int64_t p_first, int64_t p_count,
+                        int final_pass, orc_iter_stats* st)
+{
+    if (ready(m)) return -1;
+    if (np_total < 1 || p_first < 0 || p_count < 0 || p_first + p_count > np_total)
+        return fail(m, "bad packet range");
+    memset(st, 0, sizeof *st);
+    st->n_row_clamped = rows_from_T(m);
+    memset(m->acc, 0, (size_t)m->ncell * sizeof(double));
+    memset(m->acc2, 0, (size_t)m->ncell * sizeof(double));
+    clear_bins(m);
+    uint32_t key1 = final_pass ? (0x80000000u | (uint32_t)m->iter) : (uint32_t)m->iter;
+    if (transport(m, np_total, p_first, p_count, key1, final_pass, st)) return -1;
     st->iteration = m->iter;
     return 0;
 }

@@ -108,6 +108,12 @@ int orc_final_pass(orc_model* m, orc_iter_stats* st);   /* binning pass at fixed
  * accumulating into the model's absorption and binning arrays; used to time
  * the propagation on a bounded sample.  No temperature update. */
 int orc_transport_sample(orc_model* m, int64_t n_packets, orc_iter_stats* st);
+/* Packets [p_first, p_first+p_count) of a pass of np_total packets (energy
+ * per packet L/np_total), the Lucy-iteration key of the next iteration or the
+ * final-pass key; the event log covers packets from p_first on.  No
+ * temperature update. */
+int orc_transport_range(orc_model* m, int64_t np_total, int64_t p_first, int64_t p_count,
+                        int final_pass, orc_iter_stats* st);
 
 /* --- results ------------------------------------------------------------ */
 int orc_get_specific_energy(const orc_model* m, double* adot, double* adot_sigma, size_t n);

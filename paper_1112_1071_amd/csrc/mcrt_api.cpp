@@ -1,0 +1,1019 @@
+// mcrt_api.cpp -- host side of libmcrt: argument validation, FP64 table
+// construction, device memory, and the Lucy iteration driver (Robitaille
+// 2011, Sec. 2: inputs -> propagation -> Adot -> convergence -> SEDs/images).
+#include <hip/hip_runtime.h>
+#include <math.h>
+#include <string.h>
+
+#include <chrono>
+#include <string>
+#include <vector>
+
+#include "mcrt_internal.h"
+#include "mcrt_tables.h"
+
+namespace mcrt {
+template <typename R>
+hipError_t launch_transport(const TransportParams<R>& P, int blocks, int threads, hipStream_t st);
+template <typename R> int transport_max_blocks_per_cu(int threads);
+hipError_t launch_rows64(int64_t, const double*, const double*, double*, unsigned long long*, int,
+                         hipStream_t);
+hipError_t launch_rows32(int64_t, const double*, const double*, float*, unsigned long long*, int,
+                         hipStream_t);
+hipError_t launch_update(const CellParams& P, int blocks, hipStream_t st);
+hipError_t launch_select(int64_t n, const double* v, unsigned long long* sel, unsigned int* hist,
+                         int blocks, hipStream_t st);
+hipError_t launch_to_f32(int64_t n, const double* in, float* out, int blocks, hipStream_t st);
+hipError_t launch_to_f64(int64_t n, const float* in, double* out, int blocks, hipStream_t st);
+hipError_t launch_check_T(int64_t n, const double* T, unsigned long long* bad, int blocks,
+                          hipStream_t st);
+hipError_t launch_check_rho(int64_t n, const double* rho, unsigned long long* bad, int blocks,
+                            hipStream_t st);
+hipError_t launch_fill_u8(int64_t n, unsigned char* p, unsigned char v, int blocks, hipStream_t st);
+hipError_t launch_fill_f64(int64_t n, double* p, double v, int blocks, hipStream_t st);
+}  // namespace mcrt
+
+using namespace mcrt;
+
+namespace {
+
+template <typename T> struct DBuf {
+    T* p = nullptr;
+    size_t n = 0;
+    hipError_t ensure(size_t count) {
+        if (count <= n && p) return hipSuccess;
+        if (p) hipFree(p);
+        p = nullptr;
+        n = 0;
+        hipError_t e = hipMalloc((void**)&p, (count ? count : 1) * sizeof(T));
+        if (e == hipSuccess) n = count;
+        return e;
+    }
+    void release() {
+        if (p) hipFree(p);
+        p = nullptr;
+        n = 0;
+    }
+};
+
+struct Source {
+    double pos[3];
+    double lum;
+    std::vector<double> spec;  // relative luminosity per bin
+};
+
+double now_ms() {
+    return std::chrono::duration<double, std::milli>(
+               std::chrono::steady_clock::now().time_since_epoch())
+        .count();
+}
+
+}  // namespace
+
+struct mcrt_model {
+    std::string err;
+    int device = 0;
+    hipStream_t stream = nullptr;
+    bool own_stream = false;
+    int n_cu = 256;
+    // problem
+    bool have_grid = false, have_rho = false, have_nu = false, have_dust = false,
+         have_obs = false, have_run = false;
+    int n[3] = {0, 0, 0};
+    double lo[3] = {0, 0, 0}, hi[3] = {0, 0, 0}, dx[3] = {0, 0, 0}, vol = 0.0;
+    int64_t ncell = 0;
+    std::vector<double> nu, chi, alb, g, kap;
+    std::vector<Source> src;
+    int n_incl = 10, npix = 0, n_img = 0;
+    double img_hw = 0.0;
+    std::vector<int> img_bins;
+    mcrt_run_cfg cfg;
+    bool tables_dirty = true;
+    bool state_ready = false;
+    // device problem data
+    DBuf<double> rho64;
+    DBuf<float> rho32;
+    DBuf<double> chi64, kap64, alb64, g64, lcdf64, scdf64, ecdf64;
+    DBuf<float> chi32, kap32, alb32, g32, lcdf32, scdf32, ecdf32;
+    DBuf<double> spos, sweight, lnA, slope;
+    DBuf<int> img_of_bin;
+    double dy = 0.0;
+    double ltot = 0.0;
+    // device state
+    DBuf<double> acc, acc2, adot, adot_prev, adot_sig, T, T_prev, sig_rel, sig_rel_prev;
+    DBuf<unsigned char> valid, valid_prev;
+    DBuf<double> rowpos64, Rbuf, rbuf;
+    DBuf<float> rowpos32;
+    DBuf<double> sed_sum, sed_sum2, img_sum, img_sum2;
+    DBuf<unsigned long long> sed_n;
+    DBuf<mcrt_event> evlog;
+    DBuf<int32_t> evcount;
+    DBuf<unsigned long long> misc;  // pool, counters[C_COUNT], stats[8], sel[3], scratch
+    DBuf<double> energies;
+    DBuf<unsigned int> hist;
+    int64_t ev_packets = 0;
+    int ev_cap = 0;
+    // iteration state
+    int iter = 0;
+    int have_prev = 0;
+    double q_prev = INFINITY;
+    hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};
+};
+
+namespace {
+
+constexpr int MISC_POOL = 0;
+constexpr int MISC_CNT = 1;                  // C_COUNT entries
+constexpr int MISC_STATS = 1 + C_COUNT;      // 8 entries
+constexpr int MISC_SEL = MISC_STATS + 8;     // 3 entries
+constexpr int MISC_SCRATCH = MISC_SEL + 3;   // 2 entries
+constexpr int MISC_N = MISC_SCRATCH + 2;
+
+mcrt_status fail(mcrt_model* m, mcrt_status s, const std::string& msg) {
+    m->err = msg;
+    return s;
+}
+
+#define HIPCHK(expr)                                                                         \
+    do {                                                                                     \
+        hipError_t e_ = (expr);                                                              \
+        if (e_ != hipSuccess)                                                                \
+            return fail(m, e_ == hipErrorOutOfMemory ? MCRT_E_NOMEM : MCRT_E_DEVICE,         \
+                        std::string(#expr) + ": " + hipGetErrorString(e_));                  \
+    } while (0)
+
+int grid_blocks(const mcrt_model* m, int64_t n) {
+    int64_t b = (n + 255) / 256;
+    int64_t cap = (int64_t)m->n_cu * 8;
+    if (b > cap) b = cap;
+    return (int)(b < 1 ? 1 : b);
+}
+
+template <typename T>
+hipError_t upload(DBuf<T>& b, const std::vector<T>& h, hipStream_t st) {
+    hipError_t e = b.ensure(h.size());
+    if (e != hipSuccess) return e;
+    if (h.empty()) return hipSuccess;
+    return hipMemcpyAsync(b.p, h.data(), h.size() * sizeof(T), hipMemcpyHostToDevice, st);
+}
+
+std::vector<float> to_f32(const std::vector<double>& v) {
+    return std::vector<float>(v.begin(), v.end());
+}
+
+mcrt_status build_tables(mcrt_model* m) {
+    const size_t nb = m->kap.size();
+    // sources: spectral CDFs, luminosity CDF, per-source weights
+    std::vector<double> scdf(m->src.size() * nb), lcdf(m->src.size()), spos(3 * m->src.size());
+    m->ltot = 0.0;
+    for (const Source& s : m->src) m->ltot += s.lum;
+    double acc = 0.0;
+    std::vector<double> c;
+    for (size_t i = 0; i < m->src.size(); ++i) {
+        cumulative(m->src[i].spec, c);
+        for (size_t k = 0; k < nb; ++k) scdf[i * nb + k] = c[k];
+        acc += m->src[i].lum;
+        lcdf[i] = acc / m->ltot;
+        for (int a = 0; a < 3; ++a) spos[3 * i + a] = m->src[i].pos[a];
+    }
+    lcdf.back() = 1.0;
+    const size_t ns = m->src.size();
+    std::vector<double> ecdf, lnA, slope;
+    emission_rows(m->nu, m->kap, ecdf);
+    tsolve_table(m->nu, m->kap, lnA, slope, &m->dy);
+    std::vector<int> iob(nb, -1);
+    for (int i = 0; i < m->n_img; ++i) iob[m->img_bins[i]] = i;
+    hipStream_t st = m->stream;
+    HIPCHK(upload(m->chi64, m->chi, st));
+    HIPCHK(upload(m->kap64, m->kap, st));
+    HIPCHK(upload(m->alb64, m->alb, st));
+    HIPCHK(upload(m->g64, m->g, st));
+    HIPCHK(upload(m->lcdf64, lcdf, st));
+    HIPCHK(upload(m->scdf64, scdf, st));
+    HIPCHK(upload(m->ecdf64, ecdf, st));
+    // host copies stay alive until the stream synchronisation below
+    const std::vector<float> chi32 = to_f32(m->chi), kap32 = to_f32(m->kap),
+                             alb32 = to_f32(m->alb), g32 = to_f32(m->g);
+    HIPCHK(upload(m->chi32, chi32, st));
+    HIPCHK(upload(m->kap32, kap32, st));
+    HIPCHK(upload(m->alb32, alb32, st));
+    HIPCHK(upload(m->g32, g32, st));
+    std::vector<float> lcdf32 = to_f32(lcdf), scdf32 = to_f32(scdf), ecdf32 = to_f32(ecdf);
+    // a rounded CDF must still end at exactly 1
+    lcdf32.back() = 1.0f;
+    for (size_t i = 0; i < ns; ++i) scdf32[i * nb + nb - 1] = 1.0f;
+    for (int r = 0; r < kRows; ++r) ecdf32[(size_t)r * nb + nb - 1] = 1.0f;
+    HIPCHK(upload(m->lcdf32, lcdf32, st));
+    HIPCHK(upload(m->scdf32, scdf32, st));
+    HIPCHK(upload(m->ecdf32, ecdf32, st));
+    HIPCHK(upload(m->spos, spos, st));
+    HIPCHK(upload(m->lnA, lnA, st));
+    HIPCHK(upload(m->slope, slope, st));
+    HIPCHK(upload(m->img_of_bin, iob, st));
+    HIPCHK(hipStreamSynchronize(st));
+    m->tables_dirty = false;
+    return MCRT_OK;
+}
+
+mcrt_status ensure_state(mcrt_model* m) {
+    if (m->state_ready) return MCRT_OK;
+    const size_t nc = (size_t)m->ncell;
+    HIPCHK(m->acc.ensure(nc));
+    HIPCHK(m->acc2.ensure(nc));
+    HIPCHK(m->adot.ensure(nc));
+    HIPCHK(m->adot_prev.ensure(nc));
+    HIPCHK(m->adot_sig.ensure(nc));
+    HIPCHK(m->T.ensure(nc));
+    HIPCHK(m->T_prev.ensure(nc));
+    HIPCHK(m->sig_rel.ensure(nc));
+    HIPCHK(m->sig_rel_prev.ensure(nc));
+    HIPCHK(m->valid.ensure(nc));
+    HIPCHK(m->valid_prev.ensure(nc));
+    HIPCHK(m->Rbuf.ensure(nc));
+    HIPCHK(m->rbuf.ensure(nc));
+    HIPCHK(m->misc.ensure(MISC_N));
+    HIPCHK(m->energies.ensure(2));
+    HIPCHK(m->hist.ensure(256));
+    hipStream_t st = m->stream;
+    const int b = grid_blocks(m, m->ncell);
+    HIPCHK(launch_fill_f64(m->ncell, m->T.p, m->cfg.t_init, b, st));
+    HIPCHK(launch_fill_f64(m->ncell, m->adot.p, 0.0, b, st));
+    HIPCHK(launch_fill_f64(m->ncell, m->sig_rel.p, 0.0, b, st));
+    HIPCHK(launch_fill_f64(m->ncell, m->adot_sig.p, 0.0, b, st));
+    HIPCHK(launch_fill_u8(m->ncell, m->valid.p, 1, b, st));
+    HIPCHK(hipMemsetAsync(m->hist.p, 0, 256 * sizeof(unsigned int), st));
+    HIPCHK(hipStreamSynchronize(st));
+    m->iter = 0;
+    m->have_prev = 0;
+    m->q_prev = INFINITY;
+    m->state_ready = true;
+    return MCRT_OK;
+}
+
+mcrt_status ensure_bins(mcrt_model* m) {
+    const size_t ns = (size_t)m->n_incl * m->kap.size();
+    const size_t ni = (size_t)m->n_img * m->n_incl * m->npix * m->npix;
+    HIPCHK(m->sed_sum.ensure(ns));
+    HIPCHK(m->sed_sum2.ensure(ns));
+    HIPCHK(m->sed_n.ensure(ns));
+    HIPCHK(m->img_sum.ensure(ni));
+    HIPCHK(m->img_sum2.ensure(ni));
+    return MCRT_OK;
+}
+
+mcrt_status clear_bins(mcrt_model* m) {
+    const size_t ns = (size_t)m->n_incl * m->kap.size();
+    const size_t ni = (size_t)m->n_img * m->n_incl * m->npix * m->npix;
+    hipStream_t st = m->stream;
+    HIPCHK(hipMemsetAsync(m->sed_sum.p, 0, ns * sizeof(double), st));
+    HIPCHK(hipMemsetAsync(m->sed_sum2.p, 0, ns * sizeof(double), st));
+    HIPCHK(hipMemsetAsync(m->sed_n.p, 0, ns * sizeof(unsigned long long), st));
+    if (ni) {
+        HIPCHK(hipMemsetAsync(m->img_sum.p, 0, ni * sizeof(double), st));
+        HIPCHK(hipMemsetAsync(m->img_sum2.p, 0, ni * sizeof(double), st));
+    }
+    return MCRT_OK;
+}
+
+mcrt_status ready(mcrt_model* m) {
+    if (!m->have_grid || !m->have_rho) return fail(m, MCRT_E_STATE, "grid and density must be set");
+    if (!m->have_dust) return fail(m, MCRT_E_STATE, "dust must be set");
+    if (m->src.empty()) return fail(m, MCRT_E_STATE, "add at least one source");
+    if (!m->have_run) return fail(m, MCRT_E_STATE, "run parameters must be set");
+    if (!m->have_obs) {
+        mcrt_status s = mcrt_set_observers(m, 10, 0, 0.0, nullptr, 0);
+        if (s != MCRT_OK) return s;
+    }
+    if (m->tables_dirty) {
+        mcrt_status s = build_tables(m);
+        if (s != MCRT_OK) return s;
+    }
+    mcrt_status s = ensure_state(m);
+    if (s != MCRT_OK) return s;
+    return ensure_bins(m);
+}
+
+// Emission rows from T, zeroed tallies, then one transport launch.
+mcrt_status run_transport(mcrt_model* m, int64_t np, uint32_t key1, int binning,
+                          mcrt_iter_stats* st) {
+    hipStream_t s = m->stream;
+    const size_t nc = (size_t)m->ncell;
+    const bool f32 = m->cfg.precision == MCRT_FP32_TRANSPORT;
+    unsigned long long* misc = m->misc.p;
+    HIPCHK(hipMemsetAsync(misc, 0, MISC_N * sizeof(unsigned long long), s));
+    HIPCHK(hipMemsetAsync(m->energies.p, 0, 2 * sizeof(double), s));
+    const int cb = grid_blocks(m, m->ncell);
+    if (f32) {
+        HIPCHK(m->rowpos32.ensure(nc));
+        HIPCHK(launch_rows32(m->ncell, m->T.p, m->rho64.p, m->rowpos32.p, misc + MISC_SCRATCH, cb, s));
+    } else {
+        HIPCHK(m->rowpos64.ensure(nc));
+        HIPCHK(launch_rows64(m->ncell, m->T.p, m->rho64.p, m->rowpos64.p, misc + MISC_SCRATCH, cb, s));
+    }
+    HIPCHK(hipMemsetAsync(m->acc.p, 0, nc * sizeof(double), s));
+    if (m->cfg.want_noise) HIPCHK(hipMemsetAsync(m->acc2.p, 0, nc * sizeof(double), s));
+    // event log
+    m->ev_packets = m->cfg.event_log_packets < np ? m->cfg.event_log_packets : np;
+    m->ev_cap = m->cfg.event_log_cap > 0 ? m->cfg.event_log_cap : 256;
+    if (m->ev_packets > 0) {
+        HIPCHK(m->evlog.ensure((size_t)m->ev_packets * m->ev_cap));
+        HIPCHK(m->evcount.ensure((size_t)m->ev_packets));
+        HIPCHK(hipMemsetAsync(m->evcount.p, 0, (size_t)m->ev_packets * sizeof(int32_t), s));
+    }
+    const int threads = m->cfg.block_size > 0 ? m->cfg.block_size : 256;
+    int bpc = m->cfg.blocks_per_cu;
+    if (bpc <= 0)
+        bpc = f32 ? transport_max_blocks_per_cu<float>(threads)
+                  : transport_max_blocks_per_cu<double>(threads);
+    int64_t blocks = (int64_t)m->n_cu * bpc;
+    const int64_t need = (np + threads - 1) / threads;
+    if (blocks > need) blocks = need;
+    if (blocks < 1) blocks = 1;
+    const double eps0 = m->ltot / (double)np;
+    {
+        // equal-number sampling: source i gets floor(np/ns) or one more packets,
+        // each carrying L_i / count (relative to eps0)
+        const size_t ns = m->src.size();
+        std::vector<double> sw(ns);
+        for (size_t i = 0; i < ns; ++i) {
+            const int64_t cnt = np / (int64_t)ns + ((int64_t)i < np % (int64_t)ns ? 1 : 0);
+            sw[i] = (m->src[i].lum / (double)(cnt > 0 ? cnt : 1)) / eps0;
+        }
+        HIPCHK(m->sweight.ensure(ns));
+        HIPCHK(hipMemcpy(m->sweight.p, sw.data(), ns * sizeof(double), hipMemcpyHostToDevice));
+    }
+
+    auto fill = [&](auto& P, auto* rho, auto* chi, auto* kap, auto* alb, auto* gg, auto* lcdf,
+                    auto* scdf, auto* ecdf, auto* rowpos) {
+        using R = typename std::remove_pointer<decltype(rho)>::type;
+        for (int a = 0; a < 3; ++a) {
+            P.n[a] = m->n[a];
+            P.lo[a] = m->lo[a];
+            P.dx[a] = m->dx[a];
+            P.dxr[a] = (R)m->dx[a];
+            P.inv_dx[a] = (R)(1.0 / m->dx[a]);
+        }
+        P.rho = rho;
+        P.nnu = (int)m->kap.size();
+        P.chi = chi;
+        P.kap = kap;
+        P.alb = alb;
+        P.g = gg;
+        P.nsrc = (int)m->src.size();
+        P.sampling = m->cfg.source_sampling;
+        P.spos = m->spos.p;
+        P.lcdf = lcdf;
+        P.scdf = scdf;
+        P.sweight = m->sweight.p;
+        P.ecdf = ecdf;
+        P.rowpos = rowpos;
+        P.key0 = (uint32_t)(m->cfg.seed & 0xffffffffu);
+        P.key1 = key1;
+        P.n_packets = (uint64_t)np;
+        P.packet_base = 0;
+        P.pool = misc + MISC_POOL;
+        P.eps0 = eps0;
+        P.max_events = m->cfg.max_events;
+        P.defer_lanes = m->cfg.defer_lanes > 0 ? m->cfg.defer_lanes : 16;
+        P.acc = m->acc.p;
+        P.acc2 = m->cfg.want_noise ? m->acc2.p : nullptr;
+        P.binning = binning;
+        P.n_incl = m->n_incl;
+        P.sed_sum = m->sed_sum.p;
+        P.sed_sum2 = m->sed_sum2.p;
+        P.sed_n = m->sed_n.p;
+        P.n_img = m->n_img;
+        P.npix = m->npix;
+        P.img_hw = m->img_hw;
+        P.img_of_bin = m->img_of_bin.p;
+        P.img_sum = m->img_sum.p;
+        P.img_sum2 = m->img_sum2.p;
+        P.ev_packets = m->ev_packets;
+        P.ev_cap = m->ev_cap;
+        P.evlog = m->evlog.p;
+        P.evcount = m->evcount.p;
+        P.counters = misc + MISC_CNT;
+        P.energies = m->energies.p;
+    };
+    HIPCHK(hipEventRecord(m->ev[0], s));
+    if (f32) {
+        if (!m->rho32.p) return fail(m, MCRT_E_STATE, "no FP32 density");
+        TransportParams<float> P{};
+        fill(P, (const float*)m->rho32.p, (const float*)m->chi32.p, (const float*)m->kap32.p,
+             (const float*)m->alb32.p, (const float*)m->g32.p, (const float*)m->lcdf32.p,
+             (const float*)m->scdf32.p, (const float*)m->ecdf32.p, (const float*)m->rowpos32.p);
+        HIPCHK(launch_transport<float>(P, (int)blocks, threads, s));
+    } else {
+        TransportParams<double> P{};
+        fill(P, (const double*)m->rho64.p, (const double*)m->chi64.p, (const double*)m->kap64.p,
+             (const double*)m->alb64.p, (const double*)m->g64.p, (const double*)m->lcdf64.p,
+             (const double*)m->scdf64.p, (const double*)m->ecdf64.p, (const double*)m->rowpos64.p);
+        HIPCHK(launch_transport<double>(P, (int)blocks, threads, s));
+    }
+    HIPCHK(hipEventRecord(m->ev[1], s));
+    // counters
+    unsigned long long h[MISC_N];
+    double e[2];
+    HIPCHK(hipMemcpyAsync(h, misc, sizeof h, hipMemcpyDeviceToHost, s));
+    HIPCHK(hipMemcpyAsync(e, m->energies.p, sizeof e, hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    float ms = 0.f;
+    HIPCHK(hipEventElapsedTime(&ms, m->ev[0], m->ev[1]));
+    st->ms_transport = ms;
+    st->n_row_clamped = (int64_t)h[MISC_SCRATCH];
+    st->n_cross_dust = (int64_t)h[MISC_CNT + C_CROSS_DUST];
+    st->n_cross_empty = (int64_t)h[MISC_CNT + C_CROSS_EMPTY];
+    st->n_scatter = (int64_t)h[MISC_CNT + C_SCATTER];
+    st->n_absorb = (int64_t)h[MISC_CNT + C_ABSORB];
+    st->n_escape = (int64_t)h[MISC_CNT + C_ESCAPE];
+    st->n_killed = (int64_t)h[MISC_CNT + C_KILLED];
+    st->e_escaped = e[0];
+    st->e_killed = e[1];
+    st->precision = m->cfg.precision;
+    return MCRT_OK;
+}
+
+mcrt_status select_rank(mcrt_model* m, const double* v, uint64_t rank, double* out) {
+    hipStream_t s = m->stream;
+    unsigned long long init[3] = {0ull, (unsigned long long)rank, 0ull};
+    unsigned long long* sel = m->misc.p + MISC_SEL;
+    HIPCHK(hipMemcpyAsync(sel, init, sizeof init, hipMemcpyHostToDevice, s));
+    HIPCHK(launch_select(m->ncell, v, sel, m->hist.p, grid_blocks(m, m->ncell), s));
+    unsigned long long res[3];
+    HIPCHK(hipMemcpyAsync(res, sel, sizeof res, hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    double d;
+    memcpy(&d, &res[0], sizeof d);
+    *out = d;
+    return MCRT_OK;
+}
+
+uint64_t nearest_rank(double p, int64_t n) {
+    int64_t r = (int64_t)ceil(p * (double)n);
+    if (r < 1) r = 1;
+    if (r > n) r = n;
+    return (uint64_t)(r - 1);
+}
+
+// Adot, T and the convergence statistics after a Lucy pass (Eqs. 2-6).
+mcrt_status update_cells(mcrt_model* m, mcrt_iter_stats* st) {
+    hipStream_t s = m->stream;
+    unsigned long long* stats = m->misc.p + MISC_STATS;
+    HIPCHK(hipMemsetAsync(stats, 0, 8 * sizeof(unsigned long long), s));
+    CellParams P{};
+    P.ncell = m->ncell;
+    P.eps_over_vol = (m->ltot / (double)m->cfg.n_packets) / m->vol;
+    P.rho = m->rho64.p;
+    P.acc = m->acc.p;
+    P.acc2 = m->cfg.want_noise ? m->acc2.p : nullptr;
+    P.adot = m->adot.p;
+    P.adot_prev = m->adot_prev.p;
+    P.adot_sig = m->adot_sig.p;
+    P.T = m->T.p;
+    P.T_prev = m->T_prev.p;
+    P.sig_rel = m->sig_rel.p;
+    P.sig_rel_prev = m->sig_rel_prev.p;
+    P.valid = m->valid.p;
+    P.valid_prev = m->valid_prev.p;
+    P.lnA = m->lnA.p;
+    P.slope = m->slope.p;
+    P.dy = m->dy;
+    P.have_prev = m->have_prev;
+    P.want_noise = m->cfg.want_noise;
+    P.noise_thres = m->cfg.conv_noise_thres;
+    P.Rbuf = m->Rbuf.p;
+    P.rbuf = m->rbuf.p;
+    P.stats = stats;
+    HIPCHK(hipEventRecord(m->ev[2], s));
+    HIPCHK(launch_update(P, grid_blocks(m, m->ncell), s));
+    unsigned long long h[8];
+    HIPCHK(hipMemcpyAsync(h, stats, sizeof h, hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    st->n_r = (int64_t)h[0];
+    st->n_mask = (int64_t)h[1];
+    st->n_unsampled = (int64_t)h[2];
+    st->n_t_clamped = (int64_t)h[3];
+    double rmax;
+    memcpy(&rmax, &h[4], sizeof rmax);
+    if (st->n_r > 0) {
+        mcrt_status r = select_rank(m, m->Rbuf.p, nearest_rank(m->cfg.conv_p, st->n_r), &st->q);
+        if (r != MCRT_OK) return r;
+    } else {
+        st->q = INFINITY;
+    }
+    st->delta = (isfinite(st->q) && isfinite(m->q_prev))
+                    ? (st->q > m->q_prev ? st->q / m->q_prev : m->q_prev / st->q)
+                    : INFINITY;
+    st->converged_q = st->q < m->cfg.conv_q_thres && st->delta < m->cfg.conv_d_thres;
+    m->q_prev = st->q;
+    if (st->n_mask > 0) {
+        st->max_dT = rmax;
+        mcrt_status r = select_rank(m, m->rbuf.p, nearest_rank(0.999, st->n_mask), &st->p999_dT);
+        if (r != MCRT_OK) return r;
+    } else {
+        st->max_dT = INFINITY;
+        st->p999_dT = INFINITY;
+    }
+    st->converged_dT = st->n_mask > 0 && st->max_dT < m->cfg.conv_dT_thres;
+    HIPCHK(hipEventRecord(m->ev[3], s));
+    HIPCHK(hipEventSynchronize(m->ev[3]));
+    float ms = 0.f;
+    HIPCHK(hipEventElapsedTime(&ms, m->ev[2], m->ev[3]));
+    st->ms_update = ms;
+    m->have_prev = 1;
+    return MCRT_OK;
+}
+
+bool finite_all(const double* v, size_t n) {
+    for (size_t i = 0; i < n; ++i)
+        if (!isfinite(v[i])) return false;
+    return true;
+}
+
+}  // namespace
+
+extern "C" {
+
+mcrt_status mcrt_run_cfg_default(mcrt_run_cfg* c) {
+    if (!c) return MCRT_E_ARG;
+    memset(c, 0, sizeof *c);
+    c->n_packets = 100000;
+    c->n_packets_final = 0;
+    c->n_iter = 5;
+    c->precision = MCRT_FP64;
+    c->seed = 1;
+    c->t_init = 10.0;
+    c->max_events = 1000000;
+    c->conv_p = 0.999;
+    c->conv_q_thres = 2.0;
+    c->conv_d_thres = 1.1;
+    c->conv_dT_thres = 0.01;
+    c->conv_noise_thres = 0.002;
+    c->event_log_cap = 256;
+    c->block_size = 256;
+    c->defer_lanes = 16;
+    return MCRT_OK;
+}
+
+mcrt_status mcrt_create(mcrt_model** out, int hip_device) {
+    if (!out) return MCRT_E_ARG;
+    *out = nullptr;
+    int ndev = 0;
+    if (hipGetDeviceCount(&ndev) != hipSuccess || ndev < 1) return MCRT_E_DEVICE;
+    if (hip_device < 0 || hip_device >= ndev) return MCRT_E_ARG;
+    mcrt_model* m = new (std::nothrow) mcrt_model();
+    if (!m) return MCRT_E_NOMEM;
+    m->device = hip_device;
+    if (hipSetDevice(hip_device) != hipSuccess || hipStreamCreate(&m->stream) != hipSuccess) {
+        delete m;
+        return MCRT_E_DEVICE;
+    }
+    m->own_stream = true;
+    hipDeviceGetAttribute(&m->n_cu, hipDeviceAttributeMultiprocessorCount, hip_device);
+    for (int i = 0; i < 4; ++i) hipEventCreate(&m->ev[i]);
+    mcrt_run_cfg_default(&m->cfg);
+    *out = m;
+    return MCRT_OK;
+}
+
+void mcrt_destroy(mcrt_model* m) {
+    if (!m) return;
+    hipSetDevice(m->device);
+    if (m->stream) hipStreamSynchronize(m->stream);
+    for (int i = 0; i < 4; ++i)
+        if (m->ev[i]) hipEventDestroy(m->ev[i]);
+    m->rho64.release(); m->rho32.release();
+    m->chi64.release(); m->kap64.release(); m->alb64.release(); m->g64.release();
+    m->lcdf64.release(); m->scdf64.release(); m->ecdf64.release();
+    m->chi32.release(); m->kap32.release(); m->alb32.release(); m->g32.release();
+    m->lcdf32.release(); m->scdf32.release(); m->ecdf32.release();
+    m->spos.release(); m->sweight.release(); m->lnA.release(); m->slope.release();
+    m->img_of_bin.release();
+    m->acc.release(); m->acc2.release(); m->adot.release(); m->adot_prev.release();
+    m->adot_sig.release(); m->T.release(); m->T_prev.release(); m->sig_rel.release();
+    m->sig_rel_prev.release(); m->valid.release(); m->valid_prev.release();
+    m->rowpos64.release(); m->rowpos32.release(); m->Rbuf.release(); m->rbuf.release();
+    m->sed_sum.release(); m->sed_sum2.release(); m->sed_n.release();
+    m->img_sum.release(); m->img_sum2.release(); m->evlog.release(); m->evcount.release();
+    m->misc.release(); m->energies.release(); m->hist.release();
+    if (m->own_stream && m->stream) hipStreamDestroy(m->stream);
+    delete m;
+}
+
+const char* mcrt_last_error(const mcrt_model* m) { return m ? m->err.c_str() : "null model"; }
+
+mcrt_status mcrt_set_stream(mcrt_model* m, void* hip_stream) {
+    if (!m) return MCRT_E_ARG;
+    hipSetDevice(m->device);
+    hipStreamSynchronize(m->stream);
+    if (m->own_stream && m->stream) hipStreamDestroy(m->stream);
+    if (hip_stream) {
+        m->stream = (hipStream_t)hip_stream;
+        m->own_stream = false;
+    } else {
+        if (hipStreamCreate(&m->stream) != hipSuccess) return fail(m, MCRT_E_DEVICE, "stream");
+        m->own_stream = true;
+    }
+    return MCRT_OK;
+}
+
+mcrt_status mcrt_set_grid(mcrt_model* m, int nx, int ny, int nz, const double lo[3],
+                          const double hi[3]) {
+    if (!m) return MCRT_E_ARG;
+    if (nx < 1 || ny < 1 || nz < 1) return fail(m, MCRT_E_ARG, "grid dimensions must be >= 1");
+    if ((int64_t)nx * ny * nz > (int64_t)INT32_MAX)
+        return fail(m, MCRT_E_ARG, "grid has more than 2^31-1 cells");
+    if (!lo || !hi) return fail(m, MCRT_E_ARG, "null bounds");
+    for (int a = 0; a < 3; ++a)
+        if (!(hi[a] > lo[a]) || !isfinite(lo[a]) || !isfinite(hi[a]))
+            return fail(m, MCRT_E_ARG, "grid bounds must be finite with hi > lo");
+    hipSetDevice(m->device);
+    m->n[0] = nx; m->n[1] = ny; m->n[2] = nz;
+    m->vol = 1.0;
+    for (int a = 0; a < 3; ++a) {
+        m->lo[a] = lo[a];
+        m->hi[a] = hi[a];
+        m->dx[a] = (hi[a] - lo[a]) / m->n[a];
+        m->vol *= m->dx[a];
+    }
+    m->ncell = (int64_t)nx * ny * nz;
+    m->have_grid = true;
+    m->have_rho = false;
+    m->state_ready = false;
+    m->src.clear();
+    m->tables_dirty = true;
+    return MCRT_OK;
+}
+
+mcrt_status mcrt_set_density(mcrt_model* m, const double* rho, size_t n) {
+    if (!m) return MCRT_E_ARG;
+    if (!m->have_grid) return fail(m, MCRT_E_STATE, "set the grid first");
+    if (!rho) return fail(m, MCRT_E_ARG, "null density");
+    if ((int64_t)n != m->ncell) return fail(m, MCRT_E_SIZE, "density size does not match the grid");
+    for (size_t i = 0; i < n; ++i)
+        if (!(rho[i] >= 0.0) || !isfinite(rho[i]))
+            return fail(m, MCRT_E_ARG, "density must be finite and >= 0");
+    hipSetDevice(m->device);
+    HIPCHK(m->rho64.ensure(n));
+    HIPCHK(m->rho32.ensure(n));
+    HIPCHK(hipMemcpyAsync(m->rho64.p, rho, n * sizeof(double), hipMemcpyHostToDevice, m->stream));
+    HIPCHK(launch_to_f32(m->ncell, m->rho64.p, m->rho32.p, grid_blocks(m, m->ncell), m->stream));
+    HIPCHK(hipStreamSynchronize(m->stream));
+    m->have_rho = true;
+    return MCRT_OK;
+}
+
+mcrt_status mcrt_set_density_device(mcrt_model* m, const void* d_rho, int is_fp64, size_t n) {
+    if (!m) return MCRT_E_ARG;
+    if (!m->have_grid) return fail(m, MCRT_E_STATE, "set the grid first");
+    if (!d_rho) return fail(m, MCRT_E_ARG, "null density");
+    if ((int64_t)n != m->ncell) return fail(m, MCRT_E_SIZE, "density size does not match the grid");
+    hipSetDevice(m->device);
+    HIPCHK(m->rho64.ensure(n));
+    HIPCHK(m->rho32.ensure(n));
+    hipStream_t s = m->stream;
+    const int b = grid_blocks(m, m->ncell);
+    if (is_fp64) {
+        HIPCHK(hipMemcpyAsync(m->rho64.p, d_rho, n * sizeof(double), hipMemcpyDeviceToDevice, s));
+    } else {
+        HIPCHK(launch_to_f64(m->ncell, (const float*)d_rho, m->rho64.p, b, s));
+    }
+    HIPCHK(launch_to_f32(m->ncell, m->rho64.p, m->rho32.p, b, s));
+    HIPCHK(m->misc.ensure(MISC_N));
+    HIPCHK(hipMemsetAsync(m->misc.p + MISC_SCRATCH, 0, sizeof(unsigned long long), s));
+    HIPCHK(launch_check_rho(m->ncell, m->rho64.p, m->misc.p + MISC_SCRATCH, b, s));
+    unsigned long long bad = 0;
+    HIPCHK(hipMemcpyAsync(&bad, m->misc.p + MISC_SCRATCH, sizeof bad, hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    if (bad) {
+        m->have_rho = false;
+        return fail(m, MCRT_E_ARG, "density must be finite and >= 0");
+    }
+    m->have_rho = true;
+    return MCRT_OK;
+}
+
+mcrt_status mcrt_set_frequencies(mcrt_model* m, const double* nu_edges, int n_nu) {
+    if (!m) return MCRT_E_ARG;
+    if (n_nu < 1 || !nu_edges) return fail(m, MCRT_E_ARG, "need at least one frequency bin");
+    for (int k = 0; k <= n_nu; ++k)
+        if (!(nu_edges[k] > 0.0) || !isfinite(nu_edges[k]))
+            return fail(m, MCRT_E_ARG, "frequency edges must be finite and > 0");
+    for (int k = 0; k < n_nu; ++k)
+        if (!(nu_edges[k + 1] > nu_edges[k])) return fail(m, MCRT_E_ARG, "frequency edges must increase");
+    if (!m->src.empty()) return fail(m, MCRT_E_STATE, "set frequencies before adding sources");
+    m->nu.assign(nu_edges, nu_edges + n_nu + 1);
+    m->have_nu = true;
+    m->have_dust = false;
+    m->have_obs = false;
+    m->tables_dirty = true;
+    return MCRT_OK;
+}
+
+mcrt_status mcrt_set_dust(mcrt_model* m, const double* chi, const double* albedo, const double* g,
+                          int n_nu) {
+    if (!m) return MCRT_E_ARG;
+    if (!m->have_nu || n_nu != (int)m->nu.size() - 1)
+        return fail(m, MCRT_E_SIZE, "dust size does not match the frequency bins");
+    if (!chi || !albedo || !g) return fail(m, MCRT_E_ARG, "null dust array");
+    bool any = false;
+    for (int k = 0; k < n_nu; ++k) {
+        if (!(chi[k] >= 0.0) || !isfinite(chi[k])) return fail(m, MCRT_E_ARG, "chi must be finite and >= 0");
+        if (!(albedo[k] >= 0.0 && albedo[k] <= 1.0)) return fail(m, MCRT_E_ARG, "albedo must be in [0,1]");
+        if (!(fabs(g[k]) < 1.0)) return fail(m, MCRT_E_ARG, "|g| must be < 1");
+        any |= chi[k] * (1.0 - albedo[k]) > 0.0;
+    }
+    if (!any) return fail(m, MCRT_E_ARG, "dust must absorb in at least one bin");
+    m->chi.assign(chi, chi + n_nu);
+    m->alb.assign(albedo, albedo + n_nu);
+    m->g.assign(g, g + n_nu);
+    m->kap.resize(n_nu);
+    for (int k = 0; k < n_nu; ++k) m->kap[k] = chi[k] * (1.0 - albedo[k]);
+    m->have_dust = true;
+    m->tables_dirty = true;
+    return MCRT_OK;
+}
+
+static mcrt_status add_source(mcrt_model* m, const double pos[3], double lum,
+                              const std::vector<double>& spec) {
+    if (!m->have_grid || !m->have_nu)
+        return fail(m, MCRT_E_STATE, "set grid and frequencies before sources");
+    if (!pos) return fail(m, MCRT_E_ARG, "null position");
+    if (!(lum > 0.0) || !isfinite(lum)) return fail(m, MCRT_E_ARG, "luminosity must be > 0");
+    for (int a = 0; a < 3; ++a)
+        if (!(pos[a] >= m->lo[a] && pos[a] < m->hi[a]))
+            return fail(m, MCRT_E_ARG, "source outside the grid");
+    double s = 0.0;
+    for (double v : spec) {
+        if (!(v >= 0.0) || !isfinite(v)) return fail(m, MCRT_E_ARG, "spectrum must be finite and >= 0");
+        s += v;
+    }
+    if (!(s > 0.0)) return fail(m, MCRT_E_ARG, "spectrum has no power in the frequency bins");
+    Source src;
+    for (int a = 0; a < 3; ++a) src.pos[a] = pos[a];
+    src.lum = lum;
+    src.spec = spec;
+    m->src.push_back(src);
+    m->tables_dirty = true;
+    return MCRT_OK;
+}
+
+mcrt_status mcrt_add_point_source(mcrt_model* m, const double pos[3], double lum, double teff) {
+    if (!m) return MCRT_E_ARG;
+    if (!m->have_nu) return fail(m, MCRT_E_STATE, "set frequencies before sources");
+    if (!(teff > 0.0) || !isfinite(teff)) return fail(m, MCRT_E_ARG, "temperature must be > 0");
+    std::vector<double> spec;
+    blackbody_bins(m->nu, teff, spec);
+    return add_source(m, pos, lum, spec);
+}
+
+mcrt_status mcrt_add_point_source_spectrum(mcrt_model* m, const double pos[3], double lum,
+                                           const double* l_nu_bin, int n_nu) {
+    if (!m) return MCRT_E_ARG;
+    if (!m->have_nu || n_nu != (int)m->nu.size() - 1 || !l_nu_bin)
+        return fail(m, MCRT_E_SIZE, "spectrum size does not match the bins");
+    return add_source(m, pos, lum, std::vector<double>(l_nu_bin, l_nu_bin + n_nu));
+}
+
+mcrt_status mcrt_set_observers(mcrt_model* m, int n_incl, int img_npix, double img_half_width,
+                               const int* img_nu_bins, int n_img_nu) {
+    if (!m) return MCRT_E_ARG;
+    if (!m->have_nu) return fail(m, MCRT_E_STATE, "set frequencies before observers");
+    if (n_incl < 1) return fail(m, MCRT_E_ARG, "need at least one inclination bin");
+    if (n_img_nu < 0 || (n_img_nu > 0 && (img_npix < 1 || !(img_half_width > 0.0) || !img_nu_bins)))
+        return fail(m, MCRT_E_ARG, "bad image parameters");
+    const int nb = (int)m->nu.size() - 1;
+    std::vector<int> seen(nb, 0);
+    for (int i = 0; i < n_img_nu; ++i) {
+        if (img_nu_bins[i] < 0 || img_nu_bins[i] >= nb) return fail(m, MCRT_E_ARG, "image bin out of range");
+        if (seen[img_nu_bins[i]]++) return fail(m, MCRT_E_ARG, "duplicate image bin");
+    }
+    m->n_incl = n_incl;
+    m->n_img = n_img_nu;
+    m->npix = n_img_nu > 0 ? img_npix : 0;
+    m->img_hw = img_half_width;
+    m->img_bins.assign(img_nu_bins, img_nu_bins + n_img_nu);
+    m->have_obs = true;
+    m->tables_dirty = true;
+    hipSetDevice(m->device);
+    mcrt_status s = ensure_bins(m);
+    if (s != MCRT_OK) return s;
+    return clear_bins(m);
+}
+
+mcrt_status mcrt_set_run(mcrt_model* m, const mcrt_run_cfg* c) {
+    if (!m || !c) return MCRT_E_ARG;
+    if (c->n_packets < 1 || c->n_packets_final < 0) return fail(m, MCRT_E_ARG, "packet counts must be >= 1");
+    if (c->n_iter < 0) return fail(m, MCRT_E_ARG, "n_iter must be >= 0");
+    if (c->precision != MCRT_FP64 && c->precision != MCRT_FP32_TRANSPORT)
+        return fail(m, MCRT_E_ARG, "unknown precision");
+    if (!(c->t_init > 0.0) || !isfinite(c->t_init)) return fail(m, MCRT_E_ARG, "t_init must be > 0");
+    if (c->max_events < 0) return fail(m, MCRT_E_ARG, "max_events must be >= 0");
+    if (!(c->conv_p > 0.0 && c->conv_p <= 1.0)) return fail(m, MCRT_E_ARG, "conv_p must be in (0,1]");
+    if (c->event_log_packets < 0 || c->event_log_cap < 0) return fail(m, MCRT_E_ARG, "bad event log size");
+    if (c->block_size < 0 || c->block_size % 64 != 0 || c->block_size > 1024)
+        return fail(m, MCRT_E_ARG, "block_size must be a multiple of 64");
+    if (c->block_size > 256) return fail(m, MCRT_E_ARG, "block_size above 256 is not supported");
+    if (c->defer_lanes < 0 || c->defer_lanes > 64) return fail(m, MCRT_E_ARG, "defer_lanes must be in [0,64]");
+    if (c->blocks_per_cu < 0) return fail(m, MCRT_E_ARG, "blocks_per_cu must be >= 0");
+    const bool reset = !m->have_run || c->t_init != m->cfg.t_init;
+    m->cfg = *c;
+    if (m->cfg.event_log_cap == 0) m->cfg.event_log_cap = 256;
+    if (m->cfg.conv_noise_thres <= 0.0) m->cfg.conv_noise_thres = 0.002;
+    m->have_run = true;
+    if (reset) m->state_ready = false;
+    return MCRT_OK;
+}
+
+mcrt_status mcrt_set_temperature(mcrt_model* m, const double* T, size_t n) {
+    if (!m) return MCRT_E_ARG;
+    if (!m->have_grid || !m->have_run) return fail(m, MCRT_E_STATE, "set grid and run parameters first");
+    if (!T) return fail(m, MCRT_E_ARG, "null temperature");
+    if ((int64_t)n != m->ncell) return fail(m, MCRT_E_SIZE, "temperature size does not match the grid");
+    for (size_t j = 0; j < n; ++j)
+        if (!(T[j] > 0.0) || !isfinite(T[j])) return fail(m, MCRT_E_ARG, "temperature must be > 0");
+    hipSetDevice(m->device);
+    mcrt_status s = ensure_state(m);
+    if (s != MCRT_OK) return s;
+    HIPCHK(hipMemcpyAsync(m->T.p, T, n * sizeof(double), hipMemcpyHostToDevice, m->stream));
+    const int b = grid_blocks(m, m->ncell);
+    HIPCHK(launch_fill_u8(m->ncell, m->valid.p, 1, b, m->stream));
+    HIPCHK(launch_fill_f64(m->ncell, m->sig_rel.p, 0.0, b, m->stream));
+    HIPCHK(hipStreamSynchronize(m->stream));
+    m->have_prev = 0;
+    m->q_prev = INFINITY;
+    return MCRT_OK;
+}
+
+mcrt_status mcrt_set_temperature_device(mcrt_model* m, const void* d_T, int is_fp64, size_t n) {
+    if (!m) return MCRT_E_ARG;
+    if (!m->have_grid || !m->have_run) return fail(m, MCRT_E_STATE, "set grid and run parameters first");
+    if (!d_T) return fail(m, MCRT_E_ARG, "null temperature");
+    if ((int64_t)n != m->ncell) return fail(m, MCRT_E_SIZE, "temperature size does not match the grid");
+    hipSetDevice(m->device);
+    mcrt_status s = ensure_state(m);
+    if (s != MCRT_OK) return s;
+    hipStream_t st = m->stream;
+    const int b = grid_blocks(m, m->ncell);
+    if (is_fp64) HIPCHK(hipMemcpyAsync(m->T.p, d_T, n * sizeof(double), hipMemcpyDeviceToDevice, st));
+    else HIPCHK(launch_to_f64(m->ncell, (const float*)d_T, m->T.p, b, st));
+    HIPCHK(hipMemsetAsync(m->misc.p + MISC_SCRATCH, 0, sizeof(unsigned long long), st));
+    HIPCHK(launch_check_T(m->ncell, m->T.p, m->misc.p + MISC_SCRATCH, b, st));
+    unsigned long long bad = 0;
+    HIPCHK(hipMemcpyAsync(&bad, m->misc.p + MISC_SCRATCH, sizeof bad, hipMemcpyDeviceToHost, st));
+    HIPCHK(launch_fill_u8(m->ncell, m->valid.p, 1, b, st));
+    HIPCHK(launch_fill_f64(m->ncell, m->sig_rel.p, 0.0, b, st));
+    HIPCHK(hipStreamSynchronize(st));
+    if (bad) {
+        m->state_ready = false;  // the next call starts again from t_init
+        return fail(m, MCRT_E_ARG, "temperature must be finite and > 0");
+    }
+    m->have_prev = 0;
+    m->q_prev = INFINITY;
+    return MCRT_OK;
+}
+
+mcrt_status mcrt_iterate(mcrt_model* m, mcrt_iter_stats* st) {
+    if (!m || !st) return MCRT_E_ARG;
+    const double t0 = now_ms();
+    hipSetDevice(m->device);
+    mcrt_status s = ready(m);
+    if (s != MCRT_OK) return s;
+    memset(st, 0, sizeof *st);
+    if (m->cfg.bin_every_iteration) {
+        s = clear_bins(m);
+        if (s != MCRT_OK) return s;
+    }
+    s = run_transport(m, m->cfg.n_packets, (uint32_t)m->iter, m->cfg.bin_every_iteration, st);
+    if (s != MCRT_OK) return s;
+    s = update_cells(m, st);
+    if (s != MCRT_OK) return s;
+    st->iteration = m->iter;
+    m->iter++;
+    st->ms_total = now_ms() - t0;
+    return MCRT_OK;
+}
+
+mcrt_status mcrt_final_pass(mcrt_model* m, mcrt_iter_stats* st) {
+    if (!m || !st) return MCRT_E_ARG;
+    const double t0 = now_ms();
+    hipSetDevice(m->device);
+    mcrt_status s = ready(m);
+    if (s != MCRT_OK) return s;
+    memset(st, 0, sizeof *st);
+    s = clear_bins(m);
+    if (s != MCRT_OK) return s;
+    const int64_t np = m->cfg.n_packets_final > 0 ? m->cfg.n_packets_final : m->cfg.n_packets;
+    s = run_transport(m, np, 0x80000000u | (uint32_t)m->iter, 1, st);
+    if (s != MCRT_OK) return s;
+    st->iteration = m->iter;
+    st->ms_total = now_ms() - t0;
+    return MCRT_OK;
+}
+
+mcrt_status mcrt_run(mcrt_model* m, mcrt_run_stats* rs) {
+    if (!m || !rs) return MCRT_E_ARG;
+    memset(rs, 0, sizeof *rs);
+    rs->first_converged = -1;
+    const double t0 = now_ms();
+    for (int i = 0; i < m->cfg.n_iter; ++i) {
+        mcrt_status s = mcrt_iterate(m, &rs->last);
+        if (s != MCRT_OK) return s;
+        rs->n_iterations++;
+        const bool conv = m->cfg.stop_on_convergence == 1   ? rs->last.converged_dT != 0
+                          : m->cfg.stop_on_convergence == 2 ? rs->last.converged_q != 0
+                                                            : false;
+        if (conv && rs->first_converged < 0) {
+            rs->first_converged = rs->last.iteration;
+            rs->ms_to_converged = now_ms() - t0;
+            rs->converged = 1;
+            break;
+        }
+    }
+    mcrt_status s = mcrt_final_pass(m, &rs->final_pass);
+    if (s != MCRT_OK) return s;
+    rs->ms_total = now_ms() - t0;
+    return MCRT_OK;
+}
+
+mcrt_status mcrt_get_specific_energy(mcrt_model* m, double* adot, double* adot_sigma, size_t n) {
+    if (!m || !adot) return MCRT_E_ARG;
+    if (!m->state_ready) return fail(m, MCRT_E_STATE, "no iteration has run");
+    if ((int64_t)n != m->ncell) return fail(m, MCRT_E_SIZE, "buffer size does not match the grid");
+    hipSetDevice(m->device);
+    HIPCHK(hipMemcpyAsync(adot, m->adot.p, n * sizeof(double), hipMemcpyDeviceToHost, m->stream));
+    if (adot_sigma)
+        HIPCHK(hipMemcpyAsync(adot_sigma, m->adot_sig.p, n * sizeof(double), hipMemcpyDeviceToHost, m->stream));
+    HIPCHK(hipStreamSynchronize(m->stream));
+    return MCRT_OK;
+}
+
+mcrt_status mcrt_get_temperature(mcrt_model* m, double* T, size_t n) {
+    if (!m || !T) return MCRT_E_ARG;
+    if (!m->state_ready) return fail(m, MCRT_E_STATE, "no state yet");
+    if ((int64_t)n != m->ncell) return fail(m, MCRT_E_SIZE, "buffer size does not match the grid");
+    hipSetDevice(m->device);
+    HIPCHK(hipMemcpyAsync(T, m->T.p, n * sizeof(double), hipMemcpyDeviceToHost, m->stream));
+    HIPCHK(hipStreamSynchronize(m->stream));
+    return MCRT_OK;
+}
+
+mcrt_status mcrt_get_temperature_device(mcrt_model* m, const double** d_T) {
+    if (!m || !d_T) return MCRT_E_ARG;
+    if (!m->state_ready) return fail(m, MCRT_E_STATE, "no state yet");
+    *d_T = m->T.p;
+    return MCRT_OK;
+}
+
+mcrt_status mcrt_get_sed(mcrt_model* m, double* sum, double* sum2, int64_t* count, size_t n) {
+    if (!m || !sum) return MCRT_E_ARG;
+    const size_t ns = (size_t)m->n_incl * m->kap.size();
+    if (!m->sed_sum.p) return fail(m, MCRT_E_STATE, "no SED yet");
+    if (n != ns) return fail(m, MCRT_E_SIZE, "buffer size does not match n_incl*n_nu");
+    hipSetDevice(m->device);
+    HIPCHK(hipMemcpyAsync(sum, m->sed_sum.p, ns * sizeof(double), hipMemcpyDeviceToHost, m->stream));
+    if (sum2) HIPCHK(hipMemcpyAsync(sum2, m->sed_sum2.p, ns * sizeof(double), hipMemcpyDeviceToHost, m->stream));
+    if (count) HIPCHK(hipMemcpyAsync(count, m->sed_n.p, ns * sizeof(int64_t), hipMemcpyDeviceToHost, m->stream));
+    HIPCHK(hipStreamSynchronize(m->stream));
+    return MCRT_OK;
+}
+
+mcrt_status mcrt_get_images(mcrt_model* m, double* sum, double* sum2, size_t n) {
+    if (!m) return MCRT_E_ARG;
+    const size_t ni = (size_t)m->n_img * m->n_incl * m->npix * m->npix;
+    if (n != ni) return fail(m, MCRT_E_SIZE, "buffer size does not match the images");
+    if (ni == 0) return MCRT_OK;
+    if (!sum) return MCRT_E_ARG;
+    hipSetDevice(m->device);
+    HIPCHK(hipMemcpyAsync(sum, m->img_sum.p, ni * sizeof(double), hipMemcpyDeviceToHost, m->stream));
+    if (sum2) HIPCHK(hipMemcpyAsync(sum2, m->img_sum2.p, ni * sizeof(double), hipMemcpyDeviceToHost, m->stream));
+    HIPCHK(hipStreamSynchronize(m->stream));
+    return MCRT_OK;
+}
+
+mcrt_status mcrt_get_event_log(mcrt_model* m, mcrt_event* ev, size_t cap_total, int32_t* counts,
+                               size_t n_counts) {
+    if (!m || !ev || !counts) return MCRT_E_ARG;
+    if (m->ev_packets <= 0) return fail(m, MCRT_E_STATE, "no event log");
+    const size_t need = (size_t)m->ev_packets * m->ev_cap;
+    if (cap_total != need || n_counts != (size_t)m->ev_packets)
+        return fail(m, MCRT_E_SIZE, "event log buffers do not match packets*cap");
+    hipSetDevice(m->device);
+    HIPCHK(hipMemcpyAsync(ev, m->evlog.p, need * sizeof(mcrt_event), hipMemcpyDeviceToHost, m->stream));
+    HIPCHK(hipMemcpyAsync(counts, m->evcount.p, n_counts * sizeof(int32_t), hipMemcpyDeviceToHost, m->stream));
+    HIPCHK(hipStreamSynchronize(m->stream));
+    return MCRT_OK;
+}
+
+mcrt_status mcrt_device_info(mcrt_model* m, int* n_cu, int* wave_size) {
+    if (!m) return MCRT_E_ARG;
+    if (n_cu) *n_cu = m->n_cu;
+    if (wave_size) {
+        int w = 64;
+        hipDeviceGetAttribute(&w, hipDeviceAttributeWarpSize, m->device);
+        *wave_size = w;
+    }
+    return MCRT_OK;
+}
+
+}  // extern "C"

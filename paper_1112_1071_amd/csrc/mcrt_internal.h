@@ -1,0 +1,109 @@
+// mcrt_internal.h -- parameter blocks shared by the host driver and the
+// gfx950 kernels of libmcrt.  Not part of the public ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "../../include/mcrt.h"
+
+namespace mcrt {
+
+constexpr int kRows = 128;          // emissivity rows, log-spaced in T over [1 K, 1e4 K]
+constexpr double kTLo = 1.0;        // K
+constexpr double kTHi = 1.0e4;      // K
+constexpr double kTFloor = 1.0;     // K, temperature of cells that absorbed nothing
+constexpr int kTSolveRows = 2048;   // rows of the ln Adot(ln T) table of the T solve
+constexpr int kWave = 64;
+
+// Per-lane counters flushed once per wave at the end of a transport launch.
+enum CounterIdx { C_CROSS_DUST = 0, C_CROSS_EMPTY, C_SCATTER, C_ABSORB, C_ESCAPE, C_KILLED,
+                  C_COUNT };
+
+// Transport launch parameters (one model).  R is the transport precision.
+template <typename R>
+struct TransportParams {
+    // grid
+    int n[3];
+    int pad0;
+    double lo[3];
+    double dx[3];           // cell size, cm
+    R dxr[3];               // same in R
+    R inv_dx[3];            // 1/dx in R
+    const R* rho;           // [ncell] density
+    // dust per frequency bin
+    int nnu;
+    const R* chi;
+    const R* kap;
+    const R* alb;
+    const R* g;
+    // sources
+    int nsrc;
+    int sampling;           // 0 luminosity-proportional, 1 equal numbers
+    const double* spos;     // [3*nsrc]
+    const R* lcdf;          // [nsrc] luminosity CDF
+    const R* scdf;          // [nsrc*nnu] spectral CDFs
+    const double* sweight;  // [nsrc] packet weight relative to eps0 (equal sampling)
+    // emission rows of every cell: position p in [0, kRows-1]; row m = floor(p), weight p-m
+    const R* ecdf;          // [kRows*nnu]
+    const R* rowpos;        // [ncell]
+    // random numbers
+    uint32_t key0, key1;
+    // packets
+    uint64_t n_packets;
+    uint64_t packet_base;   // id of the first packet of this launch
+    unsigned long long* pool;  // packets handed out so far (relative to packet_base)
+    double eps0;            // erg per packet of weight 1
+    int64_t max_events;
+    int defer_lanes;
+    // tallies
+    double* acc;            // [ncell] sum of weight * l * kappa (cm^-1 cm^2 g^-1 ... per eps0)
+    double* acc2;           // [ncell] sum of squares, or null
+    int binning;
+    int n_incl;
+    double* sed_sum;
+    double* sed_sum2;
+    unsigned long long* sed_n;
+    int n_img, npix;
+    double img_hw;
+    const int* img_of_bin;  // [nnu] image index or -1
+    double* img_sum;
+    double* img_sum2;
+    // event log
+    int64_t ev_packets;
+    int ev_cap;
+    mcrt_event* evlog;
+    int32_t* evcount;
+    // counters
+    unsigned long long* counters;  // [C_COUNT]
+    double* energies;              // [2] escaped, killed
+};
+
+// Cell-update parameters (always FP64).
+struct CellParams {
+    int64_t ncell;
+    double eps_over_vol;    // eps0 / (Delta t V), Delta t = 1 s
+    const double* rho;
+    const double* acc;
+    const double* acc2;     // or null
+    double* adot;
+    double* adot_prev;
+    double* adot_sig;
+    double* T;
+    double* T_prev;
+    double* sig_rel;
+    double* sig_rel_prev;
+    unsigned char* valid;       // T came from a sampled cell or from the user
+    unsigned char* valid_prev;
+    const double* lnA;      // [kTSolveRows] ln Adot at ln T = i*dy
+    const double* slope;    // [kTSolveRows] dlnAdot/dlnT
+    double dy;
+    int have_prev;          // Adot of the previous iteration exists
+    int want_noise;
+    double noise_thres;
+    double* Rbuf;           // [ncell] R_j or +inf
+    double* rbuf;           // [ncell] r_j or +inf
+    unsigned long long* stats;  // [8] n_r, n_mask, n_unsampled, n_clamped, max_r bits
+};
+
+}  // namespace mcrt

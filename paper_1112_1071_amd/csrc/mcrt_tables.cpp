@@ -1,0 +1,167 @@
+// mcrt_tables.cpp -- FP64 host tables of libmcrt, built once per model:
+// bin-integrated Planck functions, source spectral and luminosity CDFs, the
+// emissivity rows j_k = kappa_k B_k(T_m) of Sec. 2.1.3 (as cumulative
+// distributions), and the ln Adot(ln T) table of the LTE balance of Eq. 3
+// over the model's bins.
+//
+// The Planck integral int_a^b x^3/(e^x - 1) dx is evaluated by composite
+// 16-point Gauss-Legendre quadrature on panels at most one unit wide (the
+// integrand is analytic within 2 pi of the real axis, so each panel is exact
+// to rounding).
+#include <math.h>
+
+#include <vector>
+
+#include "mcrt_tables.h"
+
+namespace mcrt {
+
+namespace {
+constexpr double kH = 6.62607015e-27;   // erg s
+constexpr double kK = 1.380649e-16;     // erg / K
+constexpr double kC = 2.99792458e10;    // cm / s
+constexpr double kPi = 3.14159265358979323846;
+
+struct GaussLegendre16 {
+    double x[16], w[16];
+    GaussLegendre16() {
+        const int n = 16;
+        // Newton iteration on P_16 from the usual cosine guesses; a fixed number
+        // of steps (quadratic convergence reaches rounding in a handful), then
+        // the weight 2 / ((1 - z^2) P'_16(z)^2) at the final node
+        auto legendre = [n](double z, double* dp) {
+            double p0 = 1.0, p1 = 0.0;
+            for (int j = 1; j <= n; ++j) {
+                const double p2 = p1;
+                p1 = p0;
+                p0 = ((2.0 * j - 1.0) * z * p1 - (j - 1.0) * p2) / j;
+            }
+            *dp = n * (z * p0 - p1) / (z * z - 1.0);
+            return p0;
+        };
+        for (int i = 0; i < n; ++i) {
+            double z = cos(kPi * (i + 0.75) / (n + 0.5));
+            for (int it = 0; it < 12; ++it) {
+                double dp;
+                const double p = legendre(z, &dp);
+                z -= p / dp;
+            }
+            double dp;
+            legendre(z, &dp);
+            x[i] = z;
+            w[i] = 2.0 / ((1.0 - z * z) * dp * dp);
+        }
+    }
+};
+
+const GaussLegendre16& gl16() {
+    static const GaussLegendre16 g;
+    return g;
+}
+
+inline double planck_integrand(double x) {
+    if (x <= 0.0) return 0.0;
+    if (x > 745.0) return 0.0;
+    if (x < 1e-8) return x * x * (1.0 - 0.5 * x);
+    return x * x * x / expm1(x);
+}
+}  // namespace
+
+double planck_x_integral(double a, double b) {
+    if (!(b > a)) return 0.0;
+    if (a < 0.0) a = 0.0;
+    if (a >= 745.0) return 0.0;
+    if (b > 745.0) b = 745.0;
+    const GaussLegendre16& g = gl16();
+    const int panels = (int)ceil((b - a) / 1.0);
+    const double h = (b - a) / panels;
+    double sum = 0.0;
+    for (int p = 0; p < panels; ++p) {
+        const double c = a + (p + 0.5) * h;
+        double s = 0.0;
+        for (int i = 0; i < 16; ++i) s += g.w[i] * planck_integrand(c + 0.5 * h * g.x[i]);
+        sum += 0.5 * h * s;
+    }
+    return sum;
+}
+
+// integral of B_nu(T) over [nu_lo, nu_hi]
+double planck_bin(double nu_lo, double nu_hi, double T) {
+    if (!(T > 0.0)) return 0.0;
+    const double kT = kK * T;
+    const double pref = 2.0 * kT * kT * kT * kT / (kH * kH * kH * kC * kC);
+    return pref * planck_x_integral(kH * nu_lo / kT, kH * nu_hi / kT);
+}
+
+void blackbody_bins(const std::vector<double>& nu, double T, std::vector<double>& out) {
+    const size_t nb = nu.size() - 1;
+    out.resize(nb);
+    for (size_t k = 0; k < nb; ++k) out[k] = planck_bin(nu[k], nu[k + 1], T);
+}
+
+bool cumulative(const std::vector<double>& v, std::vector<double>& cdf) {
+    cdf.resize(v.size());
+    double s = 0.0;
+    for (size_t k = 0; k < v.size(); ++k) {
+        s += v[k];
+        cdf[k] = s;
+    }
+    if (!(s > 0.0)) {
+        for (size_t k = 0; k < v.size(); ++k) cdf[k] = (double)(k + 1) / v.size();
+        return false;
+    }
+    for (size_t k = 0; k < v.size(); ++k) cdf[k] /= s;
+    cdf.back() = 1.0;
+    return true;
+}
+
+double row_temperature(int m) {
+    return exp(log(kTLo) + m * (log(kTHi) - log(kTLo)) / (kRows - 1));
+}
+
+void emission_rows(const std::vector<double>& nu, const std::vector<double>& kappa,
+                   std::vector<double>& ecdf) {
+    const size_t nb = kappa.size();
+    ecdf.assign((size_t)kRows * nb, 0.0);
+    std::vector<double> b, row(nb), c;
+    for (int m = 0; m < kRows; ++m) {
+        blackbody_bins(nu, row_temperature(m), b);
+        for (size_t k = 0; k < nb; ++k) row[k] = kappa[k] * b[k];
+        cumulative(row, c);
+        for (size_t k = 0; k < nb; ++k) ecdf[(size_t)m * nb + k] = c[k];
+    }
+}
+
+// Adot(T) = 4 pi sum_k kappa_k B_k(T) and dlnAdot/dlnT, where
+// T dB_k/dT = pref [4 I_k + a f(a) - b f(b)], f(x) = x^3/(e^x - 1), x = h nu/kT.
+void adot_of_T(const std::vector<double>& nu, const std::vector<double>& kappa, double T,
+               double* adot, double* dlnA_dlnT) {
+    const double kT = kK * T;
+    const double pref = 2.0 * kT * kT * kT * kT / (kH * kH * kH * kC * kC);
+    double s = 0.0, ds = 0.0;
+    for (size_t k = 0; k < kappa.size(); ++k) {
+        if (kappa[k] == 0.0) continue;
+        const double a = kH * nu[k] / kT, b = kH * nu[k + 1] / kT;
+        const double I = planck_x_integral(a, b);
+        s += kappa[k] * I;
+        ds += kappa[k] * (4.0 * I + a * planck_integrand(a) - b * planck_integrand(b));
+    }
+    *adot = 4.0 * kPi * pref * s;
+    *dlnA_dlnT = s > 0.0 ? ds / s : 4.0;
+}
+
+void tsolve_table(const std::vector<double>& nu, const std::vector<double>& kappa,
+                  std::vector<double>& lnA, std::vector<double>& slope, double* dy) {
+    lnA.resize(kTSolveRows);
+    slope.resize(kTSolveRows);
+    *dy = (log(kTHi) - log(kTLo)) / (kTSolveRows - 1);
+    for (int i = 0; i < kTSolveRows; ++i) {
+        const double T = exp(log(kTLo) + i * *dy);
+        double a, s;
+        adot_of_T(nu, kappa, T, &a, &s);
+        lnA[i] = log(a);
+        slope[i] = s;
+    }
+}
+
+}  // namespace mcrt

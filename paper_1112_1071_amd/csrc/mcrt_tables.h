@@ -1,0 +1,22 @@
+// mcrt_tables.h -- FP64 host tables of libmcrt (see mcrt_tables.cpp).
+#pragma once
+
+#include <vector>
+
+#include "mcrt_internal.h"
+
+namespace mcrt {
+
+double planck_x_integral(double a, double b);
+double planck_bin(double nu_lo, double nu_hi, double T);
+void blackbody_bins(const std::vector<double>& nu, double T, std::vector<double>& out);
+bool cumulative(const std::vector<double>& v, std::vector<double>& cdf);
+double row_temperature(int m);
+void emission_rows(const std::vector<double>& nu, const std::vector<double>& kappa,
+                   std::vector<double>& ecdf);
+void adot_of_T(const std::vector<double>& nu, const std::vector<double>& kappa, double T,
+               double* adot, double* dlnA_dlnT);
+void tsolve_table(const std::vector<double>& nu, const std::vector<double>& kappa,
+                  std::vector<double>& lnA, std::vector<double>& slope, double* dy);
+
+}  // namespace mcrt

@@ -1,0 +1,288 @@
+"""Thin ctypes binding of libmcrt.so (include/mcrt.h).
+
+Argument marshalling only: every step of the method runs in the library's
+HIP kernels.  If the library is missing the import of this module fails;
+there is no fallback.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libmcrt.so")
+
+MCRT_FP64 = 0
+MCRT_FP32_TRANSPORT = 1
+
+STATUS = {0: "MCRT_OK", -1: "MCRT_E_ARG", -2: "MCRT_E_STATE", -3: "MCRT_E_NOMEM",
+          -4: "MCRT_E_DEVICE", -5: "MCRT_E_UNSUPPORTED", -6: "MCRT_E_SIZE"}
+
+
+class MCRTError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__(f"{STATUS.get(status, status)}: {msg}")
+        self.status = status
+
+
+class RunCfg(C.Structure):
+    _fields_ = [
+        ("n_packets", C.c_int64), ("n_packets_final", C.c_int64), ("n_iter", C.c_int32),
+        ("precision", C.c_int32), ("seed", C.c_uint64), ("t_init", C.c_double),
+        ("max_events", C.c_int64), ("conv_p", C.c_double), ("conv_q_thres", C.c_double),
+        ("conv_d_thres", C.c_double), ("conv_dT_thres", C.c_double),
+        ("conv_noise_thres", C.c_double), ("stop_on_convergence", C.c_int32),
+        ("source_sampling", C.c_int32), ("want_noise", C.c_int32),
+        ("event_log_packets", C.c_int32), ("event_log_cap", C.c_int32),
+        ("bin_every_iteration", C.c_int32), ("block_size", C.c_int32),
+        ("blocks_per_cu", C.c_int32), ("defer_lanes", C.c_int32), ("reserved0", C.c_int32),
+    ]
+
+
+class IterStats(C.Structure):
+    _fields_ = [
+        ("iteration", C.c_int32), ("converged_q", C.c_int32), ("converged_dT", C.c_int32),
+        ("precision", C.c_int32), ("q", C.c_double), ("delta", C.c_double),
+        ("max_dT", C.c_double), ("p999_dT", C.c_double), ("n_mask", C.c_int64),
+        ("n_r", C.c_int64), ("n_unsampled", C.c_int64), ("n_t_clamped", C.c_int64),
+        ("n_row_clamped", C.c_int64), ("n_cross_dust", C.c_int64), ("n_cross_empty", C.c_int64),
+        ("n_scatter", C.c_int64), ("n_absorb", C.c_int64), ("n_escape", C.c_int64),
+        ("n_killed", C.c_int64), ("e_escaped", C.c_double), ("e_killed", C.c_double),
+        ("ms_transport", C.c_double), ("ms_update", C.c_double), ("ms_total", C.c_double),
+    ]
+
+    def as_dict(self) -> dict:
+        return {f: getattr(self, f) for f, _ in self._fields_}
+
+
+class RunStats(C.Structure):
+    _fields_ = [
+        ("n_iterations", C.c_int32), ("converged", C.c_int32), ("first_converged", C.c_int32),
+        ("reserved", C.c_int32), ("ms_total", C.c_double), ("ms_to_converged", C.c_double),
+        ("last", IterStats), ("final_pass", IterStats),
+    ]
+
+
+EVENT_DTYPE = np.dtype([("packet", "<i8"), ("index", "<i4"), ("type", "<i4"),
+                        ("cell", "<i4", (3,)), ("nu", "<i4"), ("incl", "<i4"),
+                        ("reserved", "<i4")])
+
+RUN_KEYS = [f for f, _ in RunCfg._fields_ if f != "reserved0"]
+
+_lib = None
+
+
+def lib():
+    """Load libmcrt.so (raises if it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} is missing: build it with python -m paper_1112_1071_amd.build")
+    # PyTorch provides device memory and streams to callers of this library, so
+    # both must run on one HIP runtime: load torch's first, and libmcrt binds to
+    # the already loaded libamdhip64 (same soname)
+    import torch  # noqa: F401
+
+    L = C.CDLL(LIB_PATH)
+    vp, i32, i64, sz, dbl = C.c_void_p, C.c_int, C.c_int64, C.c_size_t, C.c_double
+    sig = {
+        "mcrt_create": ([C.POINTER(vp), i32], i32),
+        "mcrt_destroy": ([vp], None),
+        "mcrt_last_error": ([vp], C.c_char_p),
+        "mcrt_set_stream": ([vp, vp], i32),
+        "mcrt_set_grid": ([vp, i32, i32, i32, vp, vp], i32),
+        "mcrt_set_density": ([vp, vp, sz], i32),
+        "mcrt_set_density_device": ([vp, vp, i32, sz], i32),
+        "mcrt_set_frequencies": ([vp, vp, i32], i32),
+        "mcrt_set_dust": ([vp, vp, vp, vp, i32], i32),
+        "mcrt_add_point_source": ([vp, vp, dbl, dbl], i32),
+        "mcrt_add_point_source_spectrum": ([vp, vp, dbl, vp, i32], i32),
+        "mcrt_set_observers": ([vp, i32, i32, dbl, vp, i32], i32),
+        "mcrt_run_cfg_default": ([C.POINTER(RunCfg)], i32),
+        "mcrt_set_run": ([vp, C.POINTER(RunCfg)], i32),
+        "mcrt_set_temperature": ([vp, vp, sz], i32),
+        "mcrt_set_temperature_device": ([vp, vp, i32, sz], i32),
+        "mcrt_iterate": ([vp, C.POINTER(IterStats)], i32),
+        "mcrt_final_pass": ([vp, C.POINTER(IterStats)], i32),
+        "mcrt_run": ([vp, C.POINTER(RunStats)], i32),
+        "mcrt_get_specific_energy": ([vp, vp, vp, sz], i32),
+        "mcrt_get_temperature": ([vp, vp, sz], i32),
+        "mcrt_get_temperature_device": ([vp, C.POINTER(vp)], i32),
+        "mcrt_get_sed": ([vp, vp, vp, vp, sz], i32),
+        "mcrt_get_images": ([vp, vp, vp, sz], i32),
+        "mcrt_get_event_log": ([vp, vp, sz, vp, sz], i32),
+        "mcrt_device_info": ([vp, C.POINTER(i32), C.POINTER(i32)], i32),
+    }
+    for name, (args, res) in sig.items():
+        f = getattr(L, name)
+        f.argtypes = args
+        f.restype = res
+    _lib = L
+    return L
+
+
+def _ptr(a):
+    return a.ctypes.data if a is not None else None
+
+
+def default_run_cfg() -> RunCfg:
+    c = RunCfg()
+    lib().mcrt_run_cfg_default(C.byref(c))
+    return c
+
+
+class Model:
+    """One libmcrt model on a HIP device, built from a synthetic-input config dict."""
+
+    def __init__(self, cfg: dict, device: int = 0, stream=None, **run_overrides):
+        self.L = lib()
+        h = C.c_void_p()
+        rc = self.L.mcrt_create(C.byref(h), int(device))
+        if rc != 0:
+            raise MCRTError(rc, "mcrt_create failed (no HIP device?)")
+        self.h = h
+        self.cfg = cfg
+        if stream is not None:
+            self._check(self.L.mcrt_set_stream(self.h, C.c_void_p(int(stream))))
+        g = cfg["grid"]
+        self.shape = tuple(int(v) for v in g["n"])
+        self.ncell = int(np.prod(self.shape))
+        lo = np.ascontiguousarray(g["lo"], dtype=np.float64)
+        hi = np.ascontiguousarray(g["hi"], dtype=np.float64)
+        self._check(self.L.mcrt_set_grid(self.h, *self.shape, _ptr(lo), _ptr(hi)))
+        if "rho_device" in cfg:
+            t = cfg["rho_device"]
+            self._check(self.L.mcrt_set_density_device(self.h, C.c_void_p(t.data_ptr()),
+                                                       int(t.element_size() == 8), t.numel()))
+        else:
+            rho = np.ascontiguousarray(cfg["rho"], dtype=np.float64).ravel()
+            self._check(self.L.mcrt_set_density(self.h, _ptr(rho), rho.size))
+        nu = np.ascontiguousarray(cfg["nu_edges"], dtype=np.float64)
+        self.nnu = nu.size - 1
+        self._check(self.L.mcrt_set_frequencies(self.h, _ptr(nu), self.nnu))
+        d = cfg["dust"]
+        chi = np.ascontiguousarray(d["chi"], dtype=np.float64)
+        alb = np.ascontiguousarray(d["albedo"], dtype=np.float64)
+        gg = np.ascontiguousarray(d["g"], dtype=np.float64)
+        self._check(self.L.mcrt_set_dust(self.h, _ptr(chi), _ptr(alb), _ptr(gg), self.nnu))
+        for s in cfg["sources"]:
+            pos = np.ascontiguousarray(s["pos"], dtype=np.float64)
+            if "spectrum" in s:
+                sp = np.ascontiguousarray(s["spectrum"], dtype=np.float64)
+                self._check(self.L.mcrt_add_point_source_spectrum(self.h, _ptr(pos), float(s["lum"]),
+                                                                  _ptr(sp), sp.size))
+            else:
+                self._check(self.L.mcrt_add_point_source(self.h, _ptr(pos), float(s["lum"]),
+                                                         float(s["teff"])))
+        ob = cfg.get("observers", {"n_incl": 10})
+        bins = np.ascontiguousarray(ob.get("img_nu_bins", []), dtype=np.int32)
+        self.n_incl = int(ob.get("n_incl", 10))
+        self.n_img = int(bins.size)
+        self.npix = int(ob.get("img_npix", 0)) if bins.size else 0
+        self._check(self.L.mcrt_set_observers(self.h, self.n_incl, self.npix,
+                                              float(ob.get("img_half_width", 0.0)),
+                                              _ptr(bins) if bins.size else None, self.n_img))
+        run = dict(cfg.get("run", {}))
+        run.update(run_overrides)
+        self.set_run(**run)
+
+    # -- plumbing --------------------------------------------------------------
+    def _check(self, rc):
+        if rc != 0:
+            raise MCRTError(rc, self.L.mcrt_last_error(self.h).decode())
+
+    def close(self):
+        if getattr(self, "h", None):
+            self.L.mcrt_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def set_run(self, **run):
+        c = default_run_cfg()
+        for k, v in run.items():
+            if k in RUN_KEYS:
+                setattr(c, k, type(getattr(c, k))(v))
+        if "n_packets_final" not in run:
+            c.n_packets_final = c.n_packets
+        self.run = {k: getattr(c, k) for k in RUN_KEYS}
+        self._check(self.L.mcrt_set_run(self.h, C.byref(c)))
+
+    # -- running ---------------------------------------------------------------
+    def set_temperature(self, T):
+        T = np.ascontiguousarray(T, dtype=np.float64).ravel()
+        self._check(self.L.mcrt_set_temperature(self.h, _ptr(T), T.size))
+
+    def set_temperature_device(self, t):
+        self._check(self.L.mcrt_set_temperature_device(self.h, C.c_void_p(t.data_ptr()),
+                                                       int(t.element_size() == 8), t.numel()))
+
+    def iterate(self) -> dict:
+        st = IterStats()
+        self._check(self.L.mcrt_iterate(self.h, C.byref(st)))
+        return st.as_dict()
+
+    def final_pass(self) -> dict:
+        st = IterStats()
+        self._check(self.L.mcrt_final_pass(self.h, C.byref(st)))
+        return st.as_dict()
+
+    def run_all(self) -> dict:
+        rs = RunStats()
+        self._check(self.L.mcrt_run(self.h, C.byref(rs)))
+        return {"n_iterations": rs.n_iterations, "converged": rs.converged,
+                "first_converged": rs.first_converged, "ms_total": rs.ms_total,
+                "ms_to_converged": rs.ms_to_converged, "last": rs.last.as_dict(),
+                "final_pass": rs.final_pass.as_dict()}
+
+    # -- results ---------------------------------------------------------------
+    def specific_energy(self, with_sigma=False):
+        a = np.zeros(self.ncell)
+        s = np.zeros(self.ncell) if with_sigma else None
+        self._check(self.L.mcrt_get_specific_energy(self.h, _ptr(a), _ptr(s), a.size))
+        return (a, s) if with_sigma else a
+
+    def temperature(self):
+        T = np.zeros(self.ncell)
+        self._check(self.L.mcrt_get_temperature(self.h, _ptr(T), T.size))
+        return T
+
+    def temperature_device_ptr(self) -> int:
+        p = C.c_void_p()
+        self._check(self.L.mcrt_get_temperature_device(self.h, C.byref(p)))
+        return p.value
+
+    def sed(self):
+        n = self.n_incl * self.nnu
+        s, s2, c = np.zeros(n), np.zeros(n), np.zeros(n, dtype=np.int64)
+        self._check(self.L.mcrt_get_sed(self.h, _ptr(s), _ptr(s2), _ptr(c), n))
+        sh = (self.n_incl, self.nnu)
+        return s.reshape(sh), s2.reshape(sh), c.reshape(sh)
+
+    def images(self):
+        n = self.n_img * self.n_incl * self.npix * self.npix
+        s, s2 = np.zeros(max(n, 1)), np.zeros(max(n, 1))
+        self._check(self.L.mcrt_get_images(self.h, _ptr(s), _ptr(s2), n))
+        sh = (self.n_img, self.n_incl, self.npix, self.npix)
+        return s[:n].reshape(sh), s2[:n].reshape(sh)
+
+    def event_log(self):
+        npk = int(self.run["event_log_packets"])
+        cap = int(self.run["event_log_cap"]) or 256
+        npk = min(npk, int(self.run["n_packets"]))
+        ev = np.zeros(npk * cap, dtype=EVENT_DTYPE)
+        cnt = np.zeros(npk, dtype=np.int32)
+        self._check(self.L.mcrt_get_event_log(self.h, _ptr(ev), ev.size, _ptr(cnt), cnt.size))
+        return ev.reshape(npk, cap), cnt
+
+    def device_info(self):
+        n, w = C.c_int(), C.c_int()
+        self._check(self.L.mcrt_device_info(self.h, C.byref(n), C.byref(w)))
+        return n.value, w.value
