@@ -78,10 +78,14 @@ def main():
     ap.add_argument("--packets", type=float, default=1e8)
     ap.add_argument("--grid", type=int, default=256)
     ap.add_argument("--precision", choices=["fp32", "fp64"], default="fp32")
-    ap.add_argument("--cpu-packets", type=int, default=150000)
+    ap.add_argument("--cpu-packets", type=int, default=10_000_000)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--defer", type=int, default=0)
     ap.add_argument("--blocks-per-cu", type=int, default=0)
+    ap.add_argument("--walk-batch", type=int, default=0)
+    ap.add_argument("--layout", type=int, default=-1)
+    ap.add_argument("--block-size", type=int, default=0)
+    ap.add_argument("--sampling", type=int, default=0, help="1: equal packets per source")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this benchmark runs on one GPU only; --gpus must be 1"}))
@@ -99,6 +103,14 @@ def main():
         run["defer_lanes"] = args.defer
     if args.blocks_per_cu:
         run["blocks_per_cu"] = args.blocks_per_cu
+    if args.walk_batch:
+        run["walk_batch"] = args.walk_batch
+    if args.layout >= 0:
+        run["grid_layout"] = args.layout
+    if args.block_size:
+        run["block_size"] = args.block_size
+    if args.sampling:
+        run["source_sampling"] = args.sampling
     model = mcrt.Model(cfg, **run)
     print(f"# workload built in {gen_s:.1f} s; warmup {args.warmup}", file=sys.stderr, flush=True)
     for i in range(args.warmup):

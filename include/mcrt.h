@@ -92,7 +92,11 @@ typedef struct {
     int32_t block_size;        /* transport threads per block, multiple of 64 [256]       */
     int32_t blocks_per_cu;     /* persistent blocks per compute unit [0 = occupancy]      */
     int32_t defer_lanes;       /* lanes of a wave that wait before events run [16]        */
-    int32_t reserved0;
+    int32_t walk_batch;        /* grid segments a lane gathers per walk step: 1,2,4,8 [4] */
+    int32_t grid_layout;       /* device layout of the transport grid: 0 x-fastest,
+                                  1 bricks of 4x4x4 cells [0]; results are identical     */
+    int32_t tally_copies;      /* absorption tallies per device: 1, or 8 (one per XCD,
+                                  summed by the cell update) [8]                          */
 } mcrt_run_cfg;
 
 /* Statistics of one pass (a Lucy iteration or the final pass). */

@@ -14,8 +14,14 @@
 
 namespace mcrt {
 template <typename R>
-hipError_t launch_transport(const TransportParams<R>& P, int blocks, int threads, hipStream_t st);
-template <typename R> int transport_max_blocks_per_cu(int threads);
+hipError_t launch_transport(const TransportParams<R>& P, int K, int brick, int blocks, int threads,
+                            hipStream_t st);
+template <typename R> int transport_max_blocks_per_cu(int K, int brick, int threads, size_t lds);
+template <typename R> size_t transport_lds_bytes(const TransportParams<R>& P);
+hipError_t launch_to_bricks_f32(int64_t n, int nx, int ny, int bx, int bxy, const float* in,
+                                float* out, int blocks, hipStream_t st);
+hipError_t launch_to_bricks_f64(int64_t n, int nx, int ny, int bx, int bxy, const double* in,
+                                double* out, int blocks, hipStream_t st);
 hipError_t launch_rows64(int64_t, const double*, const double*, double*, unsigned long long*, int,
                          hipStream_t);
 hipError_t launch_rows32(int64_t, const double*, const double*, float*, unsigned long long*, int,
@@ -96,6 +102,17 @@ struct mcrt_model {
     DBuf<double> chi64, kap64, alb64, g64, lcdf64, scdf64, ecdf64;
     DBuf<float> chi32, kap32, alb32, g32, lcdf32, scdf32, ecdf32;
     DBuf<double> spos, sweight, lnA, slope;
+    DBuf<double> ecoarse64, scoarse64;
+    DBuf<float> ecoarse32, scoarse32;
+    int npad = 0, ngroup = 0;
+    // density in the transport layout: x-fastest (aliases rho64/rho32) or bricks
+    DBuf<double> rhoT64;
+    DBuf<float> rhoT32;
+    int t_layout = -1;      // layout the transport density arrays hold, -1 = none yet
+    int bx = 0, by = 0, bz = 0;
+    int64_t nt_cells = 0;   // length of the transport-layout arrays
+    size_t acc_stride = 0;  // elements per tally copy
+    int acc_copies = 1;     // tally copies of the last transport
     DBuf<int> img_of_bin;
     double dy = 0.0;
     double ltot = 0.0;
@@ -122,6 +139,7 @@ struct mcrt_model {
 
 namespace {
 
+constexpr int kMaxTallyCopies = 8;  // one per XCD of an MI355X
 constexpr int MISC_POOL = 0;
 constexpr int MISC_CNT = 1;                  // C_COUNT entries
 constexpr int MISC_STATS = 1 + C_COUNT;      // 8 entries
@@ -161,15 +179,32 @@ std::vector<float> to_f32(const std::vector<double>& v) {
     return std::vector<float>(v.begin(), v.end());
 }
 
+// Rows of nb CDF values padded to npad = kGroup*ngroup entries with 2.0 (never
+// selected: uniforms are < 1 = the last real entry), and the coarse index of
+// every group's last entry for the two-level search of the transport kernel.
+void pad_rows(const std::vector<double>& rows, size_t nrow, size_t nb, size_t npad, size_t ng,
+              std::vector<double>& padded, std::vector<double>& coarse) {
+    padded.assign(nrow * npad, 2.0);
+    coarse.assign(nrow * ng, 2.0);
+    for (size_t r = 0; r < nrow; ++r) {
+        for (size_t k = 0; k < nb; ++k) padded[r * npad + k] = rows[r * nb + k];
+        for (size_t q = 0; q < ng; ++q) coarse[r * ng + q] = padded[r * npad + kGroup * q + kGroup - 1];
+    }
+}
+
 mcrt_status build_tables(mcrt_model* m) {
     const size_t nb = m->kap.size();
-    // sources: spectral CDFs, luminosity CDF, per-source weights
-    std::vector<double> scdf(m->src.size() * nb), lcdf(m->src.size()), spos(3 * m->src.size());
+    const size_t ns = m->src.size();
+    const size_t ng = (nb + kGroup - 1) / kGroup, npad = ng * kGroup;
+    m->ngroup = (int)ng;
+    m->npad = (int)npad;
+    // sources: spectral CDFs, luminosity CDF
+    std::vector<double> scdf(ns * nb), lcdf(ns), spos(3 * ns);
     m->ltot = 0.0;
     for (const Source& s : m->src) m->ltot += s.lum;
     double acc = 0.0;
     std::vector<double> c;
-    for (size_t i = 0; i < m->src.size(); ++i) {
+    for (size_t i = 0; i < ns; ++i) {
         cumulative(m->src[i].spec, c);
         for (size_t k = 0; k < nb; ++k) scdf[i * nb + k] = c[k];
         acc += m->src[i].lum;
@@ -177,10 +212,12 @@ mcrt_status build_tables(mcrt_model* m) {
         for (int a = 0; a < 3; ++a) spos[3 * i + a] = m->src[i].pos[a];
     }
     lcdf.back() = 1.0;
-    const size_t ns = m->src.size();
     std::vector<double> ecdf, lnA, slope;
     emission_rows(m->nu, m->kap, ecdf);
     tsolve_table(m->nu, m->kap, lnA, slope, &m->dy);
+    std::vector<double> scdf_p, scoarse, ecdf_p, ecoarse;
+    pad_rows(scdf, ns, nb, npad, ng, scdf_p, scoarse);
+    pad_rows(ecdf, kRows, nb, npad, ng, ecdf_p, ecoarse);
     std::vector<int> iob(nb, -1);
     for (int i = 0; i < m->n_img; ++i) iob[m->img_bins[i]] = i;
     hipStream_t st = m->stream;
@@ -189,8 +226,10 @@ mcrt_status build_tables(mcrt_model* m) {
     HIPCHK(upload(m->alb64, m->alb, st));
     HIPCHK(upload(m->g64, m->g, st));
     HIPCHK(upload(m->lcdf64, lcdf, st));
-    HIPCHK(upload(m->scdf64, scdf, st));
-    HIPCHK(upload(m->ecdf64, ecdf, st));
+    HIPCHK(upload(m->scdf64, scdf_p, st));
+    HIPCHK(upload(m->ecdf64, ecdf_p, st));
+    HIPCHK(upload(m->scoarse64, scoarse, st));
+    HIPCHK(upload(m->ecoarse64, ecoarse, st));
     // host copies stay alive until the stream synchronisation below
     const std::vector<float> chi32 = to_f32(m->chi), kap32 = to_f32(m->kap),
                              alb32 = to_f32(m->alb), g32 = to_f32(m->g);
@@ -198,14 +237,21 @@ mcrt_status build_tables(mcrt_model* m) {
     HIPCHK(upload(m->kap32, kap32, st));
     HIPCHK(upload(m->alb32, alb32, st));
     HIPCHK(upload(m->g32, g32, st));
-    std::vector<float> lcdf32 = to_f32(lcdf), scdf32 = to_f32(scdf), ecdf32 = to_f32(ecdf);
+    std::vector<float> lcdf32 = to_f32(lcdf), scdf32 = to_f32(scdf_p), ecdf32 = to_f32(ecdf_p);
     // a rounded CDF must still end at exactly 1
     lcdf32.back() = 1.0f;
-    for (size_t i = 0; i < ns; ++i) scdf32[i * nb + nb - 1] = 1.0f;
-    for (int r = 0; r < kRows; ++r) ecdf32[(size_t)r * nb + nb - 1] = 1.0f;
+    for (size_t i = 0; i < ns; ++i) scdf32[i * npad + nb - 1] = 1.0f;
+    for (int r = 0; r < kRows; ++r) ecdf32[(size_t)r * npad + nb - 1] = 1.0f;
+    std::vector<float> scoarse32(ns * ng), ecoarse32((size_t)kRows * ng);
+    for (size_t r = 0; r < ns; ++r)
+        for (size_t q = 0; q < ng; ++q) scoarse32[r * ng + q] = scdf32[r * npad + kGroup * q + kGroup - 1];
+    for (size_t r = 0; r < (size_t)kRows; ++r)
+        for (size_t q = 0; q < ng; ++q) ecoarse32[r * ng + q] = ecdf32[r * npad + kGroup * q + kGroup - 1];
     HIPCHK(upload(m->lcdf32, lcdf32, st));
     HIPCHK(upload(m->scdf32, scdf32, st));
     HIPCHK(upload(m->ecdf32, ecdf32, st));
+    HIPCHK(upload(m->scoarse32, scoarse32, st));
+    HIPCHK(upload(m->ecoarse32, ecoarse32, st));
     HIPCHK(upload(m->spos, spos, st));
     HIPCHK(upload(m->lnA, lnA, st));
     HIPCHK(upload(m->slope, slope, st));
@@ -215,11 +261,43 @@ mcrt_status build_tables(mcrt_model* m) {
     return MCRT_OK;
 }
 
+// Density arrays in the transport layout (x-fastest or 4x4x4 bricks).
+mcrt_status ensure_transport_grid(mcrt_model* m, int layout) {
+    m->bx = (m->n[0] + 3) / 4;
+    m->by = (m->n[1] + 3) / 4;
+    m->bz = (m->n[2] + 3) / 4;
+    if (m->t_layout == layout) return MCRT_OK;
+    hipStream_t st = m->stream;
+    const int b = grid_blocks(m, m->ncell);
+    if (layout == 1) {
+        const int64_t nt = (int64_t)m->bx * m->by * m->bz * 64;
+        HIPCHK(m->rhoT64.ensure(nt));
+        HIPCHK(m->rhoT32.ensure(nt));
+        HIPCHK(hipMemsetAsync(m->rhoT64.p, 0, nt * sizeof(double), st));
+        HIPCHK(hipMemsetAsync(m->rhoT32.p, 0, nt * sizeof(float), st));
+        HIPCHK(launch_to_bricks_f64(m->ncell, m->n[0], m->n[1], m->bx, m->bx * m->by, m->rho64.p,
+                                    m->rhoT64.p, b, st));
+        HIPCHK(launch_to_bricks_f32(m->ncell, m->n[0], m->n[1], m->bx, m->bx * m->by, m->rho32.p,
+                                    m->rhoT32.p, b, st));
+        m->nt_cells = nt;
+    } else {
+        m->rhoT64.release();
+        m->rhoT32.release();
+        m->nt_cells = m->ncell;
+    }
+    HIPCHK(hipStreamSynchronize(st));
+    m->t_layout = layout;
+    return MCRT_OK;
+}
+
 mcrt_status ensure_state(mcrt_model* m) {
     if (m->state_ready) return MCRT_OK;
     const size_t nc = (size_t)m->ncell;
-    HIPCHK(m->acc.ensure(nc));
-    HIPCHK(m->acc2.ensure(nc));
+    // tallies are indexed in the transport layout; bricks pad each axis to 4
+    const size_t nbrick = (size_t)((m->n[0] + 3) / 4) * ((m->n[1] + 3) / 4) * ((m->n[2] + 3) / 4) * 64;
+    m->acc_stride = nbrick > nc ? nbrick : nc;
+    HIPCHK(m->acc.ensure(kMaxTallyCopies * m->acc_stride));
+    HIPCHK(m->acc2.ensure(m->acc_stride));
     HIPCHK(m->adot.ensure(nc));
     HIPCHK(m->adot_prev.ensure(nc));
     HIPCHK(m->adot_sig.ensure(nc));
@@ -310,8 +388,15 @@ mcrt_status run_transport(mcrt_model* m, int64_t np, uint32_t key1, int binning,
         HIPCHK(m->rowpos64.ensure(nc));
         HIPCHK(launch_rows64(m->ncell, m->T.p, m->rho64.p, m->rowpos64.p, misc + MISC_SCRATCH, cb, s));
     }
-    HIPCHK(hipMemsetAsync(m->acc.p, 0, nc * sizeof(double), s));
-    if (m->cfg.want_noise) HIPCHK(hipMemsetAsync(m->acc2.p, 0, nc * sizeof(double), s));
+    const int layout = m->cfg.grid_layout == 1 ? 1 : 0;
+    {
+        mcrt_status r = ensure_transport_grid(m, layout);
+        if (r != MCRT_OK) return r;
+    }
+    const size_t nt = (size_t)m->nt_cells;
+    m->acc_copies = m->cfg.tally_copies == kMaxTallyCopies ? kMaxTallyCopies : 1;
+    HIPCHK(hipMemsetAsync(m->acc.p, 0, ((m->acc_copies - 1) * m->acc_stride + nt) * sizeof(double), s));
+    if (m->cfg.want_noise) HIPCHK(hipMemsetAsync(m->acc2.p, 0, nt * sizeof(double), s));
     // event log
     m->ev_packets = m->cfg.event_log_packets < np ? m->cfg.event_log_packets : np;
     m->ev_cap = m->cfg.event_log_cap > 0 ? m->cfg.event_log_cap : 256;
@@ -321,14 +406,13 @@ mcrt_status run_transport(mcrt_model* m, int64_t np, uint32_t key1, int binning,
         HIPCHK(hipMemsetAsync(m->evcount.p, 0, (size_t)m->ev_packets * sizeof(int32_t), s));
     }
     const int threads = m->cfg.block_size > 0 ? m->cfg.block_size : 256;
-    int bpc = m->cfg.blocks_per_cu;
-    if (bpc <= 0)
-        bpc = f32 ? transport_max_blocks_per_cu<float>(threads)
-                  : transport_max_blocks_per_cu<double>(threads);
-    int64_t blocks = (int64_t)m->n_cu * bpc;
-    const int64_t need = (np + threads - 1) / threads;
-    if (blocks > need) blocks = need;
-    if (blocks < 1) blocks = 1;
+    const int K = m->cfg.walk_batch == 1 || m->cfg.walk_batch == 2 || m->cfg.walk_batch == 8
+                      ? m->cfg.walk_batch
+                      : 4;
+    // coarse CDF indices and the luminosity CDF go to LDS when they are small
+    const size_t rb = f32 ? sizeof(float) : sizeof(double);
+    const size_t lds_need = (size_t)(m->src.size() + (kRows + m->src.size()) * m->ngroup) * rb;
+    const int lds_tables = lds_need <= 32768 ? 1 : 0;
     const double eps0 = m->ltot / (double)np;
     {
         // equal-number sampling: source i gets floor(np/ns) or one more packets,
@@ -344,8 +428,8 @@ mcrt_status run_transport(mcrt_model* m, int64_t np, uint32_t key1, int binning,
     }
 
     auto fill = [&](auto& P, auto* rho, auto* chi, auto* kap, auto* alb, auto* gg, auto* lcdf,
-                    auto* scdf, auto* ecdf, auto* rowpos) {
-        using R = typename std::remove_pointer<decltype(rho)>::type;
+                    auto* scdf, auto* ecdf, auto* rowpos, auto* scoarse, auto* ecoarse) {
+        using R = typename std::remove_const<typename std::remove_pointer<decltype(rho)>::type>::type;
         for (int a = 0; a < 3; ++a) {
             P.n[a] = m->n[a];
             P.lo[a] = m->lo[a];
@@ -353,7 +437,14 @@ mcrt_status run_transport(mcrt_model* m, int64_t np, uint32_t key1, int binning,
             P.dxr[a] = (R)m->dx[a];
             P.inv_dx[a] = (R)(1.0 / m->dx[a]);
         }
+        P.bx = m->bx;
+        P.bxy = m->bx * m->by;
         P.rho = rho;
+        P.npad = m->npad;
+        P.ngroup = m->ngroup;
+        P.scoarse = scoarse;
+        P.ecoarse = ecoarse;
+        P.lds_tables = lds_tables;
         P.nnu = (int)m->kap.size();
         P.chi = chi;
         P.kap = kap;
@@ -376,6 +467,7 @@ mcrt_status run_transport(mcrt_model* m, int64_t np, uint32_t key1, int binning,
         P.max_events = m->cfg.max_events;
         P.defer_lanes = m->cfg.defer_lanes > 0 ? m->cfg.defer_lanes : 16;
         P.acc = m->acc.p;
+        P.acc_stride = m->acc_copies > 1 ? m->acc_stride : 0;
         P.acc2 = m->cfg.want_noise ? m->acc2.p : nullptr;
         P.binning = binning;
         P.n_incl = m->n_incl;
@@ -395,20 +487,38 @@ mcrt_status run_transport(mcrt_model* m, int64_t np, uint32_t key1, int binning,
         P.counters = misc + MISC_CNT;
         P.energies = m->energies.p;
     };
+    // persistent grid: as many blocks as fit on the device, or the request
+    auto grid_size = [&](int bpc) {
+        int64_t blocks = (int64_t)m->n_cu * bpc;
+        const int64_t need = (np + threads - 1) / threads;
+        if (blocks > need) blocks = need;
+        return (int)(blocks < 1 ? 1 : blocks);
+    };
     HIPCHK(hipEventRecord(m->ev[0], s));
     if (f32) {
-        if (!m->rho32.p) return fail(m, MCRT_E_STATE, "no FP32 density");
         TransportParams<float> P{};
-        fill(P, (const float*)m->rho32.p, (const float*)m->chi32.p, (const float*)m->kap32.p,
-             (const float*)m->alb32.p, (const float*)m->g32.p, (const float*)m->lcdf32.p,
-             (const float*)m->scdf32.p, (const float*)m->ecdf32.p, (const float*)m->rowpos32.p);
-        HIPCHK(launch_transport<float>(P, (int)blocks, threads, s));
+        fill(P, (const float*)(layout ? m->rhoT32.p : m->rho32.p), (const float*)m->chi32.p,
+             (const float*)m->kap32.p, (const float*)m->alb32.p, (const float*)m->g32.p,
+             (const float*)m->lcdf32.p, (const float*)m->scdf32.p, (const float*)m->ecdf32.p,
+             (const float*)m->rowpos32.p, (const float*)m->scoarse32.p,
+             (const float*)m->ecoarse32.p);
+        const size_t lds = transport_lds_bytes<float>(P);
+        const int bpc = m->cfg.blocks_per_cu > 0
+                            ? m->cfg.blocks_per_cu
+                            : transport_max_blocks_per_cu<float>(K, layout, threads, lds);
+        HIPCHK(launch_transport<float>(P, K, layout, grid_size(bpc), threads, s));
     } else {
         TransportParams<double> P{};
-        fill(P, (const double*)m->rho64.p, (const double*)m->chi64.p, (const double*)m->kap64.p,
-             (const double*)m->alb64.p, (const double*)m->g64.p, (const double*)m->lcdf64.p,
-             (const double*)m->scdf64.p, (const double*)m->ecdf64.p, (const double*)m->rowpos64.p);
-        HIPCHK(launch_transport<double>(P, (int)blocks, threads, s));
+        fill(P, (const double*)(layout ? m->rhoT64.p : m->rho64.p), (const double*)m->chi64.p,
+             (const double*)m->kap64.p, (const double*)m->alb64.p, (const double*)m->g64.p,
+             (const double*)m->lcdf64.p, (const double*)m->scdf64.p, (const double*)m->ecdf64.p,
+             (const double*)m->rowpos64.p, (const double*)m->scoarse64.p,
+             (const double*)m->ecoarse64.p);
+        const size_t lds = transport_lds_bytes<double>(P);
+        const int bpc = m->cfg.blocks_per_cu > 0
+                            ? m->cfg.blocks_per_cu
+                            : transport_max_blocks_per_cu<double>(K, layout, threads, lds);
+        HIPCHK(launch_transport<double>(P, K, layout, grid_size(bpc), threads, s));
     }
     HIPCHK(hipEventRecord(m->ev[1], s));
     // counters
@@ -462,9 +572,15 @@ mcrt_status update_cells(mcrt_model* m, mcrt_iter_stats* st) {
     HIPCHK(hipMemsetAsync(stats, 0, 8 * sizeof(unsigned long long), s));
     CellParams P{};
     P.ncell = m->ncell;
+    for (int a = 0; a < 3; ++a) P.n[a] = m->n[a];
+    P.brick = m->t_layout == 1;
+    P.bx = m->bx;
+    P.bxy = m->bx * m->by;
     P.eps_over_vol = (m->ltot / (double)m->cfg.n_packets) / m->vol;
     P.rho = m->rho64.p;
     P.acc = m->acc.p;
+    P.acc_copies = m->acc_copies;
+    P.acc_stride = m->acc_stride;
     P.acc2 = m->cfg.want_noise ? m->acc2.p : nullptr;
     P.adot = m->adot.p;
     P.adot_prev = m->adot_prev.p;
@@ -552,6 +668,9 @@ mcrt_status mcrt_run_cfg_default(mcrt_run_cfg* c) {
     c->event_log_cap = 256;
     c->block_size = 256;
     c->defer_lanes = 16;
+    c->walk_batch = 4;
+    c->grid_layout = 0;
+    c->tally_copies = kMaxTallyCopies;
     return MCRT_OK;
 }
 
@@ -582,7 +701,8 @@ void mcrt_destroy(mcrt_model* m) {
     if (m->stream) hipStreamSynchronize(m->stream);
     for (int i = 0; i < 4; ++i)
         if (m->ev[i]) hipEventDestroy(m->ev[i]);
-    m->rho64.release(); m->rho32.release();
+    m->rho64.release(); m->rho32.release(); m->rhoT64.release(); m->rhoT32.release();
+    m->ecoarse64.release(); m->scoarse64.release(); m->ecoarse32.release(); m->scoarse32.release();
     m->chi64.release(); m->kap64.release(); m->alb64.release(); m->g64.release();
     m->lcdf64.release(); m->scdf64.release(); m->ecdf64.release();
     m->chi32.release(); m->kap32.release(); m->alb32.release(); m->g32.release();
@@ -640,6 +760,7 @@ mcrt_status mcrt_set_grid(mcrt_model* m, int nx, int ny, int nz, const double lo
     m->have_grid = true;
     m->have_rho = false;
     m->state_ready = false;
+    m->t_layout = -1;
     m->src.clear();
     m->tables_dirty = true;
     return MCRT_OK;
@@ -654,6 +775,7 @@ mcrt_status mcrt_set_density(mcrt_model* m, const double* rho, size_t n) {
         if (!(rho[i] >= 0.0) || !isfinite(rho[i]))
             return fail(m, MCRT_E_ARG, "density must be finite and >= 0");
     hipSetDevice(m->device);
+    m->t_layout = -1;  // transport-layout copies are rebuilt from the new density
     HIPCHK(m->rho64.ensure(n));
     HIPCHK(m->rho32.ensure(n));
     HIPCHK(hipMemcpyAsync(m->rho64.p, rho, n * sizeof(double), hipMemcpyHostToDevice, m->stream));
@@ -669,6 +791,7 @@ mcrt_status mcrt_set_density_device(mcrt_model* m, const void* d_rho, int is_fp6
     if (!d_rho) return fail(m, MCRT_E_ARG, "null density");
     if ((int64_t)n != m->ncell) return fail(m, MCRT_E_SIZE, "density size does not match the grid");
     hipSetDevice(m->device);
+    m->t_layout = -1;  // transport-layout copies are rebuilt from the new density
     HIPCHK(m->rho64.ensure(n));
     HIPCHK(m->rho32.ensure(n));
     hipStream_t s = m->stream;

@@ -88,13 +88,27 @@ __device__ __forceinline__ double wave_max(double v) {
 //   r_j = |T^i - T^{i-1}| / T^{i-1} over the mask (dust, sampled now, previous
 //         T valid, and -- with the noise estimate -- sigma_dT/T below a limit)
 // Cells outside a set get +inf so that a selection over the set ignores them.
+// index of x-fastest cell j in the 4x4x4 brick layout of the transport arrays
+__device__ __forceinline__ int64_t brick_index(int64_t j, int nx, int ny, int bx, int bxy) {
+    const int64_t nxy = (int64_t)nx * ny;
+    const int c2 = (int)(j / nxy);
+    const int64_t r = j - (int64_t)c2 * nxy;
+    const int c1 = (int)(r / nx);
+    const int c0 = (int)(r - (int64_t)c1 * nx);
+    return ((int64_t)((c2 >> 2) * bxy + (c1 >> 2) * bx + (c0 >> 2)) << 6) | ((c2 & 3) << 4) |
+           ((c1 & 3) << 2) | (c0 & 3);
+}
+
 __global__ void k_update(CellParams P) {
     unsigned long long n_r = 0, n_mask = 0, n_uns = 0, n_cl = 0;
     double rmax = 0.0;
     const double INF = __builtin_inf();
     for (int64_t j = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; j < P.ncell;
          j += (int64_t)gridDim.x * blockDim.x) {
-        const double a = P.eps_over_vol * P.acc[j];
+        const int64_t jt = P.brick ? brick_index(j, P.n[0], P.n[1], P.bx, P.bxy) : j;
+        double tally = 0.0;
+        for (int c = 0; c < P.acc_copies; ++c) tally += P.acc[jt + (size_t)c * P.acc_stride];
+        const double a = P.eps_over_vol * tally;
         const double Tp = P.T[j];
         const double sp = P.sig_rel[j];
         const unsigned char vp = P.valid[j];
@@ -107,7 +121,7 @@ __global__ void k_update(CellParams P) {
         P.adot[j] = a;
         double sig = 0.0;
         if (P.acc2) {
-            sig = P.eps_over_vol * sqrt(P.acc2[j]);
+            sig = P.eps_over_vol * sqrt(P.acc2[jt]);
             P.adot_sig[j] = sig;
         }
         double T, srel = 0.0;
@@ -267,6 +281,25 @@ __global__ void k_count_bad(int64_t n, const double* __restrict__ v, int strict_
     }
     for (int o = 32; o > 0; o >>= 1) c += __shfl_xor(c, o);
     if (__lane_id() == 0 && c) atomicAdd(bad, c);
+}
+
+// x-fastest -> 4x4x4 bricks (pad cells of partial bricks keep their zero)
+template <typename T>
+__global__ void k_to_bricks(int64_t n, int nx, int ny, int bx, int bxy, const T* __restrict__ in,
+                            T* __restrict__ out) {
+    for (int64_t j = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; j < n;
+         j += (int64_t)gridDim.x * blockDim.x)
+        out[brick_index(j, nx, ny, bx, bxy)] = in[j];
+}
+hipError_t launch_to_bricks_f32(int64_t n, int nx, int ny, int bx, int bxy, const float* in,
+                                float* out, int blocks, hipStream_t st) {
+    hipLaunchKernelGGL(k_to_bricks<float>, dim3(blocks), dim3(256), 0, st, n, nx, ny, bx, bxy, in, out);
+    return hipGetLastError();
+}
+hipError_t launch_to_bricks_f64(int64_t n, int nx, int ny, int bx, int bxy, const double* in,
+                                double* out, int blocks, hipStream_t st) {
+    hipLaunchKernelGGL(k_to_bricks<double>, dim3(blocks), dim3(256), 0, st, n, nx, ny, bx, bxy, in, out);
+    return hipGetLastError();
 }
 
 hipError_t launch_to_f32(int64_t n, const double* in, float* out, int blocks, hipStream_t st) {

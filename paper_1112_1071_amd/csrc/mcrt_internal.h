@@ -20,17 +20,26 @@ constexpr int kWave = 64;
 enum CounterIdx { C_CROSS_DUST = 0, C_CROSS_EMPTY, C_SCATTER, C_ABSORB, C_ESCAPE, C_KILLED,
                   C_COUNT };
 
+constexpr int kGroup = 16;          // CDF entries per group of the two-level search
+constexpr int kPoolChunk = 64;      // packet ids a wave takes from the pool at a time
+
 // Transport launch parameters (one model).  R is the transport precision.
 template <typename R>
 struct TransportParams {
     // grid
     int n[3];
-    int pad0;
+    int bx, bxy;            // bricks along x, bricks per z layer (4x4x4 layout)
     double lo[3];
     double dx[3];           // cell size, cm
     R dxr[3];               // same in R
     R inv_dx[3];            // 1/dx in R
-    const R* rho;           // [ncell] density
+    const R* rho;           // [ncell or bricked] density in the transport layout
+    // CDF tables are padded to npad = kGroup*ngroup entries per row (pad 2.0);
+    // coarse[r*ngroup + q] = cdf[r*npad + kGroup*q + kGroup-1]
+    int npad, ngroup;
+    const R* ecoarse;       // [kRows*ngroup]
+    const R* scoarse;       // [nsrc*ngroup]
+    int lds_tables;         // stage lcdf, ecoarse, scoarse in LDS
     // dust per frequency bin
     int nnu;
     const R* chi;
@@ -42,11 +51,11 @@ struct TransportParams {
     int sampling;           // 0 luminosity-proportional, 1 equal numbers
     const double* spos;     // [3*nsrc]
     const R* lcdf;          // [nsrc] luminosity CDF
-    const R* scdf;          // [nsrc*nnu] spectral CDFs
+    const R* scdf;          // [nsrc*npad] spectral CDFs
     const double* sweight;  // [nsrc] packet weight relative to eps0 (equal sampling)
     // emission rows of every cell: position p in [0, kRows-1]; row m = floor(p), weight p-m
-    const R* ecdf;          // [kRows*nnu]
-    const R* rowpos;        // [ncell]
+    const R* ecdf;          // [kRows*npad]
+    const R* rowpos;        // [ncell] (x-fastest)
     // random numbers
     uint32_t key0, key1;
     // packets
@@ -56,9 +65,10 @@ struct TransportParams {
     double eps0;            // erg per packet of weight 1
     int64_t max_events;
     int defer_lanes;
-    // tallies
-    double* acc;            // [ncell] sum of weight * l * kappa (cm^-1 cm^2 g^-1 ... per eps0)
+    // tallies (transport layout)
+    double* acc;            // sum of weight * l * kappa over segments (cm^3 g^-1 per eps0)
     double* acc2;           // [ncell] sum of squares, or null
+    size_t acc_stride;      // elements between the per-XCD copies of acc (0: one copy)
     int binning;
     int n_incl;
     double* sed_sum;
@@ -82,9 +92,14 @@ struct TransportParams {
 // Cell-update parameters (always FP64).
 struct CellParams {
     int64_t ncell;
+    int n[3];
+    int brick;              // acc/acc2 are in the 4x4x4 brick layout
+    int bx, bxy;
     double eps_over_vol;    // eps0 / (Delta t V), Delta t = 1 s
     const double* rho;
     const double* acc;
+    int acc_copies;         // copies of acc to sum, acc_stride elements apart
+    size_t acc_stride;
     const double* acc2;     // or null
     double* adot;
     double* adot_prev;

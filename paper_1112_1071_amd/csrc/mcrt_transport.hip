@@ -2,18 +2,28 @@
 // Sec. 2.2 propagation, Sec. 2.3 Eq. 2 Lucy estimator, Sec. 2.6.1 binning).
 //
 // One persistent launch processes a whole pass.  Every lane of a wave64 holds
-// one packet in registers.  Lanes that have finished a packet take the next
-// packet ids from a global pool counter with one atomic per wave (pool
-// refill).  Between events a lane walks the grid one cell per loop trip; a
-// wave keeps walking until `defer_lanes` of its lanes wait for an event, and
-// then handles all waiting lanes of one event type together (event-type
-// compaction by ballot), so that the expensive event code runs for many lanes
-// at once instead of once per diverging lane.
+// one packet in registers.  Lanes that have finished a packet take new packet
+// ids from a chunk that the wave draws from the global pool counter (pool
+// refill, one global atomic per 64 packets).  Between events a lane walks the
+// grid in batches of K segments: it first steps the ray K walls ahead (pure
+// arithmetic, Amanatides-Woo style: per axis the ray distance of the next wall
+// and the distance between walls), then issues the K density gathers at once,
+// then consumes the segments in order, adding weight*l*kappa to each dust
+// cell's FP64 absorption tally with a hardware FP64 atomic, until the sampled
+// optical depth is used up.  K gathers in flight per lane instead of one hide
+// the memory latency that otherwise bounds the walk.
 //
-// Per cell crossing a lane reads the cell density (one random gather) and
-// adds weight*l*kappa to the cell's FP64 absorption tally with a hardware
-// FP64 atomic.  The same template serves the FP64 path (same random stream,
-// same decisions as the CPU oracle) and the FP32 transport form.
+// A wave keeps walking until `defer_lanes` of its lanes wait for an event and
+// then handles all waiting lanes of one event type together (event-type
+// compaction by ballot).  Frequency sampling uses a two-level search: a
+// coarse index of every 16th CDF entry staged in LDS, then one 64-byte group
+// read from global memory.
+//
+// The grid arrays may be stored in bricks of 4x4x4 cells so that the few
+// cells a ray crosses inside a brick share cache lines.
+//
+// The same template serves the FP64 path (same random stream and decisions as
+// the CPU oracle) and the FP32 transport form.
 #include <math.h>
 
 #include "mcrt_internal.h"
@@ -86,9 +96,9 @@ template <> struct Const<float> {
 __device__ __forceinline__ void sin_cos(double x, double* s, double* c) { sincos(x, s, c); }
 __device__ __forceinline__ void sin_cos(float x, float* s, float* c) { sincosf(x, s, c); }
 
-// smallest k with u < cdf[k] (cdf[n-1] == 1)
+// smallest k with u < cdf[k] (cdf[n-1] == 1), plain binary search
 template <typename R>
-__device__ __forceinline__ int cdf_search(const R* __restrict__ cdf, int n, R u) {
+__device__ __forceinline__ int cdf_search(const R* cdf, int n, R u) {
     int lo = 0, hi = n - 1;
     while (lo < hi) {
         const int mid = (lo + hi) >> 1;
@@ -98,13 +108,50 @@ __device__ __forceinline__ int cdf_search(const R* __restrict__ cdf, int n, R u)
     return lo;
 }
 
+// number of entries <= u among the 16 entries of a group (64 B of FP32, 128 B of FP64)
+__device__ __forceinline__ int count_le16(const float* __restrict__ g, float u) {
+    const float4* v = reinterpret_cast<const float4*>(g);
+    int c = 0;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        const float4 q = v[i];
+        c += (q.x <= u) + (q.y <= u) + (q.z <= u) + (q.w <= u);
+    }
+    return c;
+}
+__device__ __forceinline__ int count_le16(const double* __restrict__ g, double u) {
+    const double2* v = reinterpret_cast<const double2*>(g);
+    int c = 0;
+#pragma unroll
+    for (int i = 0; i < 8; ++i) {
+        const double2 q = v[i];
+        c += (q.x <= u) + (q.y <= u);
+    }
+    return c;
+}
+
+// Same result as cdf_search on a padded row: the coarse index (every 16th
+// entry, usually in LDS) selects the group, one group read finishes it.
+template <typename R>
+__device__ __forceinline__ int cdf_search2(const R* row, const R* coarse, int ngroup, R u) {
+    int lo = 0, hi = ngroup - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi) >> 1;
+        if (u < coarse[mid]) hi = mid;
+        else lo = mid + 1;
+    }
+    return kGroup * lo + count_le16(row + kGroup * lo, u);
+}
+
 enum : int { ST_EMPTY = 0, ST_WALK = 1, ST_EVENT = 2, ST_ESC = 3, ST_DONE = 4 };
 
 template <typename R> struct Packet {
-    int c0, c1, c2;      // cell
-    R f0, f1, f2;        // position inside the cell, in cell units [0,1]
+    int c0, c1, c2;      // current cell
     R d0, d1, d2;        // direction (unit vector)
-    R is0, is1, is2;     // dx_a / |d_a|
+    R u0, u1, u2;        // flight origin in grid cell units (cell index + in-cell offset)
+    R tx, ty, tz;        // ray distance from the flight origin to the next wall per axis
+    R dtx, dty, dtz;     // ray distance between walls per axis: dx_a / |d_a|
+    R t;                 // ray distance walked in this flight
     R tau, tau_acc;      // sampled optical depth and the part used so far
     R chi, kap, wgt;     // opacity of the bin; packet weight (energy / eps0)
     int k;               // frequency bin
@@ -114,11 +161,59 @@ template <typename R> struct Packet {
     int st;
 };
 
+template <int BRICK, typename P>
+__device__ __forceinline__ int cell_index(const P& p, int c0, int c1, int c2) {
+    if (BRICK)
+        return ((((c2 >> 2) * p.bxy + (c1 >> 2) * p.bx + (c0 >> 2)) << 6) | ((c2 & 3) << 4) |
+                ((c1 & 3) << 2) | (c0 & 3));
+    return c0 + p.n[0] * (c1 + p.n[1] * c2);
+}
+
+template <int BRICK, typename P>
+__device__ __forceinline__ void cell_coords(const P& p, int j, int& c0, int& c1, int& c2) {
+    if (BRICK) {
+        const int b = j >> 6, o = j & 63;
+        const int bz = b / p.bxy, r = b - bz * p.bxy;
+        const int by = r / p.bx, bxx = r - by * p.bx;
+        c0 = (bxx << 2) | (o & 3);
+        c1 = (by << 2) | ((o >> 2) & 3);
+        c2 = (bz << 2) | (o >> 4);
+    } else {
+        const int nxy = p.n[0] * p.n[1];
+        c2 = j / nxy;
+        const int r = j - c2 * nxy;
+        c1 = r / p.n[0];
+        c0 = r - c1 * p.n[0];
+    }
+}
+
+// Start a flight from cell c with in-cell offset f: wall distances per axis,
+// then tau = -ln(u) (Sec. 2.2).
 template <typename R>
-__device__ __forceinline__ void set_direction(Packet<R>& s, const TransportParams<R>& P) {
-    s.is0 = P.dxr[0] / fabs(s.d0);
-    s.is1 = P.dxr[1] / fabs(s.d1);
-    s.is2 = P.dxr[2] / fabs(s.d2);
+__device__ __forceinline__ void begin_flight(Packet<R>& s, const TransportParams<R>& P,
+                                             Stream<R>& rs, R f0, R f1, R f2) {
+    const R INF = Const<R>::inf();
+    s.u0 = (R)s.c0 + f0;
+    s.u1 = (R)s.c1 + f1;
+    s.u2 = (R)s.c2 + f2;
+    s.dtx = P.dxr[0] / fabs(s.d0);
+    s.dty = P.dxr[1] / fabs(s.d1);
+    s.dtz = P.dxr[2] / fabs(s.d2);
+    s.tx = s.d0 == (R)0 ? INF : (s.d0 > (R)0 ? (R)1 - f0 : f0) * s.dtx;
+    s.ty = s.d1 == (R)0 ? INF : (s.d1 > (R)0 ? (R)1 - f1 : f1) * s.dty;
+    s.tz = s.d2 == (R)0 ? INF : (s.d2 > (R)0 ? (R)1 - f2 : f2) * s.dtz;
+    s.t = (R)0;
+    s.tau = -log(rs.next());
+    s.tau_acc = (R)0;
+}
+
+// in-cell offset of the point at ray distance t of the current flight
+template <typename R>
+__device__ __forceinline__ void offsets_at(const Packet<R>& s, const TransportParams<R>& P, R t,
+                                           R& f0, R& f1, R& f2) {
+    f0 = fmin((R)1, fmax((R)0, s.u0 + s.d0 * P.inv_dx[0] * t - (R)s.c0));
+    f1 = fmin((R)1, fmax((R)0, s.u1 + s.d1 * P.inv_dx[1] * t - (R)s.c1));
+    f2 = fmin((R)1, fmax((R)0, s.u2 + s.d2 * P.inv_dx[2] * t - (R)s.c2));
 }
 
 template <typename R>
@@ -188,15 +283,16 @@ __device__ __forceinline__ void log_event(Packet<R>& s, const TransportParams<R>
     P.evcount[s.id] = (int32_t)(i + 1);
 }
 
-template <typename R>
-__device__ __forceinline__ void begin_flight(Packet<R>& s, Stream<R>& rs) {
-    s.tau = -log(rs.next());
-    s.tau_acc = (R)0;
-}
+// Tables the event code searches: from LDS when they were staged there.
+template <typename R> struct Tables {
+    const R* lcdf;
+    const R* ecoarse;
+    const R* scoarse;
+};
 
 template <typename R>
 __device__ __forceinline__ void emit(Packet<R>& s, Stream<R>& rs, const TransportParams<R>& P,
-                                     uint64_t id) {
+                                     const Tables<R>& tb, uint64_t id) {
     s.id = id;
     const uint64_t gid = P.packet_base + id;
     rs.p0 = (uint32_t)gid;
@@ -205,113 +301,140 @@ __device__ __forceinline__ void emit(Packet<R>& s, Stream<R>& rs, const Transpor
     const R u_src = rs.next(), u_nu = rs.next(), u_mu = rs.next(), u_phi = rs.next();
     int src;
     if (P.sampling == 0) {
-        src = cdf_search(P.lcdf, P.nsrc, u_src);
+        src = cdf_search(tb.lcdf, P.nsrc, u_src);
         s.wgt = (R)1;
     } else {
         src = (int)(gid % (uint64_t)P.nsrc);
         s.wgt = (R)P.sweight[src];
     }
-    s.k = cdf_search(P.scdf + (size_t)src * P.nnu, P.nnu, u_nu);
+    s.k = cdf_search2(P.scdf + (size_t)src * P.npad, tb.scoarse + (size_t)src * P.ngroup, P.ngroup,
+                      u_nu);
     isotropic(s, u_mu, u_phi);
-    set_direction(s, P);
     // start cell: floor of the position in cell units; a position exactly on a
     // wall belongs to the lower cell when the direction is negative on that axis
     const double* x = P.spos + 3 * src;
-    {
-        double fp = (x[0] - P.lo[0]) / P.dx[0];
-        double fl = floor(fp);
-        s.c0 = (int)fl;
-        s.f0 = (R)(fp - fl);
-        if (fp == fl && s.d0 < (R)0) { s.c0 -= 1; s.f0 = (R)1; }
-        fp = (x[1] - P.lo[1]) / P.dx[1];
-        fl = floor(fp);
-        s.c1 = (int)fl;
-        s.f1 = (R)(fp - fl);
-        if (fp == fl && s.d1 < (R)0) { s.c1 -= 1; s.f1 = (R)1; }
-        fp = (x[2] - P.lo[2]) / P.dx[2];
-        fl = floor(fp);
-        s.c2 = (int)fl;
-        s.f2 = (R)(fp - fl);
-        if (fp == fl && s.d2 < (R)0) { s.c2 -= 1; s.f2 = (R)1; }
+    R f[3];
+    int c[3];
+    const R dd[3] = {s.d0, s.d1, s.d2};
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        const double fp = (x[a] - P.lo[a]) / P.dx[a];
+        const double fl = floor(fp);
+        c[a] = (int)fl;
+        f[a] = (R)(fp - fl);
+        if (fp == fl && dd[a] < (R)0) {
+            c[a] -= 1;
+            f[a] = (R)1;
+        }
     }
+    s.c0 = c[0];
+    s.c1 = c[1];
+    s.c2 = c[2];
     s.chi = P.chi[s.k];
     s.kap = P.kap[s.k];
     s.nev = 0;
     s.nlog = 0;
     log_event(s, P, MCRT_EV_EMIT, -1);
-    begin_flight(s, rs);
-    const bool inside = s.c0 >= 0 && s.c0 < P.n[0] && s.c1 >= 0 && s.c1 < P.n[1] && s.c2 >= 0 &&
-                        s.c2 < P.n[2];
+    begin_flight(s, P, rs, f[0], f[1], f[2]);
+    const bool inside = (unsigned)s.c0 < (unsigned)P.n[0] && (unsigned)s.c1 < (unsigned)P.n[1] &&
+                        (unsigned)s.c2 < (unsigned)P.n[2];
     s.st = inside ? ST_WALK : ST_ESC;
 }
 
-// One segment of the grid walk: to the nearest wall, or to the interaction
-// point if the sampled optical depth is used up inside this cell.
-template <typename R>
-__device__ __forceinline__ void step(Packet<R>& s, const TransportParams<R>& P, uint32_t* cnt) {
-    const R INF = Const<R>::inf();
-    const int j = s.c0 + P.n[0] * (s.c1 + P.n[1] * s.c2);
-    const R t0 = s.d0 > (R)0 ? ((R)1 - s.f0) * s.is0 : (s.d0 < (R)0 ? s.f0 * s.is0 : INF);
-    const R t1 = s.d1 > (R)0 ? ((R)1 - s.f1) * s.is1 : (s.d1 < (R)0 ? s.f1 * s.is1 : INF);
-    const R t2 = s.d2 > (R)0 ? ((R)1 - s.f2) * s.is2 : (s.d2 < (R)0 ? s.f2 * s.is2 : INF);
-    int ax = 0;
-    R tm = t0;
-    if (t1 < tm) { ax = 1; tm = t1; }
-    if (t2 < tm) { ax = 2; tm = t2; }
-    R l = fmax(tm, (R)0);
-    const R rho = P.rho[j];
-    bool interact = false;
-    if (rho > (R)0) {
-        ++cnt[C_CROSS_DUST];
-        const R rc = rho * s.chi;
-        const R dtau = rc * l;
-        if (s.tau_acc + dtau >= s.tau) {
-            l = (s.tau - s.tau_acc) / rc;
-            interact = true;
-        } else {
-            s.tau_acc += dtau;
+// K segments of the grid walk: step K walls ahead, gather K densities at
+// once, then consume the segments until the optical depth is used up.
+template <typename R, int K, int BRICK>
+__device__ __forceinline__ void walk(Packet<R>& s, const TransportParams<R>& P, double* acc,
+                                     uint32_t* cnt) {
+    int jj[K];
+    R ll[K], ts[K];
+    int nseg = 0;
+    bool esc = false;
+    const int j0 = cell_index<BRICK>(P, s.c0, s.c1, s.c2);
+    int jc = j0;
+#pragma unroll
+    for (int i = 0; i < K; ++i) {
+        jj[i] = j0;
+        ll[i] = (R)0;
+        ts[i] = s.t;
+    }
+#pragma unroll
+    for (int i = 0; i < K; ++i) {
+        if (!esc) {
+            // nearest wall; ties go to the lowest axis
+            const bool ax1 = s.ty < s.tx;
+            R tm = ax1 ? s.ty : s.tx;
+            const bool ax2 = s.tz < tm;
+            tm = ax2 ? s.tz : tm;
+            const bool ax0 = !ax1 && !ax2;
+            const bool by = ax1 && !ax2;
+            jj[i] = jc;
+            ts[i] = s.t;
+            ll[i] = fmax(tm - s.t, (R)0);
+            nseg = i + 1;
+            s.t = fmax(tm, s.t);
+            const int n0 = s.c0 + (ax0 ? (s.d0 > (R)0 ? 1 : -1) : 0);
+            const int n1 = s.c1 + (by ? (s.d1 > (R)0 ? 1 : -1) : 0);
+            const int n2 = s.c2 + (ax2 ? (s.d2 > (R)0 ? 1 : -1) : 0);
+            const bool out = (unsigned)n0 >= (unsigned)P.n[0] || (unsigned)n1 >= (unsigned)P.n[1] ||
+                             (unsigned)n2 >= (unsigned)P.n[2];
+            if (out) {
+                esc = true;
+            } else {
+                s.c0 = n0;
+                s.c1 = n1;
+                s.c2 = n2;
+                s.tx += ax0 ? s.dtx : (R)0;
+                s.ty += by ? s.dty : (R)0;
+                s.tz += ax2 ? s.dtz : (R)0;
+                jc = cell_index<BRICK>(P, n0, n1, n2);
+            }
         }
-        const R w = s.wgt * l * s.kap;
-        unsafeAtomicAdd(P.acc + j, (double)w);
-        if (P.acc2) unsafeAtomicAdd(P.acc2 + j, (double)w * (double)w);
-    } else {
-        ++cnt[C_CROSS_EMPTY];
     }
-    const R a0 = s.f0 + s.d0 * P.inv_dx[0] * l;
-    const R a1 = s.f1 + s.d1 * P.inv_dx[1] * l;
-    const R a2 = s.f2 + s.d2 * P.inv_dx[2] * l;
-    if (interact) {
-        s.f0 = fmin((R)1, fmax((R)0, a0));
-        s.f1 = fmin((R)1, fmax((R)0, a1));
-        s.f2 = fmin((R)1, fmax((R)0, a2));
+    R rr[K];
+#pragma unroll
+    for (int i = 0; i < K; ++i) rr[i] = P.rho[jj[i]];
+    bool hit = false;
+    int jhit = j0;
+    R thit = (R)0;
+#pragma unroll
+    for (int i = 0; i < K; ++i) {
+        if (i < nseg && !hit) {
+            const R rho = rr[i];
+            if (rho > (R)0) {
+                ++cnt[C_CROSS_DUST];
+                const R rc = rho * s.chi;
+                R l = ll[i];
+                const R dtau = rc * l;
+                if (s.tau_acc + dtau >= s.tau) {
+                    l = (s.tau - s.tau_acc) / rc;
+                    hit = true;
+                    jhit = jj[i];
+                    thit = ts[i] + l;
+                } else {
+                    s.tau_acc += dtau;
+                }
+                const R w = s.wgt * l * s.kap;
+                unsafeAtomicAdd(acc + jj[i], (double)w);
+                if (P.acc2) unsafeAtomicAdd(P.acc2 + jj[i], (double)w * (double)w);
+            } else {
+                ++cnt[C_CROSS_EMPTY];
+            }
+        }
+    }
+    if (hit) {
+        cell_coords<BRICK>(P, jhit, s.c0, s.c1, s.c2);
+        s.t = thit;
         s.st = ST_EVENT;
-        return;
-    }
-    s.f0 = fmin((R)1, fmax((R)0, a0));
-    s.f1 = fmin((R)1, fmax((R)0, a1));
-    s.f2 = fmin((R)1, fmax((R)0, a2));
-    if (ax == 0) {
-        const bool up = s.d0 > (R)0;
-        const int cn = s.c0 + (up ? 1 : -1);
-        if (cn < 0 || cn >= P.n[0]) { s.f0 = up ? (R)1 : (R)0; s.st = ST_ESC; }
-        else { s.c0 = cn; s.f0 = up ? (R)0 : (R)1; }
-    } else if (ax == 1) {
-        const bool up = s.d1 > (R)0;
-        const int cn = s.c1 + (up ? 1 : -1);
-        if (cn < 0 || cn >= P.n[1]) { s.f1 = up ? (R)1 : (R)0; s.st = ST_ESC; }
-        else { s.c1 = cn; s.f1 = up ? (R)0 : (R)1; }
-    } else {
-        const bool up = s.d2 > (R)0;
-        const int cn = s.c2 + (up ? 1 : -1);
-        if (cn < 0 || cn >= P.n[2]) { s.f2 = up ? (R)1 : (R)0; s.st = ST_ESC; }
-        else { s.c2 = cn; s.f2 = up ? (R)0 : (R)1; }
+    } else if (esc) {
+        s.st = ST_ESC;
     }
 }
 
 // Scatter (u <= albedo) or absorb and re-emit (Sec. 2.2), then a new flight.
 template <typename R>
 __device__ __forceinline__ void interact(Packet<R>& s, Stream<R>& rs, const TransportParams<R>& P,
-                                         uint32_t* cnt, double& e_killed) {
+                                         const Tables<R>& tb, uint32_t* cnt, double& e_killed) {
     s.nev += 1;
     if ((int64_t)s.nev > P.max_events) {
         ++cnt[C_KILLED];
@@ -320,6 +443,8 @@ __device__ __forceinline__ void interact(Packet<R>& s, Stream<R>& rs, const Tran
         s.st = ST_EMPTY;
         return;
     }
+    R f0, f1, f2;
+    offsets_at(s, P, s.t, f0, f1, f2);
     const R u_int = rs.next();
     if (u_int > P.alb[s.k]) {
         const R u_mix = rs.next(), u_nu = rs.next(), u_mu = rs.next(), u_phi = rs.next();
@@ -329,7 +454,8 @@ __device__ __forceinline__ void interact(Packet<R>& s, Stream<R>& rs, const Tran
         m = m > kRows - 2 ? kRows - 2 : m;
         const R w = p - (R)m;
         const int row = m + (u_mix < w ? 1 : 0);
-        s.k = cdf_search(P.ecdf + (size_t)row * P.nnu, P.nnu, u_nu);
+        s.k = cdf_search2(P.ecdf + (size_t)row * P.npad, tb.ecoarse + row * P.ngroup, P.ngroup,
+                          u_nu);
         isotropic(s, u_mu, u_phi);
         ++cnt[C_ABSORB];
         log_event(s, P, MCRT_EV_ABSORB, -1);
@@ -342,8 +468,7 @@ __device__ __forceinline__ void interact(Packet<R>& s, Stream<R>& rs, const Tran
         ++cnt[C_SCATTER];
         log_event(s, P, MCRT_EV_SCATTER, -1);
     }
-    set_direction(s, P);
-    begin_flight(s, rs);
+    begin_flight(s, P, rs, f0, f1, f2);
     s.st = ST_WALK;
 }
 
@@ -363,13 +488,13 @@ __device__ __forceinline__ void escape(Packet<R>& s, const TransportParams<R>& P
         atomicAdd(P.sed_n + q, 1ull);
         const int ii = P.n_img > 0 ? P.img_of_bin[s.k] : -1;
         if (ii >= 0) {
-            // project the escape point on the plane perpendicular to d
-            const double px = P.lo[0] + ((double)s.c0 + (double)s.f0) * P.dx[0] -
-                              (P.lo[0] + 0.5 * P.n[0] * P.dx[0]);
-            const double py = P.lo[1] + ((double)s.c1 + (double)s.f1) * P.dx[1] -
-                              (P.lo[1] + 0.5 * P.n[1] * P.dx[1]);
-            const double pz = P.lo[2] + ((double)s.c2 + (double)s.f2) * P.dx[2] -
-                              (P.lo[2] + 0.5 * P.n[2] * P.dx[2]);
+            // escape point (on the grid boundary), projected on the plane
+            // perpendicular to d
+            R f0, f1, f2;
+            offsets_at(s, P, s.t, f0, f1, f2);
+            const double px = ((double)s.c0 + (double)f0 - 0.5 * P.n[0]) * P.dx[0];
+            const double py = ((double)s.c1 + (double)f1 - 0.5 * P.n[1]) * P.dx[1];
+            const double pz = ((double)s.c2 + (double)f2 - 0.5 * P.n[2]) * P.dx[2];
             const double d0 = s.d0, d1 = s.d1, d2 = s.d2;
             double ex0 = -d1, ex1 = d0;
             const double en = sqrt(ex0 * ex0 + ex1 * ex1);
@@ -399,12 +524,28 @@ __device__ __forceinline__ uint64_t shfl_u64(uint64_t v, int src) {
     return ((uint64_t)hi << 32) | lo;
 }
 
-template <typename R>
+template <typename R, int K, int BRICK>
 __global__ void __launch_bounds__(256) k_transport(TransportParams<R> P) {
+    extern __shared__ unsigned char smem_raw[];
     __shared__ unsigned long long s_cnt[C_COUNT];
     __shared__ double s_energy[2];
     if (threadIdx.x < C_COUNT) s_cnt[threadIdx.x] = 0ull;
     if (threadIdx.x < 2) s_energy[threadIdx.x] = 0.0;
+    Tables<R> tb;
+    if (P.lds_tables) {
+        R* sm = reinterpret_cast<R*>(smem_raw);
+        const int ne = kRows * P.ngroup, ns = P.nsrc * P.ngroup;
+        for (int i = threadIdx.x; i < P.nsrc; i += blockDim.x) sm[i] = P.lcdf[i];
+        for (int i = threadIdx.x; i < ne; i += blockDim.x) sm[P.nsrc + i] = P.ecoarse[i];
+        for (int i = threadIdx.x; i < ns; i += blockDim.x) sm[P.nsrc + ne + i] = P.scoarse[i];
+        tb.lcdf = sm;
+        tb.ecoarse = sm + P.nsrc;
+        tb.scoarse = sm + P.nsrc + ne;
+    } else {
+        tb.lcdf = P.lcdf;
+        tb.ecoarse = P.ecoarse;
+        tb.scoarse = P.scoarse;
+    }
     __syncthreads();
 
     uint32_t cnt[C_COUNT] = {0, 0, 0, 0, 0, 0};
@@ -419,29 +560,51 @@ __global__ void __launch_bounds__(256) k_transport(TransportParams<R> P) {
     rs.p0 = rs.p1 = rs.s0 = rs.s1 = 0;
     const int lane = __lane_id();
     const int defer = P.defer_lanes;
+    // absorption tally of this block: with per-XCD copies, the copy of the XCD
+    // the block runs on (hardware XCC id), so that the FP64 atomics of different
+    // XCDs never meet on a cache line
+    double* acc = P.acc;
+    if (P.acc_stride) {
+        unsigned xcc;
+        asm volatile("s_getreg_b32 %0, hwreg(HW_REG_XCC_ID)" : "=s"(xcc));
+        acc += (size_t)(xcc & 7u) * P.acc_stride;
+    }
+    // packet ids held by this wave: [wbase, wend), the same value in every lane
+    uint64_t wbase = 0, wend = 0;
 
     for (;;) {
-        // pool refill: one atomic per wave hands consecutive ids to the empty lanes
+        // pool refill: empty lanes take ids from the wave's chunk, which is
+        // topped up from the global pool with one atomic per kPoolChunk ids
         const unsigned long long need = __ballot(s.st == ST_EMPTY);
         if (need) {
-            const int leader = __ffsll((long long)need) - 1;
-            unsigned long long base = 0;
-            if (lane == leader) base = atomicAdd(P.pool, (unsigned long long)__popcll(need));
-            base = shfl_u64(base, leader);
+            const int nneed = __popcll(need);
+            const int rank = __popcll(need & __lanemask_lt());
+            const int avail = (int)(wend - wbase);
+            const int take = nneed < avail ? nneed : avail;
+            uint64_t my = wbase + (uint64_t)rank;
+            wbase += (uint64_t)take;
+            if (nneed > take) {
+                const int leader = __ffsll((long long)need) - 1;
+                unsigned long long g = 0;
+                if (lane == leader) g = atomicAdd(P.pool, (unsigned long long)kPoolChunk);
+                g = shfl_u64(g, leader);
+                if (rank >= take) my = g + (uint64_t)(rank - take);
+                wbase = g + (uint64_t)(nneed - take);
+                wend = g + kPoolChunk;
+            }
             if (s.st == ST_EMPTY) {
-                const uint64_t my = base + __popcll(need & __lanemask_lt());
-                if (my < P.n_packets) emit(s, rs, P, my);
+                if (my < P.n_packets) emit(s, rs, P, tb, my);
                 else s.st = ST_DONE;
             }
         }
         if (__ballot(s.st != ST_DONE) == 0ull) break;
         // walk until enough lanes wait for an event (or none walks)
         for (;;) {
-            if (s.st == ST_WALK) step(s, P, cnt);
+            if (s.st == ST_WALK) walk<R, K, BRICK>(s, P, acc, cnt);
             if (__ballot(s.st == ST_WALK) == 0ull) break;
             if (__popcll(__ballot(s.st == ST_EVENT || s.st == ST_ESC)) >= defer) break;
         }
-        if (s.st == ST_EVENT) interact(s, rs, P, cnt, e_killed);
+        if (s.st == ST_EVENT) interact(s, rs, P, tb, cnt, e_killed);
         if (s.st == ST_ESC) escape(s, P, cnt, e_escaped);
     }
 
@@ -454,22 +617,53 @@ __global__ void __launch_bounds__(256) k_transport(TransportParams<R> P) {
     if (threadIdx.x < 2) unsafeAtomicAdd(P.energies + threadIdx.x, s_energy[threadIdx.x]);
 }
 
+template <typename R> using KernelFn = void (*)(TransportParams<R>);
+
+template <typename R> KernelFn<R> pick_kernel(int K, int brick) {
+    if (brick) {
+        switch (K) {
+            case 1: return k_transport<R, 1, 1>;
+            case 2: return k_transport<R, 2, 1>;
+            case 8: return k_transport<R, 8, 1>;
+            default: return k_transport<R, 4, 1>;
+        }
+    }
+    switch (K) {
+        case 1: return k_transport<R, 1, 0>;
+        case 2: return k_transport<R, 2, 0>;
+        case 8: return k_transport<R, 8, 0>;
+        default: return k_transport<R, 4, 0>;
+    }
+}
+
 template <typename R>
-hipError_t launch_transport(const TransportParams<R>& P, int blocks, int threads, hipStream_t st) {
-    hipLaunchKernelGGL(k_transport<R>, dim3(blocks), dim3(threads), 0, st, P);
+size_t transport_lds_bytes(const TransportParams<R>& P) {
+    return P.lds_tables ? (size_t)(P.nsrc + (kRows + P.nsrc) * P.ngroup) * sizeof(R) : 0;
+}
+
+template <typename R>
+hipError_t launch_transport(const TransportParams<R>& P, int K, int brick, int blocks, int threads,
+                            hipStream_t st) {
+    hipLaunchKernelGGL(pick_kernel<R>(K, brick), dim3(blocks), dim3(threads),
+                       transport_lds_bytes(P), st, P);
     return hipGetLastError();
 }
 
-template <typename R> int transport_max_blocks_per_cu(int threads) {
+template <typename R> int transport_max_blocks_per_cu(int K, int brick, int threads, size_t lds) {
     int nb = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_transport<R>, threads, 0) != hipSuccess)
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, pick_kernel<R>(K, brick), threads, lds) !=
+        hipSuccess)
         return 1;
     return nb > 0 ? nb : 1;
 }
 
-template hipError_t launch_transport<double>(const TransportParams<double>&, int, int, hipStream_t);
-template hipError_t launch_transport<float>(const TransportParams<float>&, int, int, hipStream_t);
-template int transport_max_blocks_per_cu<double>(int);
-template int transport_max_blocks_per_cu<float>(int);
+template hipError_t launch_transport<double>(const TransportParams<double>&, int, int, int, int,
+                                             hipStream_t);
+template hipError_t launch_transport<float>(const TransportParams<float>&, int, int, int, int,
+                                            hipStream_t);
+template int transport_max_blocks_per_cu<double>(int, int, int, size_t);
+template int transport_max_blocks_per_cu<float>(int, int, int, size_t);
+template size_t transport_lds_bytes<double>(const TransportParams<double>&);
+template size_t transport_lds_bytes<float>(const TransportParams<float>&);
 
 }  // namespace mcrt

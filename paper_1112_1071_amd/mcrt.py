@@ -37,7 +37,8 @@ class RunCfg(C.Structure):
         ("source_sampling", C.c_int32), ("want_noise", C.c_int32),
         ("event_log_packets", C.c_int32), ("event_log_cap", C.c_int32),
         ("bin_every_iteration", C.c_int32), ("block_size", C.c_int32),
-        ("blocks_per_cu", C.c_int32), ("defer_lanes", C.c_int32), ("reserved0", C.c_int32),
+        ("blocks_per_cu", C.c_int32), ("defer_lanes", C.c_int32), ("walk_batch", C.c_int32),
+        ("grid_layout", C.c_int32), ("tally_copies", C.c_int32),
     ]
 
 
@@ -69,7 +70,7 @@ EVENT_DTYPE = np.dtype([("packet", "<i8"), ("index", "<i4"), ("type", "<i4"),
                         ("cell", "<i4", (3,)), ("nu", "<i4"), ("incl", "<i4"),
                         ("reserved", "<i4")])
 
-RUN_KEYS = [f for f, _ in RunCfg._fields_ if f != "reserved0"]
+RUN_KEYS = [f for f, _ in RunCfg._fields_]
 
 _lib = None
 

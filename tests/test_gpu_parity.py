@@ -262,3 +262,30 @@ def test_abi_errors(M):
     assert L.mcrt_iterate(h3, C.byref(st)) == -2
     L.mcrt_destroy(h3)
     L.mcrt_destroy(None)
+
+
+@pytest.mark.parametrize("variant", [
+    dict(walk_batch=1, grid_layout=0, tally_copies=1),
+    dict(walk_batch=2, grid_layout=1, tally_copies=8),
+    dict(walk_batch=4, grid_layout=1, tally_copies=1, block_size=128),
+    dict(walk_batch=8, grid_layout=0, tally_copies=8, defer_lanes=1),
+    dict(walk_batch=8, grid_layout=1, tally_copies=8, defer_lanes=64, block_size=64),
+])
+def test_launch_variants_same_stream(M, variant):
+    # every launch configuration the library offers gives the oracle's packets
+    cfg = synth.config0(n=20, tau=2.0, n_packets=30000, n_iter=1, n_bins=40)
+    cfg["grid"]["n"] = [20, 18, 13]  # ragged bricks on every axis
+    cfg["rho"] = np.resize(cfg["rho"], (13, 18, 20))
+    run = dict(event_log_packets=3000, event_log_cap=32)
+    o = oracle.OracleModel(cfg, **run)
+    g = M.Model(cfg, precision=M.MCRT_FP64, **run, **variant)
+    so, sg = o.iterate(), g.iterate()
+    for k in ["n_cross_dust", "n_cross_empty", "n_scatter", "n_absorb", "n_escape"]:
+        assert so[k] == sg[k], k
+    eo, co = o.event_log()
+    eg, cg = g.event_log()
+    compare_logs(eo, co, eg, cg)
+    ao, ag = o.specific_energy(), g.specific_energy()
+    nz = ao > 0
+    assert np.array_equal(nz, ag > 0)
+    assert np.max(np.abs(ag[nz] / ao[nz] - 1)) < 1e-9
