@@ -202,6 +202,48 @@ mcrt_status mcrt_get_event_log(mcrt_model* m, mcrt_event* ev, size_t cap_total, 
 /* Number of compute units of the model's device. */
 mcrt_status mcrt_device_info(mcrt_model* m, int* n_cu, int* wave_size);
 
+/* ---- batching: many independent models in one launch ---------------------
+ * Sec. 3 of the paper: packets are independent within an iteration, so the
+ * packets of many small models can share one persistent launch.  Each model
+ * keeps its own grid, dust, sources, seed, packet count and results; a model's
+ * results equal those of its own mcrt_iterate calls up to the order of FP64
+ * summation.  Per-model percentile statistics (q, p999_dT) are not computed
+ * in batches. */
+typedef struct {
+    int32_t n_iter;            /* Lucy iterations [5]                                      */
+    int32_t final_pass;        /* then the final binning pass [1]                          */
+    int32_t use_graph;         /* replay iterations after the first from a hipGraph [1]    */
+    int32_t autotune;          /* choose the launch shape by timing calibration runs [1]   */
+    int32_t block_size;        /* threads per block; 0 = tuned or 256                      */
+    int32_t walk_batch;        /* 0 = tuned or 4                                           */
+    int32_t defer_lanes;       /* 0 = tuned or 16                                          */
+    int32_t blocks_per_cu;     /* 0 = tuned or occupancy limit                             */
+    double tune_fraction;      /* packet fraction of each calibration run [0.02]           */
+} mcrt_batch_cfg;
+
+typedef struct {
+    int32_t n_models;
+    int32_t n_iterations;
+    int32_t graph_used;
+    int32_t tuned;             /* 1 measured now, 2 from the tuning cache, 0 not tuned     */
+    int32_t block_size, walk_batch, defer_lanes, blocks_per_cu;  /* launch shape used      */
+    int64_t packets_per_iteration;
+    int64_t n_cross_dust;      /* summed over models, last iteration                       */
+    int64_t n_cross_empty;
+    double ms_total;           /* wall time of the call                                    */
+    double ms_iterations;      /* wall time of the Lucy iterations                         */
+    double ms_final;           /* wall time of the final pass                              */
+    double ms_tune;            /* wall time of autotuning                                  */
+    double ms_transport_last;  /* device time of the last batched transport launch         */
+} mcrt_batch_stats;
+
+mcrt_status mcrt_batch_cfg_default(mcrt_batch_cfg* cfg);
+/* All models: same device and precision, fully set up.  The work runs on the
+ * first model's stream.  Returns the first failing model's status; the error
+ * message is then on models[0]. */
+mcrt_status mcrt_batch_run(mcrt_model* const* models, int n, const mcrt_batch_cfg* cfg,
+                           mcrt_batch_stats* st);
+
 #ifdef __cplusplus
 }
 #endif

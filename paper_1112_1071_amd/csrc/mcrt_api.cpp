@@ -6,7 +6,12 @@
 #include <string.h>
 
 #include <chrono>
+#include <algorithm>
+#include <map>
+#include <mutex>
+#include <tuple>
 #include <string>
+#include <type_traits>
 #include <vector>
 
 #include "mcrt_internal.h"
@@ -37,6 +42,8 @@ hipError_t launch_check_rho(int64_t n, const double* rho, unsigned long long* ba
                             hipStream_t st);
 hipError_t launch_fill_u8(int64_t n, unsigned char* p, unsigned char v, int blocks, hipStream_t st);
 hipError_t launch_fill_f64(int64_t n, double* p, double v, int blocks, hipStream_t st);
+hipError_t launch_fill_u64(int64_t n, unsigned long long* p, unsigned long long v, int blocks,
+                           hipStream_t st);
 }  // namespace mcrt
 
 using namespace mcrt;
@@ -371,65 +378,99 @@ mcrt_status ready(mcrt_model* m) {
     return ensure_bins(m);
 }
 
-// Emission rows from T, zeroed tallies, then one transport launch.
-mcrt_status run_transport(mcrt_model* m, int64_t np, uint32_t key1, int binning,
-                          mcrt_iter_stats* st) {
+// Equal-number sampling weights of a pass of np packets: source i gets
+// floor(np/ns) or one more packets, each carrying L_i / count (relative to eps0).
+mcrt_status set_weights(mcrt_model* m, int64_t np) {
+    const double eps0 = m->ltot / (double)np;
+    const size_t ns = m->src.size();
+    std::vector<double> sw(ns);
+    for (size_t i = 0; i < ns; ++i) {
+        const int64_t cnt = np / (int64_t)ns + ((int64_t)i < np % (int64_t)ns ? 1 : 0);
+        sw[i] = (m->src[i].lum / (double)(cnt > 0 ? cnt : 1)) / eps0;
+    }
+    HIPCHK(m->sweight.ensure(ns));
+    HIPCHK(hipMemcpy(m->sweight.p, sw.data(), ns * sizeof(double), hipMemcpyHostToDevice));
+    return MCRT_OK;
+}
+
+// Device work before a transport pass: emission rows from T, zeroed tallies and
+// counters, event-log buffers.  graph_safe clears with fill kernels (a captured
+// graph records no memset nodes).
+mcrt_status prepare_pass(mcrt_model* m, int64_t np, bool graph_safe) {
     hipStream_t s = m->stream;
     const size_t nc = (size_t)m->ncell;
     const bool f32 = m->cfg.precision == MCRT_FP32_TRANSPORT;
     unsigned long long* misc = m->misc.p;
-    HIPCHK(hipMemsetAsync(misc, 0, MISC_N * sizeof(unsigned long long), s));
-    HIPCHK(hipMemsetAsync(m->energies.p, 0, 2 * sizeof(double), s));
-    const int cb = grid_blocks(m, m->ncell);
-    if (f32) {
-        HIPCHK(m->rowpos32.ensure(nc));
-        HIPCHK(launch_rows32(m->ncell, m->T.p, m->rho64.p, m->rowpos32.p, misc + MISC_SCRATCH, cb, s));
-    } else {
-        HIPCHK(m->rowpos64.ensure(nc));
-        HIPCHK(launch_rows64(m->ncell, m->T.p, m->rho64.p, m->rowpos64.p, misc + MISC_SCRATCH, cb, s));
-    }
     const int layout = m->cfg.grid_layout == 1 ? 1 : 0;
     {
         mcrt_status r = ensure_transport_grid(m, layout);
         if (r != MCRT_OK) return r;
     }
+    if (f32) HIPCHK(m->rowpos32.ensure(nc));
+    else HIPCHK(m->rowpos64.ensure(nc));
     const size_t nt = (size_t)m->nt_cells;
     m->acc_copies = m->cfg.tally_copies == kMaxTallyCopies ? kMaxTallyCopies : 1;
-    HIPCHK(hipMemsetAsync(m->acc.p, 0, ((m->acc_copies - 1) * m->acc_stride + nt) * sizeof(double), s));
-    if (m->cfg.want_noise) HIPCHK(hipMemsetAsync(m->acc2.p, 0, nt * sizeof(double), s));
-    // event log
+    const size_t nacc = (m->acc_copies - 1) * m->acc_stride + nt;
     m->ev_packets = m->cfg.event_log_packets < np ? m->cfg.event_log_packets : np;
     m->ev_cap = m->cfg.event_log_cap > 0 ? m->cfg.event_log_cap : 256;
     if (m->ev_packets > 0) {
         HIPCHK(m->evlog.ensure((size_t)m->ev_packets * m->ev_cap));
         HIPCHK(m->evcount.ensure((size_t)m->ev_packets));
-        HIPCHK(hipMemsetAsync(m->evcount.p, 0, (size_t)m->ev_packets * sizeof(int32_t), s));
     }
-    const int threads = m->cfg.block_size > 0 ? m->cfg.block_size : 256;
-    const int K = m->cfg.walk_batch == 1 || m->cfg.walk_batch == 2 || m->cfg.walk_batch == 8
-                      ? m->cfg.walk_batch
-                      : 4;
+    if (graph_safe) {
+        HIPCHK(launch_fill_u64(MISC_N, misc, 0ull, 1, s));
+        HIPCHK(launch_fill_f64(2, m->energies.p, 0.0, 1, s));
+        HIPCHK(launch_fill_f64((int64_t)nacc, m->acc.p, 0.0, grid_blocks(m, (int64_t)nacc), s));
+        if (m->cfg.want_noise)
+            HIPCHK(launch_fill_f64((int64_t)nt, m->acc2.p, 0.0, grid_blocks(m, (int64_t)nt), s));
+        if (m->ev_packets > 0)
+            HIPCHK(launch_fill_u8((int64_t)m->ev_packets * 4, (unsigned char*)m->evcount.p, 0,
+                                  grid_blocks(m, m->ev_packets), s));
+    } else {
+        HIPCHK(hipMemsetAsync(misc, 0, MISC_N * sizeof(unsigned long long), s));
+        HIPCHK(hipMemsetAsync(m->energies.p, 0, 2 * sizeof(double), s));
+        HIPCHK(hipMemsetAsync(m->acc.p, 0, nacc * sizeof(double), s));
+        if (m->cfg.want_noise) HIPCHK(hipMemsetAsync(m->acc2.p, 0, nt * sizeof(double), s));
+        if (m->ev_packets > 0)
+            HIPCHK(hipMemsetAsync(m->evcount.p, 0, (size_t)m->ev_packets * sizeof(int32_t), s));
+    }
+    const int cb = grid_blocks(m, m->ncell);
+    if (f32)
+        HIPCHK(launch_rows32(m->ncell, m->T.p, m->rho64.p, m->rowpos32.p, misc + MISC_SCRATCH, cb, s));
+    else
+        HIPCHK(launch_rows64(m->ncell, m->T.p, m->rho64.p, m->rowpos64.p, misc + MISC_SCRATCH, cb, s));
+    return MCRT_OK;
+}
+
+int walk_batch_of(const mcrt_model* m) {
+    const int w = m->cfg.walk_batch;
+    return w == 1 || w == 2 || w == 8 ? w : 4;
+}
+
+// Launch parameters of one model's pass (prepare_pass must have run).
+template <typename R>
+void make_params(mcrt_model* m, int64_t np, uint32_t key1, int binning, TransportParams<R>& P) {
+    constexpr bool f32 = std::is_same<R, float>::value;
+    const int layout = m->t_layout == 1 ? 1 : 0;
+    unsigned long long* misc = m->misc.p;
     // coarse CDF indices and the luminosity CDF go to LDS when they are small
-    const size_t rb = f32 ? sizeof(float) : sizeof(double);
-    const size_t lds_need = (size_t)(m->src.size() + (kRows + m->src.size()) * m->ngroup) * rb;
+    const size_t lds_need = (size_t)(m->src.size() + (kRows + m->src.size()) * m->ngroup) * sizeof(R);
     const int lds_tables = lds_need <= 32768 ? 1 : 0;
     const double eps0 = m->ltot / (double)np;
-    {
-        // equal-number sampling: source i gets floor(np/ns) or one more packets,
-        // each carrying L_i / count (relative to eps0)
-        const size_t ns = m->src.size();
-        std::vector<double> sw(ns);
-        for (size_t i = 0; i < ns; ++i) {
-            const int64_t cnt = np / (int64_t)ns + ((int64_t)i < np % (int64_t)ns ? 1 : 0);
-            sw[i] = (m->src[i].lum / (double)(cnt > 0 ? cnt : 1)) / eps0;
-        }
-        HIPCHK(m->sweight.ensure(ns));
-        HIPCHK(hipMemcpy(m->sweight.p, sw.data(), ns * sizeof(double), hipMemcpyHostToDevice));
+    P = TransportParams<R>{};
+    const R *rho, *chi, *kap, *alb, *gg, *lcdf, *scdf, *ecdf, *rowpos, *scoarse, *ecoarse;
+    if constexpr (f32) {
+        rho = layout ? m->rhoT32.p : m->rho32.p;
+        chi = m->chi32.p; kap = m->kap32.p; alb = m->alb32.p; gg = m->g32.p;
+        lcdf = m->lcdf32.p; scdf = m->scdf32.p; ecdf = m->ecdf32.p; rowpos = m->rowpos32.p;
+        scoarse = m->scoarse32.p; ecoarse = m->ecoarse32.p;
+    } else {
+        rho = layout ? m->rhoT64.p : m->rho64.p;
+        chi = m->chi64.p; kap = m->kap64.p; alb = m->alb64.p; gg = m->g64.p;
+        lcdf = m->lcdf64.p; scdf = m->scdf64.p; ecdf = m->ecdf64.p; rowpos = m->rowpos64.p;
+        scoarse = m->scoarse64.p; ecoarse = m->ecoarse64.p;
     }
-
-    auto fill = [&](auto& P, auto* rho, auto* chi, auto* kap, auto* alb, auto* gg, auto* lcdf,
-                    auto* scdf, auto* ecdf, auto* rowpos, auto* scoarse, auto* ecoarse) {
-        using R = typename std::remove_const<typename std::remove_pointer<decltype(rho)>::type>::type;
+    {
         for (int a = 0; a < 3; ++a) {
             P.n[a] = m->n[a];
             P.lo[a] = m->lo[a];
@@ -486,39 +527,46 @@ mcrt_status run_transport(mcrt_model* m, int64_t np, uint32_t key1, int binning,
         P.evcount = m->evcount.p;
         P.counters = misc + MISC_CNT;
         P.energies = m->energies.p;
-    };
-    // persistent grid: as many blocks as fit on the device, or the request
-    auto grid_size = [&](int bpc) {
-        int64_t blocks = (int64_t)m->n_cu * bpc;
-        const int64_t need = (np + threads - 1) / threads;
-        if (blocks > need) blocks = need;
-        return (int)(blocks < 1 ? 1 : blocks);
-    };
+    }
+}
+
+int persistent_blocks(const mcrt_model* m, int bpc, int64_t np, int threads) {
+    int64_t blocks = (int64_t)m->n_cu * bpc;
+    const int64_t need = (np + threads - 1) / threads;
+    if (blocks > need) blocks = need;
+    return (int)(blocks < 1 ? 1 : blocks);
+}
+
+// Emission rows from T, zeroed tallies, then one persistent transport launch.
+mcrt_status run_transport(mcrt_model* m, int64_t np, uint32_t key1, int binning,
+                          mcrt_iter_stats* st) {
+    hipStream_t s = m->stream;
+    const bool f32 = m->cfg.precision == MCRT_FP32_TRANSPORT;
+    unsigned long long* misc = m->misc.p;
+    mcrt_status r = set_weights(m, np);
+    if (r != MCRT_OK) return r;
+    r = prepare_pass(m, np, false);
+    if (r != MCRT_OK) return r;
+    const int threads = m->cfg.block_size > 0 ? m->cfg.block_size : 256;
+    const int K = walk_batch_of(m);
+    const int layout = m->t_layout;
     HIPCHK(hipEventRecord(m->ev[0], s));
     if (f32) {
-        TransportParams<float> P{};
-        fill(P, (const float*)(layout ? m->rhoT32.p : m->rho32.p), (const float*)m->chi32.p,
-             (const float*)m->kap32.p, (const float*)m->alb32.p, (const float*)m->g32.p,
-             (const float*)m->lcdf32.p, (const float*)m->scdf32.p, (const float*)m->ecdf32.p,
-             (const float*)m->rowpos32.p, (const float*)m->scoarse32.p,
-             (const float*)m->ecoarse32.p);
+        TransportParams<float> P;
+        make_params(m, np, key1, binning, P);
         const size_t lds = transport_lds_bytes<float>(P);
         const int bpc = m->cfg.blocks_per_cu > 0
                             ? m->cfg.blocks_per_cu
                             : transport_max_blocks_per_cu<float>(K, layout, threads, lds);
-        HIPCHK(launch_transport<float>(P, K, layout, grid_size(bpc), threads, s));
+        HIPCHK(launch_transport<float>(P, K, layout, persistent_blocks(m, bpc, np, threads), threads, s));
     } else {
-        TransportParams<double> P{};
-        fill(P, (const double*)(layout ? m->rhoT64.p : m->rho64.p), (const double*)m->chi64.p,
-             (const double*)m->kap64.p, (const double*)m->alb64.p, (const double*)m->g64.p,
-             (const double*)m->lcdf64.p, (const double*)m->scdf64.p, (const double*)m->ecdf64.p,
-             (const double*)m->rowpos64.p, (const double*)m->scoarse64.p,
-             (const double*)m->ecoarse64.p);
+        TransportParams<double> P;
+        make_params(m, np, key1, binning, P);
         const size_t lds = transport_lds_bytes<double>(P);
         const int bpc = m->cfg.blocks_per_cu > 0
                             ? m->cfg.blocks_per_cu
                             : transport_max_blocks_per_cu<double>(K, layout, threads, lds);
-        HIPCHK(launch_transport<double>(P, K, layout, grid_size(bpc), threads, s));
+        HIPCHK(launch_transport<double>(P, K, layout, persistent_blocks(m, bpc, np, threads), threads, s));
     }
     HIPCHK(hipEventRecord(m->ev[1], s));
     // counters
@@ -565,12 +613,8 @@ uint64_t nearest_rank(double p, int64_t n) {
     return (uint64_t)(r - 1);
 }
 
-// Adot, T and the convergence statistics after a Lucy pass (Eqs. 2-6).
-mcrt_status update_cells(mcrt_model* m, mcrt_iter_stats* st) {
-    hipStream_t s = m->stream;
-    unsigned long long* stats = m->misc.p + MISC_STATS;
-    HIPCHK(hipMemsetAsync(stats, 0, 8 * sizeof(unsigned long long), s));
-    CellParams P{};
+void make_cell_params(mcrt_model* m, CellParams& P) {
+    P = CellParams{};
     P.ncell = m->ncell;
     for (int a = 0; a < 3; ++a) P.n[a] = m->n[a];
     P.brick = m->t_layout == 1;
@@ -599,7 +643,16 @@ mcrt_status update_cells(mcrt_model* m, mcrt_iter_stats* st) {
     P.noise_thres = m->cfg.conv_noise_thres;
     P.Rbuf = m->Rbuf.p;
     P.rbuf = m->rbuf.p;
-    P.stats = stats;
+    P.stats = m->misc.p + MISC_STATS;
+}
+
+// Adot, T and the convergence statistics after a Lucy pass (Eqs. 2-6).
+mcrt_status update_cells(mcrt_model* m, mcrt_iter_stats* st) {
+    hipStream_t s = m->stream;
+    unsigned long long* stats = m->misc.p + MISC_STATS;
+    HIPCHK(hipMemsetAsync(stats, 0, 8 * sizeof(unsigned long long), s));
+    CellParams P;
+    make_cell_params(m, P);
     HIPCHK(hipEventRecord(m->ev[2], s));
     HIPCHK(launch_update(P, grid_blocks(m, m->ncell), s));
     unsigned long long h[8];
@@ -1137,6 +1190,371 @@ mcrt_status mcrt_device_info(mcrt_model* m, int* n_cu, int* wave_size) {
         *wave_size = w;
     }
     return MCRT_OK;
+}
+
+}  // extern "C"
+
+// ===========================================================================
+// Batching: the packets of many models in one persistent launch, iterations
+// after the first replayed from a captured hipGraph, launch shape chosen by
+// timing calibration runs (cached per workload class).
+// ===========================================================================
+namespace mcrt {
+template <typename R>
+hipError_t launch_transport_batch(const TransportParams<R>* Ps, const unsigned long long* chunk_start,
+                                  int n_models, unsigned long long* pool, const uint32_t* keys,
+                                  int K, int brick, int blocks, int threads, hipStream_t st);
+template <typename R> int batch_max_blocks_per_cu(int K, int brick, int threads);
+hipError_t launch_add_u32(int64_t n, uint32_t* p, uint32_t v, int blocks, hipStream_t st);
+hipError_t launch_fill_u32(int64_t n, uint32_t* p, uint32_t v, int blocks, hipStream_t st);
+}  // namespace mcrt
+
+namespace {
+
+struct LaunchShape {
+    int block_size, walk_batch, defer, bpc;
+};
+
+std::mutex g_tune_mu;
+std::map<std::tuple<int, int, int>, LaunchShape> g_tune_cache;  // workload class -> shape
+
+struct Batch {
+    std::vector<mcrt_model*> ms;
+    std::vector<hipStream_t> saved_streams;
+    hipStream_t s = nullptr;
+    bool f32 = false;
+    int layout = 0;
+    void* d_params = nullptr;
+    unsigned long long* d_chunks = nullptr;  // n+1 prefix of 64-packet chunks, then the pool
+    uint32_t* d_keys = nullptr;
+    int n_cu = 256;
+    ~Batch() {
+        if (d_params) hipFree(d_params);
+        if (d_chunks) hipFree(d_chunks);
+        if (d_keys) hipFree(d_keys);
+        for (size_t i = 0; i < ms.size() && i < saved_streams.size(); ++i) ms[i]->stream = saved_streams[i];
+    }
+    int n() const { return (int)ms.size(); }
+    unsigned long long* pool() const { return d_chunks + ms.size() + 1; }
+};
+
+#define BCHK(expr)                                                                           \
+    do {                                                                                     \
+        hipError_t e_ = (expr);                                                              \
+        if (e_ != hipSuccess)                                                                \
+            return fail(B.ms[0], e_ == hipErrorOutOfMemory ? MCRT_E_NOMEM : MCRT_E_DEVICE,   \
+                        std::string(#expr) + ": " + hipGetErrorString(e_));                  \
+    } while (0)
+
+// Launch parameters of every model for a pass of frac * n_packets packets per
+// model (frac = 1 for real passes), the chunk prefix and the per-model keys.
+template <typename R>
+mcrt_status batch_upload(Batch& B, double frac, int binning, const LaunchShape& sh,
+                         const std::vector<uint32_t>& keys) {
+    std::vector<TransportParams<R>> P(B.n());
+    std::vector<unsigned long long> chunks(B.n() + 2, 0ull);
+    for (int i = 0; i < B.n(); ++i) {
+        mcrt_model* m = B.ms[i];
+        int64_t np = binning ? (m->cfg.n_packets_final > 0 ? m->cfg.n_packets_final : m->cfg.n_packets)
+                             : m->cfg.n_packets;
+        if (frac < 1.0) np = std::max<int64_t>(64, (int64_t)(frac * (double)np));
+        // the parameters point at buffers that set_weights and prepare_pass
+        // allocate (source weights, emission rows, event log) and depend on the
+        // tally copies prepare_pass selects
+        mcrt_status r = set_weights(m, np);
+        if (r != MCRT_OK) return r;
+        r = prepare_pass(m, np, false);
+        if (r != MCRT_OK) return r;
+        make_params(m, np, 0u, binning, P[i]);
+        P[i].lds_tables = 0;
+        P[i].defer_lanes = sh.defer;
+        chunks[i + 1] = chunks[i] + (unsigned long long)((np + kPoolChunk - 1) / kPoolChunk);
+    }
+    BCHK(hipMemcpy(B.d_params, P.data(), P.size() * sizeof(TransportParams<R>), hipMemcpyHostToDevice));
+    BCHK(hipMemcpy(B.d_chunks, chunks.data(), chunks.size() * sizeof(unsigned long long),
+                   hipMemcpyHostToDevice));
+    BCHK(hipMemcpy(B.d_keys, keys.data(), keys.size() * sizeof(uint32_t), hipMemcpyHostToDevice));
+    return MCRT_OK;
+}
+
+// Device work of one batched pass on B.s (capturable when graph_safe).
+template <typename R>
+mcrt_status batch_pass_ops(Batch& B, double frac, const LaunchShape& sh, bool graph_safe,
+                           bool update, bool bump_keys) {
+    for (int i = 0; i < B.n(); ++i) {
+        mcrt_model* m = B.ms[i];
+        int64_t np = m->cfg.n_packets;  // the same count batch_upload gave the model
+        if (frac < 1.0) np = std::max<int64_t>(64, (int64_t)(frac * (double)np));
+        mcrt_status r = prepare_pass(m, np, graph_safe);
+        if (r != MCRT_OK) return r;
+    }
+    BCHK(launch_fill_u64(1, B.pool(), 0ull, 1, B.s));
+    int64_t total_np = 0;
+    for (mcrt_model* m : B.ms) total_np += m->cfg.n_packets;
+    int64_t blocks = (int64_t)B.n_cu * sh.bpc;
+    const int64_t need = ((int64_t)(frac * (double)total_np) + sh.block_size - 1) / sh.block_size;
+    if (blocks > need) blocks = need;
+    if (blocks < 1) blocks = 1;
+    BCHK(launch_transport_batch<R>((const TransportParams<R>*)B.d_params, B.d_chunks, B.n(), B.pool(),
+                                   B.d_keys, sh.walk_batch, B.layout, (int)blocks, sh.block_size,
+                                   B.s));
+    if (update) {
+        for (mcrt_model* m : B.ms) {
+            CellParams P;
+            make_cell_params(m, P);
+            BCHK(launch_fill_u64(8, m->misc.p + MISC_STATS, 0ull, 1, B.s));
+            BCHK(launch_update(P, grid_blocks(m, m->ncell), B.s));
+        }
+    }
+    if (bump_keys) BCHK(launch_add_u32(B.n(), B.d_keys, 1u, 1, B.s));
+    return MCRT_OK;
+}
+
+template <typename R>
+mcrt_status batch_tune(Batch& B, const mcrt_batch_cfg* c, LaunchShape& best, double* ms_tune) {
+    const double t0 = now_ms();
+    std::vector<LaunchShape> cand;
+    for (int bs : {128, 256})
+        for (int K : {2, 4, 8})
+            for (int d : {8, 32}) {
+                const int bpc = batch_max_blocks_per_cu<R>(K, B.layout, bs);
+                cand.push_back({bs, K, d, bpc});
+            }
+    const double frac = c->tune_fraction > 0.0 ? c->tune_fraction : 0.02;
+    hipEvent_t e0, e1;
+    hipEventCreate(&e0);
+    hipEventCreate(&e1);
+    float best_ms = 1e30f;
+    std::vector<uint32_t> keys(B.n());
+    for (size_t t = 0; t < cand.size(); ++t) {
+        for (int i = 0; i < B.n(); ++i) keys[i] = 0x40000000u | (uint32_t)t;
+        mcrt_status r = batch_upload<R>(B, frac, 0, cand[t], keys);
+        if (r == MCRT_OK) {
+            hipEventRecord(e0, B.s);
+            r = batch_pass_ops<R>(B, frac, cand[t], false, false, false);
+            hipEventRecord(e1, B.s);
+        }
+        if (r != MCRT_OK) {
+            hipEventDestroy(e0);
+            hipEventDestroy(e1);
+            return r;
+        }
+        hipEventSynchronize(e1);
+        float ms = 0.f;
+        hipEventElapsedTime(&ms, e0, e1);
+        if (ms < best_ms) {
+            best_ms = ms;
+            best = cand[t];
+        }
+    }
+    hipEventDestroy(e0);
+    hipEventDestroy(e1);
+    *ms_tune = now_ms() - t0;
+    return MCRT_OK;
+}
+
+template <typename R>
+mcrt_status batch_run(Batch& B, const mcrt_batch_cfg* c, mcrt_batch_stats* st) {
+    const double t0 = now_ms();
+    // launch shape: explicit fields, else tuned (cached per workload class), else defaults
+    LaunchShape sh{256, 4, 16, batch_max_blocks_per_cu<R>(4, B.layout, 256)};
+    const bool explicit_shape = c->block_size > 0 && c->walk_batch > 0 && c->defer_lanes > 0;
+    if (!explicit_shape && c->autotune) {
+        int64_t cells = 0, packets = 0;
+        for (mcrt_model* m : B.ms) {
+            cells += m->ncell;
+            packets += m->cfg.n_packets;
+        }
+        const auto key = std::make_tuple((int)B.f32, (int)lround(log2((double)cells)),
+                                         (int)lround(log2((double)packets / (double)cells)));
+        bool hit = false;
+        {
+            std::lock_guard<std::mutex> g(g_tune_mu);
+            auto it = g_tune_cache.find(key);
+            if (it != g_tune_cache.end()) {
+                sh = it->second;
+                hit = true;
+            }
+        }
+        if (hit) {
+            st->tuned = 2;
+        } else {
+            mcrt_status r = batch_tune<R>(B, c, sh, &st->ms_tune);
+            if (r != MCRT_OK) return r;
+            std::lock_guard<std::mutex> g(g_tune_mu);
+            g_tune_cache[key] = sh;
+            st->tuned = 1;
+        }
+    }
+    if (c->block_size > 0) sh.block_size = c->block_size;
+    if (c->walk_batch > 0) sh.walk_batch = c->walk_batch;
+    if (c->defer_lanes > 0) sh.defer = c->defer_lanes;
+    sh.bpc = c->blocks_per_cu > 0 ? c->blocks_per_cu
+                                  : batch_max_blocks_per_cu<R>(sh.walk_batch, B.layout, sh.block_size);
+    st->block_size = sh.block_size;
+    st->walk_batch = sh.walk_batch;
+    st->defer_lanes = sh.defer;
+    st->blocks_per_cu = sh.bpc;
+
+    // Lucy iterations
+    const double ti = now_ms();
+    std::vector<uint32_t> keys(B.n());
+    for (int i = 0; i < B.n(); ++i) {
+        mcrt_model* m = B.ms[i];
+        keys[i] = (uint32_t)m->iter;
+        mcrt_status r = set_weights(m, m->cfg.n_packets);
+        if (r != MCRT_OK) return r;
+    }
+    mcrt_status r = batch_upload<R>(B, 1.0, 0, sh, keys);
+    if (r != MCRT_OK) return r;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    for (int it = 0; it < c->n_iter; ++it) {
+        const bool replay = c->use_graph && it > 0;
+        if (replay && !exec) {
+            BCHK(hipStreamBeginCapture(B.s, hipStreamCaptureModeThreadLocal));
+            r = batch_pass_ops<R>(B, 1.0, sh, true, true, true);
+            hipGraph_t g = nullptr;
+            hipError_t e = hipStreamEndCapture(B.s, &g);
+            if (r != MCRT_OK) return r;
+            BCHK(e);
+            graph = g;
+            BCHK(hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0));
+            st->graph_used = 1;
+        }
+        if (replay) {
+            BCHK(hipGraphLaunch(exec, B.s));
+        } else {
+            hipEventRecord(B.ms[0]->ev[0], B.s);
+            r = batch_pass_ops<R>(B, 1.0, sh, false, false, false);
+            if (r != MCRT_OK) return r;
+            hipEventRecord(B.ms[0]->ev[1], B.s);
+            for (mcrt_model* m : B.ms) {
+                CellParams P;
+                make_cell_params(m, P);
+                BCHK(hipMemsetAsync(m->misc.p + MISC_STATS, 0, 8 * sizeof(unsigned long long), B.s));
+                BCHK(launch_update(P, grid_blocks(m, m->ncell), B.s));
+            }
+            BCHK(launch_add_u32(B.n(), B.d_keys, 1u, 1, B.s));
+        }
+        BCHK(hipStreamSynchronize(B.s));
+        if (!replay) {
+            float ms = 0.f;
+            hipEventElapsedTime(&ms, B.ms[0]->ev[0], B.ms[0]->ev[1]);
+            st->ms_transport_last = ms;
+        }
+        for (mcrt_model* m : B.ms) {
+            m->iter++;
+            m->have_prev = 1;
+        }
+        st->n_iterations++;
+    }
+    if (exec) hipGraphExecDestroy(exec);
+    if (graph) hipGraphDestroy(graph);
+    st->ms_iterations = now_ms() - ti;
+    st->n_cross_dust = st->n_cross_empty = 0;
+    for (mcrt_model* m : B.ms) {
+        unsigned long long h[C_COUNT];
+        BCHK(hipMemcpy(h, m->misc.p + MISC_CNT, sizeof h, hipMemcpyDeviceToHost));
+        st->n_cross_dust += (int64_t)h[C_CROSS_DUST];
+        st->n_cross_empty += (int64_t)h[C_CROSS_EMPTY];
+        st->packets_per_iteration += m->cfg.n_packets;
+    }
+
+    // final binning pass
+    if (c->final_pass) {
+        const double tf = now_ms();
+        for (int i = 0; i < B.n(); ++i) {
+            mcrt_model* m = B.ms[i];
+            keys[i] = 0x80000000u | (uint32_t)m->iter;
+            const int64_t npf = m->cfg.n_packets_final > 0 ? m->cfg.n_packets_final : m->cfg.n_packets;
+            r = set_weights(m, npf);
+            if (r != MCRT_OK) return r;
+            r = clear_bins(m);
+            if (r != MCRT_OK) return r;
+        }
+        r = batch_upload<R>(B, 1.0, 1, sh, keys);
+        if (r != MCRT_OK) return r;
+        for (mcrt_model* m : B.ms) {
+            const int64_t npf = m->cfg.n_packets_final > 0 ? m->cfg.n_packets_final : m->cfg.n_packets;
+            r = prepare_pass(m, npf, false);
+            if (r != MCRT_OK) return r;
+        }
+        BCHK(launch_fill_u64(1, B.pool(), 0ull, 1, B.s));
+        int64_t total = 0;
+        for (mcrt_model* m : B.ms)
+            total += m->cfg.n_packets_final > 0 ? m->cfg.n_packets_final : m->cfg.n_packets;
+        int64_t blocks = std::min<int64_t>((int64_t)B.n_cu * sh.bpc, (total + sh.block_size - 1) / sh.block_size);
+        BCHK(launch_transport_batch<R>((const TransportParams<R>*)B.d_params, B.d_chunks, B.n(),
+                                       B.pool(), B.d_keys, sh.walk_batch, B.layout,
+                                       (int)std::max<int64_t>(blocks, 1), sh.block_size, B.s));
+        BCHK(hipStreamSynchronize(B.s));
+        st->ms_final = now_ms() - tf;
+    }
+    st->ms_total = now_ms() - t0;
+    return MCRT_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+mcrt_status mcrt_batch_cfg_default(mcrt_batch_cfg* c) {
+    if (!c) return MCRT_E_ARG;
+    memset(c, 0, sizeof *c);
+    c->n_iter = 5;
+    c->final_pass = 1;
+    c->use_graph = 1;
+    c->autotune = 1;
+    c->tune_fraction = 0.02;
+    return MCRT_OK;
+}
+
+mcrt_status mcrt_batch_run(mcrt_model* const* models, int n, const mcrt_batch_cfg* c,
+                           mcrt_batch_stats* st) {
+    if (!models || n < 1 || !c || !st) return MCRT_E_ARG;
+    for (int i = 0; i < n; ++i)
+        if (!models[i]) return MCRT_E_ARG;
+    memset(st, 0, sizeof *st);
+    st->n_models = n;
+    Batch B;
+    B.ms.assign(models, models + n);
+    mcrt_model* m0 = models[0];
+    if (c->n_iter < 0 || c->block_size < 0 || c->block_size % 64 != 0 || c->block_size > 256 ||
+        c->defer_lanes < 0 || c->defer_lanes > 64 || c->blocks_per_cu < 0)
+        return fail(m0, MCRT_E_ARG, "bad batch configuration");
+    if (c->walk_batch != 0 && c->walk_batch != 2 && c->walk_batch != 4 && c->walk_batch != 8)
+        return fail(m0, MCRT_E_ARG, "batch walk_batch must be 2, 4 or 8");
+    hipSetDevice(m0->device);
+    B.f32 = m0->cfg.precision == MCRT_FP32_TRANSPORT;
+    B.layout = m0->cfg.grid_layout == 1 ? 1 : 0;
+    B.n_cu = m0->n_cu;
+    B.s = m0->stream;
+    for (int i = 0; i < n; ++i) {
+        mcrt_model* m = models[i];
+        if (m->device != m0->device) return fail(m0, MCRT_E_ARG, "batch models on different devices");
+        if ((m->cfg.precision == MCRT_FP32_TRANSPORT) != B.f32 || (m->cfg.grid_layout == 1) != (B.layout == 1))
+            return fail(m0, MCRT_E_ARG, "batch models differ in precision or grid layout");
+        for (int j = 0; j < i; ++j)
+            if (models[j] == m) return fail(m0, MCRT_E_ARG, "a model appears twice in the batch");
+        mcrt_status r = ready(m);
+        if (r != MCRT_OK) {
+            if (m != m0) m0->err = "model " + std::to_string(i) + ": " + m->err;
+            return r;
+        }
+    }
+    // every model works on the batch stream for the duration of the call
+    for (mcrt_model* m : B.ms) {
+        hipStreamSynchronize(m->stream);
+        B.saved_streams.push_back(m->stream);
+        m->stream = B.s;
+    }
+    const size_t psz = B.f32 ? sizeof(TransportParams<float>) : sizeof(TransportParams<double>);
+    if (hipMalloc(&B.d_params, psz * n) != hipSuccess ||
+        hipMalloc((void**)&B.d_chunks, (n + 2) * sizeof(unsigned long long)) != hipSuccess ||
+        hipMalloc((void**)&B.d_keys, n * sizeof(uint32_t)) != hipSuccess)
+        return fail(m0, MCRT_E_NOMEM, "batch buffers");
+    return B.f32 ? batch_run<float>(B, c, st) : batch_run<double>(B, c, st);
 }
 
 }  // extern "C"

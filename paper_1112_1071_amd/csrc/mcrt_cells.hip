@@ -264,6 +264,25 @@ __global__ void k_fill_u8(int64_t n, unsigned char* p, unsigned char v) {
          j += (int64_t)gridDim.x * blockDim.x)
         p[j] = v;
 }
+__global__ void k_add_u32(int64_t n, uint32_t* p, uint32_t v) {
+    for (int64_t j = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; j < n;
+         j += (int64_t)gridDim.x * blockDim.x)
+        p[j] += v;
+}
+hipError_t launch_add_u32(int64_t n, uint32_t* p, uint32_t v, int blocks, hipStream_t st) {
+    hipLaunchKernelGGL(k_add_u32, dim3(blocks), dim3(256), 0, st, n, p, v);
+    return hipGetLastError();
+}
+__global__ void k_fill_u64(int64_t n, unsigned long long* p, unsigned long long v) {
+    for (int64_t j = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; j < n;
+         j += (int64_t)gridDim.x * blockDim.x)
+        p[j] = v;
+}
+hipError_t launch_fill_u64(int64_t n, unsigned long long* p, unsigned long long v, int blocks,
+                           hipStream_t st) {
+    hipLaunchKernelGGL(k_fill_u64, dim3(blocks), dim3(256), 0, st, n, p, v);
+    return hipGetLastError();
+}
 __global__ void k_fill_f64(int64_t n, double* p, double v) {
     for (int64_t j = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; j < n;
          j += (int64_t)gridDim.x * blockDim.x)

@@ -666,4 +666,156 @@ template int transport_max_blocks_per_cu<float>(int, int, int, size_t);
 template size_t transport_lds_bytes<double>(const TransportParams<double>&);
 template size_t transport_lds_bytes<float>(const TransportParams<float>&);
 
+// ---------------------------------------------------------------------------
+// Batched transport: many independent models in one persistent launch.
+// The packets of all models form one pool of 64-id chunks; chunk c belongs to
+// the model m with chunk_start[m] <= c < chunk_start[m+1].  Each lane reads the
+// launch parameters of its packet's model from device memory, so the lanes of
+// a wave may work on different models.  Each model keeps its own random
+// streams (its seed and iteration), tallies and counters: a model's results
+// equal those of its own single-model launch up to summation order.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ void flush_counters(unsigned long long* counters, double* energies,
+                                               uint32_t* cnt, double& e_esc, double& e_kill) {
+#pragma unroll
+    for (int c = 0; c < C_COUNT; ++c) {
+        if (cnt[c]) atomicAdd(counters + c, (unsigned long long)cnt[c]);
+        cnt[c] = 0;
+    }
+    if (e_esc != 0.0) unsafeAtomicAdd(energies + 0, e_esc);
+    if (e_kill != 0.0) unsafeAtomicAdd(energies + 1, e_kill);
+    e_esc = 0.0;
+    e_kill = 0.0;
+}
+
+template <typename R, int K, int BRICK>
+__global__ void __launch_bounds__(256)
+k_transport_batch(const TransportParams<R>* __restrict__ Ps,
+                  const unsigned long long* __restrict__ chunk_start, int n_models,
+                  unsigned long long* pool, const uint32_t* __restrict__ keys) {
+    const unsigned long long total = chunk_start[n_models];
+    uint32_t cnt[C_COUNT] = {0, 0, 0, 0, 0, 0};
+    double e_escaped = 0.0, e_killed = 0.0;
+    unsigned xcc;
+    asm volatile("s_getreg_b32 %0, hwreg(HW_REG_XCC_ID)" : "=s"(xcc));
+    Packet<R> s;
+    s.st = ST_EMPTY;
+    s.id = 0;
+    Stream<R> rs;
+    rs.n = 0;
+    rs.k0 = rs.k1 = rs.p0 = rs.p1 = rs.s0 = rs.s1 = 0;
+    const int lane = __lane_id();
+    int lm = -1;     // model of the lane's packet (and of its counters)
+    // the wave's chunk: model wm, ids [wbase, wend) -- the same in every lane
+    int wm = 0;
+    uint64_t wbase = 0, wend = 0;
+    bool drained = false;
+
+    for (;;) {
+        unsigned long long need = __ballot(s.st == ST_EMPTY);
+        while (need && !drained) {
+            if (wbase >= wend) {
+                unsigned long long c = 0;
+                const int leader = __ffsll((long long)need) - 1;
+                if (lane == leader) c = atomicAdd(pool, 1ull);
+                c = shfl_u64(c, leader);
+                if (c >= total) {
+                    drained = true;
+                    break;
+                }
+                int lo = 0, hi = n_models - 1;  // last m with chunk_start[m] <= c
+                while (lo < hi) {
+                    const int mid = (lo + hi + 1) >> 1;
+                    if (chunk_start[mid] <= c) lo = mid;
+                    else hi = mid - 1;
+                }
+                wm = lo;
+                wbase = (c - chunk_start[wm]) * (uint64_t)kPoolChunk;
+                const uint64_t np = Ps[wm].n_packets;
+                wend = wbase + kPoolChunk < np ? wbase + kPoolChunk : np;
+                continue;
+            }
+            const int avail = (int)(wend - wbase);
+            const int nneed = __popcll(need);
+            const int take = nneed < avail ? nneed : avail;
+            const int rank = __popcll(need & __lanemask_lt());
+            if (s.st == ST_EMPTY && rank < take) {
+                if (lm != wm) {
+                    if (lm >= 0)
+                        flush_counters(Ps[lm].counters, Ps[lm].energies, cnt, e_escaped, e_killed);
+                    lm = wm;
+                }
+                const TransportParams<R>& P = Ps[lm];
+                const Tables<R> tb{P.lcdf, P.ecoarse, P.scoarse};
+                rs.k0 = P.key0;
+                rs.k1 = keys[lm];
+                emit(s, rs, P, tb, wbase + (uint64_t)rank);
+            }
+            wbase += (uint64_t)take;
+            need = __ballot(s.st == ST_EMPTY);
+        }
+        if (drained && s.st == ST_EMPTY) s.st = ST_DONE;
+        if (__ballot(s.st != ST_DONE) == 0ull) break;
+        const int mm = lm < 0 ? 0 : lm;
+        const TransportParams<R>& P = Ps[mm];
+        double* acc = P.acc + (P.acc_stride ? (size_t)(xcc & 7u) * P.acc_stride : (size_t)0);
+        const int defer = Ps[0].defer_lanes;  // the same for every lane of the wave
+        for (;;) {
+            if (s.st == ST_WALK) walk<R, K, BRICK>(s, P, acc, cnt);
+            if (__ballot(s.st == ST_WALK) == 0ull) break;
+            if (__popcll(__ballot(s.st == ST_EVENT || s.st == ST_ESC)) >= defer) break;
+        }
+        const Tables<R> tb{P.lcdf, P.ecoarse, P.scoarse};
+        if (s.st == ST_EVENT) interact(s, rs, P, tb, cnt, e_killed);
+        if (s.st == ST_ESC) escape(s, P, cnt, e_escaped);
+    }
+    if (lm >= 0) flush_counters(Ps[lm].counters, Ps[lm].energies, cnt, e_escaped, e_killed);
+}
+
+template <typename R> using BatchFn = void (*)(const TransportParams<R>*, const unsigned long long*,
+                                               int, unsigned long long*, const uint32_t*);
+
+template <typename R> BatchFn<R> pick_batch_kernel(int K, int brick) {
+    if (brick) {
+        switch (K) {
+            case 2: return k_transport_batch<R, 2, 1>;
+            case 8: return k_transport_batch<R, 8, 1>;
+            default: return k_transport_batch<R, 4, 1>;
+        }
+    }
+    switch (K) {
+        case 2: return k_transport_batch<R, 2, 0>;
+        case 8: return k_transport_batch<R, 8, 0>;
+        default: return k_transport_batch<R, 4, 0>;
+    }
+}
+
+template <typename R>
+hipError_t launch_transport_batch(const TransportParams<R>* Ps, const unsigned long long* chunk_start,
+                                  int n_models, unsigned long long* pool, const uint32_t* keys,
+                                  int K, int brick, int blocks, int threads, hipStream_t st) {
+    hipLaunchKernelGGL(pick_batch_kernel<R>(K, brick), dim3(blocks), dim3(threads), 0, st, Ps,
+                       chunk_start, n_models, pool, keys);
+    return hipGetLastError();
+}
+
+template <typename R> int batch_max_blocks_per_cu(int K, int brick, int threads) {
+    int nb = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, pick_batch_kernel<R>(K, brick), threads,
+                                                     0) != hipSuccess)
+        return 1;
+    return nb > 0 ? nb : 1;
+}
+
+template hipError_t launch_transport_batch<double>(const TransportParams<double>*,
+                                                   const unsigned long long*, int,
+                                                   unsigned long long*, const uint32_t*, int, int,
+                                                   int, int, hipStream_t);
+template hipError_t launch_transport_batch<float>(const TransportParams<float>*,
+                                                  const unsigned long long*, int,
+                                                  unsigned long long*, const uint32_t*, int, int,
+                                                  int, int, hipStream_t);
+template int batch_max_blocks_per_cu<double>(int, int, int);
+template int batch_max_blocks_per_cu<float>(int, int, int);
+
 }  // namespace mcrt

@@ -66,6 +66,28 @@ class RunStats(C.Structure):
     ]
 
 
+class BatchCfg(C.Structure):
+    _fields_ = [
+        ("n_iter", C.c_int32), ("final_pass", C.c_int32), ("use_graph", C.c_int32),
+        ("autotune", C.c_int32), ("block_size", C.c_int32), ("walk_batch", C.c_int32),
+        ("defer_lanes", C.c_int32), ("blocks_per_cu", C.c_int32), ("tune_fraction", C.c_double),
+    ]
+
+
+class BatchStats(C.Structure):
+    _fields_ = [
+        ("n_models", C.c_int32), ("n_iterations", C.c_int32), ("graph_used", C.c_int32),
+        ("tuned", C.c_int32), ("block_size", C.c_int32), ("walk_batch", C.c_int32),
+        ("defer_lanes", C.c_int32), ("blocks_per_cu", C.c_int32),
+        ("packets_per_iteration", C.c_int64), ("n_cross_dust", C.c_int64),
+        ("n_cross_empty", C.c_int64), ("ms_total", C.c_double), ("ms_iterations", C.c_double),
+        ("ms_final", C.c_double), ("ms_tune", C.c_double), ("ms_transport_last", C.c_double),
+    ]
+
+    def as_dict(self) -> dict:
+        return {f: getattr(self, f) for f, _ in self._fields_}
+
+
 EVENT_DTYPE = np.dtype([("packet", "<i8"), ("index", "<i4"), ("type", "<i4"),
                         ("cell", "<i4", (3,)), ("nu", "<i4"), ("incl", "<i4"),
                         ("reserved", "<i4")])
@@ -116,6 +138,8 @@ def lib():
         "mcrt_get_images": ([vp, vp, vp, sz], i32),
         "mcrt_get_event_log": ([vp, vp, sz, vp, sz], i32),
         "mcrt_device_info": ([vp, C.POINTER(i32), C.POINTER(i32)], i32),
+        "mcrt_batch_cfg_default": ([C.POINTER(BatchCfg)], i32),
+        "mcrt_batch_run": ([C.POINTER(vp), i32, C.POINTER(BatchCfg), C.POINTER(BatchStats)], i32),
     }
     for name, (args, res) in sig.items():
         f = getattr(L, name)
@@ -287,3 +311,19 @@ class Model:
         n, w = C.c_int(), C.c_int()
         self._check(self.L.mcrt_device_info(self.h, C.byref(n), C.byref(w)))
         return n.value, w.value
+
+
+def batch_run(models, **cfg) -> dict:
+    """Run Lucy iterations (and the final pass) of many models in one launch per
+    iteration (mcrt_batch_run).  Keyword arguments set mcrt_batch_cfg fields."""
+    L = lib()
+    c = BatchCfg()
+    L.mcrt_batch_cfg_default(C.byref(c))
+    for k, v in cfg.items():
+        setattr(c, k, type(getattr(c, k))(v))
+    arr = (C.c_void_p * len(models))(*[m.h.value for m in models])
+    st = BatchStats()
+    rc = L.mcrt_batch_run(arr, len(models), C.byref(c), C.byref(st))
+    if rc != 0:
+        raise MCRTError(rc, L.mcrt_last_error(models[0].h).decode())
+    return st.as_dict()
