@@ -70,9 +70,68 @@ def cpu_baseline(cfg: dict, n_packets: int) -> dict:
                       f"(FP64 oracle transport only, {st['seconds']:.1f} s)"}
 
 
+def bench_batch(args):
+    """Form 2: the batched family of uneven models, one persistent launch per
+    Lucy iteration (graph-replayed, autotuned) vs one launch per model."""
+    from paper_1112_1071_amd import mcrt, synth
+
+    t0 = time.time()
+    cfgs = [synth.config3_model(m, packets_per_cell=args.ppc, n_iter=args.steps)
+            for m in range(args.models)]
+    print(f"# {args.models} models built in {time.time() - t0:.1f} s", file=sys.stderr, flush=True)
+    prec = mcrt.MCRT_FP32_TRANSPORT if args.precision == "fp32" else mcrt.MCRT_FP64
+    batch = [mcrt.Model(c, precision=prec) for c in cfgs]
+    n_packets = sum(int(c["run"]["n_packets"]) for c in cfgs)
+    cells = sum(int(np.prod(c["grid"]["n"])) for c in cfgs)
+    # warm-up batch: tunes the launch shape (cached) and runs the first iteration
+    stw = mcrt.batch_run(batch, n_iter=1, final_pass=0, use_graph=0, autotune=1)
+    print(f"# warmup/tune: {stw['ms_total']:.0f} ms (tune {stw['ms_tune']:.0f} ms) shape "
+          f"bs={stw['block_size']} K={stw['walk_batch']} defer={stw['defer_lanes']}",
+          file=sys.stderr, flush=True)
+    st = mcrt.batch_run(batch, n_iter=args.steps, final_pass=0, use_graph=1, autotune=1)
+    ms_it = st["ms_iterations"] / st["n_iterations"]
+    value = n_packets / (ms_it * 1e-3)
+    print(f"# batched: {ms_it:.1f} ms per iteration", file=sys.stderr, flush=True)
+    # the same iteration as one launch per model
+    seq = [mcrt.Model(c, precision=prec) for c in cfgs[: args.seq_models]]
+    for m in seq:
+        m.iterate()
+    import torch
+
+    torch.cuda.synchronize()
+    ts = time.perf_counter()
+    for m in seq:
+        m.iterate()
+    torch.cuda.synchronize()
+    seq_s = time.perf_counter() - ts
+    seq_packets = sum(int(c["run"]["n_packets"]) for c in cfgs[: args.seq_models])
+    seq_value = seq_packets / seq_s
+    out = {
+        "metric": "packets/s, batched Lucy iterations of uneven models",
+        "value": value, "unit": "packets/s", "n_gpus": 1, "steps": st["n_iterations"],
+        "warmup": 1, "ms_per_step": ms_it, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "fp32" if prec == 1 else "fp64", "data": "synthetic",
+        "config": {"workload": f"batch{args.models}: {args.models} models, grids 16^3..96^3 "
+                               f"({cells} cells), sphere/disk family, {args.ppc} packets per cell "
+                               f"per iteration ({n_packets:.3e} packets)",
+                   "models": args.models, "packets_per_step": n_packets},
+        "batch": {"graph_used": st["graph_used"], "tuned": st["tuned"],
+                  "block_size": st["block_size"], "walk_batch": st["walk_batch"],
+                  "defer_lanes": st["defer_lanes"], "blocks_per_cu": st["blocks_per_cu"],
+                  "ms_tune": stw["ms_tune"]},
+        "sequential": {"value": seq_value, "unit": "packets/s", "models": args.seq_models,
+                       "seconds": seq_s, "speedup_batched": value / seq_value},
+    }
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--workload", choices=["clump256", "batch"], default="clump256")
+    ap.add_argument("--models", type=int, default=512)
+    ap.add_argument("--ppc", type=int, default=30, help="batch: packets per cell per iteration")
+    ap.add_argument("--seq-models", type=int, default=512)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--packets", type=float, default=1e8)
@@ -90,6 +149,9 @@ def main():
     if args.gpus != 1:
         print(json.dumps({"error": "this benchmark runs on one GPU only; --gpus must be 1"}))
         sys.exit(2)
+    if args.workload == "batch":
+        bench_batch(args)
+        return
 
     from paper_1112_1071_amd import mcrt, synth
 

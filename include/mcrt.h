@@ -244,6 +244,65 @@ mcrt_status mcrt_batch_cfg_default(mcrt_batch_cfg* cfg);
 mcrt_status mcrt_batch_run(mcrt_model* const* models, int n, const mcrt_batch_cfg* cfg,
                            mcrt_batch_stats* st);
 
+/* ---- learned warm start --------------------------------------------------
+ * The Lucy iteration (Sec. 2.4) converges from any starting temperature; its
+ * cost is the number of iterations.  A 3-D convolutional encoder-decoder
+ * predicts log10 T per cell from two features of the problem and is used as
+ * the starting temperature; Monte-Carlo iterations then decide convergence
+ * exactly as from a cold start.
+ *
+ * Network: 4 levels of C, 2C, 4C, 8C channels (C = base_channels, 16 or 32),
+ * two 3x3x3 convolutions (zero padding) per level, 2x2x2 stride-2 down
+ * convolutions and transposed up convolutions, skip concatenation [up, skip]
+ * in the decoder, LeakyReLU(0.1) after every convolution, a 1x1x1 head.  BF16
+ * weights and activations on the matrix cores with FP32 accumulation; FP32
+ * master parameters trained with Adam (b1 0.9, b2 0.999, eps 1e-8).
+ *
+ * Tensors of a batch are N cubes of side D (D a multiple of 8), voxel index
+ * ((n*D + z)*D + y)*D + x.  Features x: FP32 [N][D^3][2] (see
+ * mcrt_model_features); outputs y: FP32 [N][D^3], log10 T in K.
+ * Parameter vector (FP32): per layer in network order, weights
+ * [taps][C_out][C_in] (taps 27 = dz*9 + dy*3 + dx for 3x3x3 with offsets
+ * -1..1, 8 = tz*4 + ty*2 + tx for 2x2x2) then biases [C_out]; the head's
+ * weights [C] and bias last.  Input channels 2..15 of the first layer see
+ * zeros.  Device pointers are in the surrogate's device memory; the calls
+ * synchronise the surrogate's stream before returning. */
+typedef struct mcrt_surrogate mcrt_surrogate;
+
+mcrt_status mcrt_surrogate_create(mcrt_surrogate** out, int hip_device, int base_channels,
+                                  uint64_t seed);           /* He-normal init from seed */
+void mcrt_surrogate_destroy(mcrt_surrogate* s);            /* NULL-safe                */
+const char* mcrt_surrogate_last_error(const mcrt_surrogate* s);
+mcrt_status mcrt_surrogate_set_stream(mcrt_surrogate* s, void* hip_stream);
+int64_t mcrt_surrogate_param_count(const mcrt_surrogate* s);
+/* Host copies of the FP32 parameters / of the gradients of the last train step. */
+mcrt_status mcrt_surrogate_get_params(mcrt_surrogate* s, float* host, size_t n);
+mcrt_status mcrt_surrogate_set_params(mcrt_surrogate* s, const float* host, size_t n);
+mcrt_status mcrt_surrogate_get_grads(mcrt_surrogate* s, float* host, size_t n);
+/* Inference: d_y[v] = log10 T predicted for voxel v. */
+mcrt_status mcrt_surrogate_forward(mcrt_surrogate* s, const float* d_x, int N, int D, float* d_y);
+/* One training step on a batch: loss = sum_v mask_v (y_v - target_v)^2 /
+ * mask_count (mask 0 or 1 per voxel, FP32), its gradient with respect to all
+ * parameters, then (apply_update != 0) one Adam step with learning rate lr.
+ * *loss receives the loss before the update. */
+mcrt_status mcrt_surrogate_train_step(mcrt_surrogate* s, const float* d_x, const float* d_target,
+                                      const float* d_mask, int N, int D, double mask_count,
+                                      double lr, int apply_update, double* loss);
+/* Inference written as temperatures: d_T[v] = 10^y clamped to [1, 1e4] K (FP64). */
+mcrt_status mcrt_surrogate_predict_T(mcrt_surrogate* s, const float* d_x, int N, int D, double* d_T);
+
+/* Features of a model for the network, FP32 [ncell][2] in device memory
+ * (n = 2*ncell): channel 0 = log10 max(rho chi(1 um) dx, 1e-6), the optical
+ * depth of one cell width at 1 micron (chi of the bin holding 1 um, dx the x
+ * cell width); channel 1 = log10(F + 1e-30), F = (sum of the luminosities of
+ * the sources in the cell) / (4 pi dx^2) in erg s^-1 cm^-2, a source on a cell
+ * wall, edge or corner being shared equally by the cells that touch it. */
+mcrt_status mcrt_model_features(mcrt_model* m, float* d_x, size_t n);
+/* Warm start: features -> network -> temperatures of m (as by
+ * mcrt_set_temperature_device).  The grid must be a cube of cells with a side
+ * that is a multiple of 8.  *ms (may be NULL) receives the wall time. */
+mcrt_status mcrt_warm_start(mcrt_model* m, mcrt_surrogate* s, double* ms);
+
 #ifdef __cplusplus
 }
 #endif

@@ -20,6 +20,8 @@ SOURCES = [
     "mcrt_cells.hip",
     "mcrt_tables.cpp",
     "mcrt_api.cpp",
+    "mcrt_surrogate.hip",
+    "mcrt_surrogate.cpp",
 ]
 
 ARCH = os.environ.get("MCRT_ARCH", "gfx950")
@@ -40,7 +42,7 @@ COMMON = [
 
 
 def _compile(src: str) -> str:
-    out = os.path.join(BUILD_DIR, os.path.splitext(src)[0] + ".o")
+    out = os.path.join(BUILD_DIR, src.replace(".", "_") + ".o")
     cmd = [HIPCC, *COMMON, "-x", "hip", "-c", os.path.join(CSRC, src), "-o", out]
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
@@ -50,7 +52,7 @@ def _compile(src: str) -> str:
 
 def build(verbose: bool = False) -> str:
     os.makedirs(BUILD_DIR, exist_ok=True)
-    with ThreadPoolExecutor(max_workers=min(4, len(SOURCES))) as ex:
+    with ThreadPoolExecutor(max_workers=min(6, len(SOURCES))) as ex:
         objs = list(ex.map(_compile, SOURCES))
     tmp = LIB + ".tmp"
     cmd = [HIPCC, f"--offload-arch={ARCH}", "-shared", "-fPIC", "-o", tmp, *objs]

@@ -1558,3 +1558,78 @@ mcrt_status mcrt_batch_run(mcrt_model* const* models, int n, const mcrt_batch_cf
 }
 
 }  // extern "C"
+
+// ---------------------------------------------------------------------------
+// Learned warm start: features of a model, and network -> starting T.
+namespace mcrt {
+namespace nn {
+hipError_t launch_features(int64_t nvox, const double* rho, double chi1_dx, const double* flux,
+                           float* x, hipStream_t st);
+}  // namespace nn
+}  // namespace mcrt
+
+extern "C" {
+
+mcrt_status mcrt_model_features(mcrt_model* m, float* d_x, size_t n) {
+    if (!m || !d_x) return MCRT_E_ARG;
+    if (!m->have_grid || !m->have_rho || !m->have_nu || !m->have_dust)
+        return fail(m, MCRT_E_STATE, "set grid, density, frequencies and dust first");
+    if ((int64_t)n != 2 * m->ncell) return fail(m, MCRT_E_SIZE, "features need 2 values per cell");
+    hipSetDevice(m->device);
+    // extinction of the bin holding 1 micron
+    const double nu1 = 2.99792458e10 / 1e-4;
+    const int nnu = (int)m->chi.size();
+    int k = 0;
+    while (k + 1 < nnu && m->nu[k + 1] <= nu1) ++k;
+    const double dx = m->dx[0];
+    // luminosity per cell; a source on a wall/edge/corner is shared by the touching cells
+    std::vector<double> flux((size_t)m->ncell, 0.0);
+    for (const Source& s : m->src) {
+        int lo_i[3], hi_i[3];
+        for (int a = 0; a < 3; ++a) {
+            const double f = (s.pos[a] - m->lo[a]) / m->dx[a];
+            const double fl = floor(f);
+            int c = (int)fl;
+            lo_i[a] = hi_i[a] = std::min(std::max(c, 0), m->n[a] - 1);
+            if (f == fl && c > 0 && c < m->n[a]) lo_i[a] = c - 1;  // on an interior wall
+        }
+        const int cnt = (hi_i[0] - lo_i[0] + 1) * (hi_i[1] - lo_i[1] + 1) * (hi_i[2] - lo_i[2] + 1);
+        const double share = s.lum / cnt / (4.0 * M_PI * dx * dx);
+        for (int kk = lo_i[2]; kk <= hi_i[2]; ++kk)
+            for (int j = lo_i[1]; j <= hi_i[1]; ++j)
+                for (int i = lo_i[0]; i <= hi_i[0]; ++i)
+                    flux[i + (size_t)m->n[0] * (j + (size_t)m->n[1] * kk)] += share;
+    }
+    DBuf<double> dflux;
+    HIPCHK(dflux.ensure(flux.size()));
+    HIPCHK(hipMemcpyAsync(dflux.p, flux.data(), flux.size() * sizeof(double), hipMemcpyHostToDevice,
+                          m->stream));
+    HIPCHK(nn::launch_features(m->ncell, m->rho64.p, m->chi[k] * dx, dflux.p, d_x, m->stream));
+    HIPCHK(hipStreamSynchronize(m->stream));
+    dflux.release();
+    return MCRT_OK;
+}
+
+mcrt_status mcrt_warm_start(mcrt_model* m, mcrt_surrogate* s, double* ms) {
+    if (!m || !s) return MCRT_E_ARG;
+    const double t0 = now_ms();
+    if (!(m->n[0] == m->n[1] && m->n[1] == m->n[2]) || m->n[0] % 8 != 0)
+        return fail(m, MCRT_E_ARG, "warm start needs a cubic grid with a side that is a multiple of 8");
+    hipSetDevice(m->device);
+    DBuf<float> x;
+    DBuf<double> T;
+    HIPCHK(x.ensure((size_t)2 * m->ncell));
+    HIPCHK(T.ensure((size_t)m->ncell));
+    mcrt_status r = mcrt_model_features(m, x.p, (size_t)2 * m->ncell);
+    if (r == MCRT_OK) {
+        r = mcrt_surrogate_predict_T(s, x.p, 1, m->n[0], T.p);
+        if (r != MCRT_OK) m->err = std::string("surrogate: ") + mcrt_surrogate_last_error(s);
+    }
+    if (r == MCRT_OK) r = mcrt_set_temperature_device(m, T.p, 1, (size_t)m->ncell);
+    x.release();
+    T.release();
+    if (ms) *ms = now_ms() - t0;
+    return r;
+}
+
+}  // extern "C"

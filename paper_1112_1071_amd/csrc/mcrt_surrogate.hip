@@ -1,0 +1,477 @@
+// mcrt_surrogate.hip -- gfx950 kernels of the learned warm start: a 3-D
+// convolutional encoder-decoder evaluated and trained with BF16 operands on
+// the matrix cores (MFMA 16x16x16, FP32 accumulation).
+//
+// Tensors are channels-last (voxel-major, channel fastest) BF16.  Every
+// convolution is an implicit GEMM: rows = voxels, columns = output channels,
+// reduction = taps x input channels, in one of three geometries:
+//   CONV3  3x3x3 taps, stride 1, zero padding 1
+//   DOWN   2x2x2 taps, stride 2 (output grid half the input grid)
+//   UP     transposed 2x2x2, stride 2: an output voxel 2u+p receives input
+//          voxel u through tap p only, so each parity class p is a plain GEMM
+// A second input tensor may follow the first along the channel axis (the
+// skip concatenation of the decoder) without being copied.  The backward
+// data pass reuses the same kernel: CONV3 with flipped taps, DOWN <-> UP,
+// with the weights transposed; weight gradients are an MFMA reduction over
+// voxels.  Channel counts are multiples of 16.
+#include <hip/hip_bf16.h>
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace mcrt {
+namespace nn {
+
+typedef short bf16x4 __attribute__((ext_vector_type(4)));
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+
+enum Mode : int { CONV3 = 0, DOWN = 1, UP = 2 };
+
+__device__ __forceinline__ float bf2f(uint16_t h) { return __uint_as_float((uint32_t)h << 16); }
+__device__ __forceinline__ uint16_t f2bf(float x) {
+    __hip_bfloat16 b = __float2bfloat16(x);  // round to nearest even
+    return *reinterpret_cast<uint16_t*>(&b);
+}
+
+struct ConvArgs {
+    const uint16_t* in1;  // [N][Din^3][C1]
+    const uint16_t* in2;  // [N][Din^3][C2] or null
+    int C1, C2;
+    const uint16_t* w;    // [taps][Cout][C1+C2]
+    const float* bias;    // [Cout] or null
+    int Cout;
+    int N, Din, Dout;     // grid sides (cubic)
+    int mode;
+    // output: BF16 with LeakyReLU (forward) or FP32 accumulate (backward data),
+    // channels [0, Csplit) to out (stride Csplit) and the rest to out2
+    uint16_t* out_bf;
+    float* out_f;
+    float* out_f2;
+    int Csplit;
+    int act;              // apply LeakyReLU
+    float slope;
+    int accumulate;       // FP32 output: add to the existing value
+};
+
+// source voxel of GEMM row r (a voxel of the row grid) and tap t; -1 if padding.
+// Rows: CONV3/DOWN -> output voxels (grid Dout); UP -> input voxels (grid Din).
+__device__ __forceinline__ int64_t src_voxel(const ConvArgs& A, int64_t r, int t) {
+    if (A.mode == UP) return r;
+    const int Dg = A.Dout;
+    const int64_t per = (int64_t)Dg * Dg * Dg;
+    const int n = (int)(r / per);
+    int64_t q = r - (int64_t)n * per;
+    const int z = (int)(q / (Dg * Dg));
+    q -= (int64_t)z * Dg * Dg;
+    const int y = (int)(q / Dg), x = (int)(q - (int64_t)y * Dg);
+    int sz, sy, sx;
+    if (A.mode == CONV3) {
+        sz = z + t / 9 - 1;
+        sy = y + (t / 3) % 3 - 1;
+        sx = x + t % 3 - 1;
+        if ((unsigned)sz >= (unsigned)A.Din || (unsigned)sy >= (unsigned)A.Din ||
+            (unsigned)sx >= (unsigned)A.Din)
+            return -1;
+    } else {
+        sz = 2 * z + (t >> 2);
+        sy = 2 * y + ((t >> 1) & 1);
+        sx = 2 * x + (t & 1);
+    }
+    return (((int64_t)n * A.Din + sz) * A.Din + sy) * A.Din + sx;
+}
+
+// output voxel of GEMM row r (parity class p for UP)
+__device__ __forceinline__ int64_t dst_voxel(const ConvArgs& A, int64_t r, int p) {
+    if (A.mode != UP) return r;
+    const int Dg = A.Din;
+    const int64_t per = (int64_t)Dg * Dg * Dg;
+    const int n = (int)(r / per);
+    int64_t q = r - (int64_t)n * per;
+    const int z = (int)(q / (Dg * Dg));
+    q -= (int64_t)z * Dg * Dg;
+    const int y = (int)(q / Dg), x = (int)(q - (int64_t)y * Dg);
+    const int Do = A.Dout;
+    return (((int64_t)n * Do + 2 * z + (p >> 2)) * Do + 2 * y + ((p >> 1) & 1)) * Do + 2 * x + (p & 1);
+}
+
+// Implicit-GEMM convolution.  A workgroup of 4 waves covers 64 rows; each wave
+// 16 rows x 64 output channels (4 MFMA tiles) of blockIdx.y's channel block.
+__global__ void __launch_bounds__(256) k_conv(ConvArgs A, int64_t rows) {
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int64_t r0 = ((int64_t)blockIdx.x * 4 + wave) * 16;
+    const int co0 = blockIdx.y * 64;
+    const int ntile = min(4, (A.Cout - co0) / 16);
+    const int p = blockIdx.z;  // UP: parity class
+    const int taps = A.mode == CONV3 ? 27 : 8;
+    const int Cin = A.C1 + A.C2;
+    const int m = lane & 15, kq = lane >> 4;  // A: row m, channels 4kq..4kq+3
+    const int64_t row = r0 + m;
+    const bool row_ok = row < rows;
+    f32x4 acc[4];
+#pragma unroll
+    for (int t = 0; t < 4; ++t) acc[t] = (f32x4){0.f, 0.f, 0.f, 0.f};
+    const int t_lo = A.mode == UP ? p : 0, t_hi = A.mode == UP ? p + 1 : taps;
+    for (int t = t_lo; t < t_hi; ++t) {
+        const int64_t sv = row_ok ? src_voxel(A, row, t) : -1;
+        const uint16_t* wt = A.w + (size_t)t * A.Cout * Cin;
+        for (int c0 = 0; c0 < Cin; c0 += 16) {
+            bf16x4 a = {0, 0, 0, 0};
+            if (sv >= 0) {
+                const int c = c0 + 4 * kq;
+                const uint16_t* src = c < A.C1 ? A.in1 + sv * A.C1 + c : A.in2 + sv * A.C2 + (c - A.C1);
+                a = *reinterpret_cast<const bf16x4*>(src);
+            }
+#pragma unroll
+            for (int tt = 0; tt < 4; ++tt) {
+                if (tt < ntile) {
+                    // B: k = channel c0+4kq+i, n = output channel co0+16tt+m
+                    const uint16_t* wp = wt + (size_t)(co0 + 16 * tt + m) * Cin + c0 + 4 * kq;
+                    const bf16x4 b = *reinterpret_cast<const bf16x4*>(wp);
+                    acc[tt] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b, acc[tt], 0, 0, 0);
+                }
+            }
+        }
+    }
+    // D: lane holds rows 4kq+i, output channel co0+16tt+m
+#pragma unroll
+    for (int tt = 0; tt < 4; ++tt) {
+        if (tt >= ntile) continue;
+        const int co = co0 + 16 * tt + m;
+        const float b = A.bias ? A.bias[co] : 0.f;
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const int64_t r = r0 + 4 * kq + i;
+            if (r >= rows) continue;
+            const int64_t dv = dst_voxel(A, r, p);
+            float v = acc[tt][i] + b;
+            if (A.out_bf) {
+                if (A.act) v = v > 0.f ? v : A.slope * v;
+                A.out_bf[dv * A.Cout + co] = f2bf(v);
+            } else {
+                float* dst = co < A.Csplit ? A.out_f + dv * A.Csplit + co
+                                           : A.out_f2 + dv * (A.Cout - A.Csplit) + (co - A.Csplit);
+                *dst = A.accumulate ? *dst + v : v;
+            }
+        }
+    }
+}
+
+struct WgradArgs {
+    const uint16_t* x1;   // layer input(s) [N][Din^3][C1], [N][Din^3][C2]
+    const uint16_t* x2;
+    int C1, C2;
+    const uint16_t* dz;   // gradient at the layer's pre-activation [N][Dout^3][Cout]
+    int Cout;
+    int N, Din, Dout, mode;
+    float* dw;            // [taps][Cout][C1+C2], accumulated
+};
+
+// dW[t][co][ci] += sum over rows of dz[dst(row)][co] * x[src(row, t)][ci].
+// MFMA with M = output channels, N = input channels, K = rows.  Each wave
+// reduces `chunk` rows for one (tap, 16x16 channel tile) and adds its tile to
+// dW with FP32 atomics.
+__global__ void __launch_bounds__(256) k_wgrad(WgradArgs W, int64_t rows, int chunk) {
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int Cin = W.C1 + W.C2;
+    const int ct_in = Cin / 16, ct_out = W.Cout / 16;
+    const int taps = W.mode == CONV3 ? 27 : 8;
+    const int64_t task = (int64_t)blockIdx.y * 4 + wave;  // (tap, co tile, ci tile)
+    if (task >= (int64_t)taps * ct_out * ct_in) return;
+    const int t = (int)(task / (ct_out * ct_in));
+    const int rem = (int)(task - (int64_t)t * ct_out * ct_in);
+    const int cot = rem / ct_in, cit = rem - cot * ct_in;
+    ConvArgs G{};
+    G.C1 = W.C1;
+    G.C2 = W.C2;
+    G.N = W.N;
+    G.Din = W.Din;
+    G.Dout = W.Dout;
+    G.mode = W.mode;
+    const int m = lane & 15, kq = lane >> 4;
+    const int co = cot * 16 + m;  // A row (output channel), B column index uses m as ci
+    const int ci = cit * 16 + m;
+    const int64_t rbeg = (int64_t)blockIdx.x * chunk;
+    const int64_t rend = min(rows, rbeg + chunk);
+    f32x4 acc = {0.f, 0.f, 0.f, 0.f};
+    for (int64_t r0 = rbeg; r0 < rend; r0 += 16) {
+        bf16x4 a, b;
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const int64_t r = r0 + 4 * kq + i;
+            uint16_t av = 0, bv = 0;
+            if (r < rend) {
+                int64_t dv, sv;
+                if (W.mode == UP) {  // row = input voxel u, tap t = parity of the output voxel
+                    sv = r;
+                    dv = dst_voxel(G, r, t);
+                } else {
+                    dv = r;
+                    sv = src_voxel(G, r, t);
+                }
+                av = W.dz[dv * W.Cout + co];
+                if (sv >= 0)
+                    bv = ci < W.C1 ? W.x1[sv * W.C1 + ci] : W.x2[sv * W.C2 + (ci - W.C1)];
+            }
+            a[i] = (short)av;
+            b[i] = (short)bv;
+        }
+        acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b, acc, 0, 0, 0);
+    }
+    // D[m' = co tile row 4kq+i][n = ci m]
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        const int coo = cot * 16 + 4 * kq + i;
+        atomicAdd(W.dw + ((size_t)t * W.Cout + coo) * Cin + ci, acc[i]);
+    }
+}
+
+// dz = dy * LeakyReLU'(y) as BF16 (y is the layer's post-activation output,
+// whose sign equals the pre-activation's), plus the bias gradient.
+__global__ void k_act_back(int64_t n, int C, const float* __restrict__ dy,
+                           const uint16_t* __restrict__ y, float slope, int act,
+                           uint16_t* __restrict__ dz, float* __restrict__ dbias) {
+    __shared__ float sb[256];
+    for (int i = threadIdx.x; i < 256; i += blockDim.x) sb[i] = 0.f;
+    __syncthreads();
+    for (int64_t j = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; j < n;
+         j += (int64_t)gridDim.x * blockDim.x) {
+        float g = dy[j];
+        if (act && !(bf2f(y[j]) > 0.f)) g *= slope;
+        dz[j] = f2bf(g);
+        atomicAdd(&sb[j % C], g);
+    }
+    __syncthreads();
+    for (int c = threadIdx.x; c < C; c += blockDim.x) atomicAdd(dbias + c, sb[c]);
+}
+
+// Input layer: the two FP32 features of each voxel [N][V][2], shifted and
+// scaled to O(1), as BF16 channels-last with 16 channels (zero padded).
+__global__ void k_pack_input(int64_t nvox, const float* __restrict__ x, uint16_t* __restrict__ out,
+                             float sh0, float sc0, float sh1, float sc1) {
+    for (int64_t v = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; v < nvox;
+         v += (int64_t)gridDim.x * blockDim.x) {
+        uint16_t* o = out + v * 16;
+        o[0] = f2bf((x[2 * v] + sh0) * sc0);
+        o[1] = f2bf((x[2 * v + 1] + sh1) * sc1);
+#pragma unroll
+        for (int c = 2; c < 16; ++c) o[c] = 0;
+    }
+}
+
+// 1x1x1 head, C -> 1 channel, FP32 output: y[v] = sum_c w[c] x[v][c] + b
+template <int C>
+__global__ void k_head(int64_t nvox, const uint16_t* __restrict__ x, const float* __restrict__ w,
+                       const float* __restrict__ b, float* __restrict__ y) {
+    for (int64_t v = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; v < nvox;
+         v += (int64_t)gridDim.x * blockDim.x) {
+        float s = b[0];
+#pragma unroll
+        for (int c = 0; c < C; ++c) s += w[c] * bf2f(x[v * C + c]);
+        y[v] = s;
+    }
+}
+
+// masked mean-square loss of the prediction: loss += sum mask (y - t)^2;
+// dy = 2 mask (y - t) / count
+__global__ void k_loss(int64_t nvox, const float* __restrict__ y, const float* __restrict__ t,
+                       const float* __restrict__ mask, float inv_count, float* __restrict__ dy,
+                       double* loss) {
+    __shared__ double s[256];
+    double acc = 0.0;
+    for (int64_t v = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; v < nvox;
+         v += (int64_t)gridDim.x * blockDim.x) {
+        const float d = (y[v] - t[v]) * mask[v];
+        acc += (double)d * d;
+        dy[v] = 2.f * d * inv_count;
+    }
+    s[threadIdx.x] = acc;
+    __syncthreads();
+    for (int o = blockDim.x / 2; o > 0; o >>= 1) {
+        if ((int)threadIdx.x < o) s[threadIdx.x] += s[threadIdx.x + o];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) atomicAdd(loss, s[0]);
+}
+
+// head backward: dw[c] += sum dy[v] x[v][c]; db += sum dy; dx[v][c] = dy[v] w[c]
+template <int C>
+__global__ void k_head_back(int64_t nvox, const uint16_t* __restrict__ x, const float* __restrict__ w,
+                            const float* __restrict__ dy, float* __restrict__ dw,
+                            float* __restrict__ db, float* __restrict__ dx) {
+    __shared__ float s[C + 1];
+    if (threadIdx.x <= C) s[threadIdx.x] = 0.f;
+    __syncthreads();
+    float lw[C], lb = 0.f;
+#pragma unroll
+    for (int c = 0; c < C; ++c) lw[c] = 0.f;
+    for (int64_t v = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; v < nvox;
+         v += (int64_t)gridDim.x * blockDim.x) {
+        const float g = dy[v];
+        lb += g;
+#pragma unroll
+        for (int c = 0; c < C; ++c) {
+            lw[c] += g * bf2f(x[v * C + c]);
+            dx[v * C + c] = g * w[c];
+        }
+    }
+#pragma unroll
+    for (int c = 0; c < C; ++c) atomicAdd(&s[c], lw[c]);
+    atomicAdd(&s[C], lb);
+    __syncthreads();
+    if (threadIdx.x < C) atomicAdd(dw + threadIdx.x, s[threadIdx.x]);
+    if (threadIdx.x == C) atomicAdd(db, s[C]);
+}
+
+// Adam on the FP32 master parameters (bias-corrected moments; c1, c2 are
+// 1/(1 - b1^step), 1/(1 - b2^step)).
+
+__global__ void k_adam(int64_t n, float* __restrict__ p, const float* __restrict__ g,
+                       float* __restrict__ m, float* __restrict__ v, float lr, float b1, float b2,
+                       float eps, float c1, float c2) {
+    for (int64_t j = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; j < n;
+         j += (int64_t)gridDim.x * blockDim.x) {
+        const float gj = g[j];
+        const float mj = b1 * m[j] + (1.f - b1) * gj;
+        const float vj = b2 * v[j] + (1.f - b2) * gj * gj;
+        m[j] = mj;
+        v[j] = vj;
+        p[j] -= lr * (mj * c1) / (sqrtf(vj * c2) + eps);
+    }
+}
+
+// BF16 copies of one layer's weights: w16 = p, wt16[t'][ci][co] = p[t][co][ci]
+// with t' = 26 - t for CONV3 (flipped taps) and t' = t otherwise.
+__global__ void k_weights_bf16(int64_t n, const float* __restrict__ p, int taps, int Cout, int Cin,
+                               int conv3, uint16_t* __restrict__ w16, uint16_t* __restrict__ wt16) {
+    for (int64_t j = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; j < n;
+         j += (int64_t)gridDim.x * blockDim.x) {
+        const int t = (int)(j / ((int64_t)Cout * Cin));
+        const int r = (int)(j - (int64_t)t * Cout * Cin);
+        const int co = r / Cin, ci = r - co * Cin;
+        const uint16_t h = f2bf(p[j]);
+        w16[j] = h;
+        const int tt = conv3 ? taps - 1 - t : t;
+        wt16[((int64_t)tt * Cin + ci) * Cout + co] = h;
+    }
+}
+
+// Features of the warm start per cell: x[v][0] = log10 of the cell's optical
+// depth across one cell width at 1 micron (floored at 1e-6), x[v][1] =
+// log10(F + 1e-30) with F the luminosity of the sources in the cell over the
+// area 4 pi dx^2, in erg s^-1 cm^-2.
+__global__ void k_features(int64_t nvox, const double* __restrict__ rho, double chi1_dx,
+                           const double* __restrict__ flux, float* __restrict__ x) {
+    for (int64_t v = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; v < nvox;
+         v += (int64_t)gridDim.x * blockDim.x) {
+        const double tau = rho[v] * chi1_dx;
+        x[2 * v] = (float)log10(tau > 1e-6 ? tau : 1e-6);
+        x[2 * v + 1] = (float)log10(flux[v] + 1e-30);
+    }
+}
+
+// T = 10^y (bounded to the temperature range of the solver)
+__global__ void k_exp10(int64_t n, const float* __restrict__ y, double* __restrict__ T) {
+    for (int64_t v = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; v < n;
+         v += (int64_t)gridDim.x * blockDim.x) {
+        const double t = pow(10.0, (double)y[v]);
+        T[v] = t < 1.0 ? 1.0 : (t > 1e4 ? 1e4 : t);
+    }
+}
+
+// ---------------------------------------------------------------------------
+static int blocks_for(int64_t n) {
+    int64_t b = (n + 255) / 256;
+    return (int)(b > 4096 ? 4096 : (b < 1 ? 1 : b));
+}
+
+hipError_t launch_conv(const ConvArgs& A, hipStream_t st) {
+    // rows of the GEMM: output voxels (CONV3, DOWN) or input voxels (UP)
+    const int Dg = A.mode == UP ? A.Din : A.Dout;
+    const int64_t rows = (int64_t)A.N * Dg * Dg * Dg;
+    dim3 grid((unsigned)((rows + 63) / 64), (unsigned)((A.Cout + 63) / 64), A.mode == UP ? 8 : 1);
+    hipLaunchKernelGGL(k_conv, grid, dim3(256), 0, st, A, rows);
+    return hipGetLastError();
+}
+
+hipError_t launch_wgrad(const WgradArgs& W, hipStream_t st) {
+    const int Dg = W.mode == UP ? W.Din : W.Dout;
+    const int64_t rows = (int64_t)W.N * Dg * Dg * Dg;
+    const int taps = W.mode == CONV3 ? 27 : 8;
+    const int64_t tasks = (int64_t)taps * (W.Cout / 16) * ((W.C1 + W.C2) / 16);
+    // rows per wave: enough that the grid holds about 4096 workgroups (fewer
+    // FP32 atomics per weight), a multiple of 16, at least 256
+    const int64_t gy = (tasks + 3) / 4;
+    int64_t c = (rows * gy + 4095) / 4096;
+    c = (c + 15) / 16 * 16;
+    if (c < 256) c = 256;
+    if (c > (1 << 20)) c = 1 << 20;
+    const int chunk = (int)c;
+    dim3 grid((unsigned)((rows + chunk - 1) / chunk), (unsigned)((tasks + 3) / 4));
+    hipLaunchKernelGGL(k_wgrad, grid, dim3(256), 0, st, W, rows, chunk);
+    return hipGetLastError();
+}
+
+hipError_t launch_act_back(int64_t n, int C, const float* dy, const uint16_t* y, float slope, int act,
+                           uint16_t* dz, float* dbias, hipStream_t st) {
+    hipLaunchKernelGGL(k_act_back, dim3(blocks_for(n)), dim3(256), 0, st, n, C, dy, y, slope, act, dz,
+                       dbias);
+    return hipGetLastError();
+}
+hipError_t launch_pack_input(int64_t nvox, const float* x, uint16_t* out, const float* norm,
+                             hipStream_t st) {
+    hipLaunchKernelGGL(k_pack_input, dim3(blocks_for(nvox)), dim3(256), 0, st, nvox, x, out, norm[0],
+                       norm[1], norm[2], norm[3]);
+    return hipGetLastError();
+}
+hipError_t launch_head(int C, int64_t nvox, const uint16_t* x, const float* w, const float* b, float* y,
+                       hipStream_t st) {
+    if (C == 16)
+        hipLaunchKernelGGL(k_head<16>, dim3(blocks_for(nvox)), dim3(256), 0, st, nvox, x, w, b, y);
+    else if (C == 32)
+        hipLaunchKernelGGL(k_head<32>, dim3(blocks_for(nvox)), dim3(256), 0, st, nvox, x, w, b, y);
+    else
+        return hipErrorInvalidValue;
+    return hipGetLastError();
+}
+hipError_t launch_loss(int64_t nvox, const float* y, const float* t, const float* mask,
+                       float inv_count, float* dy, double* loss, hipStream_t st) {
+    hipLaunchKernelGGL(k_loss, dim3(blocks_for(nvox)), dim3(256), 0, st, nvox, y, t, mask, inv_count,
+                       dy, loss);
+    return hipGetLastError();
+}
+hipError_t launch_head_back(int C, int64_t nvox, const uint16_t* x, const float* w, const float* dy,
+                            float* dw, float* db, float* dx, hipStream_t st) {
+    if (C == 16)
+        hipLaunchKernelGGL(k_head_back<16>, dim3(blocks_for(nvox)), dim3(256), 0, st, nvox, x, w, dy,
+                           dw, db, dx);
+    else if (C == 32)
+        hipLaunchKernelGGL(k_head_back<32>, dim3(blocks_for(nvox)), dim3(256), 0, st, nvox, x, w, dy,
+                           dw, db, dx);
+    else
+        return hipErrorInvalidValue;
+    return hipGetLastError();
+}
+hipError_t launch_adam(int64_t n, float* p, const float* g, float* m, float* v, float lr, float b1,
+                       float b2, float eps, float c1, float c2, hipStream_t st) {
+    hipLaunchKernelGGL(k_adam, dim3(blocks_for(n)), dim3(256), 0, st, n, p, g, m, v, lr, b1, b2, eps,
+                       c1, c2);
+    return hipGetLastError();
+}
+hipError_t launch_weights_bf16(int64_t n, const float* p, int taps, int Cout, int Cin, int conv3,
+                               uint16_t* w16, uint16_t* wt16, hipStream_t st) {
+    hipLaunchKernelGGL(k_weights_bf16, dim3(blocks_for(n)), dim3(256), 0, st, n, p, taps, Cout, Cin,
+                       conv3, w16, wt16);
+    return hipGetLastError();
+}
+hipError_t launch_features(int64_t nvox, const double* rho, double chi1_dx, const double* flux,
+                           float* x, hipStream_t st) {
+    hipLaunchKernelGGL(k_features, dim3(blocks_for(nvox)), dim3(256), 0, st, nvox, rho, chi1_dx, flux,
+                       x);
+    return hipGetLastError();
+}
+hipError_t launch_exp10(int64_t n, const float* y, double* T, hipStream_t st) {
+    hipLaunchKernelGGL(k_exp10, dim3(blocks_for(n)), dim3(256), 0, st, n, y, T);
+    return hipGetLastError();
+}
+
+}  // namespace nn
+}  // namespace mcrt

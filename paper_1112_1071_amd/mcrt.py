@@ -140,6 +140,19 @@ def lib():
         "mcrt_device_info": ([vp, C.POINTER(i32), C.POINTER(i32)], i32),
         "mcrt_batch_cfg_default": ([C.POINTER(BatchCfg)], i32),
         "mcrt_batch_run": ([C.POINTER(vp), i32, C.POINTER(BatchCfg), C.POINTER(BatchStats)], i32),
+        "mcrt_surrogate_create": ([C.POINTER(vp), i32, i32, C.c_uint64], i32),
+        "mcrt_surrogate_destroy": ([vp], None),
+        "mcrt_surrogate_last_error": ([vp], C.c_char_p),
+        "mcrt_surrogate_set_stream": ([vp, vp], i32),
+        "mcrt_surrogate_param_count": ([vp], i64),
+        "mcrt_surrogate_get_params": ([vp, vp, sz], i32),
+        "mcrt_surrogate_set_params": ([vp, vp, sz], i32),
+        "mcrt_surrogate_get_grads": ([vp, vp, sz], i32),
+        "mcrt_surrogate_forward": ([vp, vp, i32, i32, vp], i32),
+        "mcrt_surrogate_train_step": ([vp, vp, vp, vp, i32, i32, dbl, dbl, i32, C.POINTER(dbl)], i32),
+        "mcrt_surrogate_predict_T": ([vp, vp, i32, i32, vp], i32),
+        "mcrt_model_features": ([vp, vp, sz], i32),
+        "mcrt_warm_start": ([vp, vp, C.POINTER(dbl)], i32),
     }
     for name, (args, res) in sig.items():
         f = getattr(L, name)
@@ -170,6 +183,7 @@ class Model:
             raise MCRTError(rc, "mcrt_create failed (no HIP device?)")
         self.h = h
         self.cfg = cfg
+        self.device = int(device)
         if stream is not None:
             self._check(self.L.mcrt_set_stream(self.h, C.c_void_p(int(stream))))
         g = cfg["grid"]
@@ -312,6 +326,22 @@ class Model:
         self._check(self.L.mcrt_device_info(self.h, C.byref(n), C.byref(w)))
         return n.value, w.value
 
+    # -- learned warm start ----------------------------------------------------
+    def features(self):
+        """FP32 device tensor [ncell, 2] of the network's input features."""
+        import torch
+
+        x = torch.empty((self.ncell, 2), dtype=torch.float32, device=f"cuda:{self.device}")
+        torch.cuda.synchronize(x.device)
+        self._check(self.L.mcrt_model_features(self.h, C.c_void_p(x.data_ptr()), x.numel()))
+        return x
+
+    def warm_start(self, sur: "Surrogate") -> float:
+        """Set the starting temperatures from the network; returns the wall ms."""
+        ms = C.c_double()
+        self._check(self.L.mcrt_warm_start(self.h, sur.h, C.byref(ms)))
+        return ms.value
+
 
 def batch_run(models, **cfg) -> dict:
     """Run Lucy iterations (and the final pass) of many models in one launch per
@@ -327,3 +357,82 @@ def batch_run(models, **cfg) -> dict:
     if rc != 0:
         raise MCRTError(rc, L.mcrt_last_error(models[0].h).decode())
     return st.as_dict()
+
+
+class Surrogate:
+    """The warm-start network (mcrt_surrogate_*): device tensors in, device
+    tensors out.  Tensors must be contiguous FP32 on the surrogate's device."""
+
+    def __init__(self, device: int = 0, base_channels: int = 16, seed: int = 0):
+        self.L = lib()
+        self.device = device
+        self.h = C.c_void_p()
+        rc = self.L.mcrt_surrogate_create(C.byref(self.h), device, base_channels, seed)
+        if rc != 0:
+            raise MCRTError(rc, "mcrt_surrogate_create failed")
+        self.n_params = int(self.L.mcrt_surrogate_param_count(self.h))
+
+    def _check(self, rc):
+        if rc != 0:
+            raise MCRTError(rc, self.L.mcrt_surrogate_last_error(self.h).decode())
+
+    def close(self):
+        if self.h:
+            self.L.mcrt_surrogate_destroy(self.h)
+            self.h = C.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    @staticmethod
+    def _dev(t, name):
+        import torch
+
+        if not (t.is_cuda and t.dtype == torch.float32 and t.is_contiguous()):
+            raise ValueError(f"{name}: contiguous FP32 device tensor expected")
+        return C.c_void_p(t.data_ptr())
+
+    def params(self) -> np.ndarray:
+        p = np.zeros(self.n_params, dtype=np.float32)
+        self._check(self.L.mcrt_surrogate_get_params(self.h, _ptr(p), p.size))
+        return p
+
+    def set_params(self, p):
+        p = np.ascontiguousarray(p, dtype=np.float32)
+        self._check(self.L.mcrt_surrogate_set_params(self.h, _ptr(p), p.size))
+
+    def grads(self) -> np.ndarray:
+        g = np.zeros(self.n_params, dtype=np.float32)
+        self._check(self.L.mcrt_surrogate_get_grads(self.h, _ptr(g), g.size))
+        return g
+
+    def forward(self, x, N: int, D: int):
+        """x: [N*D^3, 2] features -> [N*D^3] log10 T."""
+        import torch
+
+        torch.cuda.synchronize(x.device)
+        y = torch.empty(N * D ** 3, dtype=torch.float32, device=x.device)
+        self._check(self.L.mcrt_surrogate_forward(self.h, self._dev(x, "x"), N, D, C.c_void_p(y.data_ptr())))
+        return y
+
+    def train_step(self, x, target, mask, N: int, D: int, lr: float, apply_update: bool = True,
+                   mask_count: float | None = None) -> float:
+        import torch
+
+        if mask_count is None:
+            mask_count = float(mask.sum().item())
+        torch.cuda.synchronize(x.device)
+        loss = C.c_double()
+        self._check(self.L.mcrt_surrogate_train_step(
+            self.h, self._dev(x, "x"), self._dev(target, "target"), self._dev(mask, "mask"), N, D,
+            float(mask_count), float(lr), int(apply_update), C.byref(loss)))
+        return loss.value
+
+    def save(self, path: str):
+        np.save(path, self.params())
+
+    def load(self, path: str):
+        self.set_params(np.load(path, allow_pickle=False))

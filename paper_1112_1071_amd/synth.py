@@ -289,7 +289,7 @@ def slab(n=20, tau_1um=1.0, n_packets=200000, seed=7, n_bins=8):
 
 def clump_config4(n=128, seed=45000, n_src=50, n_packets=None, n_iter=30):
     """unseen test clump for the learned warm start: built like config2"""
-    cfg = config2(n=n, gen_seed=seed, n_src=n_src, n_packets=n_packets or 12_500_000 // 8,
+    cfg = config2(n=n, gen_seed=seed, n_src=n_src, n_packets=n_packets or 12_500_000,
                   n_iter=n_iter, seed=seed)
     cfg["name"] = f"clump{n}-{seed}"
     return cfg
