@@ -27,7 +27,7 @@ HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, published
 
 def transport_source_hash() -> str:
     h = hashlib.sha256()
-    for f in ["mcrt_transport.hip", "mcrt_internal.h"]:
+    for f in ["mcrt_transport.hip", "mcrt_sweep.hip", "mcrt_packet.h", "mcrt_internal.h"]:
         with open(os.path.join(ROOT, "paper_1112_1071_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
@@ -72,55 +72,105 @@ def cpu_baseline(cfg: dict, n_packets: int) -> dict:
 
 def bench_batch(args):
     """Form 2: the batched family of uneven models, one persistent launch per
-    Lucy iteration (graph-replayed, autotuned) vs one launch per model."""
+    Lucy iteration (graph-replayed, autotuned) vs one launch per model.  Both
+    sides run iteration 0 untimed and then time the same iterations 1..steps
+    (an iteration's cost grows as the dust warms up)."""
     from paper_1112_1071_amd import mcrt, synth
+    import torch
 
     t0 = time.time()
-    cfgs = [synth.config3_model(m, packets_per_cell=args.ppc, n_iter=args.steps)
+    cfgs = [synth.config3_model(m, packets_per_cell=args.ppc, n_iter=args.steps + 1)
             for m in range(args.models)]
     print(f"# {args.models} models built in {time.time() - t0:.1f} s", file=sys.stderr, flush=True)
     prec = mcrt.MCRT_FP32_TRANSPORT if args.precision == "fp32" else mcrt.MCRT_FP64
     batch = [mcrt.Model(c, precision=prec) for c in cfgs]
     n_packets = sum(int(c["run"]["n_packets"]) for c in cfgs)
     cells = sum(int(np.prod(c["grid"]["n"])) for c in cfgs)
-    # warm-up batch: tunes the launch shape (cached) and runs the first iteration
+    # iteration 0, which also tunes the launch shape (cached per workload class)
     stw = mcrt.batch_run(batch, n_iter=1, final_pass=0, use_graph=0, autotune=1)
-    print(f"# warmup/tune: {stw['ms_total']:.0f} ms (tune {stw['ms_tune']:.0f} ms) shape "
+    print(f"# iteration 0 + tuning: {stw['ms_total']:.0f} ms (tune {stw['ms_tune']:.0f} ms) shape "
           f"bs={stw['block_size']} K={stw['walk_batch']} defer={stw['defer_lanes']}",
           file=sys.stderr, flush=True)
+    torch.cuda.synchronize()
+    tb = time.perf_counter()
     st = mcrt.batch_run(batch, n_iter=args.steps, final_pass=0, use_graph=1, autotune=1)
-    ms_it = st["ms_iterations"] / st["n_iterations"]
-    value = n_packets / (ms_it * 1e-3)
-    print(f"# batched: {ms_it:.1f} ms per iteration", file=sys.stderr, flush=True)
-    # the same iteration as one launch per model
-    seq = [mcrt.Model(c, precision=prec) for c in cfgs[: args.seq_models]]
-    for m in seq:
-        m.iterate()
-    import torch
-
     torch.cuda.synchronize()
-    ts = time.perf_counter()
-    for m in seq:
+    batch_s = time.perf_counter() - tb
+    value = n_packets * args.steps / batch_s
+    print(f"# batched: {1e3 * batch_s / args.steps:.1f} ms per iteration", file=sys.stderr, flush=True)
+    del batch
+    # the same iterations, one model and one launch at a time
+    nseq = min(args.seq_models, args.models)
+    seq_s, seq_packets = 0.0, 0
+    for i, c in enumerate(cfgs[:nseq]):
+        m = mcrt.Model(c, precision=prec)
         m.iterate()
-    torch.cuda.synchronize()
-    seq_s = time.perf_counter() - ts
-    seq_packets = sum(int(c["run"]["n_packets"]) for c in cfgs[: args.seq_models])
+        torch.cuda.synchronize()
+        ts = time.perf_counter()
+        for _ in range(args.steps):
+            m.iterate()
+        torch.cuda.synchronize()
+        seq_s += time.perf_counter() - ts
+        seq_packets += int(c["run"]["n_packets"]) * args.steps
+        m.close()
+        if (i + 1) % 32 == 0:
+            print(f"# sequential: {i + 1}/{nseq} models", file=sys.stderr, flush=True)
     seq_value = seq_packets / seq_s
+    ms_it = 1e3 * batch_s / args.steps
     out = {
         "metric": "packets/s, batched Lucy iterations of uneven models",
-        "value": value, "unit": "packets/s", "n_gpus": 1, "steps": st["n_iterations"],
+        "value": value, "unit": "packets/s", "n_gpus": 1, "steps": args.steps,
         "warmup": 1, "ms_per_step": ms_it, "higher_is_better": True, "scaling": "weak",
         "vs_baseline": None, "dtype": "fp32" if prec == 1 else "fp64", "data": "synthetic",
         "config": {"workload": f"batch{args.models}: {args.models} models, grids 16^3..96^3 "
                                f"({cells} cells), sphere/disk family, {args.ppc} packets per cell "
-                               f"per iteration ({n_packets:.3e} packets)",
+                               f"per iteration ({n_packets:.3e} packets), iterations 1..{args.steps}",
                    "models": args.models, "packets_per_step": n_packets},
         "batch": {"graph_used": st["graph_used"], "tuned": st["tuned"],
                   "block_size": st["block_size"], "walk_batch": st["walk_batch"],
                   "defer_lanes": st["defer_lanes"], "blocks_per_cu": st["blocks_per_cu"],
                   "ms_tune": stw["ms_tune"]},
-        "sequential": {"value": seq_value, "unit": "packets/s", "models": args.seq_models,
+        "sequential": {"value": seq_value, "unit": "packets/s", "models": nseq,
                        "seconds": seq_s, "speedup_batched": value / seq_value},
+    }
+    print(json.dumps(out), flush=True)
+
+
+def bench_warmstart(args):
+    """Time to a converged temperature (max dT/T < 1 % over the noise mask) on
+    unseen 128^3 clumps, from T = 10 K and from the learned warm start; the
+    warm-start time includes feature computation and network inference."""
+    from paper_1112_1071_amd import mcrt, warmstart
+
+    sur = mcrt.Surrogate(0, 16, seed=0)
+    sur.load(args.weights)
+    runs = []
+    for i in range(args.clumps):
+        cfg = warmstart.test_clump(i, n_packets=int(args.packets))
+        cold = warmstart.converge(cfg, None)
+        warm = warmstart.converge(cfg, sur)
+        runs.append({"clump": i, "cold": cold, "warm": warm})
+        print(f"# clump {i}: cold {cold['iterations']} it {cold['ms_to_converged']:.0f} ms, warm "
+              f"{warm['iterations']} it {warm['ms_to_converged']:.0f} ms, pre-MC median |dlnT| "
+              f"{warm['pre_mc_error']['median_abs_dlnT']:.3f}", file=sys.stderr, flush=True)
+    ok = all(r["cold"]["converged"] and r["warm"]["converged"] for r in runs)
+    t_cold = float(np.mean([r["cold"]["ms_to_converged"] or np.nan for r in runs]))
+    t_warm = float(np.mean([r["warm"]["ms_to_converged"] or np.nan for r in runs]))
+    out = {
+        "metric": "time to converged T (max dT/T < 1%), learned warm start",
+        "value": t_warm, "unit": "ms", "n_gpus": 1, "steps": len(runs), "warmup": 0,
+        "ms_per_step": t_warm, "higher_is_better": False, "scaling": "weak", "vs_baseline": None,
+        "dtype": "fp32 transport, bf16 network", "data": "synthetic",
+        "config": {"workload": f"{args.clumps} unseen 128^3 clumps built like the 256^3 clump "
+                               f"(0.65 pc, 50 sources, mean tau(1 um) 50), {args.packets:.2e} "
+                               f"packets per iteration", "clumps": args.clumps},
+        "cold": {"ms_to_converged": t_cold,
+                 "iterations": [r["cold"]["iterations"] for r in runs]},
+        "warm": {"ms_to_converged": t_warm,
+                 "iterations": [r["warm"]["iterations"] for r in runs],
+                 "ms_inference": [r["warm"]["ms_warm_start"] for r in runs],
+                 "pre_mc_error": [r["warm"]["pre_mc_error"] for r in runs]},
+        "speedup": t_cold / t_warm if ok else None, "all_converged": ok,
     }
     print(json.dumps(out), flush=True)
 
@@ -128,7 +178,10 @@ def bench_batch(args):
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--workload", choices=["clump256", "batch"], default="clump256")
+    ap.add_argument("--workload", choices=["clump256", "batch", "warmstart"], default="clump256")
+    ap.add_argument("--clumps", type=int, default=2, help="warmstart: test clumps")
+    ap.add_argument("--weights", default=os.path.join(ROOT, "paper_1112_1071_amd", "weights",
+                                                      "warmstart_c16.npy"))
     ap.add_argument("--models", type=int, default=512)
     ap.add_argument("--ppc", type=int, default=30, help="batch: packets per cell per iteration")
     ap.add_argument("--seq-models", type=int, default=512)
@@ -145,12 +198,21 @@ def main():
     ap.add_argument("--layout", type=int, default=-1)
     ap.add_argument("--block-size", type=int, default=0)
     ap.add_argument("--sampling", type=int, default=0, help="1: equal packets per source")
+    ap.add_argument("--mode", type=int, default=-1,
+                    help="transport_mode: 0 per-lane persistent walk, 1 tiled sweeps")
+    ap.add_argument("--tile-z", type=int, default=0)
+    ap.add_argument("--visit-events", type=int, default=0)
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this benchmark runs on one GPU only; --gpus must be 1"}))
         sys.exit(2)
     if args.workload == "batch":
         bench_batch(args)
+        return
+    if args.workload == "warmstart":
+        if args.packets == 1e8:
+            args.packets = 2.5e8
+        bench_warmstart(args)
         return
 
     from paper_1112_1071_amd import mcrt, synth
@@ -173,6 +235,12 @@ def main():
         run["block_size"] = args.block_size
     if args.sampling:
         run["source_sampling"] = args.sampling
+    if args.mode >= 0:
+        run["transport_mode"] = args.mode
+    if args.tile_z:
+        run["tile_z"] = args.tile_z
+    if args.visit_events:
+        run["visit_events"] = args.visit_events
     model = mcrt.Model(cfg, **run)
     print(f"# workload built in {gen_s:.1f} s; warmup {args.warmup}", file=sys.stderr, flush=True)
     for i in range(args.warmup):
@@ -219,7 +287,7 @@ def main():
         },
         "roofline": {
             "bound": "hbm",
-            "kernel": "k_transport",
+            "kernel": "k_sweep (+ tile sort)" if model.run["transport_mode"] == 1 else "k_transport",
             "achieved": achieved,
             "peak": HBM_PEAK_GBS,
             "unit": "GB/s",
@@ -233,6 +301,7 @@ def main():
             "dust_crossings": last["n_cross_dust"], "empty_crossings": last["n_cross_empty"],
             "scatters": last["n_scatter"], "absorptions": last["n_absorb"],
             "killed": last["n_killed"], "ms_update": last["ms_update"],
+            "transport_mode": model.run["transport_mode"], "sweeps": last["n_sweeps"],
             "max_dT": last["max_dT"], "q": last["q"],
         },
     }

@@ -97,6 +97,14 @@ typedef struct {
                                   1 bricks of 4x4x4 cells [0]; results are identical     */
     int32_t tally_copies;      /* absorption tallies per device: 1, or 8 (one per XCD,
                                   summed by the cell update) [8]                          */
+    int32_t transport_mode;    /* 0: every lane walks its packet through the whole grid,
+                                  tallies with global FP64 atomics; 1: tiled sweeps --
+                                  packets grouped by tile of 16x16xtile_z cells, each tile
+                                  walked with density and tally in LDS, tally flushed to
+                                  FP64 once per work item [0]; same packet histories     */
+    int32_t tile_z;            /* tiled sweeps: tile extent in z, 4, 8 or 16 [8]          */
+    int32_t visit_events;      /* tiled sweeps: interactions per tile visit before a
+                                  packet waits for the next sweep [256]                   */
 } mcrt_run_cfg;
 
 /* Statistics of one pass (a Lucy iteration or the final pass). */
@@ -125,6 +133,7 @@ typedef struct {
     double ms_transport;       /* device time of the transport kernel(s)                  */
     double ms_update;          /* device time of the temperature update and statistics    */
     double ms_total;           /* host wall time of the call                              */
+    int64_t n_sweeps;          /* tiled sweeps run by the pass (transport_mode 1)         */
 } mcrt_iter_stats;
 
 typedef struct {
@@ -259,13 +268,14 @@ mcrt_status mcrt_batch_run(mcrt_model* const* models, int n, const mcrt_batch_cf
  * master parameters trained with Adam (b1 0.9, b2 0.999, eps 1e-8).
  *
  * Tensors of a batch are N cubes of side D (D a multiple of 8), voxel index
- * ((n*D + z)*D + y)*D + x.  Features x: FP32 [N][D^3][2] (see
+ * ((n*D + z)*D + y)*D + x.  Features x: FP32 [N][D^3][3] (see
  * mcrt_model_features); outputs y: FP32 [N][D^3], log10 T in K.
  * Parameter vector (FP32): per layer in network order, weights
  * [taps][C_out][C_in] (taps 27 = dz*9 + dy*3 + dx for 3x3x3 with offsets
  * -1..1, 8 = tz*4 + ty*2 + tx for 2x2x2) then biases [C_out]; the head's
- * weights [C] and bias last.  Input channels 2..15 of the first layer see
- * zeros.  Device pointers are in the surrogate's device memory; the calls
+ * weights [C] and bias last.  The first layer sees the features scaled as
+ * (x0 + 2)/2, (x1 + 30)/10, (x2 - 4)/3 in input channels 0-2; its input
+ * channels 3..15 see zeros.  Device pointers are in the surrogate's device memory; the calls
  * synchronise the surrogate's stream before returning. */
 typedef struct mcrt_surrogate mcrt_surrogate;
 
@@ -291,12 +301,16 @@ mcrt_status mcrt_surrogate_train_step(mcrt_surrogate* s, const float* d_x, const
 /* Inference written as temperatures: d_T[v] = 10^y clamped to [1, 1e4] K (FP64). */
 mcrt_status mcrt_surrogate_predict_T(mcrt_surrogate* s, const float* d_x, int N, int D, double* d_T);
 
-/* Features of a model for the network, FP32 [ncell][2] in device memory
- * (n = 2*ncell): channel 0 = log10 max(rho chi(1 um) dx, 1e-6), the optical
- * depth of one cell width at 1 micron (chi of the bin holding 1 um, dx the x
- * cell width); channel 1 = log10(F + 1e-30), F = (sum of the luminosities of
- * the sources in the cell) / (4 pi dx^2) in erg s^-1 cm^-2, a source on a cell
- * wall, edge or corner being shared equally by the cells that touch it. */
+/* Features of a model for the network, FP32 [ncell][3] in device memory
+ * (n = 3*ncell), from the density, the dust and the sources:
+ *   0: log10 max(rho chi(1 um) dx, 1e-6), the optical depth of one cell width
+ *      at 1 micron (chi of the bin holding 1 um, dx the x cell width);
+ *   1: log10(D + 1e-30), the deposit field D = (sum of the luminosities of the
+ *      sources in the cell) / (4 pi dx^2) in erg s^-1 cm^-2, a source on a cell
+ *      wall, edge or corner being shared equally by the cells that touch it;
+ *   2: log10(sum over deposit cells c of D_c dx^2 / max(r^2, dx^2/4) + 1e-30),
+ *      r the distance between cell centres: the deposit field spread by the
+ *      free-space 1/r^2 kernel (the unattenuated flux of the deposited light). */
 mcrt_status mcrt_model_features(mcrt_model* m, float* d_x, size_t n);
 /* Warm start: features -> network -> temperatures of m (as by
  * mcrt_set_temperature_device).  The grid must be a cube of cells with a side

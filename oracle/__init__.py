@@ -92,6 +92,9 @@ def lib():
         L.orc_get_absorbed_sum.argtypes = [vp, _dp, C.c_size_t]
         L.orc_get_sed.argtypes = [vp, _dp, C.c_void_p, C.c_void_p, C.c_size_t]
         L.orc_get_images.argtypes = [vp, C.c_void_p, C.c_void_p, C.c_size_t]
+        L.orc_set_peeloff.argtypes = [vp, C.c_void_p, C.c_int]
+        L.orc_get_peeled_sed.argtypes = [vp, C.c_void_p, C.c_void_p, C.c_size_t]
+        L.orc_get_peeled_images.argtypes = [vp, C.c_void_p, C.c_void_p, C.c_size_t]
         L.orc_get_event_log.argtypes = [vp, C.c_void_p, C.c_size_t, C.c_void_p, C.c_size_t]
         L.orc_get_emission_rows.argtypes = [vp, C.c_void_p, C.c_void_p, C.c_size_t]
         L.orc_philox4x32_10.argtypes = [C.c_void_p, C.c_void_p, C.c_void_p]
@@ -227,6 +230,10 @@ class OracleModel:
         self._check(L.orc_set_observers(self.h, self.n_incl, self.npix,
                                         float(ob.get("img_half_width", 0.0)),
                                         bins.ctypes.data if bins.size else None, int(bins.size)))
+        dirs = np.ascontiguousarray(cfg.get("peeloff", {}).get("dirs", np.zeros((0, 3))),
+                                    dtype=np.float64).reshape(-1, 3)
+        self.n_peel = int(dirs.shape[0])
+        self._check(L.orc_set_peeloff(self.h, dirs.ctypes.data if self.n_peel else None, self.n_peel))
         run = dict(cfg.get("run", {}))
         run.update(run_overrides)
         self.run = run
@@ -319,6 +326,21 @@ class OracleModel:
         s2 = np.zeros(max(n, 1))
         self._check(self.L.orc_get_images(self.h, s.ctypes.data, s2.ctypes.data, n))
         sh = (self.n_img, self.n_incl, self.npix, self.npix)
+        return s[:n].reshape(sh), s2[:n].reshape(sh)
+
+    def peeled_sed(self):
+        """[n_peel][2][nnu] energy per steradian (component 0 direct, 1 processed)."""
+        n = self.n_peel * 2 * self.nnu
+        s, s2 = np.zeros(max(n, 1)), np.zeros(max(n, 1))
+        self._check(self.L.orc_get_peeled_sed(self.h, s.ctypes.data, s2.ctypes.data, n))
+        sh = (self.n_peel, 2, self.nnu)
+        return s[:n].reshape(sh), s2[:n].reshape(sh)
+
+    def peeled_images(self):
+        n = self.n_img * self.n_peel * self.npix * self.npix
+        s, s2 = np.zeros(max(n, 1)), np.zeros(max(n, 1))
+        self._check(self.L.orc_get_peeled_images(self.h, s.ctypes.data, s2.ctypes.data, n))
+        sh = (self.n_img, self.n_peel, self.npix, self.npix)
         return s[:n].reshape(sh), s2[:n].reshape(sh)
 
     def event_log(self):

@@ -6,8 +6,9 @@ does.  It imports nothing from the HIP package.
 What it computes (the network that warm-starts the Lucy temperature iteration
 of Sec. 2.4): a 3-D convolutional encoder-decoder on N cubes of side D,
 
-* input: two features per cell, shifted and scaled, channel 0 -> (x0 + 2) / 2,
-  channel 1 -> (x1 + 30) / 10, zero-padded to 16 channels;
+* input: three features per cell, shifted and scaled, channel 0 -> (x0 + 2) / 2,
+  channel 1 -> (x1 + 30) / 10, channel 2 -> (x2 - 4) / 3, zero-padded to 16
+  channels;
 * level l (l = 0..3) has C * 2^l channels; encoder levels 0-2: two 3x3x3
   convolutions (zero padding 1) then a 2x2x2 stride-2 convolution; level 3:
   two 3x3x3 convolutions; decoder levels 2..0: a 2x2x2 stride-2 transposed
@@ -36,7 +37,7 @@ import torch
 import torch.nn.functional as F
 
 SLOPE = 0.1
-NORM = (2.0, 0.5, 30.0, 0.1)
+NORM = (2.0, 0.5, 30.0, 0.1, -4.0, 1.0 / 3.0)
 CONV3, DOWN, UP = 0, 1, 2
 
 
@@ -137,13 +138,11 @@ def conv(mode: int, x, W, b, fp32: bool = False):
 
 
 def inputs(x, N: int, D: int, bf16: bool = True):
-    """features [N*D^3, 2] (FP32 values) -> padded NCDHW input tensor."""
-    x = torch.as_tensor(np.asarray(x, dtype=np.float32).astype(np.float64)).reshape(N, D, D, D, 2)
-    a = (x[..., 0] + NORM[0]) * NORM[1]
-    c = (x[..., 1] + NORM[2]) * NORM[3]
+    """features [N*D^3, 3] (FP32 values) -> padded NCDHW input tensor."""
+    x = torch.as_tensor(np.asarray(x, dtype=np.float32).astype(np.float64)).reshape(N, D, D, D, 3)
     t = torch.zeros((N, 16, D, D, D), dtype=torch.float64)
-    t[:, 0] = _bf16(a, bf16)
-    t[:, 1] = _bf16(c, bf16)
+    for c in range(3):
+        t[:, c] = _bf16((x[..., c] + NORM[2 * c]) * NORM[2 * c + 1], bf16)
     return t
 
 
@@ -195,10 +194,13 @@ def adam(p, g, m, v, step: int, lr: float, b1=0.9, b2=0.999, eps=1e-8):
 
 
 def features(cfg: dict) -> np.ndarray:
-    """Network features of a model config, FP64 [ncell, 2]: log10 of the cell
-    optical depth at 1 micron (floored at 1e-6) and log10(F + 1e-30), F the
-    luminosity of the sources in the cell over 4 pi dx^2; a source on a cell
-    wall, edge or corner is shared equally by the cells touching it."""
+    """Network features of a model config, FP64 [ncell, 3]: log10 of the cell
+    optical depth at 1 micron (floored at 1e-6); log10(D + 1e-30), D the
+    deposit field (luminosity of the sources in the cell over 4 pi dx^2; a
+    source on a cell wall, edge or corner is shared equally by the cells
+    touching it); log10 of the deposit field spread by the free-space kernel,
+    sum over deposit cells of D_c dx^2 / max(r^2, dx^2/4) with r the distance
+    between cell centres, + 1e-30."""
     n = [int(v) for v in cfg["grid"]["n"]]
     lo = np.asarray(cfg["grid"]["lo"], dtype=np.float64)
     hi = np.asarray(cfg["grid"]["hi"], dtype=np.float64)
@@ -225,5 +227,11 @@ def features(cfg: dict) -> np.ndarray:
             for j in ranges[1]:
                 for i in ranges[0]:
                     lum[i + n[0] * (j + n[1] * kk)] += s["lum"] / cnt
-    flux = lum / (4.0 * math.pi * dx[0] ** 2)
-    return np.stack([np.log10(tau), np.log10(flux + 1e-30)], axis=1)
+    dep = lum / (4.0 * math.pi * dx[0] ** 2)
+    kk, jj, ii = np.meshgrid(np.arange(n[2]), np.arange(n[1]), np.arange(n[0]), indexing="ij")
+    ii, jj, kk = ii.reshape(-1), jj.reshape(-1), kk.reshape(-1)
+    spread = np.zeros(rho.size)
+    for c in np.nonzero(dep)[0]:
+        r2 = (ii - ii[c]) ** 2 + (jj - jj[c]) ** 2 + (kk - kk[c]) ** 2
+        spread += dep[c] / np.maximum(r2, 0.25)
+    return np.stack([np.log10(tau), np.log10(dep + 1e-30), np.log10(spread + 1e-30)], axis=1)

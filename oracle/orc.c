@@ -26,6 +26,8 @@
  *               are independent, so chunked parallel work gives the same
  *               result up to summation order.
  *   Sec. 2.6.1  binning escaping packets into viewing-angle bins.
+ *   Sec. 2.6.2  peeling-off: at each source emission, scattering and
+ *               re-emission, weight p exp(-tau) toward each observer.
  *
  * Readings where the paper is silent (the same contract binds the HIP path):
  *   - multigroup frequencies: a packet carries a bin index; dust properties
@@ -274,6 +276,15 @@ struct orc_model {
     int64_t* sed_n;
     double* img_sum;
     double* img_sum2;
+    /* peeling-off (Sec. 2.6.2): n_peel observer directions; SED [n_peel][2][nnu]
+     * (component 0: direct source emission, 1: scattered or re-emitted) and
+     * images [n_img][n_peel][npix][npix], energy per steradian */
+    int n_peel;
+    double* peel_dir;
+    double* psed_sum;
+    double* psed_sum2;
+    double* pimg_sum;
+    double* pimg_sum2;
     orc_event* evlog;
     int32_t* evcount;
     int ev_packets, ev_cap;
@@ -326,6 +337,7 @@ void orc_destroy(orc_model* m)
     free(m->img_bins); free(m->img_of_bin); free(m->ecdf);
     free_state(m);
     free(m->sed_sum); free(m->sed_sum2); free(m->sed_n); free(m->img_sum); free(m->img_sum2);
+    free(m->peel_dir); free(m->psed_sum); free(m->psed_sum2); free(m->pimg_sum); free(m->pimg_sum2);
     free(m->evlog); free(m->evcount);
     free(m);
 }
@@ -524,6 +536,28 @@ int orc_set_observers(orc_model* m, int n_incl, int img_npix, double img_half_wi
     return 0;
 }
 
+int orc_set_peeloff(orc_model* m, const double* dirs, int n)
+{
+    if (!m->have_obs) return fail(m, "set observers before peeling-off directions");
+    if (n < 0 || (n > 0 && !dirs)) return fail(m, "bad peeling-off directions");
+    for (int i = 0; i < n; ++i) {
+        double r = sqrt(dirs[3 * i] * dirs[3 * i] + dirs[3 * i + 1] * dirs[3 * i + 1] +
+                        dirs[3 * i + 2] * dirs[3 * i + 2]);
+        if (!(fabs(r - 1.0) < 1e-9)) return fail(m, "peeling-off directions must be unit vectors");
+    }
+    free(m->peel_dir); free(m->psed_sum); free(m->psed_sum2); free(m->pimg_sum); free(m->pimg_sum2);
+    m->n_peel = n;
+    size_t ns = (size_t)(n ? n : 1) * 2 * m->nnu;
+    size_t ni = (size_t)m->n_img * (n ? n : 1) * m->npix * m->npix;
+    m->peel_dir = (double*)malloc((size_t)(n ? n : 1) * 3 * sizeof(double));
+    if (n) memcpy(m->peel_dir, dirs, (size_t)n * 3 * sizeof(double));
+    m->psed_sum = (double*)calloc(ns, sizeof(double));
+    m->psed_sum2 = (double*)calloc(ns, sizeof(double));
+    m->pimg_sum = (double*)calloc(ni ? ni : 1, sizeof(double));
+    m->pimg_sum2 = (double*)calloc(ni ? ni : 1, sizeof(double));
+    return 0;
+}
+
 int orc_set_run(orc_model* m, const orc_run_cfg* cfg)
 {
     if (cfg->n_packets < 1 || cfg->n_packets_final < 0) return fail(m, "packet counts must be >= 1");
@@ -692,6 +726,10 @@ typedef struct {
     int64_t* sed_n;
     double* img_sum;
     double* img_sum2;
+    double* psed_sum;
+    double* psed_sum2;
+    double* pimg_sum;
+    double* pimg_sum2;
     int64_t n_cross_dust, n_cross_empty, n_scatter, n_absorb, n_escape, n_killed;
     double e_escaped, e_killed;
 } tally;
@@ -795,6 +833,84 @@ static void bin_escape(const orc_model* m, const double x[3], const double d[3],
     t->img_sum2[q] += eps * eps;
 }
 
+/* Optical depth in bin k from x to the grid boundary along the unit vector
+ * o: the same walk as for a packet, without interactions.  0 when x lies
+ * outside the grid. */
+static double tau_to_boundary(const orc_model* m, const double x0[3], const double o[3], int k)
+{
+    double x[3] = {x0[0], x0[1], x0[2]};
+    int c[3];
+    locate(m, x, o, c);
+    if (!inside(m, c)) return 0.0;
+    double tau = 0.0;
+    for (;;) {
+        int64_t j = c[0] + (int64_t)m->n[0] * (c[1] + (int64_t)m->n[1] * c[2]);
+        double tw[3];
+        for (int a = 0; a < 3; ++a) tw[a] = wall_distance(m, x, o, c, a);
+        int ax = 0;
+        if (tw[1] < tw[ax]) ax = 1;
+        if (tw[2] < tw[ax]) ax = 2;
+        double l = tw[ax] > 0.0 ? tw[ax] : 0.0;
+        tau += m->rho[j] * m->chi[k] * l;
+        for (int a = 0; a < 3; ++a) x[a] += o[a] * l;
+        if (o[ax] > 0.0) {
+            x[ax] = wall(m, ax, c[ax] + 1);
+            if (c[ax] + 1 >= m->n[ax]) return tau;
+            c[ax] += 1;
+        } else {
+            x[ax] = wall(m, ax, c[ax]);
+            if (c[ax] - 1 < 0) return tau;
+            c[ax] -= 1;
+        }
+    }
+}
+
+/* Henyey-Greenstein phase function per steradian (integrates to 1). */
+static double hg_phase(double g, double mu)
+{
+    double q = 1.0 + g * g - 2.0 * g * mu;
+    return (1.0 - g * g) / (4.0 * ORC_PI * q * sqrt(q));
+}
+
+/* Peeling-off (Sec. 2.6.2): toward every observer o, add eps * p(o) *
+ * exp(-tau(x -> boundary along o)) in bin k to the SED component comp and,
+ * for the image bins, to the pixel of x projected along o.  d_in is the
+ * incoming direction of a scattering (p from the HG phase function) or NULL
+ * for isotropic emission (p = 1/(4 pi)). */
+static void peel(const orc_model* m, const double x[3], const double* d_in, int k, double eps, int comp,
+                 tally* t)
+{
+    for (int i = 0; i < m->n_peel; ++i) {
+        const double* o = m->peel_dir + 3 * i;
+        double p = 1.0 / (4.0 * ORC_PI);
+        if (d_in) p = hg_phase(m->g[k], d_in[0] * o[0] + d_in[1] * o[1] + d_in[2] * o[2]);
+        double w = eps * p * exp(-tau_to_boundary(m, x, o, k));
+        size_t q = ((size_t)i * 2 + comp) * m->nnu + k;
+        t->psed_sum[q] += w;
+        t->psed_sum2[q] += w * w;
+        int ii = m->img_of_bin[k];
+        if (ii < 0) continue;
+        double pc[3];
+        for (int a = 0; a < 3; ++a) pc[a] = x[a] - 0.5 * (m->lo[a] + m->hi[a]);
+        double ex[3] = {-o[1], o[0], 0.0};
+        double en = sqrt(ex[0] * ex[0] + ex[1] * ex[1]);
+        if (en < 1e-12) {
+            ex[0] = 1.0; ex[1] = 0.0;
+        } else {
+            ex[0] /= en; ex[1] /= en;
+        }
+        double ey[3] = {o[1] * ex[2] - o[2] * ex[1], o[2] * ex[0] - o[0] * ex[2], o[0] * ex[1] - o[1] * ex[0]};
+        double X = pc[0] * ex[0] + pc[1] * ex[1] + pc[2] * ex[2];
+        double Y = pc[0] * ey[0] + pc[1] * ey[1] + pc[2] * ey[2];
+        double fx = floor((X + m->img_hw) / (2.0 * m->img_hw) * m->npix);
+        double fy = floor((Y + m->img_hw) / (2.0 * m->img_hw) * m->npix);
+        if (fx < 0.0 || fy < 0.0 || fx >= m->npix || fy >= m->npix) continue;
+        size_t r = (((size_t)ii * m->n_peel + i) * m->npix + (size_t)fy) * m->npix + (size_t)fx;
+        t->pimg_sum[r] += w;
+        t->pimg_sum2[r] += w * w;
+    }
+}
+
 /* Follow one source packet from emission to escape or kill (Sec. 2.2). */
 static void run_packet(const orc_model* m, uint32_t key1, int64_t p, int64_t np, int binning, tally* t)
 {
@@ -817,6 +933,8 @@ static void run_packet(const orc_model* m, uint32_t key1, int64_t p, int64_t np,
     int c[3];
     locate(m, x, d, c);
     log_event(m, p, EV_EMIT, c, k, -1);
+    const int peeling = binning && m->n_peel > 0;
+    if (peeling) peel(m, x, NULL, k, eps, 0, t);
     int64_t nev = 0;
     int in = inside(m, c);
     for (;;) {
@@ -847,10 +965,12 @@ static void run_packet(const orc_model* m, uint32_t key1, int64_t p, int64_t np,
             isotropic(u_mu2, u_phi2, d);
             t->n_absorb++;
             log_event(m, p, EV_ABSORB, c, k, -1);
+            if (peeling) peel(m, x, NULL, k, eps, 1, t);
         } else {
             double u_mu2 = draw(&rs), u_phi2 = draw(&rs);
             double mu = orc_hg_mu(m->g[k], u_mu2);
             double dn[3];
+            if (peeling) peel(m, x, d, k, eps, 1, t);
             orc_rotate(d, mu, 2.0 * ORC_PI * u_phi2, dn);
             d[0] = dn[0]; d[1] = dn[1]; d[2] = dn[2];
             t->n_scatter++;
@@ -916,6 +1036,8 @@ static int transport(orc_model* m, int64_t np, int64_t p_first, int64_t p_count,
     size_t nc = (size_t)m->ncell;
     size_t ns = (size_t)m->n_incl * m->nnu;
     size_t ni = (size_t)m->n_img * m->n_incl * m->npix * m->npix;
+    size_t nps = (size_t)m->n_peel * 2 * m->nnu;
+    size_t npi = (size_t)m->n_img * m->n_peel * m->npix * m->npix;
     tally* T = (tally*)calloc(nt, sizeof(tally));
     for (int i = 0; i < nt; ++i) {
         T[i].acc = (double*)calloc(nc, sizeof(double));
@@ -925,7 +1047,11 @@ static int transport(orc_model* m, int64_t np, int64_t p_first, int64_t p_count,
         T[i].sed_n = (int64_t*)calloc(ns, sizeof(int64_t));
         T[i].img_sum = (double*)calloc(ni ? ni : 1, sizeof(double));
         T[i].img_sum2 = (double*)calloc(ni ? ni : 1, sizeof(double));
-        if (!T[i].acc || !T[i].img_sum2) return fail(m, "out of memory");
+        T[i].psed_sum = (double*)calloc(nps ? nps : 1, sizeof(double));
+        T[i].psed_sum2 = (double*)calloc(nps ? nps : 1, sizeof(double));
+        T[i].pimg_sum = (double*)calloc(npi ? npi : 1, sizeof(double));
+        T[i].pimg_sum2 = (double*)calloc(npi ? npi : 1, sizeof(double));
+        if (!T[i].acc || !T[i].img_sum2 || !T[i].pimg_sum2) return fail(m, "out of memory");
     }
     /* event log */
     free(m->evlog); free(m->evcount);
@@ -970,6 +1096,14 @@ static int transport(orc_model* m, int64_t np, int64_t p_first, int64_t p_count,
             m->img_sum[q] += T[i].img_sum[q];
             m->img_sum2[q] += T[i].img_sum2[q];
         }
+        for (size_t q = 0; q < nps; ++q) {
+            m->psed_sum[q] += T[i].psed_sum[q];
+            m->psed_sum2[q] += T[i].psed_sum2[q];
+        }
+        for (size_t q = 0; q < npi; ++q) {
+            m->pimg_sum[q] += T[i].pimg_sum[q];
+            m->pimg_sum2[q] += T[i].pimg_sum2[q];
+        }
         st->n_cross_dust += T[i].n_cross_dust;
         st->n_cross_empty += T[i].n_cross_empty;
         st->n_scatter += T[i].n_scatter;
@@ -980,6 +1114,7 @@ static int transport(orc_model* m, int64_t np, int64_t p_first, int64_t p_count,
         st->e_killed += T[i].e_killed;
         free(T[i].acc); free(T[i].acc2); free(T[i].sed_sum); free(T[i].sed_sum2); free(T[i].sed_n);
         free(T[i].img_sum); free(T[i].img_sum2);
+        free(T[i].psed_sum); free(T[i].psed_sum2); free(T[i].pimg_sum); free(T[i].pimg_sum2);
     }
     free(T);
     st->seconds = t1 - t0;
@@ -1151,6 +1286,16 @@ static void clear_bins(orc_model* m)
         memset(m->img_sum, 0, ni * sizeof(double));
         memset(m->img_sum2, 0, ni * sizeof(double));
     }
+    size_t nps = (size_t)m->n_peel * 2 * m->nnu;
+    size_t npi = (size_t)m->n_img * m->n_peel * m->npix * m->npix;
+    if (nps) {
+        memset(m->psed_sum, 0, nps * sizeof(double));
+        memset(m->psed_sum2, 0, nps * sizeof(double));
+    }
+    if (npi) {
+        memset(m->pimg_sum, 0, npi * sizeof(double));
+        memset(m->pimg_sum2, 0, npi * sizeof(double));
+    }
 }
 
 int orc_iterate(orc_model* m, orc_iter_stats* st)
@@ -1246,6 +1391,28 @@ int orc_get_sed(const orc_model* m, double* sum, double* sum2, int64_t* count, s
     memcpy(sum, m->sed_sum, ns * sizeof(double));
     if (sum2) memcpy(sum2, m->sed_sum2, ns * sizeof(double));
     if (count) memcpy(count, m->sed_n, ns * sizeof(int64_t));
+    return 0;
+}
+
+int orc_get_peeled_sed(const orc_model* m, double* sum, double* sum2, size_t n)
+{
+    size_t ns = (size_t)m->n_peel * 2 * m->nnu;
+    if (n != ns) return -1;
+    if (ns) {
+        memcpy(sum, m->psed_sum, ns * sizeof(double));
+        if (sum2) memcpy(sum2, m->psed_sum2, ns * sizeof(double));
+    }
+    return 0;
+}
+
+int orc_get_peeled_images(const orc_model* m, double* sum, double* sum2, size_t n)
+{
+    size_t ni = (size_t)m->n_img * m->n_peel * m->npix * m->npix;
+    if (n != ni) return -1;
+    if (ni) {
+        memcpy(sum, m->pimg_sum, ni * sizeof(double));
+        if (sum2) memcpy(sum2, m->pimg_sum2, ni * sizeof(double));
+    }
     return 0;
 }
 

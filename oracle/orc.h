@@ -121,6 +121,13 @@ int orc_get_temperature(const orc_model* m, double* T, size_t n);
 int orc_get_absorbed_sum(const orc_model* m, double* acc, size_t n);  /* raw sum l*kappa */
 int orc_get_sed(const orc_model* m, double* sum, double* sum2, int64_t* count, size_t n);
 int orc_get_images(const orc_model* m, double* sum, double* sum2, size_t n);
+/* Peeling-off (Sec. 2.6.2) toward n unit directions, in the final pass (and in
+ * iterations with bin_every_iteration): SED [n][2][nnu] per steradian,
+ * component 0 direct source emission, 1 scattered or re-emitted; images
+ * [n_img][n][npix][npix] at the image bins of orc_set_observers. */
+int orc_set_peeloff(orc_model* m, const double* dirs, int n);
+int orc_get_peeled_sed(const orc_model* m, double* sum, double* sum2, size_t n);
+int orc_get_peeled_images(const orc_model* m, double* sum, double* sum2, size_t n);
 int orc_get_event_log(const orc_model* m, orc_event* ev, size_t cap, int32_t* counts, size_t n_counts);
 int orc_get_emission_rows(const orc_model* m, int32_t* row, double* w, size_t n);
 

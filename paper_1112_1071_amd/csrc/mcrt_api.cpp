@@ -44,6 +44,19 @@ hipError_t launch_fill_u8(int64_t n, unsigned char* p, unsigned char v, int bloc
 hipError_t launch_fill_f64(int64_t n, double* p, double v, int blocks, hipStream_t st);
 hipError_t launch_fill_u64(int64_t n, unsigned long long* p, unsigned long long v, int blocks,
                            hipStream_t st);
+size_t sweep_record_bytes(int fp32);
+template <typename R>
+hipError_t launch_sweep_emit(const TransportParams<R>& P, const SweepParams& S, uint64_t first,
+                             uint64_t count, int blocks, hipStream_t st);
+template <typename R>
+hipError_t launch_sweep(const TransportParams<R>& P, const SweepParams& S, int K, int blocks,
+                        size_t lds, hipStream_t st);
+template <typename R> int sweep_max_blocks_per_cu(int K, size_t lds);
+template <typename R>
+hipError_t launch_tile_sort(const SweepParams& S, const void* out, void* in, unsigned* counts,
+                            unsigned* tile_off, unsigned* item_off, unsigned* cursor, int blocks,
+                            hipStream_t st);
+hipError_t launch_zero_u32(unsigned* p, int n, hipStream_t st);
 }  // namespace mcrt
 
 using namespace mcrt;
@@ -135,6 +148,11 @@ struct mcrt_model {
     DBuf<unsigned long long> misc;  // pool, counters[C_COUNT], stats[8], sel[3], scratch
     DBuf<double> energies;
     DBuf<unsigned int> hist;
+    // tiled sweeps: packet records (two buffers), record tiles, tile counts and
+    // offsets, work-item offsets, scatter cursors, [item_next, out_count]
+    DBuf<unsigned char> sw_a, sw_b;
+    DBuf<unsigned> sw_tile, sw_counts, sw_tile_off, sw_item_off, sw_cursor, sw_ctr;
+    size_t lds_max = 65536 - 1024;  // dynamic LDS a transport kernel may take
     int64_t ev_packets = 0;
     int ev_cap = 0;
     // iteration state
@@ -401,7 +419,7 @@ mcrt_status prepare_pass(mcrt_model* m, int64_t np, bool graph_safe) {
     const size_t nc = (size_t)m->ncell;
     const bool f32 = m->cfg.precision == MCRT_FP32_TRANSPORT;
     unsigned long long* misc = m->misc.p;
-    const int layout = m->cfg.grid_layout == 1 ? 1 : 0;
+    const int layout = m->cfg.grid_layout == 1 && m->cfg.transport_mode == 0 ? 1 : 0;
     {
         mcrt_status r = ensure_transport_grid(m, layout);
         if (r != MCRT_OK) return r;
@@ -409,7 +427,8 @@ mcrt_status prepare_pass(mcrt_model* m, int64_t np, bool graph_safe) {
     if (f32) HIPCHK(m->rowpos32.ensure(nc));
     else HIPCHK(m->rowpos64.ensure(nc));
     const size_t nt = (size_t)m->nt_cells;
-    m->acc_copies = m->cfg.tally_copies == kMaxTallyCopies ? kMaxTallyCopies : 1;
+    m->acc_copies =
+        m->cfg.tally_copies == kMaxTallyCopies && m->cfg.transport_mode == 0 ? kMaxTallyCopies : 1;
     const size_t nacc = (m->acc_copies - 1) * m->acc_stride + nt;
     m->ev_packets = m->cfg.event_log_packets < np ? m->cfg.event_log_packets : np;
     m->ev_cap = m->cfg.event_log_cap > 0 ? m->cfg.event_log_cap : 256;
@@ -537,7 +556,80 @@ int persistent_blocks(const mcrt_model* m, int bpc, int64_t np, int threads) {
     return (int)(blocks < 1 ? 1 : blocks);
 }
 
-// Emission rows from T, zeroed tallies, then one persistent transport launch.
+// Tiled sweeps (transport_mode 1): emission writes every packet of a batch as
+// a record with its tile, then sort-by-tile and sweep alternate until no
+// record is left.  The host reads the record count after each sweep.
+constexpr int64_t kSweepBatch = 1ll << 25;  // packets in flight at once
+constexpr int64_t kMaxSweeps = 1ll << 24;    // every visit advances a packet; this is a backstop
+
+template <typename R>
+mcrt_status run_sweeps(mcrt_model* m, TransportParams<R>& P, int64_t np, int64_t* n_sweeps) {
+    hipStream_t s = m->stream;
+    constexpr bool f32 = std::is_same<R, float>::value;
+    SweepParams S{};
+    S.tz = m->cfg.tile_z == 4 || m->cfg.tile_z == 16 ? m->cfg.tile_z : 8;
+    S.ntx = (m->n[0] + 15) / 16;
+    S.nty = (m->n[1] + 15) / 16;
+    S.ntz = (m->n[2] + S.tz - 1) / S.tz;
+    S.ntiles = S.ntx * S.nty * S.ntz;
+    S.visit_events = m->cfg.visit_events > 0 ? m->cfg.visit_events : 256;
+    const int64_t batch = np < kSweepBatch ? np : kSweepBatch;
+    const size_t rb = sweep_record_bytes(f32 ? 1 : 0);
+    HIPCHK(m->sw_a.ensure((size_t)batch * rb));
+    HIPCHK(m->sw_b.ensure((size_t)batch * rb));
+    HIPCHK(m->sw_tile.ensure((size_t)batch));
+    const bool fresh_counts = m->sw_counts.n < (size_t)S.ntiles;
+    HIPCHK(m->sw_counts.ensure((size_t)S.ntiles));
+    HIPCHK(m->sw_tile_off.ensure((size_t)S.ntiles + 1));
+    HIPCHK(m->sw_item_off.ensure((size_t)S.ntiles + 1));
+    HIPCHK(m->sw_cursor.ensure((size_t)S.ntiles));
+    HIPCHK(m->sw_ctr.ensure(2));
+    if (fresh_counts) HIPCHK(launch_zero_u32(m->sw_counts.p, S.ntiles, s));
+    HIPCHK(launch_zero_u32(m->sw_ctr.p, 2, s));
+    S.item_next = m->sw_ctr.p;
+    S.out_count = m->sw_ctr.p + 1;
+    S.out_tile = m->sw_tile.p;
+    S.tile_off = m->sw_tile_off.p;
+    S.item_off = m->sw_item_off.p;
+    // LDS: tile density and tally (and sum of squares), then the staged tables
+    const size_t tcells = (size_t)16 * 16 * S.tz;
+    const size_t tile_lds = tcells * sizeof(R) * (P.acc2 ? 3 : 2);
+    const size_t tab_lds = (size_t)(m->src.size() + (kRows + m->src.size()) * m->ngroup) * sizeof(R);
+    if (tile_lds > m->lds_max) return fail(m, MCRT_E_UNSUPPORTED, "tile does not fit in LDS; use a smaller tile_z");
+    P.lds_tables = tile_lds + tab_lds <= m->lds_max ? 1 : 0;
+    const size_t lds = tile_lds + (P.lds_tables ? tab_lds : 0);
+    const int K = m->cfg.walk_batch == 1 || m->cfg.walk_batch == 2 ? m->cfg.walk_batch : 4;
+    const int bpc = m->cfg.blocks_per_cu > 0 ? m->cfg.blocks_per_cu : sweep_max_blocks_per_cu<R>(K, lds);
+    const int blocks = m->n_cu * bpc;
+    P.packet_base = 0;
+    int64_t sweeps = 0;
+    for (int64_t b0 = 0; b0 < np; b0 += batch) {
+        const int64_t cnt = np - b0 < batch ? np - b0 : batch;
+        S.out = m->sw_b.p;
+        const int64_t eb = (cnt + 255) / 256;
+        HIPCHK(launch_sweep_emit<R>(P, S, (uint64_t)b0, (uint64_t)cnt,
+                                    (int)(eb < (int64_t)m->n_cu * 8 ? eb : (int64_t)m->n_cu * 8), s));
+        for (;;) {
+            unsigned nout = 0;
+            HIPCHK(hipMemcpyAsync(&nout, S.out_count, sizeof nout, hipMemcpyDeviceToHost, s));
+            HIPCHK(hipStreamSynchronize(s));
+            if (nout == 0) break;
+            if (++sweeps > kMaxSweeps) return fail(m, MCRT_E_DEVICE, "tiled sweeps did not finish");
+            const int64_t sb = ((int64_t)nout + 255) / 256;
+            HIPCHK(launch_tile_sort<R>(S, m->sw_b.p, m->sw_a.p, m->sw_counts.p, m->sw_tile_off.p,
+                                       m->sw_item_off.p, m->sw_cursor.p,
+                                       (int)(sb < (int64_t)m->n_cu * 8 ? sb : (int64_t)m->n_cu * 8), s));
+            S.in = m->sw_a.p;
+            S.out = m->sw_b.p;
+            HIPCHK(launch_sweep<R>(P, S, K, blocks, lds, s));
+        }
+    }
+    *n_sweeps = sweeps;
+    return MCRT_OK;
+}
+
+// Emission rows from T, zeroed tallies, then one persistent transport launch
+// (or the tiled sweeps).
 mcrt_status run_transport(mcrt_model* m, int64_t np, uint32_t key1, int binning,
                           mcrt_iter_stats* st) {
     hipStream_t s = m->stream;
@@ -551,7 +643,20 @@ mcrt_status run_transport(mcrt_model* m, int64_t np, uint32_t key1, int binning,
     const int K = walk_batch_of(m);
     const int layout = m->t_layout;
     HIPCHK(hipEventRecord(m->ev[0], s));
-    if (f32) {
+    if (m->cfg.transport_mode == 1) {
+        int64_t sweeps = 0;
+        if (f32) {
+            TransportParams<float> P;
+            make_params(m, np, key1, binning, P);
+            r = run_sweeps<float>(m, P, np, &sweeps);
+        } else {
+            TransportParams<double> P;
+            make_params(m, np, key1, binning, P);
+            r = run_sweeps<double>(m, P, np, &sweeps);
+        }
+        if (r != MCRT_OK) return r;
+        st->n_sweeps = sweeps;
+    } else if (f32) {
         TransportParams<float> P;
         make_params(m, np, key1, binning, P);
         const size_t lds = transport_lds_bytes<float>(P);
@@ -724,6 +829,9 @@ mcrt_status mcrt_run_cfg_default(mcrt_run_cfg* c) {
     c->walk_batch = 4;
     c->grid_layout = 0;
     c->tally_copies = kMaxTallyCopies;
+    c->transport_mode = 0;
+    c->tile_z = 8;
+    c->visit_events = 256;
     return MCRT_OK;
 }
 
@@ -742,6 +850,13 @@ mcrt_status mcrt_create(mcrt_model** out, int hip_device) {
     }
     m->own_stream = true;
     hipDeviceGetAttribute(&m->n_cu, hipDeviceAttributeMultiprocessorCount, hip_device);
+    {
+        int lds = 0;
+        if (hipDeviceGetAttribute(&lds, hipDeviceAttributeMaxSharedMemoryPerBlock, hip_device) == hipSuccess &&
+            lds > 0)
+            m->lds_max = (size_t)lds < 65536 ? (size_t)lds : 65536;
+        m->lds_max -= 1024;  // static LDS of the kernels that take dynamic LDS
+    }
     for (int i = 0; i < 4; ++i) hipEventCreate(&m->ev[i]);
     mcrt_run_cfg_default(&m->cfg);
     *out = m;
@@ -769,6 +884,8 @@ void mcrt_destroy(mcrt_model* m) {
     m->sed_sum.release(); m->sed_sum2.release(); m->sed_n.release();
     m->img_sum.release(); m->img_sum2.release(); m->evlog.release(); m->evcount.release();
     m->misc.release(); m->energies.release(); m->hist.release();
+    m->sw_a.release(); m->sw_b.release(); m->sw_tile.release(); m->sw_counts.release();
+    m->sw_tile_off.release(); m->sw_item_off.release(); m->sw_cursor.release(); m->sw_ctr.release();
     if (m->own_stream && m->stream) hipStreamDestroy(m->stream);
     delete m;
 }
@@ -992,10 +1109,17 @@ mcrt_status mcrt_set_run(mcrt_model* m, const mcrt_run_cfg* c) {
     if (c->block_size > 256) return fail(m, MCRT_E_ARG, "block_size above 256 is not supported");
     if (c->defer_lanes < 0 || c->defer_lanes > 64) return fail(m, MCRT_E_ARG, "defer_lanes must be in [0,64]");
     if (c->blocks_per_cu < 0) return fail(m, MCRT_E_ARG, "blocks_per_cu must be >= 0");
+    if (c->transport_mode != 0 && c->transport_mode != 1)
+        return fail(m, MCRT_E_ARG, "transport_mode must be 0 or 1");
+    if (c->transport_mode == 1 && c->tile_z != 0 && c->tile_z != 4 && c->tile_z != 8 && c->tile_z != 16)
+        return fail(m, MCRT_E_ARG, "tile_z must be 4, 8 or 16");
+    if (c->visit_events < 0) return fail(m, MCRT_E_ARG, "visit_events must be >= 0");
     const bool reset = !m->have_run || c->t_init != m->cfg.t_init;
     m->cfg = *c;
     if (m->cfg.event_log_cap == 0) m->cfg.event_log_cap = 256;
     if (m->cfg.conv_noise_thres <= 0.0) m->cfg.conv_noise_thres = 0.002;
+    if (m->cfg.tile_z == 0) m->cfg.tile_z = 8;
+    if (m->cfg.visit_events == 0) m->cfg.visit_events = 256;
     m->have_run = true;
     if (reset) m->state_ready = false;
     return MCRT_OK;
@@ -1563,8 +1687,9 @@ mcrt_status mcrt_batch_run(mcrt_model* const* models, int n, const mcrt_batch_cf
 // Learned warm start: features of a model, and network -> starting T.
 namespace mcrt {
 namespace nn {
-hipError_t launch_features(int64_t nvox, const double* rho, double chi1_dx, const double* flux,
-                           float* x, hipStream_t st);
+hipError_t launch_features(int64_t nvox, int nx, int ny, const double* rho, double chi1_dx,
+                           const double* dep, const int* dcell, const double* dval, int nd, float* x,
+                           hipStream_t st);
 }  // namespace nn
 }  // namespace mcrt
 
@@ -1574,7 +1699,7 @@ mcrt_status mcrt_model_features(mcrt_model* m, float* d_x, size_t n) {
     if (!m || !d_x) return MCRT_E_ARG;
     if (!m->have_grid || !m->have_rho || !m->have_nu || !m->have_dust)
         return fail(m, MCRT_E_STATE, "set grid, density, frequencies and dust first");
-    if ((int64_t)n != 2 * m->ncell) return fail(m, MCRT_E_SIZE, "features need 2 values per cell");
+    if ((int64_t)n != 3 * m->ncell) return fail(m, MCRT_E_SIZE, "features need 3 values per cell");
     hipSetDevice(m->device);
     // extinction of the bin holding 1 micron
     const double nu1 = 2.99792458e10 / 1e-4;
@@ -1600,13 +1725,34 @@ mcrt_status mcrt_model_features(mcrt_model* m, float* d_x, size_t n) {
                 for (int i = lo_i[0]; i <= hi_i[0]; ++i)
                     flux[i + (size_t)m->n[0] * (j + (size_t)m->n[1] * kk)] += share;
     }
-    DBuf<double> dflux;
+    std::vector<int> dcell;
+    std::vector<double> dval;
+    for (size_t j = 0; j < flux.size(); ++j)
+        if (flux[j] > 0.0) {
+            dcell.push_back((int)(j % m->n[0]));
+            dcell.push_back((int)((j / m->n[0]) % m->n[1]));
+            dcell.push_back((int)(j / ((size_t)m->n[0] * m->n[1])));
+            dval.push_back(flux[j]);
+        }
+    const int nd = (int)dval.size();
+    DBuf<double> dflux, ddval;
+    DBuf<int> ddcell;
     HIPCHK(dflux.ensure(flux.size()));
+    HIPCHK(ddval.ensure(nd > 0 ? nd : 1));
+    HIPCHK(ddcell.ensure(nd > 0 ? 3 * nd : 3));
     HIPCHK(hipMemcpyAsync(dflux.p, flux.data(), flux.size() * sizeof(double), hipMemcpyHostToDevice,
                           m->stream));
-    HIPCHK(nn::launch_features(m->ncell, m->rho64.p, m->chi[k] * dx, dflux.p, d_x, m->stream));
+    if (nd > 0) {
+        HIPCHK(hipMemcpyAsync(ddval.p, dval.data(), nd * sizeof(double), hipMemcpyHostToDevice, m->stream));
+        HIPCHK(hipMemcpyAsync(ddcell.p, dcell.data(), 3 * nd * sizeof(int), hipMemcpyHostToDevice,
+                              m->stream));
+    }
+    HIPCHK(nn::launch_features(m->ncell, m->n[0], m->n[1], m->rho64.p, m->chi[k] * dx, dflux.p, ddcell.p,
+                               ddval.p, nd, d_x, m->stream));
     HIPCHK(hipStreamSynchronize(m->stream));
     dflux.release();
+    ddval.release();
+    ddcell.release();
     return MCRT_OK;
 }
 
@@ -1618,9 +1764,9 @@ mcrt_status mcrt_warm_start(mcrt_model* m, mcrt_surrogate* s, double* ms) {
     hipSetDevice(m->device);
     DBuf<float> x;
     DBuf<double> T;
-    HIPCHK(x.ensure((size_t)2 * m->ncell));
+    HIPCHK(x.ensure((size_t)3 * m->ncell));
     HIPCHK(T.ensure((size_t)m->ncell));
-    mcrt_status r = mcrt_model_features(m, x.p, (size_t)2 * m->ncell);
+    mcrt_status r = mcrt_model_features(m, x.p, (size_t)3 * m->ncell);
     if (r == MCRT_OK) {
         r = mcrt_surrogate_predict_T(s, x.p, 1, m->n[0], T.p);
         if (r != MCRT_OK) m->err = std::string("surrogate: ") + mcrt_surrogate_last_error(s);

@@ -89,6 +89,20 @@ struct TransportParams {
     double* energies;              // [2] escaped, killed
 };
 
+// Tiled sweeps: the tiling and the buffers of one sweep.
+struct SweepParams {
+    int tz;                     // tile extent in z (cells); 16 in x and y
+    int ntx, nty, ntz, ntiles;  // tiles per axis, total
+    int visit_events;           // interactions per visit before a packet yields
+    const void* in;             // records of this sweep, grouped by tile
+    const unsigned* tile_off;   // [ntiles+1] first record of each tile
+    const unsigned* item_off;   // [ntiles+1] first work item of each tile
+    unsigned* item_next;        // work items handed out
+    void* out;                  // records written in this sweep
+    unsigned* out_tile;         // tile of each written record
+    unsigned* out_count;
+};
+
 // Cell-update parameters (always FP64).
 struct CellParams {
     int64_t ncell;

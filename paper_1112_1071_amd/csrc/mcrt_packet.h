@@ -1,0 +1,515 @@
+// mcrt_packet.h -- device-side state and steps of one photon packet, shared
+// by the transport kernels (per-lane persistent walk and tiled sweeps):
+// random streams, emission (Sec. 2.1.1), flights and the grid walk with the
+// Lucy estimator (Sec. 2.2, Sec. 2.3 Eq. 2), scattering and absorption with
+// re-emission (Sec. 2.2), escape and binning (Sec. 2.6.1).
+#pragma once
+#include <math.h>
+
+#include "mcrt_internal.h"
+
+namespace mcrt {
+
+// ---------------------------------------------------------------------------
+// Philox4x32-10 (Salmon, Moraes, Dror & Shaw 2011): counter (call, 0, packet
+// low, packet high), key (seed, pass).  One call yields two uniforms, from the
+// 64-bit words (x0:x1) and (x2:x3).
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ void philox4x32_10(uint32_t& c0, uint32_t& c1, uint32_t& c2,
+                                              uint32_t& c3, uint32_t k0, uint32_t k1) {
+#pragma unroll
+    for (int r = 0; r < 10; ++r) {
+        if (r) {
+            k0 += 0x9E3779B9u;
+            k1 += 0xBB67AE85u;
+        }
+        const uint32_t lo0 = 0xD2511F53u * c0, hi0 = __umulhi(0xD2511F53u, c0);
+        const uint32_t lo1 = 0xCD9E8D57u * c2, hi1 = __umulhi(0xCD9E8D57u, c2);
+        const uint32_t n0 = hi1 ^ c1 ^ k0;
+        const uint32_t n2 = hi0 ^ c3 ^ k1;
+        c0 = n0;
+        c1 = lo1;
+        c2 = n2;
+        c3 = lo0;
+    }
+}
+
+// FP64: u = (floor(w / 2^12) + 1/2) 2^-52 of the 64-bit word w = hi:lo.
+// FP32: the same value truncated to 23 bits plus half a unit: (2 floor(hi/2^9) + 1) 2^-24.
+template <typename R> __device__ __forceinline__ R make_uniform(uint32_t hi, uint32_t lo);
+template <> __device__ __forceinline__ double make_uniform<double>(uint32_t hi, uint32_t lo) {
+    const uint64_t w = ((uint64_t)hi << 32) | lo;
+    return ((double)(w >> 12) + 0.5) * 0x1p-52;
+}
+template <> __device__ __forceinline__ float make_uniform<float>(uint32_t hi, uint32_t) {
+    return (float)(((hi >> 9) << 1) | 1u) * 0x1p-24f;
+}
+
+template <typename R> struct Stream {
+    uint32_t k0, k1, p0, p1;
+    uint32_t n;
+    uint32_t s0, s1;
+    __device__ __forceinline__ R next() {
+        if ((n & 1u) == 0u) {
+            uint32_t c0 = n >> 1, c1 = 0u, c2 = p0, c3 = p1;
+            philox4x32_10(c0, c1, c2, c3, k0, k1);
+            s0 = c2;
+            s1 = c3;
+            ++n;
+            return make_uniform<R>(c0, c1);
+        }
+        ++n;
+        return make_uniform<R>(s0, s1);
+    }
+};
+
+template <typename R> struct Const;
+template <> struct Const<double> {
+    static constexpr double two_pi = 6.283185307179586476925286766559;
+    static __device__ __forceinline__ double inf() { return __builtin_inf(); }
+};
+template <> struct Const<float> {
+    static constexpr float two_pi = 6.283185307179586476925286766559f;
+    static __device__ __forceinline__ float inf() { return __builtin_inff(); }
+};
+
+__device__ __forceinline__ void sin_cos(double x, double* s, double* c) { sincos(x, s, c); }
+__device__ __forceinline__ void sin_cos(float x, float* s, float* c) { sincosf(x, s, c); }
+
+// smallest k with u < cdf[k] (cdf[n-1] == 1), plain binary search
+template <typename R>
+__device__ __forceinline__ int cdf_search(const R* cdf, int n, R u) {
+    int lo = 0, hi = n - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi) >> 1;
+        if (u < cdf[mid]) hi = mid;
+        else lo = mid + 1;
+    }
+    return lo;
+}
+
+// number of entries <= u among the 16 entries of a group (64 B of FP32, 128 B of FP64)
+__device__ __forceinline__ int count_le16(const float* __restrict__ g, float u) {
+    const float4* v = reinterpret_cast<const float4*>(g);
+    int c = 0;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        const float4 q = v[i];
+        c += (q.x <= u) + (q.y <= u) + (q.z <= u) + (q.w <= u);
+    }
+    return c;
+}
+__device__ __forceinline__ int count_le16(const double* __restrict__ g, double u) {
+    const double2* v = reinterpret_cast<const double2*>(g);
+    int c = 0;
+#pragma unroll
+    for (int i = 0; i < 8; ++i) {
+        const double2 q = v[i];
+        c += (q.x <= u) + (q.y <= u);
+    }
+    return c;
+}
+
+// Same result as cdf_search on a padded row: the coarse index (every 16th
+// entry, usually in LDS) selects the group, one group read finishes it.
+template <typename R>
+__device__ __forceinline__ int cdf_search2(const R* row, const R* coarse, int ngroup, R u) {
+    int lo = 0, hi = ngroup - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi) >> 1;
+        if (u < coarse[mid]) hi = mid;
+        else lo = mid + 1;
+    }
+    return kGroup * lo + count_le16(row + kGroup * lo, u);
+}
+
+enum : int { ST_EMPTY = 0, ST_WALK = 1, ST_EVENT = 2, ST_ESC = 3, ST_DONE = 4 };
+
+template <typename R> struct Packet {
+    int c0, c1, c2;      // current cell
+    R d0, d1, d2;        // direction (unit vector)
+    R u0, u1, u2;        // flight origin in grid cell units (cell index + in-cell offset)
+    R tx, ty, tz;        // ray distance from the flight origin to the next wall per axis
+    R dtx, dty, dtz;     // ray distance between walls per axis: dx_a / |d_a|
+    R t;                 // ray distance walked in this flight
+    R tau, tau_acc;      // sampled optical depth and the part used so far
+    R chi, kap, wgt;     // opacity of the bin; packet weight (energy / eps0)
+    int k;               // frequency bin
+    uint32_t nev;        // interactions so far
+    uint32_t nlog;       // logged events so far
+    uint64_t id;
+    int st;
+};
+
+template <int BRICK, typename P>
+__device__ __forceinline__ int cell_index(const P& p, int c0, int c1, int c2) {
+    if (BRICK)
+        return ((((c2 >> 2) * p.bxy + (c1 >> 2) * p.bx + (c0 >> 2)) << 6) | ((c2 & 3) << 4) |
+                ((c1 & 3) << 2) | (c0 & 3));
+    return c0 + p.n[0] * (c1 + p.n[1] * c2);
+}
+
+template <int BRICK, typename P>
+__device__ __forceinline__ void cell_coords(const P& p, int j, int& c0, int& c1, int& c2) {
+    if (BRICK) {
+        const int b = j >> 6, o = j & 63;
+        const int bz = b / p.bxy, r = b - bz * p.bxy;
+        const int by = r / p.bx, bxx = r - by * p.bx;
+        c0 = (bxx << 2) | (o & 3);
+        c1 = (by << 2) | ((o >> 2) & 3);
+        c2 = (bz << 2) | (o >> 4);
+    } else {
+        const int nxy = p.n[0] * p.n[1];
+        c2 = j / nxy;
+        const int r = j - c2 * nxy;
+        c1 = r / p.n[0];
+        c0 = r - c1 * p.n[0];
+    }
+}
+
+// Start a flight from cell c with in-cell offset f: wall distances per axis,
+// then tau = -ln(u) (Sec. 2.2).
+template <typename R>
+__device__ __forceinline__ void begin_flight(Packet<R>& s, const TransportParams<R>& P,
+                                             Stream<R>& rs, R f0, R f1, R f2) {
+    const R INF = Const<R>::inf();
+    s.u0 = (R)s.c0 + f0;
+    s.u1 = (R)s.c1 + f1;
+    s.u2 = (R)s.c2 + f2;
+    s.dtx = P.dxr[0] / fabs(s.d0);
+    s.dty = P.dxr[1] / fabs(s.d1);
+    s.dtz = P.dxr[2] / fabs(s.d2);
+    s.tx = s.d0 == (R)0 ? INF : (s.d0 > (R)0 ? (R)1 - f0 : f0) * s.dtx;
+    s.ty = s.d1 == (R)0 ? INF : (s.d1 > (R)0 ? (R)1 - f1 : f1) * s.dty;
+    s.tz = s.d2 == (R)0 ? INF : (s.d2 > (R)0 ? (R)1 - f2 : f2) * s.dtz;
+    s.t = (R)0;
+    s.tau = -log(rs.next());
+    s.tau_acc = (R)0;
+}
+
+// in-cell offset of the point at ray distance t of the current flight
+template <typename R>
+__device__ __forceinline__ void offsets_at(const Packet<R>& s, const TransportParams<R>& P, R t,
+                                           R& f0, R& f1, R& f2) {
+    f0 = fmin((R)1, fmax((R)0, s.u0 + s.d0 * P.inv_dx[0] * t - (R)s.c0));
+    f1 = fmin((R)1, fmax((R)0, s.u1 + s.d1 * P.inv_dx[1] * t - (R)s.c1));
+    f2 = fmin((R)1, fmax((R)0, s.u2 + s.d2 * P.inv_dx[2] * t - (R)s.c2));
+}
+
+template <typename R>
+__device__ __forceinline__ void isotropic(Packet<R>& s, R u_mu, R u_phi) {
+    const R mu = (R)2 * u_mu - (R)1;
+    const R phi = Const<R>::two_pi * u_phi;
+    const R st = sqrt(fmax((R)0, (R)1 - mu * mu));
+    R sp, cp;
+    sin_cos(phi, &sp, &cp);
+    s.d0 = st * cp;
+    s.d1 = st * sp;
+    s.d2 = mu;
+}
+
+// Henyey-Greenstein: inverse cumulative distribution of cos(theta)
+template <typename R> __device__ __forceinline__ R hg_mu(R g, R u) {
+    R mu;
+    if (fabs(g) < (R)1e-6) {
+        mu = (R)2 * u - (R)1;
+    } else {
+        const R f = ((R)1 - g * g) / ((R)1 - g + (R)2 * g * u);
+        mu = ((R)1 + g * g - f * f) / ((R)2 * g);
+    }
+    return fmin((R)1, fmax((R)-1, mu));
+}
+
+// new direction at angle acos(mu) from d, azimuth phi about d; renormalised
+template <typename R> __device__ __forceinline__ void rotate(Packet<R>& s, R mu, R phi) {
+    const R st = sqrt(fmax((R)0, (R)1 - mu * mu));
+    R sp, cp;
+    sin_cos(phi, &sp, &cp);
+    R o0, o1, o2;
+    if (fabs(s.d2) > (R)1 - (R)1e-10) {
+        const R sgn = s.d2 > (R)0 ? (R)1 : (R)-1;
+        o0 = st * cp;
+        o1 = st * sp;
+        o2 = sgn * mu;
+    } else {
+        const R q = sqrt((R)1 - s.d2 * s.d2);
+        o0 = st * (s.d0 * s.d2 * cp - s.d1 * sp) / q + s.d0 * mu;
+        o1 = st * (s.d1 * s.d2 * cp + s.d0 * sp) / q + s.d1 * mu;
+        o2 = -st * cp * q + s.d2 * mu;
+    }
+    const R nrm = sqrt(o0 * o0 + o1 * o1 + o2 * o2);
+    s.d0 = o0 / nrm;
+    s.d1 = o1 / nrm;
+    s.d2 = o2 / nrm;
+}
+
+template <typename R>
+__device__ __forceinline__ void log_event(Packet<R>& s, const TransportParams<R>& P, int type,
+                                          int incl) {
+    if ((int64_t)s.id >= P.ev_packets) return;
+    const uint32_t i = s.nlog++;
+    if (i < (uint32_t)P.ev_cap) {
+        mcrt_event* e = P.evlog + (size_t)s.id * P.ev_cap + i;
+        e->packet = (int64_t)s.id;
+        e->index = (int32_t)i;
+        e->type = type;
+        e->cell[0] = s.c0;
+        e->cell[1] = s.c1;
+        e->cell[2] = s.c2;
+        e->nu = s.k;
+        e->incl = incl;
+        e->reserved = 0;
+    }
+    P.evcount[s.id] = (int32_t)(i + 1);
+}
+
+// Tables the event code searches: from LDS when they were staged there.
+template <typename R> struct Tables {
+    const R* lcdf;
+    const R* ecoarse;
+    const R* scoarse;
+};
+
+template <typename R>
+__device__ __forceinline__ void emit(Packet<R>& s, Stream<R>& rs, const TransportParams<R>& P,
+                                     const Tables<R>& tb, uint64_t id) {
+    s.id = id;
+    const uint64_t gid = P.packet_base + id;
+    rs.p0 = (uint32_t)gid;
+    rs.p1 = (uint32_t)(gid >> 32);
+    rs.n = 0;
+    const R u_src = rs.next(), u_nu = rs.next(), u_mu = rs.next(), u_phi = rs.next();
+    int src;
+    if (P.sampling == 0) {
+        src = cdf_search(tb.lcdf, P.nsrc, u_src);
+        s.wgt = (R)1;
+    } else {
+        src = (int)(gid % (uint64_t)P.nsrc);
+        s.wgt = (R)P.sweight[src];
+    }
+    s.k = cdf_search2(P.scdf + (size_t)src * P.npad, tb.scoarse + (size_t)src * P.ngroup, P.ngroup,
+                      u_nu);
+    isotropic(s, u_mu, u_phi);
+    // start cell: floor of the position in cell units; a position exactly on a
+    // wall belongs to the lower cell when the direction is negative on that axis
+    const double* x = P.spos + 3 * src;
+    R f[3];
+    int c[3];
+    const R dd[3] = {s.d0, s.d1, s.d2};
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        const double fp = (x[a] - P.lo[a]) / P.dx[a];
+        const double fl = floor(fp);
+        c[a] = (int)fl;
+        f[a] = (R)(fp - fl);
+        if (fp == fl && dd[a] < (R)0) {
+            c[a] -= 1;
+            f[a] = (R)1;
+        }
+    }
+    s.c0 = c[0];
+    s.c1 = c[1];
+    s.c2 = c[2];
+    s.chi = P.chi[s.k];
+    s.kap = P.kap[s.k];
+    s.nev = 0;
+    s.nlog = 0;
+    log_event(s, P, MCRT_EV_EMIT, -1);
+    begin_flight(s, P, rs, f[0], f[1], f[2]);
+    const bool inside = (unsigned)s.c0 < (unsigned)P.n[0] && (unsigned)s.c1 < (unsigned)P.n[1] &&
+                        (unsigned)s.c2 < (unsigned)P.n[2];
+    s.st = inside ? ST_WALK : ST_ESC;
+}
+
+// K segments of the grid walk: step K walls ahead, gather K densities at
+// once, then consume the segments until the optical depth is used up.
+// Grid fields the walk reads, held in registers by the batched kernel (whose
+// lanes may belong to different models) instead of re-read from memory.
+template <typename R> struct WalkGrid {
+    int n[3];
+    int bx, bxy;
+    const R* rho;
+    double* acc2;
+};
+
+template <typename R, int K, int BRICK, typename G>
+__device__ __forceinline__ void walk(Packet<R>& s, const G& P, double* acc, uint32_t* cnt) {
+    int jj[K];
+    R ll[K], ts[K];
+    int nseg = 0;
+    bool esc = false;
+    const int j0 = cell_index<BRICK>(P, s.c0, s.c1, s.c2);
+    int jc = j0;
+#pragma unroll
+    for (int i = 0; i < K; ++i) {
+        jj[i] = j0;
+        ll[i] = (R)0;
+        ts[i] = s.t;
+    }
+#pragma unroll
+    for (int i = 0; i < K; ++i) {
+        if (!esc) {
+            // nearest wall; ties go to the lowest axis
+            const bool ax1 = s.ty < s.tx;
+            R tm = ax1 ? s.ty : s.tx;
+            const bool ax2 = s.tz < tm;
+            tm = ax2 ? s.tz : tm;
+            const bool ax0 = !ax1 && !ax2;
+            const bool by = ax1 && !ax2;
+            jj[i] = jc;
+            ts[i] = s.t;
+            ll[i] = fmax(tm - s.t, (R)0);
+            nseg = i + 1;
+            s.t = fmax(tm, s.t);
+            const int n0 = s.c0 + (ax0 ? (s.d0 > (R)0 ? 1 : -1) : 0);
+            const int n1 = s.c1 + (by ? (s.d1 > (R)0 ? 1 : -1) : 0);
+            const int n2 = s.c2 + (ax2 ? (s.d2 > (R)0 ? 1 : -1) : 0);
+            const bool out = (unsigned)n0 >= (unsigned)P.n[0] || (unsigned)n1 >= (unsigned)P.n[1] ||
+                             (unsigned)n2 >= (unsigned)P.n[2];
+            if (out) {
+                esc = true;
+            } else {
+                s.c0 = n0;
+                s.c1 = n1;
+                s.c2 = n2;
+                s.tx += ax0 ? s.dtx : (R)0;
+                s.ty += by ? s.dty : (R)0;
+                s.tz += ax2 ? s.dtz : (R)0;
+                jc = cell_index<BRICK>(P, n0, n1, n2);
+            }
+        }
+    }
+    R rr[K];
+#pragma unroll
+    for (int i = 0; i < K; ++i) rr[i] = P.rho[jj[i]];
+    bool hit = false;
+    int jhit = j0;
+    R thit = (R)0;
+#pragma unroll
+    for (int i = 0; i < K; ++i) {
+        if (i < nseg && !hit) {
+            const R rho = rr[i];
+            if (rho > (R)0) {
+                ++cnt[C_CROSS_DUST];
+                const R rc = rho * s.chi;
+                R l = ll[i];
+                const R dtau = rc * l;
+                if (s.tau_acc + dtau >= s.tau) {
+                    l = (s.tau - s.tau_acc) / rc;
+                    hit = true;
+                    jhit = jj[i];
+                    thit = ts[i] + l;
+                } else {
+                    s.tau_acc += dtau;
+                }
+                const R w = s.wgt * l * s.kap;
+                unsafeAtomicAdd(acc + jj[i], (double)w);
+                if (P.acc2) unsafeAtomicAdd(P.acc2 + jj[i], (double)w * (double)w);
+            } else {
+                ++cnt[C_CROSS_EMPTY];
+            }
+        }
+    }
+    if (hit) {
+        cell_coords<BRICK>(P, jhit, s.c0, s.c1, s.c2);
+        s.t = thit;
+        s.st = ST_EVENT;
+    } else if (esc) {
+        s.st = ST_ESC;
+    }
+}
+
+// Scatter (u <= albedo) or absorb and re-emit (Sec. 2.2), then a new flight.
+template <typename R>
+__device__ __forceinline__ void interact(Packet<R>& s, Stream<R>& rs, const TransportParams<R>& P,
+                                         const Tables<R>& tb, uint32_t* cnt, double& e_killed) {
+    s.nev += 1;
+    if ((int64_t)s.nev > P.max_events) {
+        ++cnt[C_KILLED];
+        e_killed += P.eps0 * (double)s.wgt;
+        log_event(s, P, MCRT_EV_KILLED, -1);
+        s.st = ST_EMPTY;
+        return;
+    }
+    R f0, f1, f2;
+    offsets_at(s, P, s.t, f0, f1, f2);
+    const R u_int = rs.next();
+    if (u_int > P.alb[s.k]) {
+        const R u_mix = rs.next(), u_nu = rs.next(), u_mu = rs.next(), u_phi = rs.next();
+        const int j = s.c0 + P.n[0] * (s.c1 + P.n[1] * s.c2);
+        const R p = P.rowpos[j];
+        int m = (int)p;
+        m = m > kRows - 2 ? kRows - 2 : m;
+        const R w = p - (R)m;
+        const int row = m + (u_mix < w ? 1 : 0);
+        s.k = cdf_search2(P.ecdf + (size_t)row * P.npad, tb.ecoarse + row * P.ngroup, P.ngroup,
+                          u_nu);
+        isotropic(s, u_mu, u_phi);
+        ++cnt[C_ABSORB];
+        log_event(s, P, MCRT_EV_ABSORB, -1);
+        s.chi = P.chi[s.k];
+        s.kap = P.kap[s.k];
+    } else {
+        const R u_mu = rs.next(), u_phi = rs.next();
+        const R mu = hg_mu(P.g[s.k], u_mu);
+        rotate(s, mu, Const<R>::two_pi * u_phi);
+        ++cnt[C_SCATTER];
+        log_event(s, P, MCRT_EV_SCATTER, -1);
+    }
+    begin_flight(s, P, rs, f0, f1, f2);
+    s.st = ST_WALK;
+}
+
+template <typename R>
+__device__ __forceinline__ void escape(Packet<R>& s, const TransportParams<R>& P, uint32_t* cnt,
+                                       double& e_escaped) {
+    const R fz = fmin((R)P.n_incl, fmax((R)0, fabs(s.d2) * (R)P.n_incl));  // NaN -> 0
+    int incl = (int)fz;
+    incl = incl >= P.n_incl ? P.n_incl - 1 : incl;
+    const double eps = P.eps0 * (double)s.wgt;
+    ++cnt[C_ESCAPE];
+    e_escaped += eps;
+    if (P.binning) {
+        const size_t q = (size_t)incl * P.nnu + s.k;
+        unsafeAtomicAdd(P.sed_sum + q, eps);
+        unsafeAtomicAdd(P.sed_sum2 + q, eps * eps);
+        atomicAdd(P.sed_n + q, 1ull);
+        const int ii = P.n_img > 0 ? P.img_of_bin[s.k] : -1;
+        if (ii >= 0) {
+            // escape point (on the grid boundary), projected on the plane
+            // perpendicular to d
+            R f0, f1, f2;
+            offsets_at(s, P, s.t, f0, f1, f2);
+            const double px = ((double)s.c0 + (double)f0 - 0.5 * P.n[0]) * P.dx[0];
+            const double py = ((double)s.c1 + (double)f1 - 0.5 * P.n[1]) * P.dx[1];
+            const double pz = ((double)s.c2 + (double)f2 - 0.5 * P.n[2]) * P.dx[2];
+            const double d0 = s.d0, d1 = s.d1, d2 = s.d2;
+            double ex0 = -d1, ex1 = d0;
+            const double en = sqrt(ex0 * ex0 + ex1 * ex1);
+            if (en < 1e-12) { ex0 = 1.0; ex1 = 0.0; }
+            else { ex0 /= en; ex1 /= en; }
+            // e_y = d x e_x with e_x = (ex0, ex1, 0)
+            const double ey0 = -d2 * ex1, ey1 = d2 * ex0, ey2 = d0 * ex1 - d1 * ex0;
+            const double X = px * ex0 + py * ex1;
+            const double Y = px * ey0 + py * ey1 + pz * ey2;
+            const double fx = floor((X + P.img_hw) / (2.0 * P.img_hw) * P.npix);
+            const double fy = floor((Y + P.img_hw) / (2.0 * P.img_hw) * P.npix);
+            if (fx >= 0.0 && fy >= 0.0 && fx < P.npix && fy < P.npix) {
+                const size_t q2 = (((size_t)ii * P.n_incl + incl) * P.npix + (size_t)fy) * P.npix +
+                                  (size_t)fx;
+                unsafeAtomicAdd(P.img_sum + q2, eps);
+                unsafeAtomicAdd(P.img_sum2 + q2, eps * eps);
+            }
+        }
+    }
+    log_event(s, P, MCRT_EV_ESCAPE, incl);
+    s.st = ST_EMPTY;
+}
+
+__device__ __forceinline__ uint64_t shfl_u64(uint64_t v, int src) {
+    const uint32_t lo = __shfl((int)(uint32_t)v, src);
+    const uint32_t hi = __shfl((int)(uint32_t)(v >> 32), src);
+    return ((uint64_t)hi << 32) | lo;
+}
+
+}  // namespace mcrt

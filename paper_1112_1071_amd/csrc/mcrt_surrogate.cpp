@@ -2,7 +2,8 @@
 // convolutional encoder-decoder (channels C0, 2C0, 4C0, 8C0; two 3x3x3
 // convolutions per level; stride-2 2x2x2 down and transposed up
 // convolutions; skip concatenation; 1x1x1 head) that maps per-cell features
-// (cell optical depth, source luminosity deposit) to log10 T.  Weights are
+// (cell optical depth, source luminosity deposit, the deposit spread by
+// 1/r^2) to log10 T.  Weights are
 // FP32 masters updated by Adam with BF16 copies for the matrix cores.
 #include <hip/hip_runtime.h>
 #include <math.h>
@@ -69,8 +70,9 @@ namespace {
 
 constexpr float kSlope = 0.1f;  // LeakyReLU
 // input scaling: channel 0 (log10 cell optical depth, -6..2) -> (x + 2) / 2,
-// channel 1 (log10 source flux, -30 outside source cells) -> (x + 30) / 10
-constexpr float kNorm[4] = {2.f, 0.5f, 30.f, 0.1f};
+// channel 1 (log10 deposit field, -30 outside source cells) -> (x + 30) / 10,
+// channel 2 (log10 spread deposit field, about 0..10) -> (x - 4) / 3
+constexpr float kNorm[6] = {2.f, 0.5f, 30.f, 0.1f, -4.f, 1.f / 3.f};
 
 struct Layer {
     int mode;

@@ -243,17 +243,18 @@ __global__ void k_act_back(int64_t n, int C, const float* __restrict__ dy,
     for (int c = threadIdx.x; c < C; c += blockDim.x) atomicAdd(dbias + c, sb[c]);
 }
 
-// Input layer: the two FP32 features of each voxel [N][V][2], shifted and
+// Input layer: the NF = 3 FP32 features of each voxel [N][V][3], shifted and
 // scaled to O(1), as BF16 channels-last with 16 channels (zero padded).
 __global__ void k_pack_input(int64_t nvox, const float* __restrict__ x, uint16_t* __restrict__ out,
-                             float sh0, float sc0, float sh1, float sc1) {
+                             float sh0, float sc0, float sh1, float sc1, float sh2, float sc2) {
     for (int64_t v = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; v < nvox;
          v += (int64_t)gridDim.x * blockDim.x) {
         uint16_t* o = out + v * 16;
-        o[0] = f2bf((x[2 * v] + sh0) * sc0);
-        o[1] = f2bf((x[2 * v + 1] + sh1) * sc1);
+        o[0] = f2bf((x[3 * v] + sh0) * sc0);
+        o[1] = f2bf((x[3 * v + 1] + sh1) * sc1);
+        o[2] = f2bf((x[3 * v + 2] + sh2) * sc2);
 #pragma unroll
-        for (int c = 2; c < 16; ++c) o[c] = 0;
+        for (int c = 3; c < 16; ++c) o[c] = 0;
     }
 }
 
@@ -354,17 +355,30 @@ __global__ void k_weights_bf16(int64_t n, const float* __restrict__ p, int taps,
     }
 }
 
-// Features of the warm start per cell: x[v][0] = log10 of the cell's optical
-// depth across one cell width at 1 micron (floored at 1e-6), x[v][1] =
-// log10(F + 1e-30) with F the luminosity of the sources in the cell over the
-// area 4 pi dx^2, in erg s^-1 cm^-2.
-__global__ void k_features(int64_t nvox, const double* __restrict__ rho, double chi1_dx,
-                           const double* __restrict__ flux, float* __restrict__ x) {
+// Features of the warm start per cell v (cell coordinates i, j, k):
+//   x[v][0] = log10 max(rho chi(1 um) dx, 1e-6)  (optical depth of one cell width)
+//   x[v][1] = log10(D_v + 1e-30), D the deposit field: luminosity of the
+//             sources in the cell / (4 pi dx^2), erg s^-1 cm^-2
+//   x[v][2] = log10(sum_c D_c dx^2 / max(r_vc^2, dx^2/4) + 1e-30): the deposit
+//             field spread by the free-space kernel 1/r^2 (r between cell
+//             centres), i.e. the unattenuated flux of the deposited luminosity.
+// The nd deposit cells are listed as (i, j, k, D).
+__global__ void k_features(int64_t nvox, int nx, int ny, const double* __restrict__ rho,
+                           double chi1_dx, const double* __restrict__ dep, const int* __restrict__ dcell,
+                           const double* __restrict__ dval, int nd, float* __restrict__ x) {
     for (int64_t v = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; v < nvox;
          v += (int64_t)gridDim.x * blockDim.x) {
         const double tau = rho[v] * chi1_dx;
-        x[2 * v] = (float)log10(tau > 1e-6 ? tau : 1e-6);
-        x[2 * v + 1] = (float)log10(flux[v] + 1e-30);
+        x[3 * v] = (float)log10(tau > 1e-6 ? tau : 1e-6);
+        x[3 * v + 1] = (float)log10(dep[v] + 1e-30);
+        const int i = (int)(v % nx), j = (int)((v / nx) % ny), k = (int)(v / ((int64_t)nx * ny));
+        double f = 0.0;
+        for (int q = 0; q < nd; ++q) {
+            const double a = i - dcell[3 * q], b = j - dcell[3 * q + 1], c = k - dcell[3 * q + 2];
+            const double r2 = a * a + b * b + c * c;
+            f += dval[q] / (r2 > 0.25 ? r2 : 0.25);
+        }
+        x[3 * v + 2] = (float)log10(f + 1e-30);
     }
 }
 
@@ -419,7 +433,7 @@ hipError_t launch_act_back(int64_t n, int C, const float* dy, const uint16_t* y,
 hipError_t launch_pack_input(int64_t nvox, const float* x, uint16_t* out, const float* norm,
                              hipStream_t st) {
     hipLaunchKernelGGL(k_pack_input, dim3(blocks_for(nvox)), dim3(256), 0, st, nvox, x, out, norm[0],
-                       norm[1], norm[2], norm[3]);
+                       norm[1], norm[2], norm[3], norm[4], norm[5]);
     return hipGetLastError();
 }
 hipError_t launch_head(int C, int64_t nvox, const uint16_t* x, const float* w, const float* b, float* y,
@@ -462,10 +476,11 @@ hipError_t launch_weights_bf16(int64_t n, const float* p, int taps, int Cout, in
                        conv3, w16, wt16);
     return hipGetLastError();
 }
-hipError_t launch_features(int64_t nvox, const double* rho, double chi1_dx, const double* flux,
-                           float* x, hipStream_t st) {
-    hipLaunchKernelGGL(k_features, dim3(blocks_for(nvox)), dim3(256), 0, st, nvox, rho, chi1_dx, flux,
-                       x);
+hipError_t launch_features(int64_t nvox, int nx, int ny, const double* rho, double chi1_dx,
+                           const double* dep, const int* dcell, const double* dval, int nd, float* x,
+                           hipStream_t st) {
+    hipLaunchKernelGGL(k_features, dim3(blocks_for(nvox)), dim3(256), 0, st, nvox, nx, ny, rho, chi1_dx,
+                       dep, dcell, dval, nd, x);
     return hipGetLastError();
 }
 hipError_t launch_exp10(int64_t n, const float* y, double* T, hipStream_t st) {

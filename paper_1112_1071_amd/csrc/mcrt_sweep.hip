@@ -1,0 +1,549 @@
+// mcrt_sweep.hip -- tiled transport: packets grouped by grid tile, each tile
+// walked with its density and absorption tally staged in LDS.
+//
+// The grid is cut into tiles of 16 x 16 x tz cells.  A pass runs in sweeps.
+// Between sweeps every packet in flight is a record in global memory (its
+// full state: cell, direction, flight origin, wall distances, ray distance,
+// sampled and used optical depth, weight, bin, event counts and the position
+// in its random stream), and the records are counting-sorted by the tile the
+// packet is in.  In a sweep, a workgroup takes a work item (up to kItem
+// records of one tile), loads the tile's density into LDS and clears an LDS
+// tally, and its lanes walk those packets (Sec. 2.2; Lucy's path-length
+// estimator, Sec. 2.3 Eq. 2, added into the LDS tally) until each leaves the
+// tile, escapes the grid, is killed, or has had kVisitEvents interactions in
+// this visit; a packet that leaves (or yields) is written out with the tile it
+// is now in.  The workgroup then adds its LDS tally into the FP64 global
+// tally, one atomic per touched cell of the tile.  Sweeps repeat until no
+// packet is left.
+//
+// Every packet follows the same arithmetic, random numbers and decisions as
+// in the per-lane persistent kernel (the walk is the same segment by segment,
+// only cut at tile walls); tallies differ only in summation order (and, in
+// the FP32 form, in summing a visit's contributions in FP32 before the FP64
+// flush).
+#include <math.h>
+
+#include "mcrt_internal.h"
+#include "mcrt_packet.h"
+
+namespace mcrt {
+
+constexpr int kTX = 16, kTY = 16;    // tile extent in x and y (cells)
+constexpr unsigned kItem = 2048;     // records per work item
+enum : int { ST_MOVE = 5, ST_YIELD = 6 };
+
+// State of a packet between visits (the Packet fields that are not
+// recomputed from the direction, the bin and the stream position).
+template <typename R> struct __attribute__((aligned(16))) PacketRec {
+    int c0, c1, c2, k;
+    R d0, d1, d2, u0, u1, u2, tx, ty, tz, t, tau, tau_acc, wgt;
+    uint32_t nev, nlog, n, st;
+    uint64_t id;
+};
+
+__device__ __forceinline__ int tile_of(const SweepParams& S, int c0, int c1, int c2) {
+    return (c0 / kTX) + S.ntx * ((c1 / kTY) + S.nty * (c2 / S.tz));
+}
+
+template <typename R>
+__device__ __forceinline__ void store_rec(PacketRec<R>* r, const Packet<R>& s, const Stream<R>& rs,
+                                          int st) {
+    PacketRec<R> q;
+    q.c0 = s.c0;
+    q.c1 = s.c1;
+    q.c2 = s.c2;
+    q.k = s.k;
+    q.d0 = s.d0;
+    q.d1 = s.d1;
+    q.d2 = s.d2;
+    q.u0 = s.u0;
+    q.u1 = s.u1;
+    q.u2 = s.u2;
+    q.tx = s.tx;
+    q.ty = s.ty;
+    q.tz = s.tz;
+    q.t = s.t;
+    q.tau = s.tau;
+    q.tau_acc = s.tau_acc;
+    q.wgt = s.wgt;
+    q.nev = s.nev;
+    q.nlog = s.nlog;
+    q.n = rs.n;
+    q.st = (uint32_t)st;
+    q.id = s.id;
+    *r = q;
+}
+
+template <typename R>
+__device__ __forceinline__ void load_rec(Packet<R>& s, Stream<R>& rs, const TransportParams<R>& P,
+                                         const PacketRec<R>* r) {
+    const PacketRec<R> q = *r;
+    s.c0 = q.c0;
+    s.c1 = q.c1;
+    s.c2 = q.c2;
+    s.k = q.k;
+    s.d0 = q.d0;
+    s.d1 = q.d1;
+    s.d2 = q.d2;
+    s.u0 = q.u0;
+    s.u1 = q.u1;
+    s.u2 = q.u2;
+    s.tx = q.tx;
+    s.ty = q.ty;
+    s.tz = q.tz;
+    s.t = q.t;
+    s.tau = q.tau;
+    s.tau_acc = q.tau_acc;
+    s.wgt = q.wgt;
+    s.nev = q.nev;
+    s.nlog = q.nlog;
+    s.id = q.id;
+    s.st = (int)q.st;
+    // the same quotients begin_flight computed for this flight
+    s.dtx = P.dxr[0] / fabs(s.d0);
+    s.dty = P.dxr[1] / fabs(s.d1);
+    s.dtz = P.dxr[2] / fabs(s.d2);
+    s.chi = P.chi[s.k];
+    s.kap = P.kap[s.k];
+    const uint64_t gid = P.packet_base + s.id;
+    rs.p0 = (uint32_t)gid;
+    rs.p1 = (uint32_t)(gid >> 32);
+    rs.n = q.n;
+    if (rs.n & 1u) {  // the second uniform of the last Philox call is still unused
+        uint32_t c0 = rs.n >> 1, c1 = 0u, c2 = rs.p0, c3 = rs.p1;
+        philox4x32_10(c0, c1, c2, c3, rs.k0, rs.k1);
+        rs.s0 = c2;
+        rs.s1 = c3;
+    }
+}
+
+// Up to K segments of the walk inside the tile with origin (o0, o1, o2):
+// segment by segment the arithmetic of walk(), with density and tally in LDS.
+template <typename R, int K>
+__device__ __forceinline__ void walk_tile(Packet<R>& s, const TransportParams<R>& P, int o0, int o1,
+                                          int o2, int tz, const R* __restrict__ rho_t,
+                                          R* __restrict__ acc_t, R* __restrict__ acc2_t,
+                                          uint32_t* cnt) {
+#pragma unroll
+    for (int i = 0; i < K; ++i) {
+        const bool ax1 = s.ty < s.tx;
+        R tm = ax1 ? s.ty : s.tx;
+        const bool ax2 = s.tz < tm;
+        tm = ax2 ? s.tz : tm;
+        const bool ax0 = !ax1 && !ax2;
+        const bool by = ax1 && !ax2;
+        const R ts = s.t;
+        R l = fmax(tm - s.t, (R)0);
+        const int jl = (s.c0 - o0) + kTX * ((s.c1 - o1) + kTY * (s.c2 - o2));
+        const R rho = rho_t[jl];
+        if (rho > (R)0) {
+            ++cnt[C_CROSS_DUST];
+            const R rc = rho * s.chi;
+            const R dtau = rc * l;
+            const bool hit = s.tau_acc + dtau >= s.tau;
+            if (hit) l = (s.tau - s.tau_acc) / rc;
+            else s.tau_acc += dtau;
+            const R w = s.wgt * l * s.kap;
+            atomicAdd(acc_t + jl, w);
+            if (acc2_t) atomicAdd(acc2_t + jl, w * w);
+            if (hit) {
+                s.t = ts + l;
+                s.st = ST_EVENT;
+                return;
+            }
+        } else {
+            ++cnt[C_CROSS_EMPTY];
+        }
+        s.t = fmax(tm, s.t);
+        const int n0 = s.c0 + (ax0 ? (s.d0 > (R)0 ? 1 : -1) : 0);
+        const int n1 = s.c1 + (by ? (s.d1 > (R)0 ? 1 : -1) : 0);
+        const int n2 = s.c2 + (ax2 ? (s.d2 > (R)0 ? 1 : -1) : 0);
+        if ((unsigned)n0 >= (unsigned)P.n[0] || (unsigned)n1 >= (unsigned)P.n[1] ||
+            (unsigned)n2 >= (unsigned)P.n[2]) {
+            s.st = ST_ESC;
+            return;
+        }
+        s.c0 = n0;
+        s.c1 = n1;
+        s.c2 = n2;
+        s.tx += ax0 ? s.dtx : (R)0;
+        s.ty += by ? s.dty : (R)0;
+        s.tz += ax2 ? s.dtz : (R)0;
+        if ((unsigned)(n0 - o0) >= (unsigned)kTX || (unsigned)(n1 - o1) >= (unsigned)kTY ||
+            (unsigned)(n2 - o2) >= (unsigned)tz) {
+            s.st = ST_MOVE;
+            return;
+        }
+    }
+}
+
+// Append the lanes' records whose state is ST_MOVE or ST_YIELD (one atomic per
+// wave) and free those lanes.
+template <typename R>
+__device__ __forceinline__ void append_moves(const SweepParams& S, Packet<R>& s, const Stream<R>& rs,
+                                             int lane) {
+    const bool mine = s.st == ST_MOVE || s.st == ST_YIELD;
+    const unsigned long long mv = __ballot(mine);
+    if (!mv) return;
+    const int leader = __ffsll((long long)mv) - 1;
+    unsigned base = 0;
+    if (lane == leader) base = atomicAdd(S.out_count, (unsigned)__popcll(mv));
+    base = __shfl(base, leader);
+    if (mine) {
+        const unsigned idx = base + (unsigned)__popcll(mv & __lanemask_lt());
+        store_rec(reinterpret_cast<PacketRec<R>*>(S.out) + idx, s, rs,
+                  s.st == ST_YIELD ? ST_EVENT : ST_WALK);
+        S.out_tile[idx] = (unsigned)tile_of(S, s.c0, s.c1, s.c2);
+        s.st = ST_EMPTY;
+    }
+}
+
+template <typename R>
+__device__ __forceinline__ void flush_block_counters(const TransportParams<R>& P, uint32_t* cnt,
+                                                     double e_escaped, double e_killed,
+                                                     unsigned long long* s_cnt, double* s_energy) {
+#pragma unroll
+    for (int c = 0; c < C_COUNT; ++c) atomicAdd(&s_cnt[c], (unsigned long long)cnt[c]);
+    atomicAdd(&s_energy[0], e_escaped);
+    atomicAdd(&s_energy[1], e_killed);
+    __syncthreads();
+    if (threadIdx.x < C_COUNT) atomicAdd(P.counters + threadIdx.x, s_cnt[threadIdx.x]);
+    if (threadIdx.x < 2) unsafeAtomicAdd(P.energies + threadIdx.x, s_energy[threadIdx.x]);
+}
+
+// Emission of packets [first, first+count): each starts its first flight
+// (exactly as in the per-lane kernel) and is written out with its tile, or
+// escapes at once when it starts outside the grid.
+template <typename R>
+__global__ void __launch_bounds__(256) k_sweep_emit(TransportParams<R> P, SweepParams S,
+                                                     uint64_t first, uint64_t count) {
+    __shared__ unsigned long long s_cnt[C_COUNT];
+    __shared__ double s_energy[2];
+    if (threadIdx.x < C_COUNT) s_cnt[threadIdx.x] = 0ull;
+    if (threadIdx.x < 2) s_energy[threadIdx.x] = 0.0;
+    __syncthreads();
+    uint32_t cnt[C_COUNT] = {0, 0, 0, 0, 0, 0};
+    double e_escaped = 0.0, e_killed = 0.0;
+    const Tables<R> tb{P.lcdf, P.ecoarse, P.scoarse};
+    const int lane = __lane_id();
+    Stream<R> rs;
+    rs.k0 = P.key0;
+    rs.k1 = P.key1;
+    rs.n = 0;
+    rs.p0 = rs.p1 = rs.s0 = rs.s1 = 0;
+    const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+    for (uint64_t base = (uint64_t)blockIdx.x * blockDim.x; base < count; base += stride) {
+        const uint64_t i = base + threadIdx.x;
+        Packet<R> s;
+        s.st = ST_EMPTY;
+        if (i < count) {
+            emit(s, rs, P, tb, first + i);
+            if (s.st == ST_ESC) escape(s, P, cnt, e_escaped);
+            else s.st = ST_MOVE;
+        }
+        append_moves(S, s, rs, lane);
+    }
+    flush_block_counters(P, cnt, e_escaped, e_killed, s_cnt, s_energy);
+}
+
+// One sweep over the work items (persistent workgroups).
+template <typename R, int K>
+__global__ void __launch_bounds__(256) k_sweep(TransportParams<R> P, SweepParams S) {
+    extern __shared__ unsigned char smem_raw[];
+    __shared__ unsigned s_item, s_next;
+    __shared__ unsigned long long s_cnt[C_COUNT];
+    __shared__ double s_energy[2];
+    const int tcells = kTX * kTY * S.tz;
+    R* rho_t = reinterpret_cast<R*>(smem_raw);
+    R* acc_t = rho_t + tcells;
+    R* acc2_t = P.acc2 ? acc_t + tcells : nullptr;
+    R* sm_tab = acc_t + (P.acc2 ? 2 : 1) * tcells;
+    if (threadIdx.x < C_COUNT) s_cnt[threadIdx.x] = 0ull;
+    if (threadIdx.x < 2) s_energy[threadIdx.x] = 0.0;
+    Tables<R> tb;
+    if (P.lds_tables) {
+        const int ne = kRows * P.ngroup, ns = P.nsrc * P.ngroup;
+        for (int i = threadIdx.x; i < P.nsrc; i += blockDim.x) sm_tab[i] = P.lcdf[i];
+        for (int i = threadIdx.x; i < ne; i += blockDim.x) sm_tab[P.nsrc + i] = P.ecoarse[i];
+        for (int i = threadIdx.x; i < ns; i += blockDim.x) sm_tab[P.nsrc + ne + i] = P.scoarse[i];
+        tb.lcdf = sm_tab;
+        tb.ecoarse = sm_tab + P.nsrc;
+        tb.scoarse = sm_tab + P.nsrc + ne;
+    } else {
+        tb.lcdf = P.lcdf;
+        tb.ecoarse = P.ecoarse;
+        tb.scoarse = P.scoarse;
+    }
+    uint32_t cnt[C_COUNT] = {0, 0, 0, 0, 0, 0};
+    double e_escaped = 0.0, e_killed = 0.0;
+    const int lane = __lane_id();
+    const int defer = P.defer_lanes;
+    const PacketRec<R>* in = reinterpret_cast<const PacketRec<R>*>(S.in);
+    Stream<R> rs;
+    rs.k0 = P.key0;
+    rs.k1 = P.key1;
+    rs.n = 0;
+    rs.p0 = rs.p1 = rs.s0 = rs.s1 = 0;
+    const unsigned n_items = S.item_off[S.ntiles];
+
+    for (;;) {
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            s_item = atomicAdd(S.item_next, 1u);
+            s_next = 0u;
+        }
+        __syncthreads();
+        const unsigned item = s_item;
+        if (item >= n_items) break;
+        int lo = 0, hi = S.ntiles - 1;  // last tile whose first item is <= item
+        while (lo < hi) {
+            const int mid = (lo + hi + 1) >> 1;
+            if (S.item_off[mid] <= item) lo = mid;
+            else hi = mid - 1;
+        }
+        const int tile = lo;
+        const unsigned first = S.tile_off[tile] + (item - S.item_off[tile]) * kItem;
+        const unsigned end = min(first + kItem, S.tile_off[tile + 1]);
+        const int tzi = tile / (S.ntx * S.nty);
+        const int trem = tile - tzi * S.ntx * S.nty;
+        const int tyi = trem / S.ntx, txi = trem - tyi * S.ntx;
+        const int o0 = txi * kTX, o1 = tyi * kTY, o2 = tzi * S.tz;
+        for (int i = threadIdx.x; i < tcells; i += blockDim.x) {
+            const int lx = i % kTX, ly = (i / kTX) % kTY, lz = i / (kTX * kTY);
+            const int gx = o0 + lx, gy = o1 + ly, gz = o2 + lz;
+            R r = (R)0;
+            if (gx < P.n[0] && gy < P.n[1] && gz < P.n[2])
+                r = P.rho[gx + (int64_t)P.n[0] * (gy + (int64_t)P.n[1] * gz)];
+            rho_t[i] = r;
+            acc_t[i] = (R)0;
+            if (acc2_t) acc2_t[i] = (R)0;
+        }
+        __syncthreads();
+
+        Packet<R> s;
+        s.st = ST_EMPTY;
+        int visit = 0;
+        for (;;) {
+            const unsigned long long need = __ballot(s.st == ST_EMPTY);
+            if (need) {
+                const int leader = __ffsll((long long)need) - 1;
+                unsigned base = 0;
+                if (lane == leader) base = atomicAdd(&s_next, (unsigned)__popcll(need));
+                base = __shfl(base, leader);
+                if (s.st == ST_EMPTY) {
+                    const unsigned slot = first + base + (unsigned)__popcll(need & __lanemask_lt());
+                    if (slot < end) {
+                        load_rec(s, rs, P, in + slot);
+                        visit = 0;
+                        // a record is always mid-walk or at a pending event
+                        if (s.st != ST_WALK && s.st != ST_EVENT) s.st = ST_DONE;
+                    } else {
+                        s.st = ST_DONE;
+                    }
+                }
+            }
+            if (__ballot(s.st != ST_DONE) == 0ull) break;
+            for (;;) {
+                if (s.st == ST_WALK) walk_tile<R, K>(s, P, o0, o1, o2, S.tz, rho_t, acc_t, acc2_t, cnt);
+                if (__ballot(s.st == ST_WALK) == 0ull) break;
+                if (__popcll(__ballot(s.st != ST_WALK && s.st != ST_DONE)) >= defer) break;
+            }
+            if (s.st == ST_EVENT) {
+                if (visit >= S.visit_events) {
+                    s.st = ST_YIELD;  // back to this tile's queue for the next sweep
+                } else {
+                    ++visit;
+                    interact(s, rs, P, tb, cnt, e_killed);
+                }
+            }
+            if (s.st == ST_ESC) escape(s, P, cnt, e_escaped);
+            append_moves(S, s, rs, lane);
+        }
+        __syncthreads();
+        // the tile's partial sums into the FP64 tally (cells of this tile only)
+        for (int i = threadIdx.x; i < tcells; i += blockDim.x) {
+            const R a = acc_t[i];
+            const R a2 = acc2_t ? acc2_t[i] : (R)0;
+            if (a != (R)0 || a2 != (R)0) {
+                const int lx = i % kTX, ly = (i / kTX) % kTY, lz = i / (kTX * kTY);
+                const int64_t j = (o0 + lx) + (int64_t)P.n[0] * ((o1 + ly) + (int64_t)P.n[1] * (o2 + lz));
+                if (a != (R)0) unsafeAtomicAdd(P.acc + j, (double)a);
+                if (a2 != (R)0) unsafeAtomicAdd(P.acc2 + j, (double)a2);
+            }
+        }
+    }
+    flush_block_counters(P, cnt, e_escaped, e_killed, s_cnt, s_energy);
+}
+
+// ---- counting sort of the written records by tile --------------------------
+
+// one atomic per distinct tile of a wave
+__global__ void k_tile_hist(const unsigned* __restrict__ out_tile, const unsigned* __restrict__ n_out,
+                            unsigned* __restrict__ counts) {
+    const unsigned n = *n_out;
+    const unsigned stride = gridDim.x * blockDim.x;
+    for (unsigned base = blockIdx.x * blockDim.x; base < n; base += stride) {
+        const unsigned i = base + threadIdx.x;
+        bool pending = i < n;
+        const unsigned t = pending ? out_tile[i] : 0u;
+        for (;;) {
+            const unsigned long long act = __ballot(pending);
+            if (!act) break;
+            const int leader = __ffsll((long long)act) - 1;
+            const unsigned lt = __shfl(t, leader);
+            const unsigned long long same = __ballot(pending && t == lt);
+            if (__lane_id() == leader) atomicAdd(counts + lt, (unsigned)__popcll(same));
+            if (pending && t == lt) pending = false;
+        }
+    }
+}
+
+// exclusive scans of the counts (records and work items), cursors, and the
+// counters of the next sweep; one block
+__global__ void __launch_bounds__(1024) k_tile_scan(unsigned* __restrict__ counts, int ntiles,
+                                                    unsigned* __restrict__ tile_off,
+                                                    unsigned* __restrict__ item_off,
+                                                    unsigned* __restrict__ cursor,
+                                                    unsigned* __restrict__ item_next) {
+    __shared__ unsigned s_a[1024], s_b[1024];
+    const int per = (ntiles + (int)blockDim.x - 1) / (int)blockDim.x;
+    const int t0 = threadIdx.x * per;
+    unsigned ra = 0, rb = 0;
+    for (int t = t0; t < t0 + per && t < ntiles; ++t) {
+        ra += counts[t];
+        rb += (counts[t] + kItem - 1) / kItem;
+    }
+    s_a[threadIdx.x] = ra;
+    s_b[threadIdx.x] = rb;
+    __syncthreads();
+    for (int o = 1; o < (int)blockDim.x; o <<= 1) {
+        const unsigned va = threadIdx.x >= (unsigned)o ? s_a[threadIdx.x - o] : 0u;
+        const unsigned vb = threadIdx.x >= (unsigned)o ? s_b[threadIdx.x - o] : 0u;
+        __syncthreads();
+        s_a[threadIdx.x] += va;
+        s_b[threadIdx.x] += vb;
+        __syncthreads();
+    }
+    unsigned pa = s_a[threadIdx.x] - ra, pb = s_b[threadIdx.x] - rb;  // exclusive
+    for (int t = t0; t < t0 + per && t < ntiles; ++t) {
+        const unsigned c = counts[t];
+        tile_off[t] = pa;
+        cursor[t] = pa;
+        item_off[t] = pb;
+        pa += c;
+        pb += (c + kItem - 1) / kItem;
+        counts[t] = 0u;
+    }
+    if (threadIdx.x == blockDim.x - 1) {
+        tile_off[ntiles] = s_a[threadIdx.x];
+        item_off[ntiles] = s_b[threadIdx.x];
+        *item_next = 0u;
+    }
+}
+
+template <typename R>
+__global__ void k_tile_scatter(const PacketRec<R>* __restrict__ out,
+                               const unsigned* __restrict__ out_tile, const unsigned* __restrict__ n_out,
+                               unsigned* __restrict__ cursor, PacketRec<R>* __restrict__ in) {
+    const unsigned n = *n_out;
+    const unsigned stride = gridDim.x * blockDim.x;
+    for (unsigned base = blockIdx.x * blockDim.x; base < n; base += stride) {
+        const unsigned i = base + threadIdx.x;
+        bool pending = i < n;
+        const unsigned t = pending ? out_tile[i] : 0u;
+        unsigned pos = 0;
+        for (;;) {
+            const unsigned long long act = __ballot(pending);
+            if (!act) break;
+            const int leader = __ffsll((long long)act) - 1;
+            const unsigned lt = __shfl(t, leader);
+            const bool mine = pending && t == lt;
+            const unsigned long long same = __ballot(mine);
+            unsigned b = 0;
+            if (__lane_id() == leader) b = atomicAdd(cursor + lt, (unsigned)__popcll(same));
+            b = __shfl(b, leader);
+            if (mine) {
+                pos = b + (unsigned)__popcll(same & __lanemask_lt());
+                pending = false;
+            }
+        }
+        if (i < n) in[pos] = out[i];
+    }
+}
+
+__global__ void k_zero_u32(unsigned* p, int n) {
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) p[i] = 0u;
+}
+
+// ---------------------------------------------------------------------------
+size_t sweep_record_bytes(int fp32) {
+    return fp32 ? sizeof(PacketRec<float>) : sizeof(PacketRec<double>);
+}
+
+template <typename R> using SweepFn = void (*)(TransportParams<R>, SweepParams);
+
+template <typename R> SweepFn<R> pick_sweep(int K) {
+    switch (K) {
+        case 1: return k_sweep<R, 1>;
+        case 2: return k_sweep<R, 2>;
+        default: return k_sweep<R, 4>;
+    }
+}
+
+template <typename R>
+hipError_t launch_sweep_emit(const TransportParams<R>& P, const SweepParams& S, uint64_t first,
+                             uint64_t count, int blocks, hipStream_t st) {
+    hipLaunchKernelGGL(k_sweep_emit<R>, dim3(blocks), dim3(256), 0, st, P, S, first, count);
+    return hipGetLastError();
+}
+
+template <typename R>
+hipError_t launch_sweep(const TransportParams<R>& P, const SweepParams& S, int K, int blocks,
+                        size_t lds, hipStream_t st) {
+    hipLaunchKernelGGL(pick_sweep<R>(K), dim3(blocks), dim3(256), lds, st, P, S);
+    return hipGetLastError();
+}
+
+template <typename R> int sweep_max_blocks_per_cu(int K, size_t lds) {
+    int nb = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, pick_sweep<R>(K), 256, lds) != hipSuccess)
+        return 1;
+    return nb > 0 ? nb : 1;
+}
+
+template <typename R>
+hipError_t launch_tile_sort(const SweepParams& S, const void* out, void* in, unsigned* counts,
+                            unsigned* tile_off, unsigned* item_off, unsigned* cursor, int blocks,
+                            hipStream_t st) {
+    hipLaunchKernelGGL(k_tile_hist, dim3(blocks), dim3(256), 0, st, S.out_tile, S.out_count, counts);
+    hipLaunchKernelGGL(k_tile_scan, dim3(1), dim3(1024), 0, st, counts, S.ntiles, tile_off, item_off,
+                       cursor, S.item_next);
+    hipLaunchKernelGGL(k_tile_scatter<R>, dim3(blocks), dim3(256), 0, st,
+                       reinterpret_cast<const PacketRec<R>*>(out), S.out_tile, S.out_count, cursor,
+                       reinterpret_cast<PacketRec<R>*>(in));
+    hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(64), 0, st, S.out_count, 1);
+    return hipGetLastError();
+}
+
+hipError_t launch_zero_u32(unsigned* p, int n, hipStream_t st) {
+    hipLaunchKernelGGL(k_zero_u32, dim3((n + 255) / 256 < 1024 ? (n + 255) / 256 : 1024), dim3(256), 0,
+                       st, p, n);
+    return hipGetLastError();
+}
+
+template hipError_t launch_sweep_emit<float>(const TransportParams<float>&, const SweepParams&,
+                                             uint64_t, uint64_t, int, hipStream_t);
+template hipError_t launch_sweep_emit<double>(const TransportParams<double>&, const SweepParams&,
+                                              uint64_t, uint64_t, int, hipStream_t);
+template hipError_t launch_sweep<float>(const TransportParams<float>&, const SweepParams&, int, int,
+                                        size_t, hipStream_t);
+template hipError_t launch_sweep<double>(const TransportParams<double>&, const SweepParams&, int,
+                                         int, size_t, hipStream_t);
+template int sweep_max_blocks_per_cu<float>(int, size_t);
+template int sweep_max_blocks_per_cu<double>(int, size_t);
+template hipError_t launch_tile_sort<float>(const SweepParams&, const void*, void*, unsigned*,
+                                            unsigned*, unsigned*, unsigned*, int, hipStream_t);
+template hipError_t launch_tile_sort<double>(const SweepParams&, const void*, void*, unsigned*,
+                                             unsigned*, unsigned*, unsigned*, int, hipStream_t);
+
+}  // namespace mcrt

@@ -39,6 +39,7 @@ class RunCfg(C.Structure):
         ("bin_every_iteration", C.c_int32), ("block_size", C.c_int32),
         ("blocks_per_cu", C.c_int32), ("defer_lanes", C.c_int32), ("walk_batch", C.c_int32),
         ("grid_layout", C.c_int32), ("tally_copies", C.c_int32),
+        ("transport_mode", C.c_int32), ("tile_z", C.c_int32), ("visit_events", C.c_int32),
     ]
 
 
@@ -52,6 +53,7 @@ class IterStats(C.Structure):
         ("n_scatter", C.c_int64), ("n_absorb", C.c_int64), ("n_escape", C.c_int64),
         ("n_killed", C.c_int64), ("e_escaped", C.c_double), ("e_killed", C.c_double),
         ("ms_transport", C.c_double), ("ms_update", C.c_double), ("ms_total", C.c_double),
+        ("n_sweeps", C.c_int64),
     ]
 
     def as_dict(self) -> dict:
@@ -328,10 +330,10 @@ class Model:
 
     # -- learned warm start ----------------------------------------------------
     def features(self):
-        """FP32 device tensor [ncell, 2] of the network's input features."""
+        """FP32 device tensor [ncell, 3] of the network's input features."""
         import torch
 
-        x = torch.empty((self.ncell, 2), dtype=torch.float32, device=f"cuda:{self.device}")
+        x = torch.empty((self.ncell, 3), dtype=torch.float32, device=f"cuda:{self.device}")
         torch.cuda.synchronize(x.device)
         self._check(self.L.mcrt_model_features(self.h, C.c_void_p(x.data_ptr()), x.numel()))
         return x
@@ -410,7 +412,7 @@ class Surrogate:
         return g
 
     def forward(self, x, N: int, D: int):
-        """x: [N*D^3, 2] features -> [N*D^3] log10 T."""
+        """x: [N*D^3, 3] features -> [N*D^3] log10 T."""
         import torch
 
         torch.cuda.synchronize(x.device)

@@ -28,7 +28,7 @@ DEFAULT_WEIGHTS = os.path.join(HERE, "weights", "warmstart_c16.npy")
 SEED_TRAIN, SEED_HOLDOUT, SEED_TEST = 40000, 42000, 45000
 
 
-def family_model(seed: int, n: int = 64, packets_per_cell: float = 10.0, n_iter: int = 8,
+def family_model(seed: int, n: int = 64, packets_per_cell: float = 5.0, n_iter: int = 5,
                  members=("sphere", "disk", "clump")) -> dict:
     """One member of the training family at side n: a randomly parameterised
     sphere or disk (as in the batched family of uneven models) or a clump
@@ -62,44 +62,50 @@ def _log(msg: str):
     print(msg, file=sys.stderr, flush=True)
 
 
-def generate(seeds, n: int = 64, packets_per_cell: float = 10.0, n_iter: int = 8, device: int = 0,
-             members=("sphere", "disk", "clump")):
+def generate(seeds, n: int = 64, packets_per_cell: float = 5.0, n_iter: int = 5, device: int = 0,
+             members=("sphere", "disk", "clump"), group: int = 64):
     """Run n_iter Lucy iterations of the Monte-Carlo method from T = 10 K for
-    each member and return device tensors X [M, n^3, 2], Y [M, n^3] (log10 T) and MASK [M, n^3]
-    (1 where the cell holds dust and was sampled in the last iteration)."""
+    each member (groups of models share one batched launch per iteration) and
+    return device tensors X [M, n^3, 3] (features), Y [M, n^3] (log10 T) and
+    MASK [M, n^3] (1 where the cell holds dust and was sampled in the last
+    iteration).  Member configs are built on host threads while the GPU runs
+    the previous group."""
     import torch
+    from concurrent.futures import ThreadPoolExecutor
 
     from . import mcrt
 
     M = len(seeds)
     dev = f"cuda:{device}"
-    X = torch.empty((M, n ** 3, 2), dtype=torch.float32, device=dev)
+    X = torch.empty((M, n ** 3, 3), dtype=torch.float32, device=dev)
     Y = torch.empty((M, n ** 3), dtype=torch.float32, device=dev)
     K = torch.empty((M, n ** 3), dtype=torch.float32, device=dev)
     t0 = time.time()
-    iters = []
-    for i, s in enumerate(seeds):
-        cfg = family_model(s, n, packets_per_cell, n_iter, members)
-        m = mcrt.Model(cfg, device=device, precision=mcrt.MCRT_FP32_TRANSPORT)
-        for _ in range(n_iter):
-            st = m.iterate()
-        iters.append(st["p999_dT"])
-        X[i] = m.features()
-        T = torch.as_tensor(m.temperature(), device=dev)
-        rho = torch.as_tensor(np.asarray(cfg["rho"]).reshape(-1), device=dev)
-        Y[i] = torch.log10(T).float()
-        K[i] = ((rho > 0) & (T > 1.0)).float()
-        m.close()
-        if (i + 1) % 50 == 0 or i + 1 == M:
-            _log(f"# generated {i + 1}/{M} models in {time.time() - t0:.0f} s "
-                 f"(median p99.9 dT/T of the last iteration {np.median(iters):.3f})")
+    pool = ThreadPoolExecutor(max_workers=8)
+    futs = [pool.submit(family_model, s, n, packets_per_cell, n_iter, members) for s in seeds]
+    for g0 in range(0, M, group):
+        idx = list(range(g0, min(M, g0 + group)))
+        cfgs = [futs[i].result() for i in idx]
+        for i in idx:
+            futs[i] = None
+        models = [mcrt.Model(c, device=device, precision=mcrt.MCRT_FP32_TRANSPORT) for c in cfgs]
+        mcrt.batch_run(models, n_iter=n_iter, final_pass=0, use_graph=1, autotune=0)
+        for i, m, cfg in zip(idx, models, cfgs):
+            X[i] = m.features()
+            T = torch.as_tensor(m.temperature(), device=dev)
+            rho = torch.as_tensor(np.asarray(cfg["rho"]).reshape(-1), device=dev)
+            Y[i] = torch.log10(T).float()
+            K[i] = ((rho > 0) & (T > 1.0)).float()
+            m.close()
+        _log(f"# generated {idx[-1] + 1}/{M} models in {time.time() - t0:.0f} s")
+    pool.shutdown()
     return X, Y, K
 
 
 def train(sur, X, Y, K, epochs: int = 30, batch: int = 8, lr: float = 2e-3, holdout=None,
           seed: int = 0, log_every: int = 1):
-    """Adam on the masked mean-square error of log10 T with a cosine learning
-    rate; returns the per-epoch history."""
+    """Adam on the masked mean-square error of log10 T, learning rate with a
+    200-step linear warm-up and a cosine decay; returns the per-epoch history."""
     import torch
 
     n = int(round(X.shape[1] ** (1.0 / 3.0)))
@@ -119,13 +125,14 @@ def train(sur, X, Y, K, epochs: int = 30, batch: int = 8, lr: float = 2e-3, hold
             flips = [d for d in (1, 2, 3) if rng.random() < 0.5]
             if flips:
                 sh = (batch, n, n, n)
-                xb = xb.reshape(*sh, 2).flip(flips).reshape(batch, -1, 2)
+                xb = xb.reshape(*sh, 3).flip(flips).reshape(batch, -1, 3)
                 yb = yb.reshape(sh).flip(flips).reshape(batch, -1)
                 kb = kb.reshape(sh).flip(flips).reshape(batch, -1)
             cnt = float(kb.sum().item())
             if cnt <= 0:
                 continue
-            cur = lr * 0.5 * (1.0 + math.cos(math.pi * step / max(steps, 1)))
+            warm = min(1.0, (step + 1) / 200.0)
+            cur = lr * warm * 0.5 * (1.0 + math.cos(math.pi * step / max(steps, 1)))
             losses.append(sur.train_step(xb.contiguous(), yb.contiguous(), kb.contiguous(), batch, n,
                                          lr=cur, mask_count=cnt))
             step += 1
@@ -144,14 +151,14 @@ def evaluate_mse(sur, X, Y, K, batch: int = 8) -> float:
     for b in range(0, X.shape[0], batch):
         xb = X[b:b + batch].contiguous()
         nb = xb.shape[0]
-        y = sur.forward(xb.reshape(-1, 2), nb, n).reshape(nb, -1)
+        y = sur.forward(xb.reshape(-1, 3), nb, n).reshape(nb, -1)
         d = (y - Y[b:b + batch]) * K[b:b + batch]
         se += float((d * d).sum().item())
         cnt += float(K[b:b + batch].sum().item())
     return se / max(cnt, 1.0)
 
 
-def test_clump(i: int, n: int = 128, n_packets: int = 12_500_000, n_iter: int = 40) -> dict:
+def test_clump(i: int, n: int = 128, n_packets: int = 250_000_000, n_iter: int = 40) -> dict:
     """Unseen clump i of the warm-start test: the star-forming-clump recipe at
     side n (same 0.65 pc box), seed SEED_TEST + i."""
     return synth.clump_config4(n=n, seed=SEED_TEST + i, n_packets=n_packets, n_iter=n_iter)
@@ -170,18 +177,17 @@ def converge(cfg: dict, sur=None, device: int = 0, **run) -> dict:
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     ms_warm = 0.0
-    err0 = None
     if sur is not None:
         ms_warm = m.warm_start(sur)
-    T0 = m.temperature() if sur is not None else None
+    T0 = m.temperature() if sur is not None else np.full(m.ncell, float(cfg["run"]["t_init"]))
     rs = m.run_all()
     wall = (time.perf_counter() - t0) * 1e3
     T = m.temperature()
     rho = np.asarray(cfg["rho"]).reshape(-1)
     dust = (rho > 0) & (T > 1.0)
-    if T0 is not None:
-        e = np.abs(np.log(T0[dust] / T[dust]))
-        err0 = {"median_abs_dlnT": float(np.median(e)), "p90_abs_dlnT": float(np.percentile(e, 90))}
+    e = np.abs(np.log(T0[dust] / T[dust]))
+    err0 = {"median_abs_dlnT": float(np.median(e)), "p90_abs_dlnT": float(np.percentile(e, 90)),
+            "mass_weighted_abs_dlnT": float(np.sum(e * rho[dust]) / np.sum(rho[dust]))}
     m.close()
     return {"iterations": rs["n_iterations"], "converged": rs["converged"],
             "first_converged": rs["first_converged"],
@@ -198,11 +204,11 @@ def main():
     t.add_argument("--n-train", type=int, default=2000)
     t.add_argument("--n-holdout", type=int, default=200)
     t.add_argument("--side", type=int, default=64)
-    t.add_argument("--ppc", type=float, default=10.0)
-    t.add_argument("--mc-iter", type=int, default=8)
+    t.add_argument("--ppc", type=float, default=5.0)
+    t.add_argument("--mc-iter", type=int, default=5)
     t.add_argument("--epochs", type=int, default=30)
     t.add_argument("--batch", type=int, default=8)
-    t.add_argument("--lr", type=float, default=2e-3)
+    t.add_argument("--lr", type=float, default=1e-3)
     t.add_argument("--channels", type=int, default=16)
     t.add_argument("--members", default="sphere,disk,clump")
     t.add_argument("--history", default="")
@@ -210,7 +216,7 @@ def main():
     e.add_argument("--weights", default=DEFAULT_WEIGHTS)
     e.add_argument("--n-test", type=int, default=8)
     e.add_argument("--side", type=int, default=128)
-    e.add_argument("--packets", type=float, default=12.5e6)
+    e.add_argument("--packets", type=float, default=2.5e8)
     e.add_argument("--channels", type=int, default=16)
     args = ap.parse_args()
 

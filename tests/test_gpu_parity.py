@@ -270,6 +270,11 @@ def test_abi_errors(M):
     dict(walk_batch=4, grid_layout=1, tally_copies=1, block_size=128),
     dict(walk_batch=8, grid_layout=0, tally_copies=8, defer_lanes=1),
     dict(walk_batch=8, grid_layout=1, tally_copies=8, defer_lanes=64, block_size=64),
+    # tiled sweeps: tiles of 16x16x{4,8} (ragged at the grid edges), yields
+    # after every interaction (visit_events=1), lone-lane event handling
+    dict(transport_mode=1, tile_z=8, walk_batch=4),
+    dict(transport_mode=1, tile_z=4, walk_batch=1, visit_events=1),
+    dict(transport_mode=1, tile_z=8, walk_batch=2, defer_lanes=1, visit_events=3),
 ])
 def test_launch_variants_same_stream(M, variant):
     # every launch configuration the library offers gives the oracle's packets
@@ -289,3 +294,26 @@ def test_launch_variants_same_stream(M, variant):
     nz = ao > 0
     assert np.array_equal(nz, ag > 0)
     assert np.max(np.abs(ag[nz] / ao[nz] - 1)) < 1e-9
+
+
+@pytest.mark.parametrize("tile_z", [4, 8])
+def test_tiled_fp32_equals_persistent_fp32(M, tile_z):
+    # FP32 transport: both modes follow identical packet histories (same
+    # counters exactly); the tiled mode sums a tile visit in FP32 before the
+    # FP64 flush, so Adot agrees to a few FP32 roundings per cell
+    cfg = synth.config2(n=48, n_packets=400000, n_iter=2, gen_seed=45777, n_src=12,
+                        box=0.65 * synth.PC * 48 / 128)
+    a = M.Model(cfg, precision=M.MCRT_FP32_TRANSPORT, want_noise=1)
+    b = M.Model(cfg, precision=M.MCRT_FP32_TRANSPORT, want_noise=1, transport_mode=1, tile_z=tile_z)
+    for it in range(2):
+        sa, sb = a.iterate(), b.iterate()
+        for k in ["n_cross_dust", "n_cross_empty", "n_scatter", "n_absorb", "n_escape", "n_killed"]:
+            assert sa[k] == sb[k], (it, k)
+        assert sb["n_sweeps"] > 0
+        aa, sga = a.specific_energy(with_sigma=True)
+        ab, sgb = b.specific_energy(with_sigma=True)
+        nz = aa > 0
+        assert np.array_equal(nz, ab > 0)
+        assert np.max(np.abs(ab[nz] / aa[nz] - 1)) < 1e-4, it
+        assert np.max(np.abs(sgb[nz] / sga[nz] - 1)) < 1e-3, it
+        np.testing.assert_allclose(b.temperature(), a.temperature(), rtol=1e-4)

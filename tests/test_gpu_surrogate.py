@@ -36,9 +36,10 @@ def M():
 
 def _features(N, D, seed):
     r = np.random.default_rng(seed)
-    x = np.empty((N * D ** 3, 2), dtype=np.float32)
+    x = np.empty((N * D ** 3, 3), dtype=np.float32)
     x[:, 0] = r.uniform(-6, 2, N * D ** 3)
     x[:, 1] = np.where(r.random(N * D ** 3) < 0.05, r.uniform(1, 9, N * D ** 3), -30.0)
+    x[:, 2] = r.uniform(0, 10, N * D ** 3)
     return x
 
 
@@ -87,8 +88,8 @@ def test_forward_and_gradients_match_reference(M, N, D):
     _, g_ref32 = nn.loss_and_grad(p, x, target, mask, N, D, bf16_grad=True, fp32=True)
     assert loss == pytest.approx(loss_ref, rel=2e-2)
     g = sur.grads().astype(np.float64)
-    # input channels 2..15 are zero: their first-layer weights get zero gradient
-    assert not np.any(g[_layer_slices()[0][1]].reshape(27, 16, 16)[:, :, 2:])
+    # input channels 3..15 are zero: their first-layer weights get zero gradient
+    assert not np.any(g[_layer_slices()[0][1]].reshape(27, 16, 16)[:, :, 3:])
     rows = []
     for name, sl in _layer_slices():
         e, spread = _rel(g[sl], g_ref[sl]), _rel(g_ref32[sl], g_ref[sl])
@@ -123,7 +124,7 @@ def test_set_params_roundtrip_and_errors(M):
         sur.set_params(bad)
     import torch
 
-    x = torch.zeros((12 ** 3, 2), device="cuda:0")
+    x = torch.zeros((12 ** 3, 3), device="cuda:0")
     with pytest.raises(M.MCRTError):
         sur.forward(x, 1, 12)  # side not a multiple of 8
     sur.close()
@@ -141,6 +142,7 @@ def test_model_features_match_reference(M):
     ref = nn.features(cfg)
     np.testing.assert_allclose(x[:, 0], ref[:, 0], rtol=0, atol=2e-6)
     np.testing.assert_allclose(x[:, 1], ref[:, 1], rtol=0, atol=1e-5)
+    np.testing.assert_allclose(x[:, 2], ref[:, 2], rtol=0, atol=1e-5)
     assert np.count_nonzero(ref[:, 1] > -29) == np.count_nonzero(x[:, 1] > -29)
 
 

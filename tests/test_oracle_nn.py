@@ -76,9 +76,10 @@ def _params(C=16, seed=3):
 
 def _features(N, D, seed=4):
     r = np.random.default_rng(seed)
-    x = np.empty((N * D ** 3, 2), dtype=np.float32)
+    x = np.empty((N * D ** 3, 3), dtype=np.float32)
     x[:, 0] = r.uniform(-6, 2, N * D ** 3)
     x[:, 1] = np.where(r.random(N * D ** 3) < 0.05, r.uniform(1, 9, N * D ** 3), -30.0)
+    x[:, 2] = r.uniform(0, 10, N * D ** 3)
     return x
 
 
@@ -163,3 +164,10 @@ def test_features_by_hand():
         assert F[k, j, i] == pytest.approx(1.0 / (4 * math.pi))
     assert F[5, 1, 4] == pytest.approx(1.0)
     assert (F > 1e-20).sum() == 9
+    # spread field: sum of D_c / max(r^2, 1/4) over the 9 deposit cells
+    G = 10 ** x[:, 2].reshape(n, n, n)
+    dep = [((i, j, k), 1.0 / (4 * math.pi)) for k, j, i in itertools.product((3, 4), repeat=3)]
+    dep.append(((4, 1, 5), 1.0))
+    for (k, j, i) in [(0, 0, 0), (5, 1, 4), (3, 3, 3), (7, 2, 6)]:
+        want = sum(d / max((i - a) ** 2 + (j - b) ** 2 + (k - c) ** 2, 0.25) for (a, b, c), d in dep)
+        assert G[k, j, i] == pytest.approx(want, rel=1e-12)
