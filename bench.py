@@ -302,6 +302,7 @@ def main():
             "scatters": last["n_scatter"], "absorptions": last["n_absorb"],
             "killed": last["n_killed"], "ms_update": last["ms_update"],
             "transport_mode": model.run["transport_mode"], "sweeps": last["n_sweeps"],
+            "tile_visits": last["n_visits"],
             "max_dT": last["max_dT"], "q": last["q"],
         },
     }

@@ -134,6 +134,7 @@ typedef struct {
     double ms_update;          /* device time of the temperature update and statistics    */
     double ms_total;           /* host wall time of the call                              */
     int64_t n_sweeps;          /* tiled sweeps run by the pass (transport_mode 1)         */
+    int64_t n_visits;          /* tile visits (packet records walked) over those sweeps   */
 } mcrt_iter_stats;
 
 typedef struct {
@@ -180,6 +181,20 @@ mcrt_status mcrt_add_point_source_spectrum(mcrt_model* m, const double pos[3], d
  * frequency bins. */
 mcrt_status mcrt_set_observers(mcrt_model* m, int n_incl, int img_npix, double img_half_width,
                                const int* img_nu_bins, int n_img_nu);
+/* Peeling-off (Sec. 2.6.2) toward n observers (unit vectors dirs[3*i..3*i+2]):
+ * at each source emission, scattering and re-emission of a binning pass (the
+ * final pass, or every iteration with bin_every_iteration), a packet of weight
+ * eps p exp(-tau) is added toward every observer, p the probability per
+ * steradian of leaving in that direction (1/(4 pi) for emission and
+ * re-emission, the Henyey-Greenstein phase function for scattering) and tau
+ * the optical depth from the event to the grid boundary in the packet's bin.
+ * Call after mcrt_set_observers; images use its image bins, pixels and width. */
+mcrt_status mcrt_set_peeloff(mcrt_model* m, const double* dirs, int n);
+/* Peeled SED [n][2][n_nu] (erg/s per sr; component 0 direct source light,
+ * 1 scattered or re-emitted): sums and sums of squares of the peeled weights. */
+mcrt_status mcrt_get_peeled_sed(mcrt_model* m, double* sum, double* sum2, size_t n);
+/* Peeled images [n_img][n][npix][npix]: e_x = norm(z x o), e_y = o x e_x. */
+mcrt_status mcrt_get_peeled_images(mcrt_model* m, double* sum, double* sum2, size_t n);
 mcrt_status mcrt_run_cfg_default(mcrt_run_cfg* cfg);
 mcrt_status mcrt_set_run(mcrt_model* m, const mcrt_run_cfg* cfg);
 /* Temperatures (K, > 0) that the next iteration re-emits from (warm start). */
@@ -298,6 +313,9 @@ mcrt_status mcrt_surrogate_forward(mcrt_surrogate* s, const float* d_x, int N, i
 mcrt_status mcrt_surrogate_train_step(mcrt_surrogate* s, const float* d_x, const float* d_target,
                                       const float* d_mask, int N, int D, double mask_count,
                                       double lr, int apply_update, double* loss);
+/* Scale the gradient of later train steps by min(1, max_norm / ||g||_2) before
+ * the Adam update (0, the default, turns clipping off). */
+mcrt_status mcrt_surrogate_set_grad_clip(mcrt_surrogate* s, double max_norm);
 /* Inference written as temperatures: d_T[v] = 10^y clamped to [1, 1e4] K (FP64). */
 mcrt_status mcrt_surrogate_predict_T(mcrt_surrogate* s, const float* d_x, int N, int D, double* d_T);
 

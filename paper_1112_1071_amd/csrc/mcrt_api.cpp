@@ -142,6 +142,8 @@ struct mcrt_model {
     DBuf<double> rowpos64, Rbuf, rbuf;
     DBuf<float> rowpos32;
     DBuf<double> sed_sum, sed_sum2, img_sum, img_sum2;
+    int n_peel = 0;
+    DBuf<double> peel_dir, psed_sum, psed_sum2, pimg_sum, pimg_sum2;
     DBuf<unsigned long long> sed_n;
     DBuf<mcrt_event> evlog;
     DBuf<int32_t> evcount;
@@ -361,6 +363,12 @@ mcrt_status ensure_bins(mcrt_model* m) {
     HIPCHK(m->sed_n.ensure(ns));
     HIPCHK(m->img_sum.ensure(ni));
     HIPCHK(m->img_sum2.ensure(ni));
+    const size_t nps = (size_t)m->n_peel * 2 * m->kap.size();
+    const size_t npi = (size_t)m->n_img * m->n_peel * m->npix * m->npix;
+    HIPCHK(m->psed_sum.ensure(nps));
+    HIPCHK(m->psed_sum2.ensure(nps));
+    HIPCHK(m->pimg_sum.ensure(npi));
+    HIPCHK(m->pimg_sum2.ensure(npi));
     return MCRT_OK;
 }
 
@@ -374,6 +382,16 @@ mcrt_status clear_bins(mcrt_model* m) {
     if (ni) {
         HIPCHK(hipMemsetAsync(m->img_sum.p, 0, ni * sizeof(double), st));
         HIPCHK(hipMemsetAsync(m->img_sum2.p, 0, ni * sizeof(double), st));
+    }
+    const size_t nps = (size_t)m->n_peel * 2 * m->kap.size();
+    const size_t npi = (size_t)m->n_img * m->n_peel * m->npix * m->npix;
+    if (nps) {
+        HIPCHK(hipMemsetAsync(m->psed_sum.p, 0, nps * sizeof(double), st));
+        HIPCHK(hipMemsetAsync(m->psed_sum2.p, 0, nps * sizeof(double), st));
+    }
+    if (npi) {
+        HIPCHK(hipMemsetAsync(m->pimg_sum.p, 0, npi * sizeof(double), st));
+        HIPCHK(hipMemsetAsync(m->pimg_sum2.p, 0, npi * sizeof(double), st));
     }
     return MCRT_OK;
 }
@@ -540,6 +558,13 @@ void make_params(mcrt_model* m, int64_t np, uint32_t key1, int binning, Transpor
         P.img_of_bin = m->img_of_bin.p;
         P.img_sum = m->img_sum.p;
         P.img_sum2 = m->img_sum2.p;
+        P.n_peel = m->n_peel;
+        P.peel_dir = m->peel_dir.p;
+        P.rho_lin = f32 ? (const R*)(const void*)m->rho32.p : (const R*)(const void*)m->rho64.p;
+        P.psed_sum = m->psed_sum.p;
+        P.psed_sum2 = m->psed_sum2.p;
+        P.pimg_sum = m->pimg_sum.p;
+        P.pimg_sum2 = m->pimg_sum2.p;
         P.ev_packets = m->ev_packets;
         P.ev_cap = m->ev_cap;
         P.evlog = m->evlog.p;
@@ -563,7 +588,8 @@ constexpr int64_t kSweepBatch = 1ll << 25;  // packets in flight at once
 constexpr int64_t kMaxSweeps = 1ll << 24;    // every visit advances a packet; this is a backstop
 
 template <typename R>
-mcrt_status run_sweeps(mcrt_model* m, TransportParams<R>& P, int64_t np, int64_t* n_sweeps) {
+mcrt_status run_sweeps(mcrt_model* m, TransportParams<R>& P, int64_t np, int64_t* n_sweeps,
+                       int64_t* n_visits) {
     hipStream_t s = m->stream;
     constexpr bool f32 = std::is_same<R, float>::value;
     SweepParams S{};
@@ -593,7 +619,7 @@ mcrt_status run_sweeps(mcrt_model* m, TransportParams<R>& P, int64_t np, int64_t
     S.item_off = m->sw_item_off.p;
     // LDS: tile density and tally (and sum of squares), then the staged tables
     const size_t tcells = (size_t)16 * 16 * S.tz;
-    const size_t tile_lds = tcells * sizeof(R) * (P.acc2 ? 3 : 2);
+    const size_t tile_lds = tcells * (2 * sizeof(R) + (P.acc2 ? sizeof(double) : 0));
     const size_t tab_lds = (size_t)(m->src.size() + (kRows + m->src.size()) * m->ngroup) * sizeof(R);
     if (tile_lds > m->lds_max) return fail(m, MCRT_E_UNSUPPORTED, "tile does not fit in LDS; use a smaller tile_z");
     P.lds_tables = tile_lds + tab_lds <= m->lds_max ? 1 : 0;
@@ -602,7 +628,7 @@ mcrt_status run_sweeps(mcrt_model* m, TransportParams<R>& P, int64_t np, int64_t
     const int bpc = m->cfg.blocks_per_cu > 0 ? m->cfg.blocks_per_cu : sweep_max_blocks_per_cu<R>(K, lds);
     const int blocks = m->n_cu * bpc;
     P.packet_base = 0;
-    int64_t sweeps = 0;
+    int64_t sweeps = 0, visits = 0;
     for (int64_t b0 = 0; b0 < np; b0 += batch) {
         const int64_t cnt = np - b0 < batch ? np - b0 : batch;
         S.out = m->sw_b.p;
@@ -615,6 +641,7 @@ mcrt_status run_sweeps(mcrt_model* m, TransportParams<R>& P, int64_t np, int64_t
             HIPCHK(hipStreamSynchronize(s));
             if (nout == 0) break;
             if (++sweeps > kMaxSweeps) return fail(m, MCRT_E_DEVICE, "tiled sweeps did not finish");
+            visits += nout;
             const int64_t sb = ((int64_t)nout + 255) / 256;
             HIPCHK(launch_tile_sort<R>(S, m->sw_b.p, m->sw_a.p, m->sw_counts.p, m->sw_tile_off.p,
                                        m->sw_item_off.p, m->sw_cursor.p,
@@ -625,6 +652,7 @@ mcrt_status run_sweeps(mcrt_model* m, TransportParams<R>& P, int64_t np, int64_t
         }
     }
     *n_sweeps = sweeps;
+    *n_visits = visits;
     return MCRT_OK;
 }
 
@@ -644,18 +672,19 @@ mcrt_status run_transport(mcrt_model* m, int64_t np, uint32_t key1, int binning,
     const int layout = m->t_layout;
     HIPCHK(hipEventRecord(m->ev[0], s));
     if (m->cfg.transport_mode == 1) {
-        int64_t sweeps = 0;
+        int64_t sweeps = 0, visits = 0;
         if (f32) {
             TransportParams<float> P;
             make_params(m, np, key1, binning, P);
-            r = run_sweeps<float>(m, P, np, &sweeps);
+            r = run_sweeps<float>(m, P, np, &sweeps, &visits);
         } else {
             TransportParams<double> P;
             make_params(m, np, key1, binning, P);
-            r = run_sweeps<double>(m, P, np, &sweeps);
+            r = run_sweeps<double>(m, P, np, &sweeps, &visits);
         }
         if (r != MCRT_OK) return r;
         st->n_sweeps = sweeps;
+        st->n_visits = visits;
     } else if (f32) {
         TransportParams<float> P;
         make_params(m, np, key1, binning, P);
@@ -883,6 +912,8 @@ void mcrt_destroy(mcrt_model* m) {
     m->rowpos64.release(); m->rowpos32.release(); m->Rbuf.release(); m->rbuf.release();
     m->sed_sum.release(); m->sed_sum2.release(); m->sed_n.release();
     m->img_sum.release(); m->img_sum2.release(); m->evlog.release(); m->evcount.release();
+    m->peel_dir.release(); m->psed_sum.release(); m->psed_sum2.release();
+    m->pimg_sum.release(); m->pimg_sum2.release();
     m->misc.release(); m->energies.release(); m->hist.release();
     m->sw_a.release(); m->sw_b.release(); m->sw_tile.release(); m->sw_counts.release();
     m->sw_tile_off.release(); m->sw_item_off.release(); m->sw_cursor.release(); m->sw_ctr.release();
@@ -1092,6 +1123,55 @@ mcrt_status mcrt_set_observers(mcrt_model* m, int n_incl, int img_npix, double i
     mcrt_status s = ensure_bins(m);
     if (s != MCRT_OK) return s;
     return clear_bins(m);
+}
+
+mcrt_status mcrt_set_peeloff(mcrt_model* m, const double* dirs, int n) {
+    if (!m) return MCRT_E_ARG;
+    if (!m->have_obs) return fail(m, MCRT_E_STATE, "set observers before peeling-off directions");
+    if (n < 0 || (n > 0 && !dirs)) return fail(m, MCRT_E_ARG, "bad peeling-off directions");
+    for (int i = 0; i < n; ++i) {
+        const double r = sqrt(dirs[3 * i] * dirs[3 * i] + dirs[3 * i + 1] * dirs[3 * i + 1] +
+                              dirs[3 * i + 2] * dirs[3 * i + 2]);
+        if (!(fabs(r - 1.0) < 1e-9)) return fail(m, MCRT_E_ARG, "peeling-off directions must be unit vectors");
+    }
+    hipSetDevice(m->device);
+    m->n_peel = n;
+    HIPCHK(m->peel_dir.ensure((size_t)(n > 0 ? 3 * n : 3)));
+    if (n > 0) HIPCHK(hipMemcpy(m->peel_dir.p, dirs, (size_t)3 * n * sizeof(double), hipMemcpyHostToDevice));
+    mcrt_status s = ensure_bins(m);
+    if (s != MCRT_OK) return s;
+    s = clear_bins(m);
+    if (s != MCRT_OK) return s;
+    HIPCHK(hipStreamSynchronize(m->stream));
+    return MCRT_OK;
+}
+
+mcrt_status mcrt_get_peeled_sed(mcrt_model* m, double* sum, double* sum2, size_t n) {
+    if (!m || !sum) return MCRT_E_ARG;
+    const size_t nps = (size_t)m->n_peel * 2 * m->kap.size();
+    if (n != nps) return fail(m, MCRT_E_SIZE, "peeled SED size is n_peel*2*n_nu");
+    hipSetDevice(m->device);
+    if (nps) {
+        HIPCHK(hipMemcpyAsync(sum, m->psed_sum.p, nps * sizeof(double), hipMemcpyDeviceToHost, m->stream));
+        if (sum2)
+            HIPCHK(hipMemcpyAsync(sum2, m->psed_sum2.p, nps * sizeof(double), hipMemcpyDeviceToHost, m->stream));
+    }
+    HIPCHK(hipStreamSynchronize(m->stream));
+    return MCRT_OK;
+}
+
+mcrt_status mcrt_get_peeled_images(mcrt_model* m, double* sum, double* sum2, size_t n) {
+    if (!m || !sum) return MCRT_E_ARG;
+    const size_t npi = (size_t)m->n_img * m->n_peel * m->npix * m->npix;
+    if (n != npi) return fail(m, MCRT_E_SIZE, "peeled image size is n_img*n_peel*npix^2");
+    hipSetDevice(m->device);
+    if (npi) {
+        HIPCHK(hipMemcpyAsync(sum, m->pimg_sum.p, npi * sizeof(double), hipMemcpyDeviceToHost, m->stream));
+        if (sum2)
+            HIPCHK(hipMemcpyAsync(sum2, m->pimg_sum2.p, npi * sizeof(double), hipMemcpyDeviceToHost, m->stream));
+    }
+    HIPCHK(hipStreamSynchronize(m->stream));
+    return MCRT_OK;
 }
 
 mcrt_status mcrt_set_run(mcrt_model* m, const mcrt_run_cfg* c) {

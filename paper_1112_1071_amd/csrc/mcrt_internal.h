@@ -79,6 +79,16 @@ struct TransportParams {
     const int* img_of_bin;  // [nnu] image index or -1
     double* img_sum;
     double* img_sum2;
+    // peeling-off (Sec. 2.6.2): n_peel observer unit vectors; SED
+    // [n_peel][2][nnu] (0 direct, 1 scattered/re-emitted) and images
+    // [n_img][n_peel][npix][npix], energy per steradian
+    int n_peel;
+    const double* peel_dir;  // [3*n_peel]
+    const R* rho_lin;        // density x-fastest (the ray march to the boundary)
+    double* psed_sum;
+    double* psed_sum2;
+    double* pimg_sum;
+    double* pimg_sum2;
     // event log
     int64_t ev_packets;
     int ev_cap;

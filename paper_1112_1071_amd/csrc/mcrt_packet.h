@@ -270,6 +270,97 @@ template <typename R> struct Tables {
     const R* scoarse;
 };
 
+// Optical depth in bin k from the point (cell c, in-cell offsets f) to the
+// grid boundary along the unit vector o: the walk of a flight, without
+// interactions, on the x-fastest density.
+template <typename R>
+__device__ double tau_to_boundary(const TransportParams<R>& P, int c0, int c1, int c2, R f0, R f1,
+                                  R f2, double o0, double o1, double o2, R chi) {
+    const R INF = Const<R>::inf();
+    const R d0 = (R)o0, d1 = (R)o1, d2 = (R)o2;
+    const R dtx = P.dxr[0] / fabs(d0), dty = P.dxr[1] / fabs(d1), dtz = P.dxr[2] / fabs(d2);
+    R tx = d0 == (R)0 ? INF : (d0 > (R)0 ? (R)1 - f0 : f0) * dtx;
+    R ty = d1 == (R)0 ? INF : (d1 > (R)0 ? (R)1 - f1 : f1) * dty;
+    R tz = d2 == (R)0 ? INF : (d2 > (R)0 ? (R)1 - f2 : f2) * dtz;
+    R t = (R)0;
+    double tau = 0.0;
+    // a start point on a wall belongs to the cell the ray enters (the start
+    // cell rule of emission, applied with the direction o)
+    if (f0 == (R)1 && d0 >= (R)0) { ++c0; f0 = (R)0; tx = d0 == (R)0 ? INF : dtx; }
+    else if (f0 == (R)0 && d0 < (R)0) { --c0; f0 = (R)1; tx = dtx; }
+    if (f1 == (R)1 && d1 >= (R)0) { ++c1; f1 = (R)0; ty = d1 == (R)0 ? INF : dty; }
+    else if (f1 == (R)0 && d1 < (R)0) { --c1; f1 = (R)1; ty = dty; }
+    if (f2 == (R)1 && d2 >= (R)0) { ++c2; f2 = (R)0; tz = d2 == (R)0 ? INF : dtz; }
+    else if (f2 == (R)0 && d2 < (R)0) { --c2; f2 = (R)1; tz = dtz; }
+    if ((unsigned)c0 >= (unsigned)P.n[0] || (unsigned)c1 >= (unsigned)P.n[1] ||
+        (unsigned)c2 >= (unsigned)P.n[2])
+        return 0.0;
+    for (;;) {
+        const bool ax1 = ty < tx;
+        R tm = ax1 ? ty : tx;
+        const bool ax2 = tz < tm;
+        tm = ax2 ? tz : tm;
+        const bool ax0 = !ax1 && !ax2;
+        const bool by = ax1 && !ax2;
+        const R l = fmax(tm - t, (R)0);
+        tau += (double)(P.rho_lin[c0 + (int64_t)P.n[0] * (c1 + (int64_t)P.n[1] * c2)] * chi * l);
+        t = fmax(tm, t);
+        c0 += ax0 ? (d0 > (R)0 ? 1 : -1) : 0;
+        c1 += by ? (d1 > (R)0 ? 1 : -1) : 0;
+        c2 += ax2 ? (d2 > (R)0 ? 1 : -1) : 0;
+        if ((unsigned)c0 >= (unsigned)P.n[0] || (unsigned)c1 >= (unsigned)P.n[1] ||
+            (unsigned)c2 >= (unsigned)P.n[2])
+            return tau;
+        tx += ax0 ? dtx : (R)0;
+        ty += by ? dty : (R)0;
+        tz += ax2 ? dtz : (R)0;
+    }
+}
+
+// Peeling-off (Sec. 2.6.2): toward every observer o, eps * p(o) * exp(-tau)
+// in the packet's bin into SED component comp (0 direct, 1 processed) and,
+// for image bins, into the pixel of the packet's position projected along o.
+// p is the HG phase function per steradian for the incoming direction
+// (scattering, have_din) or 1/(4 pi) for isotropic emission.
+template <typename R>
+__device__ void peel(const Packet<R>& s, const TransportParams<R>& P, R f0, R f1, R f2, int comp,
+                     bool have_din, double di0, double di1, double di2) {
+    const double four_pi = 12.566370614359172953850573533118;
+    const double g = (double)P.g[s.k];
+    const double eps = P.eps0 * (double)s.wgt;
+    const int ii = P.n_img > 0 ? P.img_of_bin[s.k] : -1;
+    for (int i = 0; i < P.n_peel; ++i) {
+        const double o0 = P.peel_dir[3 * i], o1 = P.peel_dir[3 * i + 1], o2 = P.peel_dir[3 * i + 2];
+        double p = 1.0 / four_pi;
+        if (have_din) {
+            const double q = 1.0 + g * g - 2.0 * g * (di0 * o0 + di1 * o1 + di2 * o2);
+            p = (1.0 - g * g) / (four_pi * q * sqrt(q));
+        }
+        const double w = eps * p * exp(-tau_to_boundary(P, s.c0, s.c1, s.c2, f0, f1, f2, o0, o1, o2, s.chi));
+        const size_t q = ((size_t)i * 2 + comp) * P.nnu + s.k;
+        unsafeAtomicAdd(P.psed_sum + q, w);
+        unsafeAtomicAdd(P.psed_sum2 + q, w * w);
+        if (ii < 0) continue;
+        const double px = ((double)s.c0 + (double)f0 - 0.5 * P.n[0]) * P.dx[0];
+        const double py = ((double)s.c1 + (double)f1 - 0.5 * P.n[1]) * P.dx[1];
+        const double pz = ((double)s.c2 + (double)f2 - 0.5 * P.n[2]) * P.dx[2];
+        double ex0 = -o1, ex1 = o0;
+        const double en = sqrt(ex0 * ex0 + ex1 * ex1);
+        if (en < 1e-12) { ex0 = 1.0; ex1 = 0.0; }
+        else { ex0 /= en; ex1 /= en; }
+        const double ey0 = -o2 * ex1, ey1 = o2 * ex0, ey2 = o0 * ex1 - o1 * ex0;
+        const double X = px * ex0 + py * ex1;
+        const double Y = px * ey0 + py * ey1 + pz * ey2;
+        const double fx = floor((X + P.img_hw) / (2.0 * P.img_hw) * P.npix);
+        const double fy = floor((Y + P.img_hw) / (2.0 * P.img_hw) * P.npix);
+        if (fx >= 0.0 && fy >= 0.0 && fx < P.npix && fy < P.npix) {
+            const size_t r = (((size_t)ii * P.n_peel + i) * P.npix + (size_t)fy) * P.npix + (size_t)fx;
+            unsafeAtomicAdd(P.pimg_sum + r, w);
+            unsafeAtomicAdd(P.pimg_sum2 + r, w * w);
+        }
+    }
+}
+
 template <typename R>
 __device__ __forceinline__ void emit(Packet<R>& s, Stream<R>& rs, const TransportParams<R>& P,
                                      const Tables<R>& tb, uint64_t id) {
@@ -315,6 +406,7 @@ __device__ __forceinline__ void emit(Packet<R>& s, Stream<R>& rs, const Transpor
     s.nev = 0;
     s.nlog = 0;
     log_event(s, P, MCRT_EV_EMIT, -1);
+    if (P.binning && P.n_peel > 0) peel(s, P, f[0], f[1], f[2], 0, false, 0.0, 0.0, 0.0);
     begin_flight(s, P, rs, f[0], f[1], f[2]);
     const bool inside = (unsigned)s.c0 < (unsigned)P.n[0] && (unsigned)s.c1 < (unsigned)P.n[1] &&
                         (unsigned)s.c2 < (unsigned)P.n[2];
@@ -449,9 +541,11 @@ __device__ __forceinline__ void interact(Packet<R>& s, Stream<R>& rs, const Tran
         log_event(s, P, MCRT_EV_ABSORB, -1);
         s.chi = P.chi[s.k];
         s.kap = P.kap[s.k];
+        if (P.binning && P.n_peel > 0) peel(s, P, f0, f1, f2, 1, false, 0.0, 0.0, 0.0);
     } else {
         const R u_mu = rs.next(), u_phi = rs.next();
         const R mu = hg_mu(P.g[s.k], u_mu);
+        if (P.binning && P.n_peel > 0) peel(s, P, f0, f1, f2, 1, true, s.d0, s.d1, s.d2);
         rotate(s, mu, Const<R>::two_pi * u_phi);
         ++cnt[C_SCATTER];
         log_event(s, P, MCRT_EV_SCATTER, -1);

@@ -57,7 +57,8 @@ hipError_t launch_loss(int64_t nvox, const float* y, const float* t, const float
 hipError_t launch_head_back(int C, int64_t nvox, const uint16_t* x, const float* w, const float* dy,
                             float* dw, float* db, float* dx, hipStream_t st);
 hipError_t launch_adam(int64_t n, float* p, const float* g, float* m, float* v, float lr, float b1,
-                       float b2, float eps, float c1, float c2, hipStream_t st);
+                       float b2, float eps, float c1, float c2, float clip, double* sumsq,
+                       hipStream_t st);
 hipError_t launch_weights_bf16(int64_t n, const float* p, int taps, int Cout, int Cin, int conv3,
                                uint16_t* w16, uint16_t* wt16, hipStream_t st);
 hipError_t launch_exp10(int64_t n, const float* y, double* T, hipStream_t st);
@@ -112,11 +113,12 @@ struct mcrt_surrogate {
     uint16_t* w16 = nullptr; // BF16 forward weights (same offsets as p)
     uint16_t* wt16 = nullptr;// BF16 backward-data weights
     int64_t step = 0;
+    double grad_clip = 0.0;  // global-norm clipping of the gradient (0: off)
     // per-call buffers
     float* pred = nullptr;
     float* dpred = nullptr;
     uint16_t* dz = nullptr;
-    double* loss = nullptr;
+    double* loss = nullptr;   // [0] loss, [1] gradient sum of squares
     size_t cap_vox = 0, cap_dz = 0;
 };
 
@@ -365,7 +367,7 @@ mcrt_status mcrt_surrogate_create(mcrt_surrogate** out, int hip_device, int base
     bool ok = hipMalloc((void**)&s->p, n * 4) == hipSuccess && hipMalloc((void**)&s->gp, n * 4) == hipSuccess &&
               hipMalloc((void**)&s->m1, n * 4) == hipSuccess && hipMalloc((void**)&s->m2, n * 4) == hipSuccess &&
               hipMalloc((void**)&s->w16, n * 2) == hipSuccess && hipMalloc((void**)&s->wt16, n * 2) == hipSuccess &&
-              hipMalloc((void**)&s->loss, sizeof(double)) == hipSuccess;
+              hipMalloc((void**)&s->loss, 2 * sizeof(double)) == hipSuccess;
     if (!ok) {
         mcrt_surrogate_destroy(s);
         return MCRT_E_NOMEM;
@@ -419,6 +421,13 @@ mcrt_status mcrt_surrogate_set_stream(mcrt_surrogate* s, void* hip_stream) {
 }
 
 int64_t mcrt_surrogate_param_count(const mcrt_surrogate* s) { return s ? s->nparam : -1; }
+
+mcrt_status mcrt_surrogate_set_grad_clip(mcrt_surrogate* s, double max_norm) {
+    if (!s) return MCRT_E_ARG;
+    if (!(max_norm >= 0.0) || !isfinite(max_norm)) return sfail(s, MCRT_E_ARG, "max_norm must be >= 0");
+    s->grad_clip = max_norm;
+    return MCRT_OK;
+}
 
 mcrt_status mcrt_surrogate_get_params(mcrt_surrogate* s, float* host, size_t n) {
     if (!s || !host) return MCRT_E_ARG;
@@ -480,7 +489,7 @@ mcrt_status mcrt_surrogate_train_step(mcrt_surrogate* s, const float* d_x, const
     r = forward(s, d_x, N, D);
     if (r != MCRT_OK) return r;
     const int64_t vox = (int64_t)N * D * D * D;
-    SCHK(hipMemsetAsync(s->loss, 0, sizeof(double), s->stream));
+    SCHK(hipMemsetAsync(s->loss, 0, 2 * sizeof(double), s->stream));
     SCHK(launch_loss(vox, s->pred, d_target, d_mask, (float)(1.0 / mask_count), s->dpred, s->loss,
                      s->stream));
     r = backward(s, N, D);
@@ -491,7 +500,7 @@ mcrt_status mcrt_surrogate_train_step(mcrt_surrogate* s, const float* d_x, const
         const double c1 = 1.0 / (1.0 - pow(b1, (double)s->step));
         const double c2 = 1.0 / (1.0 - pow(b2, (double)s->step));
         SCHK(launch_adam(s->nparam, s->p, s->gp, s->m1, s->m2, (float)lr, (float)b1, (float)b2, 1e-8f,
-                         (float)c1, (float)c2, s->stream));
+                         (float)c1, (float)c2, (float)s->grad_clip, s->loss + 1, s->stream));
         r = refresh_bf16(s);
         if (r != MCRT_OK) return r;
     }

@@ -325,12 +325,34 @@ __global__ void k_head_back(int64_t nvox, const uint16_t* __restrict__ x, const 
 // Adam on the FP32 master parameters (bias-corrected moments; c1, c2 are
 // 1/(1 - b1^step), 1/(1 - b2^step)).
 
+// Sum of squares of the gradient (for clipping by global norm).
+__global__ void k_sumsq(int64_t n, const float* __restrict__ g, double* out) {
+    __shared__ double s[256];
+    double a = 0.0;
+    for (int64_t j = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; j < n;
+         j += (int64_t)gridDim.x * blockDim.x)
+        a += (double)g[j] * g[j];
+    s[threadIdx.x] = a;
+    __syncthreads();
+    for (int o = blockDim.x / 2; o > 0; o >>= 1) {
+        if ((int)threadIdx.x < o) s[threadIdx.x] += s[threadIdx.x + o];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) atomicAdd(out, s[0]);
+}
+
+// gradients are scaled by min(1, clip / ||g||) when clip > 0 (sumsq on device)
 __global__ void k_adam(int64_t n, float* __restrict__ p, const float* __restrict__ g,
                        float* __restrict__ m, float* __restrict__ v, float lr, float b1, float b2,
-                       float eps, float c1, float c2) {
+                       float eps, float c1, float c2, float clip, const double* __restrict__ sumsq) {
+    float scale = 1.f;
+    if (clip > 0.f) {
+        const double nrm = sqrt(*sumsq);
+        if (nrm > (double)clip) scale = (float)((double)clip / nrm);
+    }
     for (int64_t j = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; j < n;
          j += (int64_t)gridDim.x * blockDim.x) {
-        const float gj = g[j];
+        const float gj = g[j] * scale;
         const float mj = b1 * m[j] + (1.f - b1) * gj;
         const float vj = b2 * v[j] + (1.f - b2) * gj * gj;
         m[j] = mj;
@@ -465,9 +487,12 @@ hipError_t launch_head_back(int C, int64_t nvox, const uint16_t* x, const float*
     return hipGetLastError();
 }
 hipError_t launch_adam(int64_t n, float* p, const float* g, float* m, float* v, float lr, float b1,
-                       float b2, float eps, float c1, float c2, hipStream_t st) {
+                       float b2, float eps, float c1, float c2, float clip, double* sumsq,
+                       hipStream_t st) {
+    if (clip > 0.f)
+        hipLaunchKernelGGL(k_sumsq, dim3(blocks_for(n)), dim3(256), 0, st, n, g, sumsq);
     hipLaunchKernelGGL(k_adam, dim3(blocks_for(n)), dim3(256), 0, st, n, p, g, m, v, lr, b1, b2, eps,
-                       c1, c2);
+                       c1, c2, clip, (const double*)sumsq);
     return hipGetLastError();
 }
 hipError_t launch_weights_bf16(int64_t n, const float* p, int taps, int Cout, int Cin, int conv3,

@@ -122,7 +122,7 @@ __device__ __forceinline__ void load_rec(Packet<R>& s, Stream<R>& rs, const Tran
 template <typename R, int K>
 __device__ __forceinline__ void walk_tile(Packet<R>& s, const TransportParams<R>& P, int o0, int o1,
                                           int o2, int tz, const R* __restrict__ rho_t,
-                                          R* __restrict__ acc_t, R* __restrict__ acc2_t,
+                                          R* __restrict__ acc_t, double* __restrict__ acc2_t,
                                           uint32_t* cnt) {
 #pragma unroll
     for (int i = 0; i < K; ++i) {
@@ -145,7 +145,7 @@ __device__ __forceinline__ void walk_tile(Packet<R>& s, const TransportParams<R>
             else s.tau_acc += dtau;
             const R w = s.wgt * l * s.kap;
             atomicAdd(acc_t + jl, w);
-            if (acc2_t) atomicAdd(acc2_t + jl, w * w);
+            if (acc2_t) atomicAdd(acc2_t + jl, (double)w * (double)w);  // w^2 may exceed FP32
             if (hit) {
                 s.t = ts + l;
                 s.st = ST_EVENT;
@@ -254,10 +254,11 @@ __global__ void __launch_bounds__(256) k_sweep(TransportParams<R> P, SweepParams
     __shared__ unsigned long long s_cnt[C_COUNT];
     __shared__ double s_energy[2];
     const int tcells = kTX * kTY * S.tz;
-    R* rho_t = reinterpret_cast<R*>(smem_raw);
+    // LDS: Sum w^2 (FP64, when kept), density, tally, staged tables
+    double* acc2_t = P.acc2 ? reinterpret_cast<double*>(smem_raw) : nullptr;
+    R* rho_t = reinterpret_cast<R*>(smem_raw + (P.acc2 ? tcells * sizeof(double) : 0));
     R* acc_t = rho_t + tcells;
-    R* acc2_t = P.acc2 ? acc_t + tcells : nullptr;
-    R* sm_tab = acc_t + (P.acc2 ? 2 : 1) * tcells;
+    R* sm_tab = acc_t + tcells;
     if (threadIdx.x < C_COUNT) s_cnt[threadIdx.x] = 0ull;
     if (threadIdx.x < 2) s_energy[threadIdx.x] = 0.0;
     Tables<R> tb;
@@ -316,7 +317,7 @@ __global__ void __launch_bounds__(256) k_sweep(TransportParams<R> P, SweepParams
                 r = P.rho[gx + (int64_t)P.n[0] * (gy + (int64_t)P.n[1] * gz)];
             rho_t[i] = r;
             acc_t[i] = (R)0;
-            if (acc2_t) acc2_t[i] = (R)0;
+            if (acc2_t) acc2_t[i] = 0.0;
         }
         __syncthreads();
 
@@ -363,12 +364,12 @@ __global__ void __launch_bounds__(256) k_sweep(TransportParams<R> P, SweepParams
         // the tile's partial sums into the FP64 tally (cells of this tile only)
         for (int i = threadIdx.x; i < tcells; i += blockDim.x) {
             const R a = acc_t[i];
-            const R a2 = acc2_t ? acc2_t[i] : (R)0;
-            if (a != (R)0 || a2 != (R)0) {
+            const double a2 = acc2_t ? acc2_t[i] : 0.0;
+            if (a != (R)0 || a2 != 0.0) {
                 const int lx = i % kTX, ly = (i / kTX) % kTY, lz = i / (kTX * kTY);
                 const int64_t j = (o0 + lx) + (int64_t)P.n[0] * ((o1 + ly) + (int64_t)P.n[1] * (o2 + lz));
                 if (a != (R)0) unsafeAtomicAdd(P.acc + j, (double)a);
-                if (a2 != (R)0) unsafeAtomicAdd(P.acc2 + j, (double)a2);
+                if (a2 != 0.0) unsafeAtomicAdd(P.acc2 + j, a2);
             }
         }
     }

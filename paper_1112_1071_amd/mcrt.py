@@ -53,7 +53,7 @@ class IterStats(C.Structure):
         ("n_scatter", C.c_int64), ("n_absorb", C.c_int64), ("n_escape", C.c_int64),
         ("n_killed", C.c_int64), ("e_escaped", C.c_double), ("e_killed", C.c_double),
         ("ms_transport", C.c_double), ("ms_update", C.c_double), ("ms_total", C.c_double),
-        ("n_sweeps", C.c_int64),
+        ("n_sweeps", C.c_int64), ("n_visits", C.c_int64),
     ]
 
     def as_dict(self) -> dict:
@@ -147,6 +147,7 @@ def lib():
         "mcrt_surrogate_last_error": ([vp], C.c_char_p),
         "mcrt_surrogate_set_stream": ([vp, vp], i32),
         "mcrt_surrogate_param_count": ([vp], i64),
+        "mcrt_surrogate_set_grad_clip": ([vp, dbl], i32),
         "mcrt_surrogate_get_params": ([vp, vp, sz], i32),
         "mcrt_surrogate_set_params": ([vp, vp, sz], i32),
         "mcrt_surrogate_get_grads": ([vp, vp, sz], i32),
@@ -154,6 +155,9 @@ def lib():
         "mcrt_surrogate_train_step": ([vp, vp, vp, vp, i32, i32, dbl, dbl, i32, C.POINTER(dbl)], i32),
         "mcrt_surrogate_predict_T": ([vp, vp, i32, i32, vp], i32),
         "mcrt_model_features": ([vp, vp, sz], i32),
+        "mcrt_set_peeloff": ([vp, vp, i32], i32),
+        "mcrt_get_peeled_sed": ([vp, vp, vp, sz], i32),
+        "mcrt_get_peeled_images": ([vp, vp, vp, sz], i32),
         "mcrt_warm_start": ([vp, vp, C.POINTER(dbl)], i32),
     }
     for name, (args, res) in sig.items():
@@ -226,6 +230,11 @@ class Model:
         self._check(self.L.mcrt_set_observers(self.h, self.n_incl, self.npix,
                                               float(ob.get("img_half_width", 0.0)),
                                               _ptr(bins) if bins.size else None, self.n_img))
+        dirs = np.ascontiguousarray(cfg.get("peeloff", {}).get("dirs", np.zeros((0, 3))),
+                                    dtype=np.float64).reshape(-1, 3)
+        self.n_peel = int(dirs.shape[0])
+        if self.n_peel:
+            self._check(self.L.mcrt_set_peeloff(self.h, _ptr(dirs), self.n_peel))
         run = dict(cfg.get("run", {}))
         run.update(run_overrides)
         self.set_run(**run)
@@ -314,6 +323,21 @@ class Model:
         sh = (self.n_img, self.n_incl, self.npix, self.npix)
         return s[:n].reshape(sh), s2[:n].reshape(sh)
 
+    def peeled_sed(self):
+        """[n_peel][2][nnu] erg/s per sr (component 0 direct, 1 processed)."""
+        n = self.n_peel * 2 * self.nnu
+        s, s2 = np.zeros(max(n, 1)), np.zeros(max(n, 1))
+        self._check(self.L.mcrt_get_peeled_sed(self.h, _ptr(s), _ptr(s2), n))
+        sh = (self.n_peel, 2, self.nnu)
+        return s[:n].reshape(sh), s2[:n].reshape(sh)
+
+    def peeled_images(self):
+        n = self.n_img * self.n_peel * self.npix * self.npix
+        s, s2 = np.zeros(max(n, 1)), np.zeros(max(n, 1))
+        self._check(self.L.mcrt_get_peeled_images(self.h, _ptr(s), _ptr(s2), n))
+        sh = (self.n_img, self.n_peel, self.npix, self.npix)
+        return s[:n].reshape(sh), s2[:n].reshape(sh)
+
     def event_log(self):
         npk = int(self.run["event_log_packets"])
         cap = int(self.run["event_log_cap"]) or 256
@@ -396,6 +420,9 @@ class Surrogate:
         if not (t.is_cuda and t.dtype == torch.float32 and t.is_contiguous()):
             raise ValueError(f"{name}: contiguous FP32 device tensor expected")
         return C.c_void_p(t.data_ptr())
+
+    def set_grad_clip(self, max_norm: float):
+        self._check(self.L.mcrt_surrogate_set_grad_clip(self.h, float(max_norm)))
 
     def params(self) -> np.ndarray:
         p = np.zeros(self.n_params, dtype=np.float32)

@@ -208,7 +208,8 @@ def main():
     t.add_argument("--mc-iter", type=int, default=5)
     t.add_argument("--epochs", type=int, default=30)
     t.add_argument("--batch", type=int, default=8)
-    t.add_argument("--lr", type=float, default=1e-3)
+    t.add_argument("--lr", type=float, default=3e-4)
+    t.add_argument("--clip", type=float, default=1.0)
     t.add_argument("--channels", type=int, default=16)
     t.add_argument("--members", default="sphere,disk,clump")
     t.add_argument("--history", default="")
@@ -229,6 +230,7 @@ def main():
         H = generate([SEED_HOLDOUT + i for i in range(args.n_holdout)], args.side, args.ppc,
                      args.mc_iter, members=members)
         sur = mcrt.Surrogate(0, args.channels, seed=1)
+        sur.set_grad_clip(args.clip)
         hist = train(sur, X, Y, K, args.epochs, args.batch, args.lr, holdout=H)
         os.makedirs(os.path.dirname(os.path.abspath(args.out)), exist_ok=True)
         sur.save(args.out)

@@ -110,6 +110,28 @@ def test_forward_and_gradients_match_reference(M, N, D):
     sur.close()
 
 
+def test_gradient_clipping(M):
+    import torch
+
+    N, D = 1, 8
+    sur = M.Surrogate(0, 16, seed=5)
+    p = sur.params().astype(np.float64)
+    x = torch.as_tensor(_features(N, D, seed=3), device="cuda:0").contiguous()
+    r = np.random.default_rng(9)
+    t = torch.as_tensor(r.uniform(1, 2.5, D ** 3).astype(np.float32), device="cuda:0")
+    k = torch.ones(D ** 3, dtype=torch.float32, device="cuda:0")
+    sur.train_step(x, t, k, N, D, lr=0.0, apply_update=False)
+    g = sur.grads().astype(np.float64)
+    clip = 0.25 * np.linalg.norm(g)
+    sur.set_grad_clip(clip)
+    sur.train_step(x, t, k, N, D, lr=1e-3, apply_update=True)
+    q_ref, _, _ = nn.adam(p, g * clip / np.linalg.norm(g), np.zeros_like(p), np.zeros_like(p), 1, 1e-3)
+    np.testing.assert_allclose(sur.params().astype(np.float64), q_ref, rtol=1e-5, atol=1e-7)
+    with pytest.raises(M.MCRTError):
+        sur.set_grad_clip(-1.0)
+    sur.close()
+
+
 def test_set_params_roundtrip_and_errors(M):
     sur = M.Surrogate(0, 16, seed=1)
     p = sur.params()
