@@ -201,6 +201,8 @@ def main():
     ap.add_argument("--mode", type=int, default=-1,
                     help="transport_mode: 0 per-lane persistent walk, 1 tiled sweeps")
     ap.add_argument("--tile-z", type=int, default=0)
+    ap.add_argument("--tile-xy", type=int, default=0)
+    ap.add_argument("--tally-copies", type=int, default=0)
     ap.add_argument("--visit-events", type=int, default=0)
     args = ap.parse_args()
     if args.gpus != 1:
@@ -239,6 +241,10 @@ def main():
         run["transport_mode"] = args.mode
     if args.tile_z:
         run["tile_z"] = args.tile_z
+    if args.tile_xy:
+        run["tile_xy"] = args.tile_xy
+    if args.tally_copies:
+        run["tally_copies"] = args.tally_copies
     if args.visit_events:
         run["visit_events"] = args.visit_events
     model = mcrt.Model(cfg, **run)

@@ -102,9 +102,10 @@ typedef struct {
                                   packets grouped by tile of 16x16xtile_z cells, each tile
                                   walked with density and tally in LDS, tally flushed to
                                   FP64 once per work item [0]; same packet histories     */
-    int32_t tile_z;            /* tiled sweeps: tile extent in z, 4, 8 or 16 [8]          */
+    int32_t tile_z;            /* tiled sweeps: tile extent in z, 4, 8, 16 or 32 [8]      */
     int32_t visit_events;      /* tiled sweeps: interactions per tile visit before a
                                   packet waits for the next sweep [256]                   */
+    int32_t tile_xy;           /* tiled sweeps: tile extent in x and y, 16 or 32 [16]     */
 } mcrt_run_cfg;
 
 /* Statistics of one pass (a Lucy iteration or the final pass). */

@@ -50,12 +50,10 @@ hipError_t launch_sweep_emit(const TransportParams<R>& P, const SweepParams& S, 
                              uint64_t count, int blocks, hipStream_t st);
 template <typename R>
 hipError_t launch_sweep(const TransportParams<R>& P, const SweepParams& S, int K, int blocks,
-                        size_t lds, hipStream_t st);
-template <typename R> int sweep_max_blocks_per_cu(int K, size_t lds);
-template <typename R>
-hipError_t launch_tile_sort(const SweepParams& S, const void* out, void* in, unsigned* counts,
-                            unsigned* tile_off, unsigned* item_off, unsigned* cursor, int blocks,
-                            hipStream_t st);
+                        int threads, size_t lds, hipStream_t st);
+template <typename R> int sweep_max_blocks_per_cu(int K, int threads, size_t lds);
+hipError_t launch_tile_sort(const SweepParams& S, unsigned* order, unsigned* tile_off,
+                            unsigned* item_off, unsigned* cursor, int blocks, hipStream_t st);
 hipError_t launch_zero_u32(unsigned* p, int n, hipStream_t st);
 }  // namespace mcrt
 
@@ -153,7 +151,7 @@ struct mcrt_model {
     // tiled sweeps: packet records (two buffers), record tiles, tile counts and
     // offsets, work-item offsets, scatter cursors, [item_next, out_count]
     DBuf<unsigned char> sw_a, sw_b;
-    DBuf<unsigned> sw_tile, sw_counts, sw_tile_off, sw_item_off, sw_cursor, sw_ctr;
+    DBuf<unsigned> sw_tile, sw_counts, sw_tile_off, sw_item_off, sw_cursor, sw_ctr, sw_order;
     size_t lds_max = 65536 - 1024;  // dynamic LDS a transport kernel may take
     int64_t ev_packets = 0;
     int ev_cap = 0;
@@ -585,7 +583,7 @@ int persistent_blocks(const mcrt_model* m, int bpc, int64_t np, int threads) {
 // a record with its tile, then sort-by-tile and sweep alternate until no
 // record is left.  The host reads the record count after each sweep.
 constexpr int64_t kSweepBatch = 1ll << 25;  // packets in flight at once
-constexpr int64_t kMaxSweeps = 1ll << 24;    // every visit advances a packet; this is a backstop
+constexpr int64_t kMaxSweeps = 1ll << 20;    // every visit advances a packet; this is a backstop
 
 template <typename R>
 mcrt_status run_sweeps(mcrt_model* m, TransportParams<R>& P, int64_t np, int64_t* n_sweeps,
@@ -593,9 +591,10 @@ mcrt_status run_sweeps(mcrt_model* m, TransportParams<R>& P, int64_t np, int64_t
     hipStream_t s = m->stream;
     constexpr bool f32 = std::is_same<R, float>::value;
     SweepParams S{};
-    S.tz = m->cfg.tile_z == 4 || m->cfg.tile_z == 16 ? m->cfg.tile_z : 8;
-    S.ntx = (m->n[0] + 15) / 16;
-    S.nty = (m->n[1] + 15) / 16;
+    S.txy = m->cfg.tile_xy == 32 ? 32 : 16;
+    S.tz = m->cfg.tile_z == 4 || m->cfg.tile_z == 16 || m->cfg.tile_z == 32 ? m->cfg.tile_z : 8;
+    S.ntx = (m->n[0] + S.txy - 1) / S.txy;
+    S.nty = (m->n[1] + S.txy - 1) / S.txy;
     S.ntz = (m->n[2] + S.tz - 1) / S.tz;
     S.ntiles = S.ntx * S.nty * S.ntz;
     S.visit_events = m->cfg.visit_events > 0 ? m->cfg.visit_events : 256;
@@ -604,6 +603,7 @@ mcrt_status run_sweeps(mcrt_model* m, TransportParams<R>& P, int64_t np, int64_t
     HIPCHK(m->sw_a.ensure((size_t)batch * rb));
     HIPCHK(m->sw_b.ensure((size_t)batch * rb));
     HIPCHK(m->sw_tile.ensure((size_t)batch));
+    HIPCHK(m->sw_order.ensure((size_t)batch));
     const bool fresh_counts = m->sw_counts.n < (size_t)S.ntiles;
     HIPCHK(m->sw_counts.ensure((size_t)S.ntiles));
     HIPCHK(m->sw_tile_off.ensure((size_t)S.ntiles + 1));
@@ -615,23 +615,32 @@ mcrt_status run_sweeps(mcrt_model* m, TransportParams<R>& P, int64_t np, int64_t
     S.item_next = m->sw_ctr.p;
     S.out_count = m->sw_ctr.p + 1;
     S.out_tile = m->sw_tile.p;
+    S.counts = m->sw_counts.p;
+    S.order = m->sw_order.p;
     S.tile_off = m->sw_tile_off.p;
     S.item_off = m->sw_item_off.p;
     // LDS: tile density and tally (and sum of squares), then the staged tables
-    const size_t tcells = (size_t)16 * 16 * S.tz;
-    const size_t tile_lds = tcells * (2 * sizeof(R) + (P.acc2 ? sizeof(double) : 0));
+    const size_t tcells = (size_t)S.txy * S.txy * S.tz;
+    const size_t tile_lds = tcells * (2 * sizeof(R) + (P.acc2 ? sizeof(double) : 0)) +
+                            2 * m->kap.size() * sizeof(R);  // + bin opacities chi, kappa
     const size_t tab_lds = (size_t)(m->src.size() + (kRows + m->src.size()) * m->ngroup) * sizeof(R);
     if (tile_lds > m->lds_max) return fail(m, MCRT_E_UNSUPPORTED, "tile does not fit in LDS; use a smaller tile_z");
     P.lds_tables = tile_lds + tab_lds <= m->lds_max ? 1 : 0;
     const size_t lds = tile_lds + (P.lds_tables ? tab_lds : 0);
     const int K = m->cfg.walk_batch == 1 || m->cfg.walk_batch == 2 ? m->cfg.walk_batch : 4;
-    const int bpc = m->cfg.blocks_per_cu > 0 ? m->cfg.blocks_per_cu : sweep_max_blocks_per_cu<R>(K, lds);
+    // a workgroup shares one tile: larger tiles get larger workgroups
+    const int threads = tcells >= 8192 ? 1024 : 256;
+    S.item = (unsigned)threads * 8u;
+    const int bpc =
+        m->cfg.blocks_per_cu > 0 ? m->cfg.blocks_per_cu : sweep_max_blocks_per_cu<R>(K, threads, lds);
     const int blocks = m->n_cu * bpc;
     P.packet_base = 0;
     int64_t sweeps = 0, visits = 0;
     for (int64_t b0 = 0; b0 < np; b0 += batch) {
         const int64_t cnt = np - b0 < batch ? np - b0 : batch;
-        S.out = m->sw_b.p;
+        unsigned char* bufs[2] = {m->sw_a.p, m->sw_b.p};
+        int w = 0;  // buffer the next records are written to
+        S.out = bufs[w];
         const int64_t eb = (cnt + 255) / 256;
         HIPCHK(launch_sweep_emit<R>(P, S, (uint64_t)b0, (uint64_t)cnt,
                                     (int)(eb < (int64_t)m->n_cu * 8 ? eb : (int64_t)m->n_cu * 8), s));
@@ -643,12 +652,13 @@ mcrt_status run_sweeps(mcrt_model* m, TransportParams<R>& P, int64_t np, int64_t
             if (++sweeps > kMaxSweeps) return fail(m, MCRT_E_DEVICE, "tiled sweeps did not finish");
             visits += nout;
             const int64_t sb = ((int64_t)nout + 255) / 256;
-            HIPCHK(launch_tile_sort<R>(S, m->sw_b.p, m->sw_a.p, m->sw_counts.p, m->sw_tile_off.p,
-                                       m->sw_item_off.p, m->sw_cursor.p,
-                                       (int)(sb < (int64_t)m->n_cu * 8 ? sb : (int64_t)m->n_cu * 8), s));
-            S.in = m->sw_a.p;
-            S.out = m->sw_b.p;
-            HIPCHK(launch_sweep<R>(P, S, K, blocks, lds, s));
+            HIPCHK(launch_tile_sort(S, m->sw_order.p, m->sw_tile_off.p, m->sw_item_off.p, m->sw_cursor.p,
+                                    (int)(sb < (int64_t)m->n_cu * 8 ? sb : (int64_t)m->n_cu * 8), s));
+            HIPCHK(launch_zero_u32(S.out_count, 1, s));
+            S.in = bufs[w];
+            w ^= 1;
+            S.out = bufs[w];
+            HIPCHK(launch_sweep<R>(P, S, K, blocks, threads, lds, s));
         }
     }
     *n_sweeps = sweeps;
@@ -861,6 +871,7 @@ mcrt_status mcrt_run_cfg_default(mcrt_run_cfg* c) {
     c->transport_mode = 0;
     c->tile_z = 8;
     c->visit_events = 256;
+    c->tile_xy = 16;
     return MCRT_OK;
 }
 
@@ -883,7 +894,7 @@ mcrt_status mcrt_create(mcrt_model** out, int hip_device) {
         int lds = 0;
         if (hipDeviceGetAttribute(&lds, hipDeviceAttributeMaxSharedMemoryPerBlock, hip_device) == hipSuccess &&
             lds > 0)
-            m->lds_max = (size_t)lds < 65536 ? (size_t)lds : 65536;
+            m->lds_max = (size_t)lds;
         m->lds_max -= 1024;  // static LDS of the kernels that take dynamic LDS
     }
     for (int i = 0; i < 4; ++i) hipEventCreate(&m->ev[i]);
@@ -917,6 +928,7 @@ void mcrt_destroy(mcrt_model* m) {
     m->misc.release(); m->energies.release(); m->hist.release();
     m->sw_a.release(); m->sw_b.release(); m->sw_tile.release(); m->sw_counts.release();
     m->sw_tile_off.release(); m->sw_item_off.release(); m->sw_cursor.release(); m->sw_ctr.release();
+    m->sw_order.release();
     if (m->own_stream && m->stream) hipStreamDestroy(m->stream);
     delete m;
 }
@@ -1191,9 +1203,12 @@ mcrt_status mcrt_set_run(mcrt_model* m, const mcrt_run_cfg* c) {
     if (c->blocks_per_cu < 0) return fail(m, MCRT_E_ARG, "blocks_per_cu must be >= 0");
     if (c->transport_mode != 0 && c->transport_mode != 1)
         return fail(m, MCRT_E_ARG, "transport_mode must be 0 or 1");
-    if (c->transport_mode == 1 && c->tile_z != 0 && c->tile_z != 4 && c->tile_z != 8 && c->tile_z != 16)
-        return fail(m, MCRT_E_ARG, "tile_z must be 4, 8 or 16");
+    if (c->transport_mode == 1 && c->tile_z != 0 && c->tile_z != 4 && c->tile_z != 8 && c->tile_z != 16 &&
+        c->tile_z != 32)
+        return fail(m, MCRT_E_ARG, "tile_z must be 4, 8, 16 or 32");
     if (c->visit_events < 0) return fail(m, MCRT_E_ARG, "visit_events must be >= 0");
+    if (c->tile_xy != 0 && c->tile_xy != 16 && c->tile_xy != 32)
+        return fail(m, MCRT_E_ARG, "tile_xy must be 16 or 32");
     const bool reset = !m->have_run || c->t_init != m->cfg.t_init;
     m->cfg = *c;
     if (m->cfg.event_log_cap == 0) m->cfg.event_log_cap = 256;

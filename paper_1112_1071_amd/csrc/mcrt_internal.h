@@ -101,16 +101,20 @@ struct TransportParams {
 
 // Tiled sweeps: the tiling and the buffers of one sweep.
 struct SweepParams {
-    int tz;                     // tile extent in z (cells); 16 in x and y
+    int txy;                    // tile extent in x and y (cells): 16 or 32
+    int tz;                     // tile extent in z (cells)
     int ntx, nty, ntz, ntiles;  // tiles per axis, total
     int visit_events;           // interactions per visit before a packet yields
-    const void* in;             // records of this sweep, grouped by tile
-    const unsigned* tile_off;   // [ntiles+1] first record of each tile
+    unsigned item;              // records per work item
+    const void* in;             // records of this sweep (in the order they were written)
+    const unsigned* order;      // record indices grouped by tile
+    const unsigned* tile_off;   // [ntiles+1] first entry of each tile in order
     const unsigned* item_off;   // [ntiles+1] first work item of each tile
     unsigned* item_next;        // work items handed out
     void* out;                  // records written in this sweep
     unsigned* out_tile;         // tile of each written record
     unsigned* out_count;
+    unsigned* counts;           // [ntiles] records written per tile (for the next sort)
 };
 
 // Cell-update parameters (always FP64).

@@ -28,8 +28,7 @@
 
 namespace mcrt {
 
-constexpr int kTX = 16, kTY = 16;    // tile extent in x and y (cells)
-constexpr unsigned kItem = 2048;     // records per work item
+constexpr int kDrainEvents = 32;     // interactions per visit once an item is drained
 enum : int { ST_MOVE = 5, ST_YIELD = 6 };
 
 // State of a packet between visits (the Packet fields that are not
@@ -42,7 +41,7 @@ template <typename R> struct __attribute__((aligned(16))) PacketRec {
 };
 
 __device__ __forceinline__ int tile_of(const SweepParams& S, int c0, int c1, int c2) {
-    return (c0 / kTX) + S.ntx * ((c1 / kTY) + S.nty * (c2 / S.tz));
+    return (c0 / S.txy) + S.ntx * ((c1 / S.txy) + S.nty * (c2 / S.tz));
 }
 
 template <typename R>
@@ -75,9 +74,8 @@ __device__ __forceinline__ void store_rec(PacketRec<R>* r, const Packet<R>& s, c
 }
 
 template <typename R>
-__device__ __forceinline__ void load_rec(Packet<R>& s, Stream<R>& rs, const TransportParams<R>& P,
-                                         const PacketRec<R>* r) {
-    const PacketRec<R> q = *r;
+__device__ __forceinline__ void unpack_rec(Packet<R>& s, Stream<R>& rs, const TransportParams<R>& P,
+                                           const PacketRec<R>& q, const R* chi_t, const R* kap_t) {
     s.c0 = q.c0;
     s.c1 = q.c1;
     s.c2 = q.c2;
@@ -103,8 +101,8 @@ __device__ __forceinline__ void load_rec(Packet<R>& s, Stream<R>& rs, const Tran
     s.dtx = P.dxr[0] / fabs(s.d0);
     s.dty = P.dxr[1] / fabs(s.d1);
     s.dtz = P.dxr[2] / fabs(s.d2);
-    s.chi = P.chi[s.k];
-    s.kap = P.kap[s.k];
+    s.chi = chi_t[s.k];
+    s.kap = kap_t[s.k];
     const uint64_t gid = P.packet_base + s.id;
     rs.p0 = (uint32_t)gid;
     rs.p1 = (uint32_t)(gid >> 32);
@@ -121,7 +119,7 @@ __device__ __forceinline__ void load_rec(Packet<R>& s, Stream<R>& rs, const Tran
 // segment by segment the arithmetic of walk(), with density and tally in LDS.
 template <typename R, int K>
 __device__ __forceinline__ void walk_tile(Packet<R>& s, const TransportParams<R>& P, int o0, int o1,
-                                          int o2, int tz, const R* __restrict__ rho_t,
+                                          int o2, int txy, int tz, const R* __restrict__ rho_t,
                                           R* __restrict__ acc_t, double* __restrict__ acc2_t,
                                           uint32_t* cnt) {
 #pragma unroll
@@ -134,7 +132,7 @@ __device__ __forceinline__ void walk_tile(Packet<R>& s, const TransportParams<R>
         const bool by = ax1 && !ax2;
         const R ts = s.t;
         R l = fmax(tm - s.t, (R)0);
-        const int jl = (s.c0 - o0) + kTX * ((s.c1 - o1) + kTY * (s.c2 - o2));
+        const int jl = (s.c0 - o0) + txy * ((s.c1 - o1) + txy * (s.c2 - o2));
         const R rho = rho_t[jl];
         if (rho > (R)0) {
             ++cnt[C_CROSS_DUST];
@@ -169,7 +167,7 @@ __device__ __forceinline__ void walk_tile(Packet<R>& s, const TransportParams<R>
         s.tx += ax0 ? s.dtx : (R)0;
         s.ty += by ? s.dty : (R)0;
         s.tz += ax2 ? s.dtz : (R)0;
-        if ((unsigned)(n0 - o0) >= (unsigned)kTX || (unsigned)(n1 - o1) >= (unsigned)kTY ||
+        if ((unsigned)(n0 - o0) >= (unsigned)txy || (unsigned)(n1 - o1) >= (unsigned)txy ||
             (unsigned)(n2 - o2) >= (unsigned)tz) {
             s.st = ST_MOVE;
             return;
@@ -178,10 +176,11 @@ __device__ __forceinline__ void walk_tile(Packet<R>& s, const TransportParams<R>
 }
 
 // Append the lanes' records whose state is ST_MOVE or ST_YIELD (one atomic per
-// wave) and free those lanes.
+// wave) and free those lanes.  Returns the record's tile in dest (or -1).
 template <typename R>
 __device__ __forceinline__ void append_moves(const SweepParams& S, Packet<R>& s, const Stream<R>& rs,
-                                             int lane) {
+                                             int lane, int& dest) {
+    dest = -1;
     const bool mine = s.st == ST_MOVE || s.st == ST_YIELD;
     const unsigned long long mv = __ballot(mine);
     if (!mv) return;
@@ -193,8 +192,25 @@ __device__ __forceinline__ void append_moves(const SweepParams& S, Packet<R>& s,
         const unsigned idx = base + (unsigned)__popcll(mv & __lanemask_lt());
         store_rec(reinterpret_cast<PacketRec<R>*>(S.out) + idx, s, rs,
                   s.st == ST_YIELD ? ST_EVENT : ST_WALK);
-        S.out_tile[idx] = (unsigned)tile_of(S, s.c0, s.c1, s.c2);
+        dest = tile_of(S, s.c0, s.c1, s.c2);
+        S.out_tile[idx] = (unsigned)dest;
         s.st = ST_EMPTY;
+    }
+}
+
+// count records per destination tile: one global atomic per distinct tile of
+// the wave
+__device__ __forceinline__ void count_tiles(unsigned* counts, int dest) {
+    bool pending = dest >= 0;
+    for (;;) {
+        const unsigned long long act = __ballot(pending);
+        if (!act) break;
+        const int leader = __ffsll((long long)act) - 1;
+        const int lt = __shfl(dest, leader);
+        const bool mine = pending && dest == lt;
+        const unsigned long long same = __ballot(mine);
+        if (__lane_id() == leader) atomicAdd(counts + lt, (unsigned)__popcll(same));
+        if (mine) pending = false;
     }
 }
 
@@ -241,24 +257,34 @@ __global__ void __launch_bounds__(256) k_sweep_emit(TransportParams<R> P, SweepP
             if (s.st == ST_ESC) escape(s, P, cnt, e_escaped);
             else s.st = ST_MOVE;
         }
-        append_moves(S, s, rs, lane);
+        int dest;
+        append_moves(S, s, rs, lane, dest);
+        count_tiles(S.counts, dest);
     }
     flush_block_counters(P, cnt, e_escaped, e_killed, s_cnt, s_energy);
 }
 
 // One sweep over the work items (persistent workgroups).
 template <typename R, int K>
-__global__ void __launch_bounds__(256) k_sweep(TransportParams<R> P, SweepParams S) {
+__global__ void __launch_bounds__(1024) k_sweep(TransportParams<R> P, SweepParams S) {
     extern __shared__ unsigned char smem_raw[];
     __shared__ unsigned s_item, s_next;
+    __shared__ unsigned s_nb[7];  // records leaving for this tile, -x, +x, -y, +y, -z, +z
     __shared__ unsigned long long s_cnt[C_COUNT];
     __shared__ double s_energy[2];
-    const int tcells = kTX * kTY * S.tz;
+    const int txy = S.txy;
+    const int tcells = txy * txy * S.tz;
     // LDS: Sum w^2 (FP64, when kept), density, tally, staged tables
     double* acc2_t = P.acc2 ? reinterpret_cast<double*>(smem_raw) : nullptr;
     R* rho_t = reinterpret_cast<R*>(smem_raw + (P.acc2 ? tcells * sizeof(double) : 0));
     R* acc_t = rho_t + tcells;
-    R* sm_tab = acc_t + tcells;
+    R* chi_t = acc_t + tcells;  // bin opacities
+    R* kap_t = chi_t + P.nnu;
+    R* sm_tab = kap_t + P.nnu;
+    for (int i = threadIdx.x; i < P.nnu; i += blockDim.x) {
+        chi_t[i] = P.chi[i];
+        kap_t[i] = P.kap[i];
+    }
     if (threadIdx.x < C_COUNT) s_cnt[threadIdx.x] = 0ull;
     if (threadIdx.x < 2) s_energy[threadIdx.x] = 0.0;
     Tables<R> tb;
@@ -293,6 +319,7 @@ __global__ void __launch_bounds__(256) k_sweep(TransportParams<R> P, SweepParams
             s_item = atomicAdd(S.item_next, 1u);
             s_next = 0u;
         }
+        if (threadIdx.x < 7) s_nb[threadIdx.x] = 0u;
         __syncthreads();
         const unsigned item = s_item;
         if (item >= n_items) break;
@@ -303,14 +330,14 @@ __global__ void __launch_bounds__(256) k_sweep(TransportParams<R> P, SweepParams
             else hi = mid - 1;
         }
         const int tile = lo;
-        const unsigned first = S.tile_off[tile] + (item - S.item_off[tile]) * kItem;
-        const unsigned end = min(first + kItem, S.tile_off[tile + 1]);
+        const unsigned first = S.tile_off[tile] + (item - S.item_off[tile]) * S.item;
+        const unsigned end = min(first + S.item, S.tile_off[tile + 1]);
         const int tzi = tile / (S.ntx * S.nty);
         const int trem = tile - tzi * S.ntx * S.nty;
         const int tyi = trem / S.ntx, txi = trem - tyi * S.ntx;
-        const int o0 = txi * kTX, o1 = tyi * kTY, o2 = tzi * S.tz;
+        const int o0 = txi * txy, o1 = tyi * txy, o2 = tzi * S.tz;
         for (int i = threadIdx.x; i < tcells; i += blockDim.x) {
-            const int lx = i % kTX, ly = (i / kTX) % kTY, lz = i / (kTX * kTY);
+            const int lx = i % txy, ly = (i / txy) % txy, lz = i / (txy * txy);
             const int gx = o0 + lx, gy = o1 + ly, gz = o2 + lz;
             R r = (R)0;
             if (gx < P.n[0] && gy < P.n[1] && gz < P.n[2])
@@ -324,6 +351,7 @@ __global__ void __launch_bounds__(256) k_sweep(TransportParams<R> P, SweepParams
         Packet<R> s;
         s.st = ST_EMPTY;
         int visit = 0;
+        bool drained = false;  // this item's records are all taken (wave-uniform)
         for (;;) {
             const unsigned long long need = __ballot(s.st == ST_EMPTY);
             if (need) {
@@ -334,7 +362,7 @@ __global__ void __launch_bounds__(256) k_sweep(TransportParams<R> P, SweepParams
                 if (s.st == ST_EMPTY) {
                     const unsigned slot = first + base + (unsigned)__popcll(need & __lanemask_lt());
                     if (slot < end) {
-                        load_rec(s, rs, P, in + slot);
+                        unpack_rec(s, rs, P, in[S.order[slot]], chi_t, kap_t);
                         visit = 0;
                         // a record is always mid-walk or at a pending event
                         if (s.st != ST_WALK && s.st != ST_EVENT) s.st = ST_DONE;
@@ -344,29 +372,52 @@ __global__ void __launch_bounds__(256) k_sweep(TransportParams<R> P, SweepParams
                 }
             }
             if (__ballot(s.st != ST_DONE) == 0ull) break;
+            drained = drained || __ballot(s.st == ST_DONE) != 0ull;
             for (;;) {
-                if (s.st == ST_WALK) walk_tile<R, K>(s, P, o0, o1, o2, S.tz, rho_t, acc_t, acc2_t, cnt);
+                if (s.st == ST_WALK) walk_tile<R, K>(s, P, o0, o1, o2, txy, S.tz, rho_t, acc_t, acc2_t, cnt);
                 if (__ballot(s.st == ST_WALK) == 0ull) break;
                 if (__popcll(__ballot(s.st != ST_WALK && s.st != ST_DONE)) >= defer) break;
             }
             if (s.st == ST_EVENT) {
-                if (visit >= S.visit_events) {
-                    s.st = ST_YIELD;  // back to this tile's queue for the next sweep
+                // a packet yields (back to this tile's queue for the next sweep)
+                // after visit_events interactions in this visit, or after
+                // kDrainEvents once the item is drained, so that no workgroup
+                // waits long on one random walk; every visit makes progress
+                // (a crossing of the tile wall, an escape, or an interaction)
+                const int cap = drained && S.visit_events > kDrainEvents ? kDrainEvents : S.visit_events;
+                if (visit >= cap) {
+                    s.st = ST_YIELD;
                 } else {
                     ++visit;
                     interact(s, rs, P, tb, cnt, e_killed);
                 }
             }
             if (s.st == ST_ESC) escape(s, P, cnt, e_escaped);
-            append_moves(S, s, rs, lane);
+            int dest;
+            append_moves(S, s, rs, lane, dest);
+            if (dest >= 0) {
+                int nb = 0;  // a packet moves at most one cell: this tile or a face neighbour
+                const int dt = dest - tile;
+                if (dt == -1) nb = 1;
+                else if (dt == 1) nb = 2;
+                else if (dt == -S.ntx) nb = 3;
+                else if (dt == S.ntx) nb = 4;
+                else if (dt == -S.ntx * S.nty) nb = 5;
+                else if (dt == S.ntx * S.nty) nb = 6;
+                atomicAdd(&s_nb[nb], 1u);
+            }
         }
         __syncthreads();
+        if (threadIdx.x < 7 && s_nb[threadIdx.x]) {
+            const int off[7] = {0, -1, 1, -S.ntx, S.ntx, -S.ntx * S.nty, S.ntx * S.nty};
+            atomicAdd(S.counts + tile + off[threadIdx.x], s_nb[threadIdx.x]);
+        }
         // the tile's partial sums into the FP64 tally (cells of this tile only)
         for (int i = threadIdx.x; i < tcells; i += blockDim.x) {
             const R a = acc_t[i];
             const double a2 = acc2_t ? acc2_t[i] : 0.0;
             if (a != (R)0 || a2 != 0.0) {
-                const int lx = i % kTX, ly = (i / kTX) % kTY, lz = i / (kTX * kTY);
+                const int lx = i % txy, ly = (i / txy) % txy, lz = i / (txy * txy);
                 const int64_t j = (o0 + lx) + (int64_t)P.n[0] * ((o1 + ly) + (int64_t)P.n[1] * (o2 + lz));
                 if (a != (R)0) unsafeAtomicAdd(P.acc + j, (double)a);
                 if (a2 != 0.0) unsafeAtomicAdd(P.acc2 + j, a2);
@@ -376,32 +427,13 @@ __global__ void __launch_bounds__(256) k_sweep(TransportParams<R> P, SweepParams
     flush_block_counters(P, cnt, e_escaped, e_killed, s_cnt, s_energy);
 }
 
-// ---- counting sort of the written records by tile --------------------------
-
-// one atomic per distinct tile of a wave
-__global__ void k_tile_hist(const unsigned* __restrict__ out_tile, const unsigned* __restrict__ n_out,
-                            unsigned* __restrict__ counts) {
-    const unsigned n = *n_out;
-    const unsigned stride = gridDim.x * blockDim.x;
-    for (unsigned base = blockIdx.x * blockDim.x; base < n; base += stride) {
-        const unsigned i = base + threadIdx.x;
-        bool pending = i < n;
-        const unsigned t = pending ? out_tile[i] : 0u;
-        for (;;) {
-            const unsigned long long act = __ballot(pending);
-            if (!act) break;
-            const int leader = __ffsll((long long)act) - 1;
-            const unsigned lt = __shfl(t, leader);
-            const unsigned long long same = __ballot(pending && t == lt);
-            if (__lane_id() == leader) atomicAdd(counts + lt, (unsigned)__popcll(same));
-            if (pending && t == lt) pending = false;
-        }
-    }
-}
+// ---- grouping the written records by tile ---------------------------------
+// (the counts per tile were taken while the records were written)
 
 // exclusive scans of the counts (records and work items), cursors, and the
 // counters of the next sweep; one block
 __global__ void __launch_bounds__(1024) k_tile_scan(unsigned* __restrict__ counts, int ntiles,
+                                                    unsigned kItem,
                                                     unsigned* __restrict__ tile_off,
                                                     unsigned* __restrict__ item_off,
                                                     unsigned* __restrict__ cursor,
@@ -442,10 +474,9 @@ __global__ void __launch_bounds__(1024) k_tile_scan(unsigned* __restrict__ count
     }
 }
 
-template <typename R>
-__global__ void k_tile_scatter(const PacketRec<R>* __restrict__ out,
-                               const unsigned* __restrict__ out_tile, const unsigned* __restrict__ n_out,
-                               unsigned* __restrict__ cursor, PacketRec<R>* __restrict__ in) {
+// order[cursor[tile]++] = record index, one atomic per distinct tile of a wave
+__global__ void k_tile_order(const unsigned* __restrict__ out_tile, const unsigned* __restrict__ n_out,
+                             unsigned* __restrict__ cursor, unsigned* __restrict__ order) {
     const unsigned n = *n_out;
     const unsigned stride = gridDim.x * blockDim.x;
     for (unsigned base = blockIdx.x * blockDim.x; base < n; base += stride) {
@@ -468,7 +499,7 @@ __global__ void k_tile_scatter(const PacketRec<R>* __restrict__ out,
                 pending = false;
             }
         }
-        if (i < n) in[pos] = out[i];
+        if (i < n) order[pos] = i;
     }
 }
 
@@ -500,29 +531,32 @@ hipError_t launch_sweep_emit(const TransportParams<R>& P, const SweepParams& S, 
 
 template <typename R>
 hipError_t launch_sweep(const TransportParams<R>& P, const SweepParams& S, int K, int blocks,
-                        size_t lds, hipStream_t st) {
-    hipLaunchKernelGGL(pick_sweep<R>(K), dim3(blocks), dim3(256), lds, st, P, S);
+                        int threads, size_t lds, hipStream_t st) {
+    if (lds > 65536) {
+        hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(pick_sweep<R>(K)),
+                                           hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+        if (e != hipSuccess) return e;
+    }
+    hipLaunchKernelGGL(pick_sweep<R>(K), dim3(blocks), dim3(threads), lds, st, P, S);
     return hipGetLastError();
 }
 
-template <typename R> int sweep_max_blocks_per_cu(int K, size_t lds) {
+template <typename R> int sweep_max_blocks_per_cu(int K, int threads, size_t lds) {
     int nb = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, pick_sweep<R>(K), 256, lds) != hipSuccess)
+    if (lds > 65536)
+        hipFuncSetAttribute(reinterpret_cast<const void*>(pick_sweep<R>(K)),
+                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, pick_sweep<R>(K), threads, lds) != hipSuccess)
         return 1;
     return nb > 0 ? nb : 1;
 }
 
-template <typename R>
-hipError_t launch_tile_sort(const SweepParams& S, const void* out, void* in, unsigned* counts,
-                            unsigned* tile_off, unsigned* item_off, unsigned* cursor, int blocks,
-                            hipStream_t st) {
-    hipLaunchKernelGGL(k_tile_hist, dim3(blocks), dim3(256), 0, st, S.out_tile, S.out_count, counts);
-    hipLaunchKernelGGL(k_tile_scan, dim3(1), dim3(1024), 0, st, counts, S.ntiles, tile_off, item_off,
-                       cursor, S.item_next);
-    hipLaunchKernelGGL(k_tile_scatter<R>, dim3(blocks), dim3(256), 0, st,
-                       reinterpret_cast<const PacketRec<R>*>(out), S.out_tile, S.out_count, cursor,
-                       reinterpret_cast<PacketRec<R>*>(in));
-    hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(64), 0, st, S.out_count, 1);
+hipError_t launch_tile_sort(const SweepParams& S, unsigned* order, unsigned* tile_off,
+                            unsigned* item_off, unsigned* cursor, int blocks, hipStream_t st) {
+    hipLaunchKernelGGL(k_tile_scan, dim3(1), dim3(1024), 0, st, S.counts, S.ntiles, S.item, tile_off,
+                       item_off, cursor, S.item_next);
+    hipLaunchKernelGGL(k_tile_order, dim3(blocks), dim3(256), 0, st, S.out_tile, S.out_count, cursor,
+                       order);
     return hipGetLastError();
 }
 
@@ -537,14 +571,10 @@ template hipError_t launch_sweep_emit<float>(const TransportParams<float>&, cons
 template hipError_t launch_sweep_emit<double>(const TransportParams<double>&, const SweepParams&,
                                               uint64_t, uint64_t, int, hipStream_t);
 template hipError_t launch_sweep<float>(const TransportParams<float>&, const SweepParams&, int, int,
-                                        size_t, hipStream_t);
+                                        int, size_t, hipStream_t);
 template hipError_t launch_sweep<double>(const TransportParams<double>&, const SweepParams&, int,
-                                         int, size_t, hipStream_t);
-template int sweep_max_blocks_per_cu<float>(int, size_t);
-template int sweep_max_blocks_per_cu<double>(int, size_t);
-template hipError_t launch_tile_sort<float>(const SweepParams&, const void*, void*, unsigned*,
-                                            unsigned*, unsigned*, unsigned*, int, hipStream_t);
-template hipError_t launch_tile_sort<double>(const SweepParams&, const void*, void*, unsigned*,
-                                             unsigned*, unsigned*, unsigned*, int, hipStream_t);
+                                         int, int, size_t, hipStream_t);
+template int sweep_max_blocks_per_cu<float>(int, int, size_t);
+template int sweep_max_blocks_per_cu<double>(int, int, size_t);
 
 }  // namespace mcrt

@@ -40,6 +40,7 @@ class RunCfg(C.Structure):
         ("blocks_per_cu", C.c_int32), ("defer_lanes", C.c_int32), ("walk_batch", C.c_int32),
         ("grid_layout", C.c_int32), ("tally_copies", C.c_int32),
         ("transport_mode", C.c_int32), ("tile_z", C.c_int32), ("visit_events", C.c_int32),
+        ("tile_xy", C.c_int32),
     ]
 
 

@@ -275,6 +275,7 @@ def test_abi_errors(M):
     dict(transport_mode=1, tile_z=8, walk_batch=4),
     dict(transport_mode=1, tile_z=4, walk_batch=1, visit_events=1),
     dict(transport_mode=1, tile_z=8, walk_batch=2, defer_lanes=1, visit_events=3),
+    dict(transport_mode=1, tile_xy=32, tile_z=8, walk_batch=4),  # 1024-thread workgroups
 ])
 def test_launch_variants_same_stream(M, variant):
     # every launch configuration the library offers gives the oracle's packets
