@@ -11,7 +11,6 @@ inputs resident in device memory.  Prints one JSON line.
 from __future__ import annotations
 
 import argparse
-import hashlib
 import json
 import os
 import sys
@@ -25,14 +24,6 @@ sys.path.insert(0, ROOT)
 HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, published
 
 
-def transport_source_hash() -> str:
-    h = hashlib.sha256()
-    for f in ["mcrt_transport.hip", "mcrt_sweep.hip", "mcrt_packet.h", "mcrt_internal.h"]:
-        with open(os.path.join(ROOT, "paper_1112_1071_amd", "csrc", f), "rb") as fh:
-            h.update(fh.read())
-    return h.hexdigest()[:16]
-
-
 def algorithmic_bytes(st: dict, precision: int) -> float:
     """Bytes the method must move per launch: per dust-cell segment a density
     gather (4 B FP32 / 8 B FP64) and an FP64 read-modify-write of the cell's
@@ -42,9 +33,12 @@ def algorithmic_bytes(st: dict, precision: int) -> float:
     return (st["n_cross_dust"] * (rb + 16) + st["n_cross_empty"] * rb + st["n_absorb"] * rb)
 
 
-def measured_traffic(precision: int):
-    """HBM bytes per launch from the committed rocprofv3 FETCH_SIZE/WRITE_SIZE
-    summary, if it was taken on the current transport source."""
+def measured_traffic(precision: int, mode: int):
+    """HBM bytes per transport pass from the committed rocprofv3 FETCH_SIZE /
+    WRITE_SIZE summary, if it was taken on the current transport source, in the
+    same precision and transport mode."""
+    from paper_1112_1071_amd.profiling import transport_source_hash
+
     p = os.path.join(ROOT, "profiles", "transport_clump256_pmc.json")
     if not os.path.exists(p):
         return None
@@ -52,7 +46,8 @@ def measured_traffic(precision: int):
         d = json.load(open(p))
     except Exception:
         return None
-    if d.get("source_hash") != transport_source_hash() or d.get("precision") != precision:
+    if (d.get("source_hash") != transport_source_hash() or d.get("precision") != precision
+            or d.get("mode") != mode):
         return None
     return d.get("hbm_bytes_per_launch")
 
@@ -270,7 +265,7 @@ def main():
     ms_tr = float(np.mean([s["ms_transport"] for s in stats]))
     abytes = float(np.mean([algorithmic_bytes(s, prec) for s in stats]))
     achieved = abytes / (ms_tr * 1e-3) / 1e9
-    traffic = measured_traffic(prec)
+    traffic = measured_traffic(prec, int(model.run["transport_mode"]))
     last = stats[-1]
     out = {
         "metric": "packets/s at 256^3 (Lucy iterations)",

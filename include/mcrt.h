@@ -91,7 +91,8 @@ typedef struct {
     int32_t bin_every_iteration; /* bin escapes into SED/images in Lucy iterations too [0]*/
     int32_t block_size;        /* transport threads per block, multiple of 64 [256]       */
     int32_t blocks_per_cu;     /* persistent blocks per compute unit [0 = occupancy]      */
-    int32_t defer_lanes;       /* lanes of a wave that wait before events run [16]        */
+    int32_t defer_lanes;       /* lanes of a wave that wait before events run; 0: 16 for
+                                  the per-lane walk, 64 for tiled sweeps [0]              */
     int32_t walk_batch;        /* grid segments a lane gathers per walk step: 1,2,4,8 [4] */
     int32_t grid_layout;       /* device layout of the transport grid: 0 x-fastest,
                                   1 bricks of 4x4x4 cells [0]; results are identical     */
@@ -99,10 +100,11 @@ typedef struct {
                                   summed by the cell update) [8]                          */
     int32_t transport_mode;    /* 0: every lane walks its packet through the whole grid,
                                   tallies with global FP64 atomics; 1: tiled sweeps --
-                                  packets grouped by tile of 16x16xtile_z cells, each tile
-                                  walked with density and tally in LDS, tally flushed to
-                                  FP64 once per work item [0]; same packet histories     */
-    int32_t tile_z;            /* tiled sweeps: tile extent in z, 4, 8, 16 or 32 [8]      */
+                                  packets grouped by tile of tile_xy^2 x tile_z cells, each
+                                  tile walked with density and tally in LDS, tally flushed
+                                  to FP64 once per work item [1]; same packet histories  */
+    int32_t tile_z;            /* tiled sweeps: tile extent in z, 4, 8, 16 or 32, halved
+                                  while the tile does not fit in LDS [32]                 */
     int32_t visit_events;      /* tiled sweeps: interactions per tile visit before a
                                   packet waits for the next sweep [256]                   */
     int32_t tile_xy;           /* tiled sweeps: tile extent in x and y, 16 or 32 [16]     */

@@ -541,7 +541,9 @@ void make_params(mcrt_model* m, int64_t np, uint32_t key1, int binning, Transpor
         P.pool = misc + MISC_POOL;
         P.eps0 = eps0;
         P.max_events = m->cfg.max_events;
-        P.defer_lanes = m->cfg.defer_lanes > 0 ? m->cfg.defer_lanes : 16;
+        // 0: the mode's default -- a per-lane walk handles events once 16 lanes
+        // wait; a tile walk waits for every lane (its walks are short and alike)
+        P.defer_lanes = m->cfg.defer_lanes > 0 ? m->cfg.defer_lanes : (m->cfg.transport_mode == 1 ? 64 : 16);
         P.acc = m->acc.p;
         P.acc_stride = m->acc_copies > 1 ? m->acc_stride : 0;
         P.acc2 = m->cfg.want_noise ? m->acc2.p : nullptr;
@@ -592,7 +594,14 @@ mcrt_status run_sweeps(mcrt_model* m, TransportParams<R>& P, int64_t np, int64_t
     constexpr bool f32 = std::is_same<R, float>::value;
     SweepParams S{};
     S.txy = m->cfg.tile_xy == 32 ? 32 : 16;
-    S.tz = m->cfg.tile_z == 4 || m->cfg.tile_z == 16 || m->cfg.tile_z == 32 ? m->cfg.tile_z : 8;
+    S.tz = m->cfg.tile_z == 4 || m->cfg.tile_z == 8 || m->cfg.tile_z == 16 ? m->cfg.tile_z : 32;
+    // LDS: tile density and tally (and sum of squares), bin opacities, then the
+    // staged tables; a tile too deep for LDS is halved in z
+    auto tile_bytes = [&](int tz) {
+        return (size_t)S.txy * S.txy * tz * (2 * sizeof(R) + (P.acc2 ? sizeof(double) : 0)) +
+               2 * m->kap.size() * sizeof(R);
+    };
+    while (tile_bytes(S.tz) > m->lds_max && S.tz > 4) S.tz /= 2;
     S.ntx = (m->n[0] + S.txy - 1) / S.txy;
     S.nty = (m->n[1] + S.txy - 1) / S.txy;
     S.ntz = (m->n[2] + S.tz - 1) / S.tz;
@@ -604,13 +613,12 @@ mcrt_status run_sweeps(mcrt_model* m, TransportParams<R>& P, int64_t np, int64_t
     HIPCHK(m->sw_b.ensure((size_t)batch * rb));
     HIPCHK(m->sw_tile.ensure((size_t)batch));
     HIPCHK(m->sw_order.ensure((size_t)batch));
-    const bool fresh_counts = m->sw_counts.n < (size_t)S.ntiles;
     HIPCHK(m->sw_counts.ensure((size_t)S.ntiles));
     HIPCHK(m->sw_tile_off.ensure((size_t)S.ntiles + 1));
     HIPCHK(m->sw_item_off.ensure((size_t)S.ntiles + 1));
     HIPCHK(m->sw_cursor.ensure((size_t)S.ntiles));
     HIPCHK(m->sw_ctr.ensure(2));
-    if (fresh_counts) HIPCHK(launch_zero_u32(m->sw_counts.p, S.ntiles, s));
+    HIPCHK(launch_zero_u32(m->sw_counts.p, S.ntiles, s));
     HIPCHK(launch_zero_u32(m->sw_ctr.p, 2, s));
     S.item_next = m->sw_ctr.p;
     S.out_count = m->sw_ctr.p + 1;
@@ -619,17 +627,14 @@ mcrt_status run_sweeps(mcrt_model* m, TransportParams<R>& P, int64_t np, int64_t
     S.order = m->sw_order.p;
     S.tile_off = m->sw_tile_off.p;
     S.item_off = m->sw_item_off.p;
-    // LDS: tile density and tally (and sum of squares), then the staged tables
-    const size_t tcells = (size_t)S.txy * S.txy * S.tz;
-    const size_t tile_lds = tcells * (2 * sizeof(R) + (P.acc2 ? sizeof(double) : 0)) +
-                            2 * m->kap.size() * sizeof(R);  // + bin opacities chi, kappa
+    const size_t tile_lds = tile_bytes(S.tz);
     const size_t tab_lds = (size_t)(m->src.size() + (kRows + m->src.size()) * m->ngroup) * sizeof(R);
-    if (tile_lds > m->lds_max) return fail(m, MCRT_E_UNSUPPORTED, "tile does not fit in LDS; use a smaller tile_z");
+    if (tile_lds > m->lds_max) return fail(m, MCRT_E_UNSUPPORTED, "tile does not fit in LDS; use smaller tiles");
     P.lds_tables = tile_lds + tab_lds <= m->lds_max ? 1 : 0;
     const size_t lds = tile_lds + (P.lds_tables ? tab_lds : 0);
     const int K = m->cfg.walk_batch == 1 || m->cfg.walk_batch == 2 ? m->cfg.walk_batch : 4;
-    // a workgroup shares one tile: larger tiles get larger workgroups
-    const int threads = tcells >= 8192 ? 1024 : 256;
+    // workgroups of 256 (the kernel's register budget does not fit 1024 threads)
+    const int threads = 256;
     S.item = (unsigned)threads * 8u;
     const int bpc =
         m->cfg.blocks_per_cu > 0 ? m->cfg.blocks_per_cu : sweep_max_blocks_per_cu<R>(K, threads, lds);
@@ -651,7 +656,7 @@ mcrt_status run_sweeps(mcrt_model* m, TransportParams<R>& P, int64_t np, int64_t
             if (nout == 0) break;
             if (++sweeps > kMaxSweeps) return fail(m, MCRT_E_DEVICE, "tiled sweeps did not finish");
             visits += nout;
-            const int64_t sb = ((int64_t)nout + 255) / 256;
+            const int64_t sb = ((int64_t)nout + 4095) / 4096;  // one chunk of 4096 records per block
             HIPCHK(launch_tile_sort(S, m->sw_order.p, m->sw_tile_off.p, m->sw_item_off.p, m->sw_cursor.p,
                                     (int)(sb < (int64_t)m->n_cu * 8 ? sb : (int64_t)m->n_cu * 8), s));
             HIPCHK(launch_zero_u32(S.out_count, 1, s));
@@ -864,12 +869,12 @@ mcrt_status mcrt_run_cfg_default(mcrt_run_cfg* c) {
     c->conv_noise_thres = 0.002;
     c->event_log_cap = 256;
     c->block_size = 256;
-    c->defer_lanes = 16;
+    c->defer_lanes = 0;
     c->walk_batch = 4;
     c->grid_layout = 0;
     c->tally_copies = kMaxTallyCopies;
-    c->transport_mode = 0;
-    c->tile_z = 8;
+    c->transport_mode = 1;
+    c->tile_z = 32;
     c->visit_events = 256;
     c->tile_xy = 16;
     return MCRT_OK;
@@ -1213,7 +1218,7 @@ mcrt_status mcrt_set_run(mcrt_model* m, const mcrt_run_cfg* c) {
     m->cfg = *c;
     if (m->cfg.event_log_cap == 0) m->cfg.event_log_cap = 256;
     if (m->cfg.conv_noise_thres <= 0.0) m->cfg.conv_noise_thres = 0.002;
-    if (m->cfg.tile_z == 0) m->cfg.tile_z = 8;
+    if (m->cfg.tile_z == 0) m->cfg.tile_z = 32;
     if (m->cfg.visit_events == 0) m->cfg.visit_events = 256;
     m->have_run = true;
     if (reset) m->state_ready = false;

@@ -266,7 +266,7 @@ __global__ void __launch_bounds__(256) k_sweep_emit(TransportParams<R> P, SweepP
 
 // One sweep over the work items (persistent workgroups).
 template <typename R, int K>
-__global__ void __launch_bounds__(1024) k_sweep(TransportParams<R> P, SweepParams S) {
+__global__ void __launch_bounds__(256) k_sweep(TransportParams<R> P, SweepParams S) {
     extern __shared__ unsigned char smem_raw[];
     __shared__ unsigned s_item, s_next;
     __shared__ unsigned s_nb[7];  // records leaving for this tile, -x, +x, -y, +y, -z, +z
@@ -474,32 +474,62 @@ __global__ void __launch_bounds__(1024) k_tile_scan(unsigned* __restrict__ count
     }
 }
 
-// order[cursor[tile]++] = record index, one atomic per distinct tile of a wave
-__global__ void k_tile_order(const unsigned* __restrict__ out_tile, const unsigned* __restrict__ n_out,
-                             unsigned* __restrict__ cursor, unsigned* __restrict__ order) {
+// order[cursor[tile]++] = record index.  A block takes kOrderChunk consecutive
+// records (written by a few hundred waves, so they fall into few tiles), counts
+// them per tile in an LDS hash table, reserves each tile's range with one global
+// atomic, and places every record at its reserved base + its rank in the block.
+// A record whose tile finds no free hash slot takes its position directly.
+constexpr int kOrderChunk = 4096;
+constexpr int kOrderHash = 1024;
+
+__global__ void __launch_bounds__(256) k_tile_order(const unsigned* __restrict__ out_tile,
+                                                    const unsigned* __restrict__ n_out,
+                                                    unsigned* __restrict__ cursor,
+                                                    unsigned* __restrict__ order) {
+    __shared__ unsigned h_key[kOrderHash], h_cnt[kOrderHash];
+    constexpr int per = kOrderChunk / 256;
     const unsigned n = *n_out;
-    const unsigned stride = gridDim.x * blockDim.x;
-    for (unsigned base = blockIdx.x * blockDim.x; base < n; base += stride) {
-        const unsigned i = base + threadIdx.x;
-        bool pending = i < n;
-        const unsigned t = pending ? out_tile[i] : 0u;
-        unsigned pos = 0;
-        for (;;) {
-            const unsigned long long act = __ballot(pending);
-            if (!act) break;
-            const int leader = __ffsll((long long)act) - 1;
-            const unsigned lt = __shfl(t, leader);
-            const bool mine = pending && t == lt;
-            const unsigned long long same = __ballot(mine);
-            unsigned b = 0;
-            if (__lane_id() == leader) b = atomicAdd(cursor + lt, (unsigned)__popcll(same));
-            b = __shfl(b, leader);
-            if (mine) {
-                pos = b + (unsigned)__popcll(same & __lanemask_lt());
-                pending = false;
+    for (unsigned c0 = blockIdx.x * (unsigned)kOrderChunk; c0 < n; c0 += gridDim.x * (unsigned)kOrderChunk) {
+        for (int i = threadIdx.x; i < kOrderHash; i += blockDim.x) {
+            h_key[i] = 0xffffffffu;
+            h_cnt[i] = 0u;
+        }
+        __syncthreads();
+        int slot[per];
+        unsigned rank[per];
+#pragma unroll
+        for (int j = 0; j < per; ++j) {
+            const unsigned i = c0 + (unsigned)(j * 256) + threadIdx.x;
+            slot[j] = -1;
+            rank[j] = 0u;
+            if (i < n) {
+                const unsigned t = out_tile[i];
+                unsigned h = (t * 2654435761u) >> 22;
+                int found = -1;
+                for (int probe = 0; probe < kOrderHash; ++probe) {
+                    const unsigned k = atomicCAS(&h_key[h], 0xffffffffu, t);
+                    if (k == 0xffffffffu || k == t) {
+                        found = (int)h;
+                        break;
+                    }
+                    h = (h + 1u) & (kOrderHash - 1);
+                }
+                if (found >= 0) {
+                    slot[j] = found;
+                    rank[j] = atomicAdd(&h_cnt[found], 1u);
+                } else {
+                    order[atomicAdd(cursor + t, 1u)] = i;  // table full
+                }
             }
         }
-        if (i < n) order[pos] = i;
+        __syncthreads();
+        for (int e = threadIdx.x; e < kOrderHash; e += blockDim.x)
+            if (h_cnt[e]) h_cnt[e] = atomicAdd(cursor + h_key[e], h_cnt[e]);  // count -> base
+        __syncthreads();
+#pragma unroll
+        for (int j = 0; j < per; ++j)
+            if (slot[j] >= 0) order[h_cnt[slot[j]] + rank[j]] = c0 + (unsigned)(j * 256) + threadIdx.x;
+        __syncthreads();
     }
 }
 

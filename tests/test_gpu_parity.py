@@ -265,17 +265,19 @@ def test_abi_errors(M):
 
 
 @pytest.mark.parametrize("variant", [
-    dict(walk_batch=1, grid_layout=0, tally_copies=1),
-    dict(walk_batch=2, grid_layout=1, tally_copies=8),
-    dict(walk_batch=4, grid_layout=1, tally_copies=1, block_size=128),
-    dict(walk_batch=8, grid_layout=0, tally_copies=8, defer_lanes=1),
-    dict(walk_batch=8, grid_layout=1, tally_copies=8, defer_lanes=64, block_size=64),
+    # per-lane persistent walk (transport_mode 0)
+    dict(transport_mode=0, walk_batch=1, grid_layout=0, tally_copies=1),
+    dict(transport_mode=0, walk_batch=2, grid_layout=1, tally_copies=8),
+    dict(transport_mode=0, walk_batch=4, grid_layout=1, tally_copies=1, block_size=128),
+    dict(transport_mode=0, walk_batch=8, grid_layout=0, tally_copies=8, defer_lanes=1),
+    dict(transport_mode=0, walk_batch=8, grid_layout=1, tally_copies=8, defer_lanes=64, block_size=64),
     # tiled sweeps: tiles of 16x16x{4,8} (ragged at the grid edges), yields
     # after every interaction (visit_events=1), lone-lane event handling
     dict(transport_mode=1, tile_z=8, walk_batch=4),
     dict(transport_mode=1, tile_z=4, walk_batch=1, visit_events=1),
     dict(transport_mode=1, tile_z=8, walk_batch=2, defer_lanes=1, visit_events=3),
-    dict(transport_mode=1, tile_xy=32, tile_z=8, walk_batch=4),  # 1024-thread workgroups
+    dict(transport_mode=1, tile_xy=32, tile_z=8, walk_batch=4),
+    dict(transport_mode=1),  # the defaults: 16x16x32 tiles, full-wave deferral
 ])
 def test_launch_variants_same_stream(M, variant):
     # every launch configuration the library offers gives the oracle's packets
@@ -297,7 +299,7 @@ def test_launch_variants_same_stream(M, variant):
     assert np.max(np.abs(ag[nz] / ao[nz] - 1)) < 1e-9
 
 
-@pytest.mark.parametrize("tile_z", [4, 8])
+@pytest.mark.parametrize("tile_z", [4, 32])
 def test_tiled_fp32_equals_persistent_fp32(M, tile_z):
     # FP32 transport: both modes follow identical packet histories in the first
     # iteration (same counters exactly); the tiled mode sums a tile visit in
@@ -307,7 +309,7 @@ def test_tiled_fp32_equals_persistent_fp32(M, tile_z):
     # counters and Adot agree to 1e-4 except in a few cells.
     cfg = synth.config2(n=48, n_packets=400000, n_iter=2, gen_seed=45777, n_src=12,
                         box=0.65 * synth.PC * 48 / 128)
-    a = M.Model(cfg, precision=M.MCRT_FP32_TRANSPORT, want_noise=1)
+    a = M.Model(cfg, precision=M.MCRT_FP32_TRANSPORT, want_noise=1, transport_mode=0)
     b = M.Model(cfg, precision=M.MCRT_FP32_TRANSPORT, want_noise=1, transport_mode=1, tile_z=tile_z)
     for it in range(2):
         sa, sb = a.iterate(), b.iterate()
