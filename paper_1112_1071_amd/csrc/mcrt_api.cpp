@@ -47,14 +47,14 @@ hipError_t launch_fill_u64(int64_t n, unsigned long long* p, unsigned long long 
 size_t sweep_record_bytes(int fp32);
 template <typename R>
 hipError_t launch_sweep_emit(const TransportParams<R>& P, const SweepParams& S, uint64_t first,
-                             uint64_t count, int blocks, hipStream_t st);
+                             uint64_t count, unsigned base, int blocks, hipStream_t st);
 template <typename R>
 hipError_t launch_sweep(const TransportParams<R>& P, const SweepParams& S, int K, int blocks,
                         int threads, size_t lds, hipStream_t st);
 template <typename R> int sweep_max_blocks_per_cu(int K, int threads, size_t lds);
 hipError_t launch_tile_sort(const SweepParams& S, unsigned* order, unsigned* tile_off,
                             unsigned* item_off, unsigned* cursor, int blocks, hipStream_t st);
-hipError_t launch_zero_u32(unsigned* p, int n, hipStream_t st);
+hipError_t launch_fill_u32(unsigned* p, int n, unsigned v, hipStream_t st);
 }  // namespace mcrt
 
 using namespace mcrt;
@@ -581,10 +581,13 @@ int persistent_blocks(const mcrt_model* m, int bpc, int64_t np, int threads) {
     return (int)(blocks < 1 ? 1 : blocks);
 }
 
-// Tiled sweeps (transport_mode 1): emission writes every packet of a batch as
-// a record with its tile, then sort-by-tile and sweep alternate until no
-// record is left.  The host reads the record count after each sweep.
-constexpr int64_t kSweepBatch = 1ll << 25;  // packets in flight at once
+// Tiled sweeps (transport_mode 1): emission writes packets as records with
+// their tiles, then sort-by-tile and sweep alternate until no record is left.
+// The pool is refilled: whenever fewer than kSweepBatch records are in flight
+// after a sweep, the next kSweepBatch packets are emitted into the same output,
+// so only the end of the pass drains (one tail of short sweeps, not one per
+// batch).  The host reads the record count after each sweep.
+constexpr int64_t kSweepBatch = 1ll << 25;  // packets emitted at once
 constexpr int64_t kMaxSweeps = 1ll << 20;    // every visit advances a packet; this is a backstop
 
 template <typename R>
@@ -608,18 +611,19 @@ mcrt_status run_sweeps(mcrt_model* m, TransportParams<R>& P, int64_t np, int64_t
     S.ntiles = S.ntx * S.nty * S.ntz;
     S.visit_events = m->cfg.visit_events > 0 ? m->cfg.visit_events : 256;
     const int64_t batch = np < kSweepBatch ? np : kSweepBatch;
+    const int64_t cap = np < 2 * batch ? np : 2 * batch;  // records in flight: < batch + batch
     const size_t rb = sweep_record_bytes(f32 ? 1 : 0);
-    HIPCHK(m->sw_a.ensure((size_t)batch * rb));
-    HIPCHK(m->sw_b.ensure((size_t)batch * rb));
-    HIPCHK(m->sw_tile.ensure((size_t)batch));
-    HIPCHK(m->sw_order.ensure((size_t)batch));
+    HIPCHK(m->sw_a.ensure((size_t)cap * rb));
+    HIPCHK(m->sw_b.ensure((size_t)cap * rb));
+    HIPCHK(m->sw_tile.ensure((size_t)cap));
+    HIPCHK(m->sw_order.ensure((size_t)cap));
     HIPCHK(m->sw_counts.ensure((size_t)S.ntiles));
     HIPCHK(m->sw_tile_off.ensure((size_t)S.ntiles + 1));
     HIPCHK(m->sw_item_off.ensure((size_t)S.ntiles + 1));
     HIPCHK(m->sw_cursor.ensure((size_t)S.ntiles));
     HIPCHK(m->sw_ctr.ensure(2));
-    HIPCHK(launch_zero_u32(m->sw_counts.p, S.ntiles, s));
-    HIPCHK(launch_zero_u32(m->sw_ctr.p, 2, s));
+    HIPCHK(launch_fill_u32(m->sw_counts.p, S.ntiles, 0u, s));
+    HIPCHK(launch_fill_u32(m->sw_ctr.p, 2, 0u, s));
     S.item_next = m->sw_ctr.p;
     S.out_count = m->sw_ctr.p + 1;
     S.out_tile = m->sw_tile.p;
@@ -641,30 +645,35 @@ mcrt_status run_sweeps(mcrt_model* m, TransportParams<R>& P, int64_t np, int64_t
     const int blocks = m->n_cu * bpc;
     P.packet_base = 0;
     int64_t sweeps = 0, visits = 0;
-    for (int64_t b0 = 0; b0 < np; b0 += batch) {
-        const int64_t cnt = np - b0 < batch ? np - b0 : batch;
-        unsigned char* bufs[2] = {m->sw_a.p, m->sw_b.p};
-        int w = 0;  // buffer the next records are written to
-        S.out = bufs[w];
-        const int64_t eb = (cnt + 255) / 256;
-        HIPCHK(launch_sweep_emit<R>(P, S, (uint64_t)b0, (uint64_t)cnt,
-                                    (int)(eb < (int64_t)m->n_cu * 8 ? eb : (int64_t)m->n_cu * 8), s));
-        for (;;) {
-            unsigned nout = 0;
-            HIPCHK(hipMemcpyAsync(&nout, S.out_count, sizeof nout, hipMemcpyDeviceToHost, s));
-            HIPCHK(hipStreamSynchronize(s));
-            if (nout == 0) break;
-            if (++sweeps > kMaxSweeps) return fail(m, MCRT_E_DEVICE, "tiled sweeps did not finish");
-            visits += nout;
-            const int64_t sb = ((int64_t)nout + 4095) / 4096;  // one chunk of 4096 records per block
-            HIPCHK(launch_tile_sort(S, m->sw_order.p, m->sw_tile_off.p, m->sw_item_off.p, m->sw_cursor.p,
-                                    (int)(sb < (int64_t)m->n_cu * 8 ? sb : (int64_t)m->n_cu * 8), s));
-            HIPCHK(launch_zero_u32(S.out_count, 1, s));
-            S.in = bufs[w];
-            w ^= 1;
-            S.out = bufs[w];
-            HIPCHK(launch_sweep<R>(P, S, K, blocks, threads, lds, s));
+    unsigned char* bufs[2] = {m->sw_a.p, m->sw_b.p};
+    int w = 0;  // buffer the next records are written to
+    S.out = bufs[w];
+    int64_t emitted = 0;
+    for (;;) {
+        unsigned nout = 0;
+        HIPCHK(hipMemcpyAsync(&nout, S.out_count, sizeof nout, hipMemcpyDeviceToHost, s));
+        HIPCHK(hipStreamSynchronize(s));
+        if ((int64_t)nout < batch && emitted < np) {
+            // refill: appended after the records the last sweep wrote, counted per tile
+            const int64_t cnt = np - emitted < batch ? np - emitted : batch;
+            const int64_t eb = (cnt + 255) / 256;
+            HIPCHK(launch_sweep_emit<R>(P, S, (uint64_t)emitted, (uint64_t)cnt, nout,
+                                        (int)(eb < (int64_t)m->n_cu * 8 ? eb : (int64_t)m->n_cu * 8), s));
+            HIPCHK(launch_fill_u32(S.out_count, 1, nout + (unsigned)cnt, s));
+            emitted += cnt;
+            continue;
         }
+        if (nout == 0) break;
+        if (++sweeps > kMaxSweeps) return fail(m, MCRT_E_DEVICE, "tiled sweeps did not finish");
+        visits += nout;
+        const int64_t sb = ((int64_t)nout + 4095) / 4096;  // one chunk of 4096 records per block
+        HIPCHK(launch_tile_sort(S, m->sw_order.p, m->sw_tile_off.p, m->sw_item_off.p, m->sw_cursor.p,
+                                (int)(sb < (int64_t)m->n_cu * 8 ? sb : (int64_t)m->n_cu * 8), s));
+        HIPCHK(launch_fill_u32(S.out_count, 1, 0u, s));
+        S.in = bufs[w];
+        w ^= 1;
+        S.out = bufs[w];
+        HIPCHK(launch_sweep<R>(P, S, K, blocks, threads, lds, s));
     }
     *n_sweeps = sweeps;
     *n_visits = visits;

@@ -1,20 +1,20 @@
 // mcrt_sweep.hip -- tiled transport: packets grouped by grid tile, each tile
 // walked with its density and absorption tally staged in LDS.
 //
-// The grid is cut into tiles of 16 x 16 x tz cells.  A pass runs in sweeps.
+// The grid is cut into tiles of txy x txy x tz cells.  A pass runs in sweeps.
 // Between sweeps every packet in flight is a record in global memory (its
 // full state: cell, direction, flight origin, wall distances, ray distance,
 // sampled and used optical depth, weight, bin, event counts and the position
-// in its random stream), and the records are counting-sorted by the tile the
-// packet is in.  In a sweep, a workgroup takes a work item (up to kItem
-// records of one tile), loads the tile's density into LDS and clears an LDS
-// tally, and its lanes walk those packets (Sec. 2.2; Lucy's path-length
-// estimator, Sec. 2.3 Eq. 2, added into the LDS tally) until each leaves the
-// tile, escapes the grid, is killed, or has had kVisitEvents interactions in
-// this visit; a packet that leaves (or yields) is written out with the tile it
-// is now in.  The workgroup then adds its LDS tally into the FP64 global
-// tally, one atomic per touched cell of the tile.  Sweeps repeat until no
-// packet is left.
+// in its random stream), and the records are grouped by the tile the packet
+// is in.  In a sweep, a workgroup takes work items (each up to S.item
+// records of one tile); for each new tile it loads the tile's density into
+// LDS and clears an LDS tally, and its lanes walk the item's packets (Sec. 2.2; Lucy's path-length estimator, Sec. 2.3 Eq. 2,
+// added into the LDS tally) until each leaves the tile, escapes the grid, is
+// killed, or has had visit_events interactions in this visit; a packet that
+// leaves (or yields) is written out with the tile it is now in.  When the
+// workgroup moves on to another tile (or ends), it adds the LDS tally into
+// the FP64 global tally, one atomic per touched cell of the tile.  Sweeps
+// repeat until no packet is left.
 //
 // Every packet follows the same arithmetic, random numbers and decisions as
 // in the per-lane persistent kernel (the walk is the same segment by segment,
@@ -29,6 +29,8 @@
 namespace mcrt {
 
 constexpr int kDrainEvents = 32;     // interactions per visit once an item is drained
+constexpr unsigned kNoTile = 0xffffffffu;  // tile of a hole in the records (no packet)
+constexpr int kEmitHistTiles = 16384;      // tiles counted in LDS by the emission (64 KB)
 enum : int { ST_MOVE = 5, ST_YIELD = 6 };
 
 // State of a packet between visits (the Packet fields that are not
@@ -115,13 +117,35 @@ __device__ __forceinline__ void unpack_rec(Packet<R>& s, Stream<R>& rs, const Tr
     }
 }
 
+// Local LDS index of the packet's cell in the tile with origin (o0, o1, o2).
+__device__ __forceinline__ int tile_index(int c0, int c1, int c2, int o0, int o1, int o2, int txy) {
+    return (c0 - o0) + txy * ((c1 - o1) + txy * (c2 - o2));
+}
+
 // Up to K segments of the walk inside the tile with origin (o0, o1, o2):
 // segment by segment the arithmetic of walk(), with density and tally in LDS.
+// The segments are written without branches (a lane that stopped keeps its
+// values through selects), so that a wave runs straight-line code; the one
+// division, for the segment that ends in an interaction, is taken after the
+// loop.  The lane carries its cell's LDS index jl and density rho between
+// calls (an interaction leaves the cell unchanged); the next cell's density
+// is read as soon as the next cell is known, ahead of the segment's arithmetic.
 template <typename R, int K>
 __device__ __forceinline__ void walk_tile(Packet<R>& s, const TransportParams<R>& P, int o0, int o1,
                                           int o2, int txy, int tz, const R* __restrict__ rho_t,
                                           R* __restrict__ acc_t, double* __restrict__ acc2_t,
-                                          uint32_t* cnt) {
+                                          uint32_t* cnt, int& jl, R& rho) {
+    const int sx = s.d0 > (R)0 ? 1 : -1;
+    const int sy = s.d1 > (R)0 ? 1 : -1;
+    const int sz = s.d2 > (R)0 ? 1 : -1;
+    const int dyj = sy * txy, dzj = sz * txy * txy;
+    const int g0 = P.n[0], g1 = P.n[1], g2 = P.n[2];
+    bool act = true;   // still walking in this call
+    bool hit = false;  // the last segment ends in an interaction
+    R rc_h = (R)1, ts_h = (R)0;
+    int jl_h = jl;
+    int st = ST_WALK;
+    uint32_t nd = 0, ne = 0;
 #pragma unroll
     for (int i = 0; i < K; ++i) {
         const bool ax1 = s.ty < s.tx;
@@ -130,49 +154,61 @@ __device__ __forceinline__ void walk_tile(Packet<R>& s, const TransportParams<R>
         tm = ax2 ? s.tz : tm;
         const bool ax0 = !ax1 && !ax2;
         const bool by = ax1 && !ax2;
+        // the next cell along the moving axis, whether it leaves the grid or
+        // the tile (a cell past the grid inside a ragged tile holds 0)
+        const int na = ax0 ? s.c0 + sx : (by ? s.c1 + sy : s.c2 + sz);
+        const int oa = ax0 ? o0 : (by ? o1 : o2);
+        const int ga = ax0 ? g0 : (by ? g1 : g2);
+        const int la = ax2 ? tz : txy;
+        const bool out_grid = (unsigned)na >= (unsigned)ga;
+        const bool out_tile = (unsigned)(na - oa) >= (unsigned)la;
+        const int jn = out_tile ? jl : jl + (ax0 ? sx : (by ? dyj : dzj));
+        const R rho_n = rho_t[jn];
+        // this segment
         const R ts = s.t;
-        R l = fmax(tm - s.t, (R)0);
-        const int jl = (s.c0 - o0) + txy * ((s.c1 - o1) + txy * (s.c2 - o2));
-        const R rho = rho_t[jl];
-        if (rho > (R)0) {
-            ++cnt[C_CROSS_DUST];
-            const R rc = rho * s.chi;
-            const R dtau = rc * l;
-            const bool hit = s.tau_acc + dtau >= s.tau;
-            if (hit) l = (s.tau - s.tau_acc) / rc;
-            else s.tau_acc += dtau;
+        const R l = fmax(tm - s.t, (R)0);
+        const bool dust = rho > (R)0;
+        const R rc = rho * s.chi;
+        const R dtau = rc * l;
+        const bool h = act && dust && s.tau_acc + dtau >= s.tau;
+        const bool cross = act && !h;  // the segment reaches the cell wall
+        nd += (act && dust) ? 1u : 0u;
+        ne += (act && !dust) ? 1u : 0u;
+        if (h) {
+            hit = true;
+            rc_h = rc;
+            ts_h = ts;
+            jl_h = jl;
+        }
+        if (cross && dust) {
+            s.tau_acc += dtau;
             const R w = s.wgt * l * s.kap;
             atomicAdd(acc_t + jl, w);
             if (acc2_t) atomicAdd(acc2_t + jl, (double)w * (double)w);  // w^2 may exceed FP32
-            if (hit) {
-                s.t = ts + l;
-                s.st = ST_EVENT;
-                return;
-            }
-        } else {
-            ++cnt[C_CROSS_EMPTY];
         }
-        s.t = fmax(tm, s.t);
-        const int n0 = s.c0 + (ax0 ? (s.d0 > (R)0 ? 1 : -1) : 0);
-        const int n1 = s.c1 + (by ? (s.d1 > (R)0 ? 1 : -1) : 0);
-        const int n2 = s.c2 + (ax2 ? (s.d2 > (R)0 ? 1 : -1) : 0);
-        if ((unsigned)n0 >= (unsigned)P.n[0] || (unsigned)n1 >= (unsigned)P.n[1] ||
-            (unsigned)n2 >= (unsigned)P.n[2]) {
-            s.st = ST_ESC;
-            return;
-        }
-        s.c0 = n0;
-        s.c1 = n1;
-        s.c2 = n2;
-        s.tx += ax0 ? s.dtx : (R)0;
-        s.ty += by ? s.dty : (R)0;
-        s.tz += ax2 ? s.dtz : (R)0;
-        if ((unsigned)(n0 - o0) >= (unsigned)txy || (unsigned)(n1 - o1) >= (unsigned)txy ||
-            (unsigned)(n2 - o2) >= (unsigned)tz) {
-            s.st = ST_MOVE;
-            return;
-        }
+        s.t = cross ? fmax(tm, s.t) : s.t;
+        const bool mv = cross && !out_grid;
+        s.c0 += (mv && ax0) ? sx : 0;
+        s.c1 += (mv && by) ? sy : 0;
+        s.c2 += (mv && ax2) ? sz : 0;
+        s.tx += (mv && ax0) ? s.dtx : (R)0;
+        s.ty += (mv && by) ? s.dty : (R)0;
+        s.tz += (mv && ax2) ? s.dtz : (R)0;
+        st = (cross && out_grid) ? ST_ESC : ((mv && out_tile) ? ST_MOVE : (h ? ST_EVENT : st));
+        act = mv && !out_tile;
+        jl = act ? jn : jl;
+        rho = act ? rho_n : rho;
     }
+    if (hit) {
+        const R l = (s.tau - s.tau_acc) / rc_h;
+        const R w = s.wgt * l * s.kap;
+        atomicAdd(acc_t + jl_h, w);
+        if (acc2_t) atomicAdd(acc2_t + jl_h, (double)w * (double)w);
+        s.t = ts_h + l;
+    }
+    s.st = st;
+    cnt[C_CROSS_DUST] += nd;
+    cnt[C_CROSS_EMPTY] += ne;
 }
 
 // Append the lanes' records whose state is ST_MOVE or ST_YIELD (one atomic per
@@ -228,40 +264,84 @@ __device__ __forceinline__ void flush_block_counters(const TransportParams<R>& P
 }
 
 // Emission of packets [first, first+count): each starts its first flight
-// (exactly as in the per-lane kernel) and is written out with its tile, or
-// escapes at once when it starts outside the grid.
+// (exactly as in the per-lane kernel) and is written as record base+i with its
+// tile; a packet that starts outside the grid escapes at once and leaves a hole
+// (tile kNoTile, skipped by the ordering).  Positions need no atomics; the
+// per-tile counts are gathered in an LDS histogram per block when the tiles
+// fit (hist), else per wave.
 template <typename R>
 __global__ void __launch_bounds__(256) k_sweep_emit(TransportParams<R> P, SweepParams S,
-                                                     uint64_t first, uint64_t count) {
+                                                     uint64_t first, uint64_t count, unsigned base,
+                                                     int hist) {
+    extern __shared__ unsigned s_hist[];
     __shared__ unsigned long long s_cnt[C_COUNT];
     __shared__ double s_energy[2];
     if (threadIdx.x < C_COUNT) s_cnt[threadIdx.x] = 0ull;
     if (threadIdx.x < 2) s_energy[threadIdx.x] = 0.0;
+    if (hist)
+        for (int t = threadIdx.x; t < S.ntiles; t += blockDim.x) s_hist[t] = 0u;
     __syncthreads();
     uint32_t cnt[C_COUNT] = {0, 0, 0, 0, 0, 0};
     double e_escaped = 0.0, e_killed = 0.0;
     const Tables<R> tb{P.lcdf, P.ecoarse, P.scoarse};
-    const int lane = __lane_id();
     Stream<R> rs;
     rs.k0 = P.key0;
     rs.k1 = P.key1;
     rs.n = 0;
     rs.p0 = rs.p1 = rs.s0 = rs.s1 = 0;
+    PacketRec<R>* out = reinterpret_cast<PacketRec<R>*>(S.out);
     const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
-    for (uint64_t base = (uint64_t)blockIdx.x * blockDim.x; base < count; base += stride) {
-        const uint64_t i = base + threadIdx.x;
-        Packet<R> s;
-        s.st = ST_EMPTY;
+    for (uint64_t b0 = (uint64_t)blockIdx.x * blockDim.x; b0 < count; b0 += stride) {
+        const uint64_t i = b0 + threadIdx.x;
+        int dest = -1;
         if (i < count) {
+            Packet<R> s;
             emit(s, rs, P, tb, first + i);
-            if (s.st == ST_ESC) escape(s, P, cnt, e_escaped);
-            else s.st = ST_MOVE;
+            const unsigned idx = base + (unsigned)i;
+            if (s.st == ST_ESC) {
+                escape(s, P, cnt, e_escaped);
+                S.out_tile[idx] = kNoTile;
+            } else {
+                store_rec(out + idx, s, rs, ST_WALK);
+                dest = tile_of(S, s.c0, s.c1, s.c2);
+                S.out_tile[idx] = (unsigned)dest;
+                if (hist) atomicAdd(&s_hist[dest], 1u);
+            }
         }
-        int dest;
-        append_moves(S, s, rs, lane, dest);
-        count_tiles(S.counts, dest);
+        if (!hist) count_tiles(S.counts, dest);
+    }
+    if (hist) {
+        __syncthreads();
+        for (int t = threadIdx.x; t < S.ntiles; t += blockDim.x)
+            if (s_hist[t]) atomicAdd(S.counts + t, s_hist[t]);
     }
     flush_block_counters(P, cnt, e_escaped, e_killed, s_cnt, s_energy);
+}
+
+// The tile's counts of records written for it and its face neighbours, and its
+// LDS partial sums into the FP64 tally (cells of this tile only); the LDS is
+// free again on return.
+template <typename R>
+__device__ __forceinline__ void flush_tile(const TransportParams<R>& P, const SweepParams& S, int tile,
+                                           int o0, int o1, int o2, int txy, int tcells,
+                                           const R* acc_t, const double* acc2_t, unsigned* s_nb) {
+    __syncthreads();
+    if (threadIdx.x < 7 && s_nb[threadIdx.x]) {
+        const int off[7] = {0, -1, 1, -S.ntx, S.ntx, -S.ntx * S.nty, S.ntx * S.nty};
+        atomicAdd(S.counts + tile + off[threadIdx.x], s_nb[threadIdx.x]);
+    }
+    for (int i = threadIdx.x; i < tcells; i += blockDim.x) {
+        const R a = acc_t[i];
+        const double a2 = acc2_t ? acc2_t[i] : 0.0;
+        if (a != (R)0 || a2 != 0.0) {
+            const int lx = i % txy, ly = (i / txy) % txy, lz = i / (txy * txy);
+            const int64_t j = (o0 + lx) + (int64_t)P.n[0] * ((o1 + ly) + (int64_t)P.n[1] * (o2 + lz));
+            if (a != (R)0) unsafeAtomicAdd(P.acc + j, (double)a);
+            if (a2 != 0.0) unsafeAtomicAdd(P.acc2 + j, a2);
+        }
+    }
+    __syncthreads();
+    if (threadIdx.x < 7) s_nb[threadIdx.x] = 0u;
 }
 
 // One sweep over the work items (persistent workgroups).
@@ -312,14 +392,13 @@ __global__ void __launch_bounds__(256) k_sweep(TransportParams<R> P, SweepParams
     rs.n = 0;
     rs.p0 = rs.p1 = rs.s0 = rs.s1 = 0;
     const unsigned n_items = S.item_off[S.ntiles];
+    if (threadIdx.x < 7) s_nb[threadIdx.x] = 0u;
+    int tile = -1;  // the tile held in LDS (block-uniform)
+    int o0 = 0, o1 = 0, o2 = 0;
 
     for (;;) {
         __syncthreads();
-        if (threadIdx.x == 0) {
-            s_item = atomicAdd(S.item_next, 1u);
-            s_next = 0u;
-        }
-        if (threadIdx.x < 7) s_nb[threadIdx.x] = 0u;
+        if (threadIdx.x == 0) s_item = atomicAdd(S.item_next, 1u);
         __syncthreads();
         const unsigned item = s_item;
         if (item >= n_items) break;
@@ -329,27 +408,37 @@ __global__ void __launch_bounds__(256) k_sweep(TransportParams<R> P, SweepParams
             if (S.item_off[mid] <= item) lo = mid;
             else hi = mid - 1;
         }
-        const int tile = lo;
+        if (lo != tile) {
+            // an item of the tile already in LDS keeps it; otherwise the tile
+            // in LDS goes out before the item's tile comes in
+            if (tile >= 0) flush_tile(P, S, tile, o0, o1, o2, txy, tcells, acc_t, acc2_t, s_nb);
+            tile = lo;
+            const int tzi = tile / (S.ntx * S.nty);
+            const int trem = tile - tzi * S.ntx * S.nty;
+            const int tyi = trem / S.ntx, txi = trem - tyi * S.ntx;
+            o0 = txi * txy;
+            o1 = tyi * txy;
+            o2 = tzi * S.tz;
+            for (int i = threadIdx.x; i < tcells; i += blockDim.x) {
+                const int lx = i % txy, ly = (i / txy) % txy, lz = i / (txy * txy);
+                const int gx = o0 + lx, gy = o1 + ly, gz = o2 + lz;
+                R r = (R)0;
+                if (gx < P.n[0] && gy < P.n[1] && gz < P.n[2])
+                    r = P.rho[gx + (int64_t)P.n[0] * (gy + (int64_t)P.n[1] * gz)];
+                rho_t[i] = r;
+                acc_t[i] = (R)0;
+                if (acc2_t) acc2_t[i] = 0.0;
+            }
+        }
+        if (threadIdx.x == 0) s_next = 0u;
+        __syncthreads();
         const unsigned first = S.tile_off[tile] + (item - S.item_off[tile]) * S.item;
         const unsigned end = min(first + S.item, S.tile_off[tile + 1]);
-        const int tzi = tile / (S.ntx * S.nty);
-        const int trem = tile - tzi * S.ntx * S.nty;
-        const int tyi = trem / S.ntx, txi = trem - tyi * S.ntx;
-        const int o0 = txi * txy, o1 = tyi * txy, o2 = tzi * S.tz;
-        for (int i = threadIdx.x; i < tcells; i += blockDim.x) {
-            const int lx = i % txy, ly = (i / txy) % txy, lz = i / (txy * txy);
-            const int gx = o0 + lx, gy = o1 + ly, gz = o2 + lz;
-            R r = (R)0;
-            if (gx < P.n[0] && gy < P.n[1] && gz < P.n[2])
-                r = P.rho[gx + (int64_t)P.n[0] * (gy + (int64_t)P.n[1] * gz)];
-            rho_t[i] = r;
-            acc_t[i] = (R)0;
-            if (acc2_t) acc2_t[i] = 0.0;
-        }
-        __syncthreads();
 
         Packet<R> s;
         s.st = ST_EMPTY;
+        int jl = 0;       // the packet's cell in LDS
+        R rho = (R)0;     // and its density
         int visit = 0;
         bool drained = false;  // this item's records are all taken (wave-uniform)
         for (;;) {
@@ -363,6 +452,8 @@ __global__ void __launch_bounds__(256) k_sweep(TransportParams<R> P, SweepParams
                     const unsigned slot = first + base + (unsigned)__popcll(need & __lanemask_lt());
                     if (slot < end) {
                         unpack_rec(s, rs, P, in[S.order[slot]], chi_t, kap_t);
+                        jl = tile_index(s.c0, s.c1, s.c2, o0, o1, o2, txy);
+                        rho = rho_t[jl];
                         visit = 0;
                         // a record is always mid-walk or at a pending event
                         if (s.st != ST_WALK && s.st != ST_EVENT) s.st = ST_DONE;
@@ -374,7 +465,8 @@ __global__ void __launch_bounds__(256) k_sweep(TransportParams<R> P, SweepParams
             if (__ballot(s.st != ST_DONE) == 0ull) break;
             drained = drained || __ballot(s.st == ST_DONE) != 0ull;
             for (;;) {
-                if (s.st == ST_WALK) walk_tile<R, K>(s, P, o0, o1, o2, txy, S.tz, rho_t, acc_t, acc2_t, cnt);
+                if (s.st == ST_WALK)
+                    walk_tile<R, K>(s, P, o0, o1, o2, txy, S.tz, rho_t, acc_t, acc2_t, cnt, jl, rho);
                 if (__ballot(s.st == ST_WALK) == 0ull) break;
                 if (__popcll(__ballot(s.st != ST_WALK && s.st != ST_DONE)) >= defer) break;
             }
@@ -407,23 +499,8 @@ __global__ void __launch_bounds__(256) k_sweep(TransportParams<R> P, SweepParams
                 atomicAdd(&s_nb[nb], 1u);
             }
         }
-        __syncthreads();
-        if (threadIdx.x < 7 && s_nb[threadIdx.x]) {
-            const int off[7] = {0, -1, 1, -S.ntx, S.ntx, -S.ntx * S.nty, S.ntx * S.nty};
-            atomicAdd(S.counts + tile + off[threadIdx.x], s_nb[threadIdx.x]);
-        }
-        // the tile's partial sums into the FP64 tally (cells of this tile only)
-        for (int i = threadIdx.x; i < tcells; i += blockDim.x) {
-            const R a = acc_t[i];
-            const double a2 = acc2_t ? acc2_t[i] : 0.0;
-            if (a != (R)0 || a2 != 0.0) {
-                const int lx = i % txy, ly = (i / txy) % txy, lz = i / (txy * txy);
-                const int64_t j = (o0 + lx) + (int64_t)P.n[0] * ((o1 + ly) + (int64_t)P.n[1] * (o2 + lz));
-                if (a != (R)0) unsafeAtomicAdd(P.acc + j, (double)a);
-                if (a2 != 0.0) unsafeAtomicAdd(P.acc2 + j, a2);
-            }
-        }
     }
+    if (tile >= 0) flush_tile(P, S, tile, o0, o1, o2, txy, tcells, acc_t, acc2_t, s_nb);
     flush_block_counters(P, cnt, e_escaped, e_killed, s_cnt, s_energy);
 }
 
@@ -502,8 +579,8 @@ __global__ void __launch_bounds__(256) k_tile_order(const unsigned* __restrict__
             const unsigned i = c0 + (unsigned)(j * 256) + threadIdx.x;
             slot[j] = -1;
             rank[j] = 0u;
-            if (i < n) {
-                const unsigned t = out_tile[i];
+            const unsigned t = i < n ? out_tile[i] : kNoTile;
+            if (t != kNoTile) {
                 unsigned h = (t * 2654435761u) >> 22;
                 int found = -1;
                 for (int probe = 0; probe < kOrderHash; ++probe) {
@@ -533,8 +610,8 @@ __global__ void __launch_bounds__(256) k_tile_order(const unsigned* __restrict__
     }
 }
 
-__global__ void k_zero_u32(unsigned* p, int n) {
-    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) p[i] = 0u;
+__global__ void k_fill_u32(unsigned* p, int n, unsigned v) {
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) p[i] = v;
 }
 
 // ---------------------------------------------------------------------------
@@ -554,8 +631,10 @@ template <typename R> SweepFn<R> pick_sweep(int K) {
 
 template <typename R>
 hipError_t launch_sweep_emit(const TransportParams<R>& P, const SweepParams& S, uint64_t first,
-                             uint64_t count, int blocks, hipStream_t st) {
-    hipLaunchKernelGGL(k_sweep_emit<R>, dim3(blocks), dim3(256), 0, st, P, S, first, count);
+                             uint64_t count, unsigned base, int blocks, hipStream_t st) {
+    const int hist = S.ntiles <= kEmitHistTiles ? 1 : 0;
+    hipLaunchKernelGGL(k_sweep_emit<R>, dim3(blocks), dim3(256), hist ? S.ntiles * sizeof(unsigned) : 0, st,
+                       P, S, first, count, base, hist);
     return hipGetLastError();
 }
 
@@ -590,16 +669,16 @@ hipError_t launch_tile_sort(const SweepParams& S, unsigned* order, unsigned* til
     return hipGetLastError();
 }
 
-hipError_t launch_zero_u32(unsigned* p, int n, hipStream_t st) {
-    hipLaunchKernelGGL(k_zero_u32, dim3((n + 255) / 256 < 1024 ? (n + 255) / 256 : 1024), dim3(256), 0,
-                       st, p, n);
+hipError_t launch_fill_u32(unsigned* p, int n, unsigned v, hipStream_t st) {
+    hipLaunchKernelGGL(k_fill_u32, dim3((n + 255) / 256 < 1024 ? (n + 255) / 256 : 1024), dim3(256), 0,
+                       st, p, n, v);
     return hipGetLastError();
 }
 
 template hipError_t launch_sweep_emit<float>(const TransportParams<float>&, const SweepParams&,
-                                             uint64_t, uint64_t, int, hipStream_t);
+                                             uint64_t, uint64_t, unsigned, int, hipStream_t);
 template hipError_t launch_sweep_emit<double>(const TransportParams<double>&, const SweepParams&,
-                                              uint64_t, uint64_t, int, hipStream_t);
+                                              uint64_t, uint64_t, unsigned, int, hipStream_t);
 template hipError_t launch_sweep<float>(const TransportParams<float>&, const SweepParams&, int, int,
                                         int, size_t, hipStream_t);
 template hipError_t launch_sweep<double>(const TransportParams<double>&, const SweepParams&, int,
