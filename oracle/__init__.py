@@ -95,6 +95,7 @@ def lib():
         L.orc_set_peeloff.argtypes = [vp, C.c_void_p, C.c_int]
         L.orc_get_peeled_sed.argtypes = [vp, C.c_void_p, C.c_void_p, C.c_size_t]
         L.orc_get_peeled_images.argtypes = [vp, C.c_void_p, C.c_void_p, C.c_size_t]
+        L.orc_raytrace.argtypes = [vp, C.c_int, C.c_double, C.c_void_p, C.c_void_p]
         L.orc_get_event_log.argtypes = [vp, C.c_void_p, C.c_size_t, C.c_void_p, C.c_size_t]
         L.orc_get_emission_rows.argtypes = [vp, C.c_void_p, C.c_void_p, C.c_size_t]
         L.orc_philox4x32_10.argtypes = [C.c_void_p, C.c_void_p, C.c_void_p]
@@ -342,6 +343,16 @@ class OracleModel:
         self._check(self.L.orc_get_peeled_images(self.h, s.ctypes.data, s2.ctypes.data, n))
         sh = (self.n_img, self.n_peel, self.npix, self.npix)
         return s[:n].reshape(sh), s2[:n].reshape(sh)
+
+    def raytrace(self, npix: int, half_width: float):
+        """Raytraced emission (Sec. 2.6.3) toward the peel-off observers at the
+        current temperatures: sed [n_peel][2][nnu] (0 sources, 1 dust) and the
+        spectral cube [n_peel][npix][npix][nnu], erg/s/sr per pixel."""
+        cube = np.zeros(self.n_peel * npix * npix * self.nnu)
+        sed = np.zeros(self.n_peel * 2 * self.nnu)
+        self._check(self.L.orc_raytrace(self.h, int(npix), float(half_width), cube.ctypes.data,
+                                        sed.ctypes.data))
+        return sed.reshape(self.n_peel, 2, self.nnu), cube.reshape(self.n_peel, npix, npix, self.nnu)
 
     def event_log(self):
         npk = int(self.run.get("event_log_packets", 0))

@@ -1473,3 +1473,148 @@ int64_t orc_trace_ray(const orc_model* m, const double x0[3], const double d[3],
     }
     return n;
 }
+
+/* ======================================================================= */
+/* Raytracing of source and dust emission (Sec. 2.6.3).                    */
+/* ======================================================================= */
+
+/* Image axes of the observer direction o: e_x = norm(z x o) (e_x = x when o is
+ * along z), e_y = o x e_x -- the axes of the peeled images. */
+static void image_axes(const double o[3], double ex[3], double ey[3])
+{
+    ex[0] = -o[1];
+    ex[1] = o[0];
+    ex[2] = 0.0;
+    double en = sqrt(ex[0] * ex[0] + ex[1] * ex[1]);
+    if (en < 1e-12) {
+        ex[0] = 1.0;
+        ex[1] = 0.0;
+    } else {
+        ex[0] /= en;
+        ex[1] /= en;
+    }
+    ey[0] = -o[2] * ex[1];
+    ey[1] = o[2] * ex[0];
+    ey[2] = o[0] * ex[1] - o[1] * ex[0];
+}
+
+/* The raytraced emission, in post-processing at the current temperatures,
+ * toward every peel-off observer o.  The image has npix x npix pixels over
+ * +-hw (cm) around the grid centre on the axes of image_axes.  Through each
+ * pixel centre X e_x + Y e_y a ray is followed from the observer's side of
+ * the grid along -o; in every bin k it accumulates the formal solution of the
+ * transfer equation through cells of constant density and temperature,
+ *     I_k = sum over cells, front to back, of
+ *           exp(-tau_k in front of the cell) S_k (1 - exp(-dtau_k)),
+ * with dtau_k = rho chi_k l over the cell's chord l and the source function
+ * S_k = (kappa_k / chi_k) B_k(T): thermal emission rho kappa_k B_k(T) over
+ * extinction rho chi_k, B_k the Planck function integrated over the bin (per
+ * steradian).  Scattered light is not part of it (peeling-off's share).
+ * cube[o][iy][ix][k] = I_k (2 hw / npix)^2 (erg/s/sr from the pixel); each
+ * point source adds L_k / (4 pi) exp(-tau_k(source -> grid boundary along o))
+ * to the pixel it projects into.  sed[o][0][k]: the sources, sed[o][1][k]: the
+ * sum of the dust part over the pixels. */
+int orc_raytrace(orc_model* m, int npix, double hw, double* cube, double* sed)
+{
+    if (!m->have_grid || !m->have_rho || !m->have_dust) return fail(m, "model is not set up");
+    if (m->n_peel <= 0) return fail(m, "no observers: call orc_set_peeloff first");
+    if (npix <= 0 || !(hw > 0.0)) return fail(m, "bad image size");
+    const int nnu = m->nnu;
+    const double apix = (2.0 * hw / npix) * (2.0 * hw / npix);
+    double* I = (double*)malloc(2 * (size_t)nnu * sizeof(double));
+    double* tau = I + nnu;
+    double cen[3];
+    for (int a = 0; a < 3; ++a) cen[a] = 0.5 * (m->lo[a] + m->hi[a]);
+    memset(sed, 0, (size_t)m->n_peel * 2 * nnu * sizeof(double));
+    for (int i = 0; i < m->n_peel; ++i) {
+        const double* o = m->peel_dir + 3 * i;
+        double ex[3], ey[3], d[3] = {-o[0], -o[1], -o[2]};
+        image_axes(o, ex, ey);
+        for (int iy = 0; iy < npix; ++iy)
+            for (int ix = 0; ix < npix; ++ix) {
+                double* out = cube + (((size_t)i * npix + iy) * npix + ix) * nnu;
+                for (int k = 0; k < nnu; ++k) I[k] = tau[k] = 0.0;
+                const double X = -hw + (ix + 0.5) * (2.0 * hw / npix);
+                const double Y = -hw + (iy + 0.5) * (2.0 * hw / npix);
+                double q[3];
+                for (int a = 0; a < 3; ++a) q[a] = cen[a] + X * ex[a] + Y * ey[a];
+                /* the line q + s o meets the grid box for s in [s0, s1] */
+                double s0 = -INFINITY, s1 = INFINITY;
+                int miss = 0;
+                for (int a = 0; a < 3; ++a) {
+                    if (o[a] != 0.0) {
+                        double u = (m->lo[a] - q[a]) / o[a], v = (m->hi[a] - q[a]) / o[a];
+                        if (u > v) { double w = u; u = v; v = w; }
+                        if (u > s0) s0 = u;
+                        if (v < s1) s1 = v;
+                    } else if (q[a] < m->lo[a] || q[a] >= m->hi[a]) {
+                        miss = 1;
+                    }
+                }
+                if (!miss && s1 > s0) {
+                    double x[3];
+                    int c[3];
+                    for (int a = 0; a < 3; ++a) x[a] = q[a] + s1 * o[a];
+                    locate(m, x, d, c);
+                    for (int a = 0; a < 3; ++a) { /* the entry point lies on the box */
+                        if (c[a] < 0) c[a] = 0;
+                        if (c[a] >= m->n[a]) c[a] = m->n[a] - 1;
+                    }
+                    while (inside(m, c)) {
+                        double tw[3];
+                        for (int a = 0; a < 3; ++a) tw[a] = wall_distance(m, x, d, c, a);
+                        int ax = 0;
+                        if (tw[1] < tw[ax]) ax = 1;
+                        if (tw[2] < tw[ax]) ax = 2;
+                        const double l = tw[ax] > 0.0 ? tw[ax] : 0.0;
+                        const int64_t j = c[0] + (int64_t)m->n[0] * (c[1] + (int64_t)m->n[1] * c[2]);
+                        const double r = m->rho[j];
+                        if (r > 0.0) {
+                            const double T = m->T[j];
+                            for (int k = 0; k < nnu; ++k) {
+                                const double dt = r * m->chi[k] * l;
+                                const double S = T > 0.0 ? m->kap[k] / m->chi[k] *
+                                                               orc_planck_bin(m->nu[k], m->nu[k + 1], T)
+                                                         : 0.0;
+                                I[k] += exp(-tau[k]) * S * -expm1(-dt);
+                                tau[k] += dt;
+                            }
+                        }
+                        for (int a = 0; a < 3; ++a) x[a] += d[a] * l;
+                        if (d[ax] > 0.0) {
+                            x[ax] = wall(m, ax, c[ax] + 1);
+                            c[ax] += 1;
+                        } else {
+                            x[ax] = wall(m, ax, c[ax]);
+                            c[ax] -= 1;
+                        }
+                    }
+                }
+                for (int k = 0; k < nnu; ++k) {
+                    out[k] = I[k] * apix;
+                    sed[((size_t)i * 2 + 1) * nnu + k] += out[k];
+                }
+            }
+        /* point sources */
+        for (int s = 0; s < m->nsrc; ++s) {
+            const double* p = m->spos + 3 * s;
+            double tot = 0.0;
+            for (int k = 0; k < nnu; ++k) tot += m->sspec[(size_t)s * nnu + k];
+            double pc[3];
+            for (int a = 0; a < 3; ++a) pc[a] = p[a] - cen[a];
+            const double X = pc[0] * ex[0] + pc[1] * ex[1] + pc[2] * ex[2];
+            const double Y = pc[0] * ey[0] + pc[1] * ey[1] + pc[2] * ey[2];
+            const double fx = floor((X + hw) / (2.0 * hw) * npix);
+            const double fy = floor((Y + hw) / (2.0 * hw) * npix);
+            const int in_img = fx >= 0.0 && fy >= 0.0 && fx < npix && fy < npix;
+            for (int k = 0; k < nnu; ++k) {
+                const double Lk = m->slum[s] * m->sspec[(size_t)s * nnu + k] / tot;
+                const double v = Lk / (4.0 * ORC_PI) * exp(-tau_to_boundary(m, p, o, k));
+                sed[((size_t)i * 2) * nnu + k] += v;
+                if (in_img) cube[(((size_t)i * npix + (size_t)fy) * npix + (size_t)fx) * nnu + k] += v;
+            }
+        }
+    }
+    free(I);
+    return 0;
+}

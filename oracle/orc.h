@@ -128,6 +128,11 @@ int orc_get_images(const orc_model* m, double* sum, double* sum2, size_t n);
 int orc_set_peeloff(orc_model* m, const double* dirs, int n);
 int orc_get_peeled_sed(const orc_model* m, double* sum, double* sum2, size_t n);
 int orc_get_peeled_images(const orc_model* m, double* sum, double* sum2, size_t n);
+/* Raytracing (Sec. 2.6.3) of the dust's thermal emission at the current
+ * temperatures and of the point sources toward the peel-off observers:
+ * cube [n_peel][npix][npix][nnu] (erg/s/sr per pixel of an image over +-hw cm
+ * on the peeled images' axes), sed [n_peel][2][nnu] (0 sources, 1 dust). */
+int orc_raytrace(orc_model* m, int npix, double hw, double* cube, double* sed);
 int orc_get_event_log(const orc_model* m, orc_event* ev, size_t cap, int32_t* counts, size_t n_counts);
 int orc_get_emission_rows(const orc_model* m, int32_t* row, double* w, size_t n);
 
