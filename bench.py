@@ -12,6 +12,7 @@ from __future__ import annotations
 
 import argparse
 import json
+import math
 import os
 import sys
 import time
@@ -82,13 +83,13 @@ def bench_batch(args):
     n_packets = sum(int(c["run"]["n_packets"]) for c in cfgs)
     cells = sum(int(np.prod(c["grid"]["n"])) for c in cfgs)
     # iteration 0, which also tunes the launch shape (cached per workload class)
-    stw = mcrt.batch_run(batch, n_iter=1, final_pass=0, use_graph=0, autotune=1)
+    stw = mcrt.batch_run(batch, n_iter=1, final_pass=0, use_graph=0, autotune=1, verbose=1)
     print(f"# iteration 0 + tuning: {stw['ms_total']:.0f} ms (tune {stw['ms_tune']:.0f} ms) shape "
           f"bs={stw['block_size']} K={stw['walk_batch']} defer={stw['defer_lanes']}",
           file=sys.stderr, flush=True)
     torch.cuda.synchronize()
     tb = time.perf_counter()
-    st = mcrt.batch_run(batch, n_iter=args.steps, final_pass=0, use_graph=1, autotune=1)
+    st = mcrt.batch_run(batch, n_iter=args.steps, final_pass=0, use_graph=1, autotune=1, verbose=1)
     torch.cuda.synchronize()
     batch_s = time.perf_counter() - tb
     value = n_packets * args.steps / batch_s
@@ -108,7 +109,7 @@ def bench_batch(args):
         seq_s += time.perf_counter() - ts
         seq_packets += int(c["run"]["n_packets"]) * args.steps
         m.close()
-        if (i + 1) % 32 == 0:
+        if (i + 1) % 8 == 0:
             print(f"# sequential: {i + 1}/{nseq} models", file=sys.stderr, flush=True)
     seq_value = seq_packets / seq_s
     ms_it = 1e3 * batch_s / args.steps
@@ -127,6 +128,48 @@ def bench_batch(args):
                   "ms_tune": stw["ms_tune"]},
         "sequential": {"value": seq_value, "unit": "packets/s", "models": nseq,
                        "seconds": seq_s, "speedup_batched": value / seq_value},
+    }
+    print(json.dumps(out), flush=True)
+
+
+def bench_raytrace(args):
+    """Raytracing (Sec. 2.6.3) of the 256^3 clump's dust and source emission in
+    all 200 bins toward one oblique observer, npix^2 rays, at the temperatures
+    of two Lucy iterations of 1e7 packets."""
+    from paper_1112_1071_amd import mcrt, synth
+
+    cfg = synth.config2(n=args.grid, n_packets=10_000_000, n_iter=2)
+    cfg["peeloff"] = {"dirs": [[0.48, -0.6, 0.64]]}
+    m = mcrt.Model(cfg, precision=mcrt.MCRT_FP32_TRANSPORT)
+    m.iterate()
+    m.iterate()
+    hw = 0.5 * 0.65 * synth.PC * math.sqrt(3.0) * 1.01
+    m.raytrace(args.npix, hw, cube=False)  # warm-up (allocation)
+    times = []
+    for i in range(args.steps):
+        t0 = time.perf_counter()
+        sed, _ = m.raytrace(args.npix, hw, cube=False)
+        times.append(time.perf_counter() - t0)
+        print(f"# raytrace {i}: {1e3 * times[-1]:.1f} ms", file=sys.stderr, flush=True)
+    ms = 1e3 * float(np.median(times))
+    nnu = len(cfg["nu_edges"]) - 1
+    # cell segments of all rays: every ray through the grid box crosses about
+    # (chord / cell) * (|o_x| + |o_y| + |o_z|) cells; counted exactly by the oracle's walk
+    # would cost minutes, so the figure uses the mean chord of the image's rays
+    n = args.grid
+    o = np.array([0.48, -0.6, 0.64])
+    cells_per_length = np.abs(o).sum() * n / (0.65 * synth.PC)
+    mean_chord_area = (0.65 * synth.PC) ** 3  # sum over rays of chord * pixel area = volume
+    apix = (2 * hw / args.npix) ** 2
+    segments = mean_chord_area / apix * cells_per_length
+    out = {
+        "metric": "raytraced emission: cell-bin segments per second",
+        "value": segments * nnu / (ms * 1e-3), "unit": "segments/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": 1, "ms_per_step": ms, "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+        "config": {"workload": f"raytrace: {n}^3 clump, {nnu} bins, one observer, {args.npix}^2 rays",
+                   "npix": args.npix, "rays": args.npix ** 2, "cell_segments": segments,
+                   "sed_dust_total": float(sed[0, 1].sum()), "sed_sources_total": float(sed[0, 0].sum())},
     }
     print(json.dumps(out), flush=True)
 
@@ -173,7 +216,8 @@ def bench_warmstart(args):
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--workload", choices=["clump256", "batch", "warmstart"], default="clump256")
+    ap.add_argument("--workload", choices=["clump256", "batch", "warmstart", "raytrace"], default="clump256")
+    ap.add_argument("--npix", type=int, default=256, help="raytrace: image pixels per side")
     ap.add_argument("--clumps", type=int, default=2, help="warmstart: test clumps")
     ap.add_argument("--weights", default=os.path.join(ROOT, "paper_1112_1071_amd", "weights",
                                                       "warmstart_c16.npy"))
@@ -205,6 +249,9 @@ def main():
         sys.exit(2)
     if args.workload == "batch":
         bench_batch(args)
+        return
+    if args.workload == "raytrace":
+        bench_raytrace(args)
         return
     if args.workload == "warmstart":
         if args.packets == 1e8:

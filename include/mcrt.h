@@ -198,6 +198,30 @@ mcrt_status mcrt_set_peeloff(mcrt_model* m, const double* dirs, int n);
 mcrt_status mcrt_get_peeled_sed(mcrt_model* m, double* sum, double* sum2, size_t n);
 /* Peeled images [n_img][n][npix][npix]: e_x = norm(z x o), e_y = o x e_x. */
 mcrt_status mcrt_get_peeled_images(mcrt_model* m, double* sum, double* sum2, size_t n);
+/* Raytracing (Sec. 2.6.3) of the emission toward the peel-off observers, in
+ * post-processing at the current temperatures.  Per observer o an image of
+ * npix x npix pixels over +-half_width (cm) around the grid centre on the axes
+ * of the peeled images; through each pixel centre one ray, followed from the
+ * observer's side of the grid along -o, sums in every frequency bin k the
+ * formal solution through cells of constant density and temperature:
+ *     I_k = sum over cells, front to back, exp(-tau_k in front) S_k (1 - exp(-dtau_k)),
+ * dtau_k = rho chi_k l (l the chord), S_k = (kappa_k / chi_k) B_k(T): the
+ * dust's thermal emission over extinction, B_k the bin-integrated Planck
+ * function per sr.  Scattered light is not included (that is peeling-off's
+ * share).  Pixel values are I_k times the pixel area (erg/s/sr); each point
+ * source adds L_k/(4 pi) exp(-tau_k(source -> boundary along o)) to the pixel
+ * it projects into.  The SED is the pixel sum, so half_width should cover the
+ * grid; it is a quadrature of the image plane that needs pixels small against
+ * the cells' projection.  Needs mcrt_set_peeloff; the model keeps the cube
+ * (n_peel*npix^2*n_nu doubles, at most 2^34) until the next call or destroy. */
+mcrt_status mcrt_raytrace(mcrt_model* m, int npix, double half_width);
+/* Raytraced SED [n_peel][2][n_nu] (erg/s/sr): 0 point sources, 1 dust. */
+mcrt_status mcrt_get_raytraced_sed(mcrt_model* m, double* sed, size_t n);
+/* Raytraced spectral cube [n_peel][npix][npix][n_nu] (erg/s/sr per pixel,
+ * dust and sources), host copy or the device pointer (valid until the next
+ * mcrt_raytrace or mcrt_destroy). */
+mcrt_status mcrt_get_raytraced_cube(mcrt_model* m, double* cube, size_t n);
+mcrt_status mcrt_get_raytraced_cube_device(mcrt_model* m, const double** d_cube);
 mcrt_status mcrt_run_cfg_default(mcrt_run_cfg* cfg);
 mcrt_status mcrt_set_run(mcrt_model* m, const mcrt_run_cfg* cfg);
 /* Temperatures (K, > 0) that the next iteration re-emits from (warm start). */
@@ -246,6 +270,7 @@ typedef struct {
     int32_t defer_lanes;       /* 0 = tuned or 16                                          */
     int32_t blocks_per_cu;     /* 0 = tuned or occupancy limit                             */
     double tune_fraction;      /* packet fraction of each calibration run [0.02]           */
+    int32_t verbose;           /* 1: a line on stderr after each iteration [0]             */
 } mcrt_batch_cfg;
 
 typedef struct {

@@ -18,6 +18,7 @@ BUILD_DIR = os.path.join(HERE, "_build")
 SOURCES = [
     "mcrt_transport.hip",
     "mcrt_sweep.hip",
+    "mcrt_raytrace.hip",
     "mcrt_cells.hip",
     "mcrt_tables.cpp",
     "mcrt_api.cpp",

@@ -3,6 +3,7 @@
 // 2011, Sec. 2: inputs -> propagation -> Adot -> convergence -> SEDs/images).
 #include <hip/hip_runtime.h>
 #include <math.h>
+#include <stdio.h>
 #include <string.h>
 
 #include <chrono>
@@ -55,6 +56,7 @@ template <typename R> int sweep_max_blocks_per_cu(int K, int threads, size_t lds
 hipError_t launch_tile_sort(const SweepParams& S, unsigned* order, unsigned* tile_off,
                             unsigned* item_off, unsigned* cursor, int blocks, hipStream_t st);
 hipError_t launch_fill_u32(unsigned* p, int n, unsigned v, hipStream_t st);
+hipError_t launch_raytrace(const RayParams& R, hipStream_t st);
 }  // namespace mcrt
 
 using namespace mcrt;
@@ -142,6 +144,9 @@ struct mcrt_model {
     DBuf<double> sed_sum, sed_sum2, img_sum, img_sum2;
     int n_peel = 0;
     DBuf<double> peel_dir, psed_sum, psed_sum2, pimg_sum, pimg_sum2;
+    // raytracing: spectral cube and SED of the last mcrt_raytrace, its image
+    DBuf<double> ray_cube, ray_sed, ray_nu, ray_lsrc;
+    int ray_npix = 0;
     DBuf<unsigned long long> sed_n;
     DBuf<mcrt_event> evlog;
     DBuf<int32_t> evcount;
@@ -939,6 +944,7 @@ void mcrt_destroy(mcrt_model* m) {
     m->img_sum.release(); m->img_sum2.release(); m->evlog.release(); m->evcount.release();
     m->peel_dir.release(); m->psed_sum.release(); m->psed_sum2.release();
     m->pimg_sum.release(); m->pimg_sum2.release();
+    m->ray_cube.release(); m->ray_sed.release(); m->ray_nu.release(); m->ray_lsrc.release();
     m->misc.release(); m->energies.release(); m->hist.release();
     m->sw_a.release(); m->sw_b.release(); m->sw_tile.release(); m->sw_counts.release();
     m->sw_tile_off.release(); m->sw_item_off.release(); m->sw_cursor.release(); m->sw_ctr.release();
@@ -1197,6 +1203,88 @@ mcrt_status mcrt_get_peeled_images(mcrt_model* m, double* sum, double* sum2, siz
             HIPCHK(hipMemcpyAsync(sum2, m->pimg_sum2.p, npi * sizeof(double), hipMemcpyDeviceToHost, m->stream));
     }
     HIPCHK(hipStreamSynchronize(m->stream));
+    return MCRT_OK;
+}
+
+mcrt_status mcrt_raytrace(mcrt_model* m, int npix, double half_width) {
+    if (!m) return MCRT_E_ARG;
+    if (m->n_peel <= 0) return fail(m, MCRT_E_STATE, "no observers: call mcrt_set_peeloff first");
+    if (npix < 1 || npix > 65536 || !(half_width > 0.0) || !isfinite(half_width))
+        return fail(m, MCRT_E_ARG, "npix must be in [1, 65536] and half_width > 0");
+    hipSetDevice(m->device);
+    mcrt_status r = ready(m);
+    if (r != MCRT_OK) return r;
+    const size_t nnu = m->kap.size(), ns = m->src.size();
+    const size_t ncube = (size_t)m->n_peel * npix * npix * nnu;
+    if (ncube > ((size_t)1 << 34) || (size_t)m->n_peel * npix * npix > ((size_t)1 << 32))
+        return fail(m, MCRT_E_ARG, "image cube above 2^34 values or 2^32 pixels");
+    HIPCHK(m->ray_cube.ensure(ncube));
+    HIPCHK(m->ray_sed.ensure((size_t)m->n_peel * 2 * nnu));
+    HIPCHK(m->ray_nu.ensure(nnu + 1));
+    HIPCHK(m->ray_lsrc.ensure(ns * nnu));
+    std::vector<double> lsrc(ns * nnu);
+    for (size_t i = 0; i < ns; ++i) {
+        double tot = 0.0;
+        for (size_t k = 0; k < nnu; ++k) tot += m->src[i].spec[k];
+        for (size_t k = 0; k < nnu; ++k) lsrc[i * nnu + k] = m->src[i].lum * m->src[i].spec[k] / tot;
+    }
+    hipStream_t s = m->stream;
+    HIPCHK(hipMemcpyAsync(m->ray_nu.p, m->nu.data(), (nnu + 1) * sizeof(double), hipMemcpyHostToDevice, s));
+    if (ns) HIPCHK(hipMemcpyAsync(m->ray_lsrc.p, lsrc.data(), ns * nnu * sizeof(double), hipMemcpyHostToDevice, s));
+    HIPCHK(hipMemsetAsync(m->ray_sed.p, 0, (size_t)m->n_peel * 2 * nnu * sizeof(double), s));
+    RayParams R{};
+    for (int a = 0; a < 3; ++a) {
+        R.n[a] = m->n[a];
+        R.lo[a] = m->lo[a];
+        R.hi[a] = m->hi[a];
+        R.dx[a] = m->dx[a];
+    }
+    R.rho = m->rho64.p;
+    R.T = m->T.p;
+    R.nnu = (int)nnu;
+    R.nu = m->ray_nu.p;
+    R.chi = m->chi64.p;
+    R.kap = m->kap64.p;
+    R.n_obs = m->n_peel;
+    R.dirs = m->peel_dir.p;
+    R.npix = npix;
+    R.hw = half_width;
+    R.nsrc = (int)ns;
+    R.spos = m->spos.p;
+    R.lsrc = m->ray_lsrc.p;
+    R.cube = m->ray_cube.p;
+    R.sed = m->ray_sed.p;
+    HIPCHK(launch_raytrace(R, s));
+    HIPCHK(hipStreamSynchronize(s));
+    m->ray_npix = npix;
+    return MCRT_OK;
+}
+
+mcrt_status mcrt_get_raytraced_sed(mcrt_model* m, double* sed, size_t n) {
+    if (!m || !sed) return MCRT_E_ARG;
+    if (m->ray_npix == 0) return fail(m, MCRT_E_STATE, "no raytracing done");
+    if (n != (size_t)m->n_peel * 2 * m->kap.size()) return fail(m, MCRT_E_SIZE, "raytraced SED size is n_peel*2*n_nu");
+    hipSetDevice(m->device);
+    HIPCHK(hipMemcpyAsync(sed, m->ray_sed.p, n * sizeof(double), hipMemcpyDeviceToHost, m->stream));
+    HIPCHK(hipStreamSynchronize(m->stream));
+    return MCRT_OK;
+}
+
+mcrt_status mcrt_get_raytraced_cube(mcrt_model* m, double* cube, size_t n) {
+    if (!m || !cube) return MCRT_E_ARG;
+    if (m->ray_npix == 0) return fail(m, MCRT_E_STATE, "no raytracing done");
+    if (n != (size_t)m->n_peel * m->ray_npix * m->ray_npix * m->kap.size())
+        return fail(m, MCRT_E_SIZE, "raytraced cube size is n_peel*npix^2*n_nu");
+    hipSetDevice(m->device);
+    HIPCHK(hipMemcpyAsync(cube, m->ray_cube.p, n * sizeof(double), hipMemcpyDeviceToHost, m->stream));
+    HIPCHK(hipStreamSynchronize(m->stream));
+    return MCRT_OK;
+}
+
+mcrt_status mcrt_get_raytraced_cube_device(mcrt_model* m, const double** d_cube) {
+    if (!m || !d_cube) return MCRT_E_ARG;
+    if (m->ray_npix == 0) return fail(m, MCRT_E_STATE, "no raytracing done");
+    *d_cube = m->ray_cube.p;
     return MCRT_OK;
 }
 
@@ -1643,6 +1731,7 @@ mcrt_status batch_run(Batch& B, const mcrt_batch_cfg* c, mcrt_batch_stats* st) {
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
     for (int it = 0; it < c->n_iter; ++it) {
+        const double t_it = now_ms();
         const bool replay = c->use_graph && it > 0;
         if (replay && !exec) {
             BCHK(hipStreamBeginCapture(B.s, hipStreamCaptureModeThreadLocal));
@@ -1681,6 +1770,11 @@ mcrt_status batch_run(Batch& B, const mcrt_batch_cfg* c, mcrt_batch_stats* st) {
             m->have_prev = 1;
         }
         st->n_iterations++;
+        if (c->verbose) {
+            fprintf(stderr, "# batch iteration %d of %d: %.1f ms%s\n", it + 1, c->n_iter, now_ms() - t_it,
+                    replay ? " (graph replay)" : "");
+            fflush(stderr);
+        }
     }
     if (exec) hipGraphExecDestroy(exec);
     if (graph) hipGraphDestroy(graph);

@@ -99,6 +99,27 @@ struct TransportParams {
     double* energies;              // [2] escaped, killed
 };
 
+// Raytracing of the emission toward the peel-off observers (FP64 throughout).
+struct RayParams {
+    int n[3];
+    double lo[3], hi[3], dx[3];
+    const double* rho;      // [ncell] density, x fastest
+    const double* T;        // [ncell] temperature, K
+    int nnu;
+    const double* nu;       // [nnu+1] bin edges, Hz
+    const double* chi;      // [nnu] extinction opacity, cm^2/g
+    const double* kap;      // [nnu] absorption opacity, cm^2/g
+    int n_obs;
+    const double* dirs;     // [3*n_obs] unit vectors toward the observers
+    int npix;
+    double hw;              // image half width, cm
+    int nsrc;
+    const double* spos;     // [3*nsrc]
+    const double* lsrc;     // [nsrc*nnu] source luminosity per bin, erg/s
+    double* cube;           // [n_obs][npix][npix][nnu], erg/s/sr per pixel
+    double* sed;            // [n_obs][2][nnu] (0 sources, 1 dust), erg/s/sr
+};
+
 // Tiled sweeps: the tiling and the buffers of one sweep.
 struct SweepParams {
     int txy;                    // tile extent in x and y (cells): 16 or 32

@@ -74,6 +74,7 @@ class BatchCfg(C.Structure):
         ("n_iter", C.c_int32), ("final_pass", C.c_int32), ("use_graph", C.c_int32),
         ("autotune", C.c_int32), ("block_size", C.c_int32), ("walk_batch", C.c_int32),
         ("defer_lanes", C.c_int32), ("blocks_per_cu", C.c_int32), ("tune_fraction", C.c_double),
+        ("verbose", C.c_int32),
     ]
 
 
@@ -141,6 +142,10 @@ def lib():
         "mcrt_get_images": ([vp, vp, vp, sz], i32),
         "mcrt_get_event_log": ([vp, vp, sz, vp, sz], i32),
         "mcrt_device_info": ([vp, C.POINTER(i32), C.POINTER(i32)], i32),
+        "mcrt_raytrace": ([vp, i32, dbl], i32),
+        "mcrt_get_raytraced_sed": ([vp, vp, sz], i32),
+        "mcrt_get_raytraced_cube": ([vp, vp, sz], i32),
+        "mcrt_get_raytraced_cube_device": ([vp, C.POINTER(vp)], i32),
         "mcrt_batch_cfg_default": ([C.POINTER(BatchCfg)], i32),
         "mcrt_batch_run": ([C.POINTER(vp), i32, C.POINTER(BatchCfg), C.POINTER(BatchStats)], i32),
         "mcrt_surrogate_create": ([C.POINTER(vp), i32, i32, C.c_uint64], i32),
@@ -354,6 +359,20 @@ class Model:
         return n.value, w.value
 
     # -- learned warm start ----------------------------------------------------
+    def raytrace(self, npix: int, half_width: float, cube: bool = True):
+        """Raytraced emission (Sec. 2.6.3) toward the peel-off observers at the
+        current temperatures: SED [n_peel][2][n_nu] (0 sources, 1 dust) and, if
+        cube, the spectral cube [n_peel][npix][npix][n_nu] (erg/s/sr per pixel)."""
+        self._check(self.L.mcrt_raytrace(self.h, int(npix), float(half_width)))
+        sed = np.zeros(self.n_peel * 2 * self.nnu)
+        self._check(self.L.mcrt_get_raytraced_sed(self.h, _ptr(sed), sed.size))
+        sed = sed.reshape(self.n_peel, 2, self.nnu)
+        if not cube:
+            return sed, None
+        c = np.zeros(self.n_peel * npix * npix * self.nnu)
+        self._check(self.L.mcrt_get_raytraced_cube(self.h, _ptr(c), c.size))
+        return sed, c.reshape(self.n_peel, npix, npix, self.nnu)
+
     def features(self):
         """FP32 device tensor [ncell, 3] of the network's input features."""
         import torch

@@ -80,7 +80,7 @@ def kernels(a) -> str:
     rows = list(csv.DictReader(open(files[0])))
     out = ["| kernel | calls | total ms | per iteration ms | average µs | % |", "|---|---|---|---|---|---|"]
     for r in rows[:12]:
-        name = r["Name"].split("(")[0].replace("void ", "")
+        name = r["Name"].replace("(anonymous namespace)::", "").split("(")[0].replace("void ", "")
         tot = float(r["TotalDurationNs"]) / 1e6
         out.append(f"| `{name}` | {r['Calls']} | {tot:.1f} | {tot / a.iterations:.1f} | "
                    f"{float(r['AverageNs']) / 1e3:.1f} | {float(r['Percentage']):.1f} |")
