@@ -35,6 +35,7 @@ class RunCfg(C.Structure):
         ("source_sampling", C.c_int32), ("want_noise", C.c_int32),
         ("event_log_packets", C.c_int32), ("event_log_cap", C.c_int32),
         ("bin_every_iteration", C.c_int32), ("n_threads", C.c_int32), ("chunk", C.c_int32),
+        ("mrw_gamma", C.c_double),
     ]
 
 
@@ -47,6 +48,7 @@ class IterStats(C.Structure):
         ("n_cross_dust", C.c_int64), ("n_cross_empty", C.c_int64), ("n_scatter", C.c_int64),
         ("n_absorb", C.c_int64), ("n_escape", C.c_int64), ("n_killed", C.c_int64),
         ("e_escaped", C.c_double), ("e_killed", C.c_double), ("seconds", C.c_double),
+        ("n_mrw", C.c_int64),
     ]
 
     def as_dict(self) -> dict:
@@ -56,7 +58,7 @@ class IterStats(C.Structure):
 EVENT_DTYPE = np.dtype([("packet", "<i8"), ("index", "<i4"), ("type", "<i4"),
                         ("cell", "<i4", (3,)), ("nu", "<i4"), ("incl", "<i4"),
                         ("reserved", "<i4")])
-EV_EMIT, EV_SCATTER, EV_ABSORB, EV_ESCAPE, EV_KILLED = range(5)
+EV_EMIT, EV_SCATTER, EV_ABSORB, EV_ESCAPE, EV_KILLED, EV_MRW = range(6)
 
 _lib = None
 _dp = np.ctypeslib.ndpointer(dtype=np.float64, flags="C_CONTIGUOUS")
@@ -108,6 +110,12 @@ def lib():
         L.orc_planck_x_integral.argtypes = [C.c_double, C.c_double]
         L.orc_planck_bin.restype = C.c_double
         L.orc_planck_bin.argtypes = [C.c_double, C.c_double, C.c_double]
+        for f in ("orc_mrw_escape_y", "orc_mrw_escape_cdf"):
+            getattr(L, f).restype = C.c_double
+            getattr(L, f).argtypes = [C.c_double]
+        for f in ("orc_planck_mean_kappa", "orc_rosseland_chi"):
+            getattr(L, f).restype = C.c_double
+            getattr(L, f).argtypes = [vp, C.c_double]
         L.orc_adot_of_T.restype = C.c_double
         L.orc_adot_of_T.argtypes = [vp, C.c_double]
         L.orc_solve_T.restype = C.c_double
@@ -155,6 +163,16 @@ def planck_bin(nu_lo, nu_hi, T):
     return lib().orc_planck_bin(float(nu_lo), float(nu_hi), float(T))
 
 
+def mrw_escape_y(u):
+    """y with F(y) = u, F the first-passage distribution of diffusion from the
+    centre of a sphere (modified random walk)."""
+    return lib().orc_mrw_escape_y(float(u))
+
+
+def mrw_escape_cdf(y):
+    return lib().orc_mrw_escape_cdf(float(y))
+
+
 def hg_mu(g, u):
     return lib().orc_hg_mu(float(g), float(u))
 
@@ -190,6 +208,7 @@ def _cfg_from(run: dict) -> RunCfg:
     c.bin_every_iteration = int(run.get("bin_every_iteration", 0))
     c.n_threads = int(run.get("n_threads", 0))
     c.chunk = int(run.get("chunk", 0))
+    c.mrw_gamma = float(run.get("mrw_gamma", 0.0))
     return c
 
 
@@ -343,6 +362,12 @@ class OracleModel:
         self._check(self.L.orc_get_peeled_images(self.h, s.ctypes.data, s2.ctypes.data, n))
         sh = (self.n_img, self.n_peel, self.npix, self.npix)
         return s[:n].reshape(sh), s2[:n].reshape(sh)
+
+    def planck_mean_kappa(self, T: float) -> float:
+        return self.L.orc_planck_mean_kappa(self.h, float(T))
+
+    def rosseland_chi(self, T: float) -> float:
+        return self.L.orc_rosseland_chi(self.h, float(T))
 
     def raytrace(self, npix: int, half_width: float):
         """Raytraced emission (Sec. 2.6.3) toward the peel-off observers at the

@@ -42,7 +42,9 @@
  *     u = (floor(w/2^12) + 1/2) 2^-52 from the 64-bit words (x0:x1), (x2:x3);
  *   - draw order: emission u_src u_nu u_mu u_phi; each flight u_tau; each
  *     interaction u_int then (scatter) u_mu u_phi or (absorb) u_mix u_nu
- *     u_mu u_phi; every draw is consumed even when it cannot matter;
+ *     u_mu u_phi; every draw is consumed even when it cannot matter; a
+ *     modified-random-walk step (mrw_gamma > 0, at the start of a flight)
+ *     draws u_y u_mu u_phi u_mix u_nu u_mu u_phi;
  *   - grid walk: per axis the distance to the next wall; the smallest wins,
  *     ties go to the lowest axis (x, y, z) and one axis steps per segment;
  *     the stepped coordinate is set exactly onto the wall; walls are at
@@ -84,7 +86,7 @@
 #define ORC_T_HI 1.0e4
 #define ORC_T_FLOOR 1.0
 
-enum { EV_EMIT = 0, EV_SCATTER = 1, EV_ABSORB = 2, EV_ESCAPE = 3, EV_KILLED = 4 };
+enum { EV_EMIT = 0, EV_SCATTER = 1, EV_ABSORB = 2, EV_ESCAPE = 3, EV_KILLED = 4, EV_MRW = 5 };
 
 /* ======================================================================= */
 /* Philox4x32-10, from the published description (Salmon, Moraes, Dror &   */
@@ -271,6 +273,8 @@ struct orc_model {
     double* acc2;
     int32_t* row_m;
     double* row_w;
+    double* mrw_kp;   /* per cell, modified random walk: Planck-mean kappa at T */
+    double* mrw_chir; /* and Rosseland-mean chi at T (cm^2/g)                   */
     double* sed_sum;
     double* sed_sum2;
     int64_t* sed_n;
@@ -322,7 +326,8 @@ static void free_state(orc_model* m)
 {
     free(m->T); free(m->T_prev); free(m->T_valid); free(m->sig_rel); free(m->sig_rel_prev);
     free(m->adot); free(m->adot_prev); free(m->adot_sig);
-    free(m->acc); free(m->acc2); free(m->row_m); free(m->row_w);
+    free(m->acc); free(m->acc2); free(m->row_m); free(m->row_w); free(m->mrw_kp); free(m->mrw_chir);
+    m->mrw_kp = m->mrw_chir = NULL;
     m->T = m->T_prev = m->sig_rel = m->sig_rel_prev = NULL;
     m->T_valid = NULL;
     m->adot = m->adot_prev = m->adot_sig = m->acc = m->acc2 = m->row_w = NULL;
@@ -564,6 +569,7 @@ int orc_set_run(orc_model* m, const orc_run_cfg* cfg)
     if (cfg->n_iter < 0) return fail(m, "n_iter must be >= 0");
     if (!(cfg->t_init > 0.0)) return fail(m, "t_init must be > 0");
     if (cfg->max_events < 0) return fail(m, "max_events must be >= 0");
+    if (!(cfg->mrw_gamma >= 0.0)) return fail(m, "mrw_gamma must be >= 0");
     if (!(cfg->conv_p > 0.0 && cfg->conv_p <= 1.0)) return fail(m, "conv_p must be in (0,1]");
     if (cfg->event_log_packets < 0 || cfg->event_log_cap < 0) return fail(m, "bad event log size");
     m->cfg = *cfg;
@@ -730,7 +736,7 @@ typedef struct {
     double* psed_sum2;
     double* pimg_sum;
     double* pimg_sum2;
-    int64_t n_cross_dust, n_cross_empty, n_scatter, n_absorb, n_escape, n_killed;
+    int64_t n_cross_dust, n_cross_empty, n_scatter, n_absorb, n_escape, n_killed, n_mrw;
     double e_escaped, e_killed;
 } tally;
 
@@ -911,6 +917,145 @@ static void peel(const orc_model* m, const double x[3], const double* d_in, int 
     }
 }
 
+/* ======================================================================= */
+/* Modified random walk (Sec. 2.2).                                         */
+/* ======================================================================= */
+/* The paper names the method (Min et al. 2009, in the form of Robitaille 2010)
+ * without its steps; they are taken here from diffusion in a sphere.  A
+ * packet at x in a cell of density rho whose nearest wall is R0 away, with
+ * rho chi_R R0 >= gamma (chi_R the Rosseland mean at the cell's T), diffuses
+ * with coefficient D = 1/(3 rho chi_R) (per unit path length) from the centre
+ * of the sphere of radius R0; the path length s until it first reaches the
+ * sphere has the distribution of first-passage times of diffusion from the
+ * centre, F(y) = 1 + 2 sum_{n>=1} (-1)^n exp(-n^2 y), y = pi^2 D s / R0^2.
+ * The step moves x to a uniformly random point of the sphere, adds
+ * eps kappa_P s to the cell's path-length tally (the estimator of Eq. 2 with
+ * the Planck-mean absorption of the cell's T: the radiation inside an
+ * optically thick cell is thermal), and re-emits the packet in a bin drawn
+ * from the cell's emissivity, in an isotropic direction.  Steps repeat while
+ * the condition holds; each counts as an interaction. */
+double orc_mrw_escape_cdf(double y)
+{
+    if (!(y > 0.0)) return 0.0;
+    double f = 0.0;
+    if (y < 2.0) {
+        /* the same function after Jacobi's transformation (fast for small y) */
+        for (int m = 0; m < 50; ++m) {
+            double a = (2.0 * m + 1.0) * ORC_PI;
+            double term = exp(-a * a / (4.0 * y));
+            f += term;
+            if (term < 1e-300) break;
+        }
+        return 2.0 * sqrt(ORC_PI / y) * f;
+    }
+    double sgn = -1.0;
+    for (int n = 1; n < 50; ++n) {
+        double term = exp(-(double)n * n * y);
+        f += sgn * term;
+        sgn = -sgn;
+        if (term < 1e-300) break;
+    }
+    return 1.0 + 2.0 * f;
+}
+
+double orc_mrw_escape_y(double u)
+{
+    double lo = 1e-3, hi = 80.0; /* F(1e-3) ~ 1e-1070, 1 - F(80) ~ 1e-34 */
+    for (int i = 0; i < 200; ++i) {
+        double mid = 0.5 * (lo + hi);
+        if (mid <= lo || mid >= hi) break;
+        if (orc_mrw_escape_cdf(mid) < u) lo = mid;
+        else hi = mid;
+    }
+    return 0.5 * (lo + hi);
+}
+
+double orc_planck_mean_kappa(const orc_model* m, double T)
+{
+    double num = 0.0, den = 0.0;
+    for (int k = 0; k < m->nnu; ++k) {
+        double b = orc_planck_bin(m->nu[k], m->nu[k + 1], T);
+        num += m->kap[k] * b;
+        den += b;
+    }
+    return den > 0.0 ? num / den : 0.0;
+}
+
+/* int_a^b x^4 e^x / (e^x - 1)^2 dx by composite Simpson (step <= 0.01); the
+ * integrand beyond x = 60 holds less than 1e-20 of the total and is left out */
+static double dplanck_x_integral(double a, double b)
+{
+    if (a > 60.0) return 0.0;
+    if (b > 60.0) b = 60.0;
+    int n = (int)ceil((b - a) / 0.01);
+    if (n < 8) n = 8;
+    if (n % 2) n += 1;
+    double h = (b - a) / n, s = 0.0;
+    for (int i = 0; i <= n; ++i) {
+        double x = a + i * h;
+        double sh = sinh(0.5 * x);
+        double f = x > 0.0 ? x * x * x * x / (4.0 * sh * sh) : 0.0;
+        s += f * (i == 0 || i == n ? 1.0 : (i % 2 ? 4.0 : 2.0));
+    }
+    return s * h / 3.0;
+}
+
+double orc_rosseland_chi(const orc_model* m, double T)
+{
+    /* 1/chi_R = sum_k (1/chi_k) dB_k/dT / sum_k dB_k/dT; the common factor
+     * 2 k^4 T^3 / (h^3 c^2) of dB_k/dT cancels */
+    double kT = ORC_K_BOLTZ * T, num = 0.0, den = 0.0;
+    for (int k = 0; k < m->nnu; ++k) {
+        double w = dplanck_x_integral(ORC_H_PLANCK * m->nu[k] / kT, ORC_H_PLANCK * m->nu[k + 1] / kT);
+        num += w / m->chi[k];
+        den += w;
+    }
+    return num > 0.0 ? den / num : INFINITY;
+}
+
+/* Modified-random-walk steps from x in cell c (see above); returns 1 when
+ * the packet was killed at the event limit. */
+static int mrw(const orc_model* m, orc_stream* rs, int64_t p, double x[3], double d[3], const int c[3],
+               int* k, double eps, int peeling, int64_t* nev, tally* t)
+{
+    const int64_t j = c[0] + (int64_t)m->n[0] * (c[1] + (int64_t)m->n[1] * c[2]);
+    const double r = m->rho[j];
+    if (!(r > 0.0)) return 0;
+    const double chir = m->mrw_chir[j], kp = m->mrw_kp[j];
+    for (;;) {
+        double R0 = INFINITY;
+        for (int a = 0; a < 3; ++a) {
+            double dl = x[a] - wall(m, a, c[a]), dh = wall(m, a, c[a] + 1) - x[a];
+            if (dl < R0) R0 = dl;
+            if (dh < R0) R0 = dh;
+        }
+        if (!(r * chir * R0 >= m->cfg.mrw_gamma)) return 0;
+        (*nev)++;
+        if (*nev > m->cfg.max_events) {
+            t->n_killed++;
+            t->e_killed += eps;
+            log_event(m, p, EV_KILLED, c, *k, -1);
+            return 1;
+        }
+        double u_y = draw(rs), u_mu = draw(rs), u_phi = draw(rs), u_mix = draw(rs), u_nu = draw(rs);
+        double u_mu2 = draw(rs), u_phi2 = draw(rs);
+        double y = orc_mrw_escape_y(u_y);
+        double s = 3.0 * r * chir * R0 * R0 * y / (ORC_PI * ORC_PI);
+        double w = eps * kp * s;
+        t->acc[j] += w;
+        if (t->acc2) t->acc2[j] += w * w;
+        double u[3];
+        isotropic(u_mu, u_phi, u);
+        for (int a = 0; a < 3; ++a) x[a] += R0 * u[a];
+        int row = m->row_m[j] + (u_mix < m->row_w[j] ? 1 : 0);
+        *k = cdf_search(m->ecdf + (size_t)row * m->nnu, m->nnu, u_nu);
+        isotropic(u_mu2, u_phi2, d);
+        t->n_mrw++;
+        log_event(m, p, EV_MRW, c, *k, -1);
+        if (peeling) peel(m, x, NULL, *k, eps, 1, t);
+    }
+}
+
 /* Follow one source packet from emission to escape or kill (Sec. 2.2). */
 static void run_packet(const orc_model* m, uint32_t key1, int64_t p, int64_t np, int binning, tally* t)
 {
@@ -938,6 +1083,7 @@ static void run_packet(const orc_model* m, uint32_t key1, int64_t p, int64_t np,
     int64_t nev = 0;
     int in = inside(m, c);
     for (;;) {
+        if (in && m->cfg.mrw_gamma > 0.0 && mrw(m, &rs, p, x, d, c, &k, eps, peeling, &nev, t)) return;
         double tau = -log(draw(&rs));
         int hit = in ? walk(m, x, d, c, k, tau, eps, t) : 0;
         if (!hit) {
@@ -1014,6 +1160,17 @@ static int64_t rows_from_T(orc_model* m)
         double w = p - (double)r;
         m->row_m[j] = r;
         m->row_w[j] = w;
+    }
+    if (m->cfg.mrw_gamma > 0.0) {
+        if (!m->mrw_kp) {
+            m->mrw_kp = (double*)calloc((size_t)m->ncell, sizeof(double));
+            m->mrw_chir = (double*)calloc((size_t)m->ncell, sizeof(double));
+        }
+        for (int64_t j = 0; j < m->ncell; ++j) {
+            if (!(m->rho[j] > 0.0)) continue;
+            m->mrw_kp[j] = orc_planck_mean_kappa(m, m->T[j]);
+            m->mrw_chir[j] = orc_rosseland_chi(m, m->T[j]);
+        }
     }
     return clamped;
 }
@@ -1110,6 +1267,7 @@ static int transport(orc_model* m, int64_t np, int64_t p_first, int64_t p_count,
         st->n_absorb += T[i].n_absorb;
         st->n_escape += T[i].n_escape;
         st->n_killed += T[i].n_killed;
+        st->n_mrw += T[i].n_mrw;
         st->e_escaped += T[i].e_escaped;
         st->e_killed += T[i].e_killed;
         free(T[i].acc); free(T[i].acc2); free(T[i].sed_sum); free(T[i].sed_sum2); free(T[i].sed_n);

@@ -58,6 +58,9 @@ typedef struct {
     int32_t bin_every_iteration;/* bin escapes in the Lucy iterations too   */
     int32_t n_threads;          /* OpenMP threads (0 = default)             */
     int32_t chunk;              /* packets per work chunk (0 = 1024)        */
+    double mrw_gamma;           /* modified random walk: step when the sphere
+                                   to the nearest cell wall holds at least this
+                                   many Rosseland mean free paths (0 = off)  */
 } orc_run_cfg;
 
 typedef struct {
@@ -83,6 +86,7 @@ typedef struct {
     double e_escaped;           /* energy of escaped packets [erg]          */
     double e_killed;            /* energy of killed packets [erg]           */
     double seconds;             /* wall time of the transport               */
+    int64_t n_mrw;              /* modified-random-walk steps               */
 } orc_iter_stats;
 
 /* --- model setup (host arrays are copied) ------------------------------ */
@@ -137,6 +141,15 @@ int orc_get_event_log(const orc_model* m, orc_event* ev, size_t cap, int32_t* co
 int orc_get_emission_rows(const orc_model* m, int32_t* row, double* w, size_t n);
 
 /* --- building blocks exposed for closed-form pins ----------------------- */
+/* Modified random walk: y with F(y) = u for the escape-time distribution of
+ * diffusion from the centre of a sphere, F(y) = 1 + 2 sum_n (-1)^n exp(-n^2 y)
+ * (y = pi^2 D t / R^2), and F itself. */
+double orc_mrw_escape_y(double u);
+double orc_mrw_escape_cdf(double y);
+/* Planck-mean absorption and Rosseland-mean extinction opacities of the
+ * model's dust at temperature T over its bins (cm^2/g). */
+double orc_planck_mean_kappa(const orc_model* m, double T);
+double orc_rosseland_chi(const orc_model* m, double T);
 void orc_philox4x32_10(const uint32_t ctr[4], const uint32_t key[2], uint32_t out[4]);
 /* n-th FP64 uniform of the stream (key, packet). */
 double orc_uniform(uint32_t key0, uint32_t key1, uint64_t packet, uint64_t n);
