@@ -54,7 +54,7 @@ typedef enum {
 
 /* Event types of the per-packet log. */
 enum { MCRT_EV_EMIT = 0, MCRT_EV_SCATTER = 1, MCRT_EV_ABSORB = 2, MCRT_EV_ESCAPE = 3,
-       MCRT_EV_KILLED = 4 };
+       MCRT_EV_KILLED = 4, MCRT_EV_MRW = 5 };
 
 /* One event.  cell: the cell of the event (for ESCAPE the last cell inside the
  * grid); nu: frequency bin after the event; incl: SED inclination bin of an
@@ -108,6 +108,12 @@ typedef struct {
     int32_t visit_events;      /* tiled sweeps: interactions per tile visit before a
                                   packet waits for the next sweep [256]                   */
     int32_t tile_xy;           /* tiled sweeps: tile extent in x and y, 16 or 32 [16]     */
+    double mrw_gamma;          /* modified random walk (Sec. 2.2): at the start of a flight,
+                                  while the sphere to the nearest wall of the cell holds at
+                                  least mrw_gamma Rosseland mean free paths, one diffusion
+                                  step to its surface (path length from the first-passage
+                                  distribution, tally with the Planck-mean absorption,
+                                  re-emission from the cell); 0 = off [0]                 */
 } mcrt_run_cfg;
 
 /* Statistics of one pass (a Lucy iteration or the final pass). */
@@ -138,6 +144,7 @@ typedef struct {
     double ms_total;           /* host wall time of the call                              */
     int64_t n_sweeps;          /* tiled sweeps run by the pass (transport_mode 1)         */
     int64_t n_visits;          /* tile visits (packet records walked) over those sweeps   */
+    int64_t n_mrw;             /* modified-random-walk steps                              */
 } mcrt_iter_stats;
 
 typedef struct {

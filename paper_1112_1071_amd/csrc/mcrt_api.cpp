@@ -146,6 +146,9 @@ struct mcrt_model {
     DBuf<double> peel_dir, psed_sum, psed_sum2, pimg_sum, pimg_sum2;
     // raytracing: spectral cube and SED of the last mcrt_raytrace, its image
     DBuf<double> ray_cube, ray_sed, ray_nu, ray_lsrc;
+    // modified random walk: Planck/Rosseland mean table (built when mrw_gamma > 0)
+    DBuf<double> mrw_tab;
+    bool mrw_tab_built = false;
     int ray_npix = 0;
     DBuf<unsigned long long> sed_n;
     DBuf<mcrt_event> evlog;
@@ -286,6 +289,12 @@ mcrt_status build_tables(mcrt_model* m) {
     HIPCHK(upload(m->lnA, lnA, st));
     HIPCHK(upload(m->slope, slope, st));
     HIPCHK(upload(m->img_of_bin, iob, st));
+    std::vector<double> mrw;
+    if (m->cfg.mrw_gamma > 0.0) {
+        mrw_table(m->nu, m->kap, m->chi, mrw);
+        HIPCHK(upload(m->mrw_tab, mrw, st));
+    }
+    m->mrw_tab_built = m->cfg.mrw_gamma > 0.0;
     HIPCHK(hipStreamSynchronize(st));
     m->tables_dirty = false;
     return MCRT_OK;
@@ -566,6 +575,9 @@ void make_params(mcrt_model* m, int64_t np, uint32_t key1, int binning, Transpor
         P.n_peel = m->n_peel;
         P.peel_dir = m->peel_dir.p;
         P.rho_lin = f32 ? (const R*)(const void*)m->rho32.p : (const R*)(const void*)m->rho64.p;
+        P.mrw_gamma = m->cfg.mrw_gamma;
+        P.Tcell = m->T.p;
+        P.mrw_tab = m->mrw_tab.p;
         P.psed_sum = m->psed_sum.p;
         P.psed_sum2 = m->psed_sum2.p;
         P.pimg_sum = m->pimg_sum.p;
@@ -748,6 +760,7 @@ mcrt_status run_transport(mcrt_model* m, int64_t np, uint32_t key1, int binning,
     st->n_absorb = (int64_t)h[MISC_CNT + C_ABSORB];
     st->n_escape = (int64_t)h[MISC_CNT + C_ESCAPE];
     st->n_killed = (int64_t)h[MISC_CNT + C_KILLED];
+    st->n_mrw = (int64_t)h[MISC_CNT + C_MRW];
     st->e_escaped = e[0];
     st->e_killed = e[1];
     st->precision = m->cfg.precision;
@@ -945,6 +958,7 @@ void mcrt_destroy(mcrt_model* m) {
     m->peel_dir.release(); m->psed_sum.release(); m->psed_sum2.release();
     m->pimg_sum.release(); m->pimg_sum2.release();
     m->ray_cube.release(); m->ray_sed.release(); m->ray_nu.release(); m->ray_lsrc.release();
+    m->mrw_tab.release();
     m->misc.release(); m->energies.release(); m->hist.release();
     m->sw_a.release(); m->sw_b.release(); m->sw_tile.release(); m->sw_counts.release();
     m->sw_tile_off.release(); m->sw_item_off.release(); m->sw_cursor.release(); m->sw_ctr.release();
@@ -1311,8 +1325,10 @@ mcrt_status mcrt_set_run(mcrt_model* m, const mcrt_run_cfg* c) {
     if (c->visit_events < 0) return fail(m, MCRT_E_ARG, "visit_events must be >= 0");
     if (c->tile_xy != 0 && c->tile_xy != 16 && c->tile_xy != 32)
         return fail(m, MCRT_E_ARG, "tile_xy must be 16 or 32");
+    if (!(c->mrw_gamma >= 0.0) || !isfinite(c->mrw_gamma)) return fail(m, MCRT_E_ARG, "mrw_gamma must be >= 0");
     const bool reset = !m->have_run || c->t_init != m->cfg.t_init;
     m->cfg = *c;
+    if (m->cfg.mrw_gamma > 0.0 && !m->mrw_tab_built) m->tables_dirty = true;
     if (m->cfg.event_log_cap == 0) m->cfg.event_log_cap = 256;
     if (m->cfg.conv_noise_thres <= 0.0) m->cfg.conv_noise_thres = 0.002;
     if (m->cfg.tile_z == 0) m->cfg.tile_z = 32;

@@ -14,11 +14,12 @@ constexpr double kTLo = 1.0;        // K
 constexpr double kTHi = 1.0e4;      // K
 constexpr double kTFloor = 1.0;     // K, temperature of cells that absorbed nothing
 constexpr int kTSolveRows = 2048;   // rows of the ln Adot(ln T) table of the T solve
+constexpr int kMrwRows = 2048;      // rows of the Planck/Rosseland mean table, log-spaced in T
 constexpr int kWave = 64;
 
 // Per-lane counters flushed once per wave at the end of a transport launch.
 enum CounterIdx { C_CROSS_DUST = 0, C_CROSS_EMPTY, C_SCATTER, C_ABSORB, C_ESCAPE, C_KILLED,
-                  C_COUNT };
+                  C_MRW, C_COUNT };
 
 constexpr int kGroup = 16;          // CDF entries per group of the two-level search
 constexpr int kPoolChunk = 64;      // packet ids a wave takes from the pool at a time
@@ -85,6 +86,12 @@ struct TransportParams {
     int n_peel;
     const double* peel_dir;  // [3*n_peel]
     const R* rho_lin;        // density x-fastest (the ray march to the boundary)
+    // modified random walk (mrw_gamma 0 = off): cell temperatures (x-fastest)
+    // and the table of kappa_P, d kappa_P / d ln T, chi_R, d chi_R / d ln T
+    // per row of ln T over [kTLo, kTHi]
+    double mrw_gamma;
+    const double* Tcell;
+    const double* mrw_tab;   // [kMrwRows * 4]
     double* psed_sum;
     double* psed_sum2;
     double* pimg_sum;

@@ -361,9 +361,160 @@ __device__ void peel(const Packet<R>& s, const TransportParams<R>& P, R f0, R f1
     }
 }
 
+// Where a modified-random-walk step adds to the absorption tally: the global
+// FP64 tally in the per-lane walk's layout, or the tile's LDS tally.
+template <int BRICK> struct GlobalDeposit {
+    double* acc;
+    double* acc2;
+    int n[3];
+    int bx, bxy;
+    template <typename R> __device__ void operator()(int c0, int c1, int c2, R w) const {
+        const int j = cell_index<BRICK>(*this, c0, c1, c2);
+        unsafeAtomicAdd(acc + j, (double)w);
+        if (acc2) unsafeAtomicAdd(acc2 + j, (double)w * (double)w);
+    }
+};
+
+template <int BRICK, typename R>
+__device__ __forceinline__ GlobalDeposit<BRICK> global_deposit(const TransportParams<R>& P, double* acc) {
+    return GlobalDeposit<BRICK>{acc, P.acc2, {P.n[0], P.n[1], P.n[2]}, P.bx, P.bxy};
+}
+
+template <typename R> struct TileDeposit {
+    R* acc;
+    double* acc2;
+    int o0, o1, o2, txy;
+    __device__ void operator()(int c0, int c1, int c2, R w) const {
+        const int jl = (c0 - o0) + txy * ((c1 - o1) + txy * (c2 - o2));
+        atomicAdd(acc + jl, w);
+        if (acc2) atomicAdd(acc2 + jl, (double)w * (double)w);
+    }
+};
+
+// Re-emission bin from the emissivity of cell j: row m or m+1 of the cell's
+// row position (u_mix), then the row's CDF (u_nu).
 template <typename R>
+__device__ __forceinline__ int reemission_bin(const TransportParams<R>& P, const Tables<R>& tb, int64_t j,
+                                              R u_mix, R u_nu) {
+    const R p = P.rowpos[j];
+    int m = (int)p;
+    m = m > kRows - 2 ? kRows - 2 : m;
+    const R w = p - (R)m;
+    const int row = m + (u_mix < w ? 1 : 0);
+    return cdf_search2(P.ecdf + (size_t)row * P.npad, tb.ecoarse + row * P.ngroup, P.ngroup, u_nu);
+}
+
+// ---- modified random walk (Sec. 2.2) ---------------------------------------
+// The paper names the method (with its gamma) without its steps; they follow
+// from diffusion in a sphere.  First-passage distribution of diffusion from
+// the centre of a sphere, y = pi^2 D t / R^2:
+//   F(y) = 1 + 2 sum_{n>=1} (-1)^n exp(-n^2 y)
+//        = 2 sqrt(pi/y) sum_{m>=0} exp(-pi^2 (2m+1)^2 / (4y))   (Jacobi),
+// the second form for y < 2.
+__device__ inline double mrw_cdf(double y) {
+    const double pi = 3.14159265358979323846;
+    if (!(y > 0.0)) return 0.0;
+    double f = 0.0;
+    if (y < 2.0) {
+        for (int m = 0; m < 40; ++m) {
+            const double a = (2 * m + 1) * pi;
+            const double t = exp(-a * a / (4.0 * y));
+            f += t;
+            if (t < 1e-20 * f) break;
+        }
+        return 2.0 * sqrt(pi / y) * f;
+    }
+    double sg = -1.0;
+    for (int n = 1; n < 40; ++n) {
+        const double t = exp(-(double)(n * n) * y);
+        f += sg * t;
+        sg = -sg;
+        if (t < 1e-20) break;
+    }
+    return 1.0 + 2.0 * f;
+}
+
+// y with F(y) = u, by bisection on [1e-3, 80] to the last bit
+__device__ inline double mrw_escape_y(double u) {
+    double lo = 1e-3, hi = 80.0;
+    for (int i = 0; i < 200; ++i) {
+        const double mid = 0.5 * (lo + hi);
+        if (mid <= lo || mid >= hi) break;
+        if (mrw_cdf(mid) < u) lo = mid;
+        else hi = mid;
+    }
+    return 0.5 * (lo + hi);
+}
+
+// Planck-mean kappa and Rosseland-mean chi of cell j at its temperature:
+// cubic Hermite interpolation in ln T of the table
+template <typename R>
+__device__ inline void mrw_opacities(const TransportParams<R>& P, int64_t j, double& kp, double& chir) {
+    const double lo = log(kTLo), h = (log(kTHi) - lo) / (kMrwRows - 1);
+    double p = (log(P.Tcell[j]) - lo) / h;
+    p = fmin(fmax(p, 0.0), (double)(kMrwRows - 1));
+    int i = (int)p;
+    i = i > kMrwRows - 2 ? kMrwRows - 2 : i;
+    const double t = p - i, t2 = t * t, t3 = t2 * t;
+    const double h00 = 2 * t3 - 3 * t2 + 1, h10 = t3 - 2 * t2 + t, h01 = -2 * t3 + 3 * t2, h11 = t3 - t2;
+    const double* a = P.mrw_tab + 4 * (size_t)i;
+    const double* b = a + 4;
+    kp = h00 * a[0] + h10 * h * a[1] + h01 * b[0] + h11 * h * b[1];
+    chir = h00 * a[2] + h10 * h * a[3] + h01 * b[2] + h11 * h * b[3];
+}
+
+// Modified-random-walk steps from the in-cell offsets f: while the sphere to
+// the nearest cell wall (radius R0) holds at least mrw_gamma Rosseland mean
+// free paths, the packet diffuses to a uniformly random point of it over the
+// path length s = 3 rho chi_R R0^2 y / pi^2 (y from F), adds w kappa_P s to
+// the cell's tally (dep), and is re-emitted from the cell's emissivity in an
+// isotropic direction.  Draws u_y u_mu u_phi u_mix u_nu u_mu u_phi per step.
+// Returns false when the packet was killed at the event limit.
+template <typename R, typename Dep>
+__device__ bool mrw_steps(Packet<R>& s, Stream<R>& rs, const TransportParams<R>& P, const Tables<R>& tb,
+                          R& f0, R& f1, R& f2, uint32_t* cnt, double& e_killed, const Dep& dep) {
+    const double pi = 3.14159265358979323846;
+    const int64_t j = s.c0 + (int64_t)P.n[0] * (s.c1 + (int64_t)P.n[1] * s.c2);
+    const double r = (double)P.rho_lin[j];
+    if (!(r > 0.0)) return true;
+    double kp, chir;
+    mrw_opacities(P, j, kp, chir);
+    for (;;) {
+        const double g0 = (double)f0 * P.dx[0], g1 = (double)f1 * P.dx[1], g2 = (double)f2 * P.dx[2];
+        const double R0 = fmin(fmin(fmin(g0, P.dx[0] - g0), fmin(g1, P.dx[1] - g1)), fmin(g2, P.dx[2] - g2));
+        if (!(r * chir * R0 >= P.mrw_gamma)) return true;
+        s.nev += 1;
+        if ((int64_t)s.nev > P.max_events) {
+            ++cnt[C_KILLED];
+            e_killed += P.eps0 * (double)s.wgt;
+            log_event(s, P, MCRT_EV_KILLED, -1);
+            s.st = ST_EMPTY;
+            return false;
+        }
+        const R u_y = rs.next(), u_mu = rs.next(), u_phi = rs.next(), u_mix = rs.next(), u_nu = rs.next();
+        const R u_mu2 = rs.next(), u_phi2 = rs.next();
+        const double y = mrw_escape_y((double)u_y);
+        const double sp = 3.0 * r * chir * R0 * R0 * y / (pi * pi);
+        dep(s.c0, s.c1, s.c2, (R)((double)s.wgt * kp * sp));
+        const double mu = 2.0 * (double)u_mu - 1.0, phi = 2.0 * pi * (double)u_phi;
+        const double st = sqrt(fmax(0.0, 1.0 - mu * mu));
+        f0 = (R)fmin(1.0, fmax(0.0, (g0 + R0 * st * cos(phi)) / P.dx[0]));
+        f1 = (R)fmin(1.0, fmax(0.0, (g1 + R0 * st * sin(phi)) / P.dx[1]));
+        f2 = (R)fmin(1.0, fmax(0.0, (g2 + R0 * mu) / P.dx[2]));
+        s.k = reemission_bin(P, tb, j, u_mix, u_nu);
+        isotropic(s, u_mu2, u_phi2);
+        s.chi = P.chi[s.k];
+        s.kap = P.kap[s.k];
+        ++cnt[C_MRW];
+        log_event(s, P, MCRT_EV_MRW, -1);
+        if (P.binning && P.n_peel > 0) peel(s, P, f0, f1, f2, 1, false, 0.0, 0.0, 0.0);
+    }
+}
+
+template <typename R, typename Dep>
 __device__ __forceinline__ void emit(Packet<R>& s, Stream<R>& rs, const TransportParams<R>& P,
-                                     const Tables<R>& tb, uint64_t id) {
+                                     const Tables<R>& tb, uint64_t id, uint32_t* cnt, double& e_killed,
+                                     const Dep& dep) {
     s.id = id;
     const uint64_t gid = P.packet_base + id;
     rs.p0 = (uint32_t)gid;
@@ -407,9 +558,11 @@ __device__ __forceinline__ void emit(Packet<R>& s, Stream<R>& rs, const Transpor
     s.nlog = 0;
     log_event(s, P, MCRT_EV_EMIT, -1);
     if (P.binning && P.n_peel > 0) peel(s, P, f[0], f[1], f[2], 0, false, 0.0, 0.0, 0.0);
-    begin_flight(s, P, rs, f[0], f[1], f[2]);
     const bool inside = (unsigned)s.c0 < (unsigned)P.n[0] && (unsigned)s.c1 < (unsigned)P.n[1] &&
                         (unsigned)s.c2 < (unsigned)P.n[2];
+    if (inside && P.mrw_gamma > 0.0 && !mrw_steps(s, rs, P, tb, f[0], f[1], f[2], cnt, e_killed, dep))
+        return;  // killed (s.st = ST_EMPTY)
+    begin_flight(s, P, rs, f[0], f[1], f[2]);
     s.st = inside ? ST_WALK : ST_ESC;
 }
 
@@ -512,9 +665,10 @@ __device__ __forceinline__ void walk(Packet<R>& s, const G& P, double* acc, uint
 }
 
 // Scatter (u <= albedo) or absorb and re-emit (Sec. 2.2), then a new flight.
-template <typename R>
+template <typename R, typename Dep>
 __device__ __forceinline__ void interact(Packet<R>& s, Stream<R>& rs, const TransportParams<R>& P,
-                                         const Tables<R>& tb, uint32_t* cnt, double& e_killed) {
+                                         const Tables<R>& tb, uint32_t* cnt, double& e_killed,
+                                         const Dep& dep) {
     s.nev += 1;
     if ((int64_t)s.nev > P.max_events) {
         ++cnt[C_KILLED];
@@ -528,14 +682,8 @@ __device__ __forceinline__ void interact(Packet<R>& s, Stream<R>& rs, const Tran
     const R u_int = rs.next();
     if (u_int > P.alb[s.k]) {
         const R u_mix = rs.next(), u_nu = rs.next(), u_mu = rs.next(), u_phi = rs.next();
-        const int j = s.c0 + P.n[0] * (s.c1 + P.n[1] * s.c2);
-        const R p = P.rowpos[j];
-        int m = (int)p;
-        m = m > kRows - 2 ? kRows - 2 : m;
-        const R w = p - (R)m;
-        const int row = m + (u_mix < w ? 1 : 0);
-        s.k = cdf_search2(P.ecdf + (size_t)row * P.npad, tb.ecoarse + row * P.ngroup, P.ngroup,
-                          u_nu);
+        const int64_t j = s.c0 + (int64_t)P.n[0] * (s.c1 + (int64_t)P.n[1] * s.c2);
+        s.k = reemission_bin(P, tb, j, u_mix, u_nu);
         isotropic(s, u_mu, u_phi);
         ++cnt[C_ABSORB];
         log_event(s, P, MCRT_EV_ABSORB, -1);
@@ -550,6 +698,7 @@ __device__ __forceinline__ void interact(Packet<R>& s, Stream<R>& rs, const Tran
         ++cnt[C_SCATTER];
         log_event(s, P, MCRT_EV_SCATTER, -1);
     }
+    if (P.mrw_gamma > 0.0 && !mrw_steps(s, rs, P, tb, f0, f1, f2, cnt, e_killed, dep)) return;
     begin_flight(s, P, rs, f0, f1, f2);
     s.st = ST_WALK;
 }

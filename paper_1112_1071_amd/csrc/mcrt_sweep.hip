@@ -8,8 +8,9 @@
 // in its random stream), and the records are grouped by the tile the packet
 // is in.  In a sweep, a workgroup takes work items (each up to S.item
 // records of one tile); for each new tile it loads the tile's density into
-// LDS and clears an LDS tally, and its lanes walk the item's packets (Sec. 2.2; Lucy's path-length estimator, Sec. 2.3 Eq. 2,
-// added into the LDS tally) until each leaves the tile, escapes the grid, is
+// LDS and clears an LDS tally, and its lanes walk the item's packets
+// (Sec. 2.2; Lucy's path-length estimator, Sec. 2.3 Eq. 2, added into the
+// LDS tally) until each leaves the tile, escapes the grid, is
 // killed, or has had visit_events interactions in this visit; a packet that
 // leaves (or yields) is written out with the tile it is now in.  When the
 // workgroup moves on to another tile (or ends), it adds the LDS tally into
@@ -265,7 +266,8 @@ __device__ __forceinline__ void flush_block_counters(const TransportParams<R>& P
 
 // Emission of packets [first, first+count): each starts its first flight
 // (exactly as in the per-lane kernel) and is written as record base+i with its
-// tile; a packet that starts outside the grid escapes at once and leaves a hole
+// tile; a packet that starts outside the grid escapes at once (or is killed by
+// the modified random walk at the event limit) and leaves a hole
 // (tile kNoTile, skipped by the ordering).  Positions need no atomics; the
 // per-tile counts are gathered in an LDS histogram per block when the tiles
 // fit (hist), else per wave.
@@ -296,10 +298,10 @@ __global__ void __launch_bounds__(256) k_sweep_emit(TransportParams<R> P, SweepP
         int dest = -1;
         if (i < count) {
             Packet<R> s;
-            emit(s, rs, P, tb, first + i);
+            emit(s, rs, P, tb, first + i, cnt, e_killed, global_deposit<0>(P, P.acc));
             const unsigned idx = base + (unsigned)i;
-            if (s.st == ST_ESC) {
-                escape(s, P, cnt, e_escaped);
+            if (s.st == ST_ESC || s.st == ST_EMPTY) {  // escaped at once, or killed by the walk
+                if (s.st == ST_ESC) escape(s, P, cnt, e_escaped);
                 S.out_tile[idx] = kNoTile;
             } else {
                 store_rec(out + idx, s, rs, ST_WALK);
@@ -481,7 +483,7 @@ __global__ void __launch_bounds__(256) k_sweep(TransportParams<R> P, SweepParams
                     s.st = ST_YIELD;
                 } else {
                     ++visit;
-                    interact(s, rs, P, tb, cnt, e_killed);
+                    interact(s, rs, P, tb, cnt, e_killed, TileDeposit<R>{acc_t, acc2_t, o0, o1, o2, txy});
                 }
             }
             if (s.st == ST_ESC) escape(s, P, cnt, e_escaped);

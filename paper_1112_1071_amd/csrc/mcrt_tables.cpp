@@ -165,3 +165,73 @@ void tsolve_table(const std::vector<double>& nu, const std::vector<double>& kapp
 }
 
 }  // namespace mcrt
+
+namespace mcrt {
+namespace {
+
+// x^4 e^x / (e^x - 1)^2, the integrand of dB_nu/dT in x = h nu / kT
+inline double dplanck_integrand(double x) {
+    if (x <= 0.0 || x > 745.0) return 0.0;
+    if (x < 1e-8) return x * x;
+    const double e = exp(-x), d = -expm1(-x);
+    return x * x * x * x * e / (d * d);
+}
+
+double dplanck_x_integral(double a, double b) {
+    if (!(b > a)) return 0.0;
+    if (a < 0.0) a = 0.0;
+    if (a >= 745.0) return 0.0;
+    if (b > 745.0) b = 745.0;
+    const GaussLegendre16& g = gl16();
+    const int panels = (int)ceil((b - a) / 1.0);
+    const double h = (b - a) / panels;
+    double sum = 0.0;
+    for (int p = 0; p < panels; ++p) {
+        const double c = a + (p + 0.5) * h;
+        double s = 0.0;
+        for (int i = 0; i < 16; ++i) s += g.w[i] * dplanck_integrand(c + 0.5 * h * g.x[i]);
+        sum += 0.5 * h * s;
+    }
+    return sum;
+}
+
+// Planck-mean absorption and Rosseland-mean extinction at T over the bins
+void mean_opacities(const std::vector<double>& nu, const std::vector<double>& kappa,
+                    const std::vector<double>& chi, double T, double* kp, double* chir) {
+    const double kT = kK * T;
+    double nb = 0.0, db = 0.0, nr = 0.0, dr = 0.0;
+    for (size_t k = 0; k < kappa.size(); ++k) {
+        const double a = kH * nu[k] / kT, b = kH * nu[k + 1] / kT;
+        const double B = planck_x_integral(a, b), dB = dplanck_x_integral(a, b);
+        nb += kappa[k] * B;
+        db += B;
+        nr += dB;
+        dr += dB / chi[k];
+    }
+    *kp = db > 0.0 ? nb / db : 0.0;
+    *chir = dr > 0.0 ? nr / dr : INFINITY;
+}
+
+}  // namespace
+
+// kMrwRows rows, log-spaced in T over [kTLo, kTHi]: kappa_P, d kappa_P / d ln T,
+// chi_R, d chi_R / d ln T (central differences at +-1e-4 in ln T), for cubic
+// Hermite interpolation in ln T
+void mrw_table(const std::vector<double>& nu, const std::vector<double>& kappa,
+               const std::vector<double>& chi, std::vector<double>& tab) {
+    tab.resize((size_t)kMrwRows * 4);
+    const double h = (log(kTHi) - log(kTLo)) / (kMrwRows - 1), e = 1e-4;
+    for (int i = 0; i < kMrwRows; ++i) {
+        const double lt = log(kTLo) + i * h;
+        double kp, cr, kp1, cr1, kp0, cr0;
+        mean_opacities(nu, kappa, chi, exp(lt), &kp, &cr);
+        mean_opacities(nu, kappa, chi, exp(lt + e), &kp1, &cr1);
+        mean_opacities(nu, kappa, chi, exp(lt - e), &kp0, &cr0);
+        tab[4 * (size_t)i + 0] = kp;
+        tab[4 * (size_t)i + 1] = (kp1 - kp0) / (2.0 * e);
+        tab[4 * (size_t)i + 2] = cr;
+        tab[4 * (size_t)i + 3] = (cr1 - cr0) / (2.0 * e);
+    }
+}
+
+}  // namespace mcrt

@@ -18,5 +18,8 @@ void adot_of_T(const std::vector<double>& nu, const std::vector<double>& kappa, 
                double* adot, double* dlnA_dlnT);
 void tsolve_table(const std::vector<double>& nu, const std::vector<double>& kappa,
                   std::vector<double>& lnA, std::vector<double>& slope, double* dy);
+// modified random walk: Planck-mean kappa and Rosseland-mean chi against ln T
+void mrw_table(const std::vector<double>& nu, const std::vector<double>& kappa,
+               const std::vector<double>& chi, std::vector<double>& tab);
 
 }  // namespace mcrt

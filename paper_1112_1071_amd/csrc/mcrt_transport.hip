@@ -100,7 +100,7 @@ __global__ void __launch_bounds__(256) k_transport(TransportParams<R> P) {
                 wend = g + kPoolChunk;
             }
             if (s.st == ST_EMPTY) {
-                if (my < P.n_packets) emit(s, rs, P, tb, my);
+                if (my < P.n_packets) emit(s, rs, P, tb, my, cnt, e_killed, global_deposit<BRICK>(P, acc));
                 else s.st = ST_DONE;
             }
         }
@@ -111,7 +111,7 @@ __global__ void __launch_bounds__(256) k_transport(TransportParams<R> P) {
             if (__ballot(s.st == ST_WALK) == 0ull) break;
             if (__popcll(__ballot(s.st == ST_EVENT || s.st == ST_ESC)) >= defer) break;
         }
-        if (s.st == ST_EVENT) interact(s, rs, P, tb, cnt, e_killed);
+        if (s.st == ST_EVENT) interact(s, rs, P, tb, cnt, e_killed, global_deposit<BRICK>(P, acc));
         if (s.st == ST_ESC) escape(s, P, cnt, e_escaped);
     }
 
@@ -256,7 +256,7 @@ k_transport_batch(const TransportParams<R>* __restrict__ Ps,
                 const Tables<R> tb{P.lcdf, P.ecoarse, P.scoarse};
                 rs.k0 = P.key0;
                 rs.k1 = keys[lm];
-                emit(s, rs, P, tb, wbase + (uint64_t)rank);
+                emit(s, rs, P, tb, wbase + (uint64_t)rank, cnt, e_killed, global_deposit<BRICK>(P, P.acc));
             }
             wbase += (uint64_t)take;
             need = __ballot(s.st == ST_EMPTY);
@@ -281,7 +281,7 @@ k_transport_batch(const TransportParams<R>* __restrict__ Ps,
             if (__popcll(__ballot(s.st == ST_EVENT || s.st == ST_ESC)) >= defer) break;
         }
         const Tables<R> tb{P.lcdf, P.ecoarse, P.scoarse};
-        if (s.st == ST_EVENT) interact(s, rs, P, tb, cnt, e_killed);
+        if (s.st == ST_EVENT) interact(s, rs, P, tb, cnt, e_killed, global_deposit<BRICK>(P, acc));
         if (s.st == ST_ESC) escape(s, P, cnt, e_escaped);
     }
     if (lm >= 0) flush_counters(Ps[lm].counters, Ps[lm].energies, cnt, e_escaped, e_killed);

@@ -40,7 +40,7 @@ class RunCfg(C.Structure):
         ("blocks_per_cu", C.c_int32), ("defer_lanes", C.c_int32), ("walk_batch", C.c_int32),
         ("grid_layout", C.c_int32), ("tally_copies", C.c_int32),
         ("transport_mode", C.c_int32), ("tile_z", C.c_int32), ("visit_events", C.c_int32),
-        ("tile_xy", C.c_int32),
+        ("tile_xy", C.c_int32), ("mrw_gamma", C.c_double),
     ]
 
 
@@ -54,7 +54,7 @@ class IterStats(C.Structure):
         ("n_scatter", C.c_int64), ("n_absorb", C.c_int64), ("n_escape", C.c_int64),
         ("n_killed", C.c_int64), ("e_escaped", C.c_double), ("e_killed", C.c_double),
         ("ms_transport", C.c_double), ("ms_update", C.c_double), ("ms_total", C.c_double),
-        ("n_sweeps", C.c_int64), ("n_visits", C.c_int64),
+        ("n_sweeps", C.c_int64), ("n_visits", C.c_int64), ("n_mrw", C.c_int64),
     ]
 
     def as_dict(self) -> dict:
