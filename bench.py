@@ -79,7 +79,8 @@ def bench_batch(args):
             for m in range(args.models)]
     print(f"# {args.models} models built in {time.time() - t0:.1f} s", file=sys.stderr, flush=True)
     prec = mcrt.MCRT_FP32_TRANSPORT if args.precision == "fp32" else mcrt.MCRT_FP64
-    batch = [mcrt.Model(c, precision=prec) for c in cfgs]
+    extra = {"mrw_gamma": args.mrw} if args.mrw > 0 else {}
+    batch = [mcrt.Model(c, precision=prec, **extra) for c in cfgs]
     n_packets = sum(int(c["run"]["n_packets"]) for c in cfgs)
     cells = sum(int(np.prod(c["grid"]["n"])) for c in cfgs)
     # iteration 0, which also tunes the launch shape (cached per workload class)
@@ -99,7 +100,7 @@ def bench_batch(args):
     nseq = min(args.seq_models, args.models)
     seq_s, seq_packets = 0.0, 0
     for i, c in enumerate(cfgs[:nseq]):
-        m = mcrt.Model(c, precision=prec)
+        m = mcrt.Model(c, precision=prec, **extra)
         m.iterate()
         torch.cuda.synchronize()
         ts = time.perf_counter()
@@ -120,7 +121,8 @@ def bench_batch(args):
         "vs_baseline": None, "dtype": "fp32" if prec == 1 else "fp64", "data": "synthetic",
         "config": {"workload": f"batch{args.models}: {args.models} models, grids 16^3..96^3 "
                                f"({cells} cells), sphere/disk family, {args.ppc} packets per cell "
-                               f"per iteration ({n_packets:.3e} packets), iterations 1..{args.steps}",
+                               f"per iteration ({n_packets:.3e} packets), iterations 1..{args.steps}"
+                               + (f", modified random walk gamma {args.mrw}" if args.mrw > 0 else ""),
                    "models": args.models, "packets_per_step": n_packets},
         "batch": {"graph_used": st["graph_used"], "tuned": st["tuned"],
                   "block_size": st["block_size"], "walk_batch": st["walk_batch"],
@@ -243,6 +245,7 @@ def main():
     ap.add_argument("--tile-xy", type=int, default=0)
     ap.add_argument("--tally-copies", type=int, default=0)
     ap.add_argument("--visit-events", type=int, default=0)
+    ap.add_argument("--mrw", type=float, default=0.0, help="modified random walk gamma (0 = off)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this benchmark runs on one GPU only; --gpus must be 1"}))
@@ -279,6 +282,8 @@ def main():
         run["block_size"] = args.block_size
     if args.sampling:
         run["source_sampling"] = args.sampling
+    if args.mrw > 0:
+        run["mrw_gamma"] = args.mrw
     if args.mode >= 0:
         run["transport_mode"] = args.mode
     if args.tile_z:

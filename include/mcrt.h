@@ -222,6 +222,25 @@ mcrt_status mcrt_get_peeled_images(mcrt_model* m, double* sum, double* sum2, siz
  * the cells' projection.  Needs mcrt_set_peeloff; the model keeps the cube
  * (n_peel*npix^2*n_nu doubles, at most 2^34) until the next call or destroy. */
 mcrt_status mcrt_raytrace(mcrt_model* m, int npix, double half_width);
+/* Partial diffusion approximation (Appendix A) after a Lucy iteration: dust
+ * cells whose absorption estimate is zero, or (with want_noise) whose relative
+ * error exceeds noise, take T from div(D grad T^4) = 0, D = 1/(3 rho chi_R),
+ * with the other dust cells as boundary values.  Cartesian form of the
+ * appendix's discrete equation: a face between cells c and n (axis a) has the
+ * conductance 1/(dx_a^2 (rho_c chi_R,c + rho_n chi_R,n)); empty cells and the
+ * outside carry no flux; chi_R is the Rosseland mean at the current T, the
+ * linear system is solved passes times (Picard) by conjugate gradients to a
+ * relative residual of 1e-12.  Groups of such cells with no other dust cell
+ * next to them keep their T.  Sets T, Adot (Eq. 3) and the emission of the
+ * solved cells for the next iteration. */
+typedef struct {
+    int64_t n_pda;             /* cells selected                                          */
+    int64_t n_solved;          /* of them connected to a sampled cell, given a new T      */
+    int32_t passes;            /* linear solves done                                      */
+    int32_t cg_iterations;     /* conjugate-gradient iterations of the last solve         */
+    double residual;           /* its relative residual |b - A x| / |b|                   */
+} mcrt_pda_stats;
+mcrt_status mcrt_apply_pda(mcrt_model* m, double noise, int passes, mcrt_pda_stats* st);
 /* Raytraced SED [n_peel][2][n_nu] (erg/s/sr): 0 point sources, 1 dust. */
 mcrt_status mcrt_get_raytraced_sed(mcrt_model* m, double* sed, size_t n);
 /* Raytraced spectral cube [n_peel][npix][npix][n_nu] (erg/s/sr per pixel,

@@ -19,6 +19,7 @@ SOURCES = [
     "mcrt_transport.hip",
     "mcrt_sweep.hip",
     "mcrt_raytrace.hip",
+    "mcrt_pda.hip",
     "mcrt_cells.hip",
     "mcrt_tables.cpp",
     "mcrt_api.cpp",

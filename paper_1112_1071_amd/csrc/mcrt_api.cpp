@@ -57,6 +57,12 @@ hipError_t launch_tile_sort(const SweepParams& S, unsigned* order, unsigned* til
                             unsigned* item_off, unsigned* cursor, int blocks, hipStream_t st);
 hipError_t launch_fill_u32(unsigned* p, int n, unsigned v, hipStream_t st);
 hipError_t launch_raytrace(const RayParams& R, hipStream_t st);
+hipError_t launch_pda_coefficients(const PdaParams& P, int select, hipStream_t st);
+hipError_t launch_pda_connect(const PdaParams& P, hipStream_t st);
+hipError_t launch_pda_init(const PdaParams& P, hipStream_t st);
+hipError_t launch_pda_iteration(const PdaParams& P, hipStream_t st);
+hipError_t launch_pda_shift(const PdaParams& P, hipStream_t st);
+hipError_t launch_pda_finish(const PdaParams& P, hipStream_t st);
 }  // namespace mcrt
 
 using namespace mcrt;
@@ -146,9 +152,14 @@ struct mcrt_model {
     DBuf<double> peel_dir, psed_sum, psed_sum2, pimg_sum, pimg_sum2;
     // raytracing: spectral cube and SED of the last mcrt_raytrace, its image
     DBuf<double> ray_cube, ray_sed, ray_nu, ray_lsrc;
-    // modified random walk: Planck/Rosseland mean table (built when mrw_gamma > 0)
+    // modified random walk: Planck/Rosseland mean table (built when mrw_gamma > 0
+    // or for the partial diffusion approximation)
     DBuf<double> mrw_tab;
     bool mrw_tab_built = false;
+    // partial diffusion approximation: flags, CG vectors (8 x ncell), reductions
+    DBuf<unsigned char> pda_flag;
+    DBuf<double> pda_vec, pda_red;
+    DBuf<unsigned> pda_count;
     int ray_npix = 0;
     DBuf<unsigned long long> sed_n;
     DBuf<mcrt_event> evlog;
@@ -959,6 +970,7 @@ void mcrt_destroy(mcrt_model* m) {
     m->pimg_sum.release(); m->pimg_sum2.release();
     m->ray_cube.release(); m->ray_sed.release(); m->ray_nu.release(); m->ray_lsrc.release();
     m->mrw_tab.release();
+    m->pda_flag.release(); m->pda_vec.release(); m->pda_red.release(); m->pda_count.release();
     m->misc.release(); m->energies.release(); m->hist.release();
     m->sw_a.release(); m->sw_b.release(); m->sw_tile.release(); m->sw_counts.release();
     m->sw_tile_off.release(); m->sw_item_off.release(); m->sw_cursor.release(); m->sw_ctr.release();
@@ -1271,6 +1283,108 @@ mcrt_status mcrt_raytrace(mcrt_model* m, int npix, double half_width) {
     HIPCHK(launch_raytrace(R, s));
     HIPCHK(hipStreamSynchronize(s));
     m->ray_npix = npix;
+    return MCRT_OK;
+}
+
+mcrt_status mcrt_apply_pda(mcrt_model* m, double noise, int passes, mcrt_pda_stats* st) {
+    if (!m || !st) return MCRT_E_ARG;
+    if (!(noise > 0.0) || !isfinite(noise) || passes < 1 || passes > 100)
+        return fail(m, MCRT_E_ARG, "noise must be > 0 and passes in [1, 100]");
+    if (m->iter < 1) return fail(m, MCRT_E_STATE, "run a Lucy iteration first");
+    hipSetDevice(m->device);
+    mcrt_status r = ready(m);
+    if (r != MCRT_OK) return r;
+    memset(st, 0, sizeof *st);
+    hipStream_t s = m->stream;
+    if (!m->mrw_tab_built) {
+        std::vector<double> tab;
+        mrw_table(m->nu, m->kap, m->chi, tab);
+        HIPCHK(upload(m->mrw_tab, tab, s));
+        HIPCHK(hipStreamSynchronize(s));
+        m->mrw_tab_built = true;
+    }
+    const size_t nc = (size_t)m->ncell;
+    HIPCHK(m->pda_flag.ensure(nc));
+    HIPCHK(m->pda_vec.ensure(8 * nc));
+    HIPCHK(m->pda_red.ensure(5));
+    HIPCHK(m->pda_count.ensure(1));
+    PdaParams P{};
+    P.ncell = m->ncell;
+    for (int a = 0; a < 3; ++a) {
+        P.n[a] = m->n[a];
+        P.dx[a] = m->dx[a];
+    }
+    P.rho = m->rho64.p;
+    P.T = m->T.p;
+    P.adot = m->adot.p;
+    P.adot_sig = m->cfg.want_noise ? m->adot_sig.p : nullptr;
+    P.noise = noise;
+    P.mrw_tab = m->mrw_tab.p;
+    P.lnA = m->lnA.p;
+    P.slope = m->slope.p;
+    P.dy = m->dy;
+    P.flag = m->pda_flag.p;
+    double* v = m->pda_vec.p;
+    P.a = v;
+    P.x = v + nc;
+    P.r = v + 2 * nc;
+    P.z = v + 3 * nc;
+    P.p = v + 4 * nc;
+    P.q = v + 5 * nc;
+    P.diag = v + 6 * nc;
+    P.b = v + 7 * nc;
+    P.red = m->pda_red.p;
+    P.count = m->pda_count.p;
+    P.adot_out = m->adot.p;
+    P.valid = m->valid.p;
+    auto read_count = [&](unsigned* out) -> hipError_t {
+        hipError_t e = hipMemcpyAsync(out, P.count, sizeof *out, hipMemcpyDeviceToHost, s);
+        if (e != hipSuccess) return e;
+        return hipStreamSynchronize(s);
+    };
+    for (int pass = 0; pass < passes; ++pass) {
+        // the cells are chosen once, from the Monte-Carlo estimate; chi_R is
+        // evaluated at the current temperatures on every pass
+        HIPCHK(launch_fill_u32(P.count, 1, 0u, s));
+        HIPCHK(launch_pda_coefficients(P, pass == 0 ? 1 : 0, s));
+        if (pass == 0) {
+            unsigned n_pda = 0;
+            HIPCHK(read_count(&n_pda));
+            st->n_pda = n_pda;
+            if (n_pda == 0) break;
+            for (unsigned round = 0; round <= n_pda; ++round) {
+                HIPCHK(launch_fill_u32(P.count, 1, 0u, s));
+                HIPCHK(launch_pda_connect(P, s));
+                unsigned changed = 0;
+                HIPCHK(read_count(&changed));
+                st->n_solved += changed;
+                if (changed == 0) break;
+            }
+            if (st->n_solved == 0) break;
+        }
+        HIPCHK(hipMemsetAsync(P.red, 0, 5 * sizeof(double), s));
+        HIPCHK(launch_pda_init(P, s));
+        double red[5];
+        HIPCHK(hipMemcpyAsync(red, P.red, sizeof red, hipMemcpyDeviceToHost, s));
+        HIPCHK(hipStreamSynchronize(s));
+        const double bb = red[4];
+        double rr = red[0] > 0.0 ? 1.0 : 0.0;  // nothing to do when the start solves it
+        int it = 0;
+        const int max_it = (int)std::min<int64_t>(100000, 10 * st->n_solved + 100);
+        while (rr > 0.0 && it < max_it) {
+            HIPCHK(launch_pda_iteration(P, s));
+            HIPCHK(hipMemcpyAsync(&rr, P.red + 3, sizeof rr, hipMemcpyDeviceToHost, s));
+            HIPCHK(hipStreamSynchronize(s));
+            ++it;
+            if (!(rr > 1e-24 * bb)) break;  // relative residual 1e-12
+            HIPCHK(launch_pda_shift(P, s));
+        }
+        st->cg_iterations = it;
+        st->residual = bb > 0.0 ? sqrt(fmax(rr, 0.0) / bb) : 0.0;
+        st->passes = pass + 1;
+        HIPCHK(launch_pda_finish(P, s));
+    }
+    HIPCHK(hipStreamSynchronize(s));
     return MCRT_OK;
 }
 

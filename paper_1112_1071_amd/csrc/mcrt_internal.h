@@ -127,6 +127,29 @@ struct RayParams {
     double* sed;            // [n_obs][2][nnu] (0 sources, 1 dust), erg/s/sr
 };
 
+// Partial diffusion approximation: the grid, the selection inputs and the
+// conjugate-gradient vectors (all [ncell], x-fastest).
+struct PdaParams {
+    int64_t ncell;
+    int n[3];
+    double dx[3];
+    const double* rho;
+    double* T;               // read; the connected PDA cells' T written at the end
+    const double* adot;      // the Monte-Carlo estimate the selection uses
+    const double* adot_sig;  // its error, or null
+    double noise;            // relative error above which a cell is a PDA cell
+    const double* mrw_tab;   // Rosseland mean table (kMrwRows x 4)
+    const double* lnA;       // ln Adot(ln T) table and slopes (Eq. 3)
+    const double* slope;
+    double dy;
+    unsigned char* flag;     // 0 not PDA, 1 PDA, 2 PDA connected to a sampled cell
+    double *a, *x, *r, *z, *p, *q, *diag, *b;
+    double* red;             // [5] r.z, p.q, new r.z, r.r, b.b
+    unsigned* count;         // cells connected in a round
+    double* adot_out;        // Adot of the connected PDA cells
+    unsigned char* valid;
+};
+
 // Tiled sweeps: the tiling and the buffers of one sweep.
 struct SweepParams {
     int txy;                    // tile extent in x and y (cells): 16 or 32

@@ -3,8 +3,9 @@
 //
 // Dust: one wavefront per image pixel.  The wave follows the ray through the
 // pixel centre from the observer's side of the grid along -o, cell by cell (a
-// DDA on the ray parameter), and its lanes hold 64 frequency bins at a time:
-// every lane adds exp(-tau in front) S (1 - exp(-dtau)) for its bin, with
+// DDA on the ray parameter), and its lanes hold the frequency bins (up to 256
+// per walk, four per lane): a lane adds exp(-tau in front) S (1 - exp(-dtau)) for
+// each of its bins, with
 // dtau = rho chi l over the cell's chord l and S = kappa/chi B(T), the bin
 // integral of the Planck function taken by composite 4-point Gauss-Legendre
 // quadrature in x = h nu / k T.  All lanes of a wave walk the same cells, so the
@@ -24,6 +25,7 @@ constexpr double kH = 6.62607015e-27;   // erg s
 constexpr double kKB = 1.380649e-16;    // erg / K
 constexpr double kC = 2.99792458e10;    // cm / s
 constexpr double kPi = 3.14159265358979323846;
+constexpr int kRayBins = 4;             // frequency bins per lane in one walk of a ray
 
 // int_a^b x^3 / (e^x - 1) dx: composite 4-point Gauss-Legendre on panels of
 // width <= 1/2 (at most 64); nothing beyond x = 300 (below 1e-120 of the peak)
@@ -161,31 +163,46 @@ __global__ void __launch_bounds__(256) k_raytrace_dust(RayParams R) {
     }
     RayWalk w0;
     walk_start(R, x0, d, true, w0);
-    for (int kb = 0; kb < R.nnu; kb += kWave) {
-        const int k = kb + lane;
-        const bool act = k < R.nnu;
-        const double chi = act ? R.chi[k] : 0.0, kap = act ? R.kap[k] : 0.0;
-        const double nlo = act ? R.nu[k] : 1.0, nhi = act ? R.nu[k + 1] : 1.0;
-        double I = 0.0, tau = 0.0;
+    // a lane holds bins k = lane + 64 i (i < kRayBins) through one walk of
+    // the ray; more bins take further walks.  The attenuation in front is
+    // carried as a product: one expm1 per bin and cell gives both 1 - e^-dtau
+    // and the factor e^-dtau.
+    for (int kb = 0; kb < R.nnu; kb += kWave * kRayBins) {
+        double chi[kRayBins], sk[kRayBins], xlo[kRayBins], xhi[kRayBins], I[kRayBins], att[kRayBins];
+#pragma unroll
+        for (int i = 0; i < kRayBins; ++i) {
+            const int k = kb + lane + kWave * i;
+            const bool act = k < R.nnu;
+            chi[i] = act ? R.chi[k] : 0.0;
+            sk[i] = act ? R.kap[k] / R.chi[k] : 0.0;  // S = (kappa / chi) B
+            xlo[i] = act ? kH * R.nu[k] : 0.0;        // h nu, divided by kT per cell
+            xhi[i] = act ? kH * R.nu[k + 1] : 0.0;
+            I[i] = 0.0;
+            att[i] = 1.0;
+        }
         RayWalk w = w0;
         while (walk_inside(R, w)) {
             int64_t j;
             const double l = walk_step(w, j, R);
             const double r = R.rho[j];
-            if (r > 0.0 && act) {
-                const double T = R.T[j];
-                const double dtau = r * chi * l;
-                double S = 0.0;
-                if (T > 0.0) {
-                    const double kT = kKB * T;
-                    const double pref = 2.0 * kT * kT * kT * kT / (kH * kH * kH * kC * kC);
-                    S = kap / chi * pref * planck_x_integral(kH * nlo / kT, kH * nhi / kT);
-                }
-                I += exp(-tau) * S * -expm1(-dtau);
-                tau += dtau;
+            if (!(r > 0.0)) continue;
+            const double T = R.T[j];
+            const double kT = kKB * T;
+            const double pref = T > 0.0 ? 2.0 * kT * kT * kT * kT / (kH * kH * kH * kC * kC) : 0.0;
+            const double ikT = T > 0.0 ? 1.0 / kT : 0.0;
+#pragma unroll
+            for (int i = 0; i < kRayBins; ++i) {
+                const double em = expm1(-r * chi[i] * l);  // e^-dtau - 1
+                const double S = T > 0.0 ? sk[i] * pref * planck_x_integral(xlo[i] * ikT, xhi[i] * ikT) : 0.0;
+                I[i] += att[i] * S * -em;
+                att[i] *= 1.0 + em;
             }
         }
-        if (act) out[k] = I * apix;
+#pragma unroll
+        for (int i = 0; i < kRayBins; ++i) {
+            const int k = kb + lane + kWave * i;
+            if (k < R.nnu) out[k] = I[i] * apix;
+        }
     }
 }
 

@@ -69,6 +69,16 @@ class RunStats(C.Structure):
     ]
 
 
+class PdaStats(C.Structure):
+    _fields_ = [
+        ("n_pda", C.c_int64), ("n_solved", C.c_int64), ("passes", C.c_int32),
+        ("cg_iterations", C.c_int32), ("residual", C.c_double),
+    ]
+
+    def as_dict(self) -> dict:
+        return {f: getattr(self, f) for f, _ in self._fields_}
+
+
 class BatchCfg(C.Structure):
     _fields_ = [
         ("n_iter", C.c_int32), ("final_pass", C.c_int32), ("use_graph", C.c_int32),
@@ -143,6 +153,7 @@ def lib():
         "mcrt_get_event_log": ([vp, vp, sz, vp, sz], i32),
         "mcrt_device_info": ([vp, C.POINTER(i32), C.POINTER(i32)], i32),
         "mcrt_raytrace": ([vp, i32, dbl], i32),
+        "mcrt_apply_pda": ([vp, dbl, i32, C.POINTER(PdaStats)], i32),
         "mcrt_get_raytraced_sed": ([vp, vp, sz], i32),
         "mcrt_get_raytraced_cube": ([vp, vp, sz], i32),
         "mcrt_get_raytraced_cube_device": ([vp, C.POINTER(vp)], i32),
@@ -359,6 +370,13 @@ class Model:
         return n.value, w.value
 
     # -- learned warm start ----------------------------------------------------
+    def apply_pda(self, noise: float, passes: int = 3) -> dict:
+        """Partial diffusion approximation (Appendix A) on the poorly sampled
+        cells of the last iteration; returns its statistics."""
+        st = PdaStats()
+        self._check(self.L.mcrt_apply_pda(self.h, float(noise), int(passes), C.byref(st)))
+        return st.as_dict()
+
     def raytrace(self, npix: int, half_width: float, cube: bool = True):
         """Raytraced emission (Sec. 2.6.3) toward the peel-off observers at the
         current temperatures: SED [n_peel][2][n_nu] (0 sources, 1 dust) and, if
