@@ -185,12 +185,21 @@ def bench_warmstart(args):
     sur = mcrt.Surrogate(0, 16, seed=0)
     sur.load(args.weights)
     runs = []
-    for i in range(args.clumps):
-        cfg = warmstart.test_clump(i, n_packets=int(args.packets))
+    if args.family == "disk":
+        cfgs = warmstart.thick_holdout_disks(args.clumps, packets_per_cell=args.ppc)
+        n_packets = int(cfgs[0]["run"]["n_packets"])
+        workload = (f"{args.clumps} thick holdout disks of the training family (64^3, mid-plane "
+                    f"tau(1 um) >= 100), {args.ppc:g} packets per cell per iteration")
+    else:
+        cfgs = [warmstart.test_clump(i, n_packets=int(args.packets)) for i in range(args.clumps)]
+        n_packets = int(args.packets)
+        workload = (f"{args.clumps} unseen 128^3 clumps built like the 256^3 clump (0.65 pc, "
+                    f"50 sources, mean tau(1 um) 50), {args.packets:.2e} packets per iteration")
+    for i, cfg in enumerate(cfgs):
         cold = warmstart.converge(cfg, None)
         warm = warmstart.converge(cfg, sur)
         runs.append({"clump": i, "cold": cold, "warm": warm})
-        print(f"# clump {i}: cold {cold['iterations']} it {cold['ms_to_converged']:.0f} ms, warm "
+        print(f"# model {i}: cold {cold['iterations']} it {cold['ms_to_converged']:.0f} ms, warm "
               f"{warm['iterations']} it {warm['ms_to_converged']:.0f} ms, pre-MC median |dlnT| "
               f"{warm['pre_mc_error']['median_abs_dlnT']:.3f}", file=sys.stderr, flush=True)
     ok = all(r["cold"]["converged"] and r["warm"]["converged"] for r in runs)
@@ -201,9 +210,7 @@ def bench_warmstart(args):
         "value": t_warm, "unit": "ms", "n_gpus": 1, "steps": len(runs), "warmup": 0,
         "ms_per_step": t_warm, "higher_is_better": False, "scaling": "weak", "vs_baseline": None,
         "dtype": "fp32 transport, bf16 network", "data": "synthetic",
-        "config": {"workload": f"{args.clumps} unseen 128^3 clumps built like the 256^3 clump "
-                               f"(0.65 pc, 50 sources, mean tau(1 um) 50), {args.packets:.2e} "
-                               f"packets per iteration", "clumps": args.clumps},
+        "config": {"workload": workload, "models": args.clumps, "packets_per_step": n_packets},
         "cold": {"ms_to_converged": t_cold,
                  "iterations": [r["cold"]["iterations"] for r in runs]},
         "warm": {"ms_to_converged": t_warm,
@@ -220,11 +227,14 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--workload", choices=["clump256", "batch", "warmstart", "raytrace"], default="clump256")
     ap.add_argument("--npix", type=int, default=256, help="raytrace: image pixels per side")
-    ap.add_argument("--clumps", type=int, default=2, help="warmstart: test clumps")
+    ap.add_argument("--clumps", type=int, default=2, help="warmstart: test models")
+    ap.add_argument("--family", choices=["clump", "disk"], default="clump",
+                    help="warmstart: unseen 128^3 clumps or thick holdout disks (64^3)")
     ap.add_argument("--weights", default=os.path.join(ROOT, "paper_1112_1071_amd", "weights",
                                                       "warmstart_c16.npy"))
     ap.add_argument("--models", type=int, default=512)
-    ap.add_argument("--ppc", type=int, default=30, help="batch: packets per cell per iteration")
+    ap.add_argument("--ppc", type=int, default=0,
+                    help="packets per cell per iteration (batch: default 30; warmstart disks: 400)")
     ap.add_argument("--seq-models", type=int, default=512)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
@@ -251,6 +261,7 @@ def main():
         print(json.dumps({"error": "this benchmark runs on one GPU only; --gpus must be 1"}))
         sys.exit(2)
     if args.workload == "batch":
+        args.ppc = args.ppc or 30
         bench_batch(args)
         return
     if args.workload == "raytrace":
@@ -259,6 +270,7 @@ def main():
     if args.workload == "warmstart":
         if args.packets == 1e8:
             args.packets = 2.5e8
+        args.ppc = args.ppc or 400
         bench_warmstart(args)
         return
 

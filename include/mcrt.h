@@ -89,7 +89,9 @@ typedef struct {
     int32_t event_log_packets; /* log events of packets [0, this) of each pass [0]        */
     int32_t event_log_cap;     /* events kept per logged packet [256]                     */
     int32_t bin_every_iteration; /* bin escapes into SED/images in Lucy iterations too [0]*/
-    int32_t block_size;        /* transport threads per block, multiple of 64 [256]       */
+    int32_t block_size;        /* transport threads per block, multiple of 64, at most
+                                  256 (512 for FP32 tiled sweeps); 0: 512 for FP32 tiled
+                                  sweeps, else 256 [0]                                    */
     int32_t blocks_per_cu;     /* persistent blocks per compute unit [0 = occupancy]      */
     int32_t defer_lanes;       /* lanes of a wave that wait before events run; 0: 16 for
                                   the per-lane walk, 64 for tiled sweeps [0]              */
@@ -104,10 +106,12 @@ typedef struct {
                                   tile walked with density and tally in LDS, tally flushed
                                   to FP64 once per work item [1]; same packet histories  */
     int32_t tile_z;            /* tiled sweeps: tile extent in z, 4, 8, 16 or 32, halved
-                                  while the tile does not fit in LDS [32]                 */
+                                  while the tile does not fit in LDS; 0: 16 in FP32, 32
+                                  in FP64 [0]                                             */
     int32_t visit_events;      /* tiled sweeps: interactions per tile visit before a
                                   packet waits for the next sweep [256]                   */
-    int32_t tile_xy;           /* tiled sweeps: tile extent in x and y, 16 or 32 [16]     */
+    int32_t tile_xy;           /* tiled sweeps: tile extent in x and y, 16 or 32; 0: 32
+                                  in FP32, 16 in FP64 [0]                                 */
     double mrw_gamma;          /* modified random walk (Sec. 2.2): at the start of a flight,
                                   while the sphere to the nearest wall of the cell holds at
                                   least mrw_gamma Rosseland mean free paths, one diffusion

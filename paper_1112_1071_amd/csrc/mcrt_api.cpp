@@ -624,8 +624,11 @@ mcrt_status run_sweeps(mcrt_model* m, TransportParams<R>& P, int64_t np, int64_t
     hipStream_t s = m->stream;
     constexpr bool f32 = std::is_same<R, float>::value;
     SweepParams S{};
-    S.txy = m->cfg.tile_xy == 32 ? 32 : 16;
-    S.tz = m->cfg.tile_z == 4 || m->cfg.tile_z == 8 || m->cfg.tile_z == 16 ? m->cfg.tile_z : 32;
+    // tile shape and group size, 0 = by precision: FP32 32x32x16 tiles (128 KB
+    // of LDS) walked by one group of 512 threads per compute unit; FP64
+    // 16x16x32 tiles and 256 threads (its register budget)
+    S.txy = m->cfg.tile_xy == 0 ? (f32 ? 32 : 16) : m->cfg.tile_xy;
+    S.tz = m->cfg.tile_z == 0 ? (f32 ? 16 : 32) : m->cfg.tile_z;
     // LDS: tile density and tally (and sum of squares), bin opacities, then the
     // staged tables; a tile too deep for LDS is halved in z
     auto tile_bytes = [&](int tz) {
@@ -665,8 +668,7 @@ mcrt_status run_sweeps(mcrt_model* m, TransportParams<R>& P, int64_t np, int64_t
     P.lds_tables = tile_lds + tab_lds <= m->lds_max ? 1 : 0;
     const size_t lds = tile_lds + (P.lds_tables ? tab_lds : 0);
     const int K = m->cfg.walk_batch == 1 || m->cfg.walk_batch == 2 ? m->cfg.walk_batch : 4;
-    // workgroups of 256 (the kernel's register budget does not fit 1024 threads)
-    const int threads = 256;
+    const int threads = m->cfg.block_size > 0 ? m->cfg.block_size : (f32 ? 512 : 256);
     S.item = (unsigned)threads * 8u;
     const int bpc =
         m->cfg.blocks_per_cu > 0 ? m->cfg.blocks_per_cu : sweep_max_blocks_per_cu<R>(K, threads, lds);
@@ -906,15 +908,15 @@ mcrt_status mcrt_run_cfg_default(mcrt_run_cfg* c) {
     c->conv_dT_thres = 0.01;
     c->conv_noise_thres = 0.002;
     c->event_log_cap = 256;
-    c->block_size = 256;
+    c->block_size = 0;
     c->defer_lanes = 0;
     c->walk_batch = 4;
     c->grid_layout = 0;
     c->tally_copies = kMaxTallyCopies;
     c->transport_mode = 1;
-    c->tile_z = 32;
+    c->tile_z = 0;
     c->visit_events = 256;
-    c->tile_xy = 16;
+    c->tile_xy = 0;
     return MCRT_OK;
 }
 
@@ -1428,7 +1430,8 @@ mcrt_status mcrt_set_run(mcrt_model* m, const mcrt_run_cfg* c) {
     if (c->event_log_packets < 0 || c->event_log_cap < 0) return fail(m, MCRT_E_ARG, "bad event log size");
     if (c->block_size < 0 || c->block_size % 64 != 0 || c->block_size > 1024)
         return fail(m, MCRT_E_ARG, "block_size must be a multiple of 64");
-    if (c->block_size > 256) return fail(m, MCRT_E_ARG, "block_size above 256 is not supported");
+    if (c->block_size > (c->transport_mode == 1 && c->precision == MCRT_FP32_TRANSPORT ? 512 : 256))
+        return fail(m, MCRT_E_ARG, "block_size above 256 (512 for FP32 tiled sweeps) is not supported");
     if (c->defer_lanes < 0 || c->defer_lanes > 64) return fail(m, MCRT_E_ARG, "defer_lanes must be in [0,64]");
     if (c->blocks_per_cu < 0) return fail(m, MCRT_E_ARG, "blocks_per_cu must be >= 0");
     if (c->transport_mode != 0 && c->transport_mode != 1)
@@ -1445,7 +1448,6 @@ mcrt_status mcrt_set_run(mcrt_model* m, const mcrt_run_cfg* c) {
     if (m->cfg.mrw_gamma > 0.0 && !m->mrw_tab_built) m->tables_dirty = true;
     if (m->cfg.event_log_cap == 0) m->cfg.event_log_cap = 256;
     if (m->cfg.conv_noise_thres <= 0.0) m->cfg.conv_noise_thres = 0.002;
-    if (m->cfg.tile_z == 0) m->cfg.tile_z = 32;
     if (m->cfg.visit_events == 0) m->cfg.visit_events = 256;
     m->have_run = true;
     if (reset) m->state_ready = false;

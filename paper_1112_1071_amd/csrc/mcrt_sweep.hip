@@ -131,21 +131,34 @@ __device__ __forceinline__ int tile_index(int c0, int c1, int c2, int o0, int o1
 // loop.  The lane carries its cell's LDS index jl and density rho between
 // calls (an interaction leaves the cell unchanged); the next cell's density
 // is read as soon as the next cell is known, ahead of the segment's arithmetic.
-template <typename R, int K>
+// Cell coordinates are not stepped per segment: each axis counts the moves
+// left before the packet reaches the last cell of the tile (or of the grid,
+// in a ragged tile) in its direction, and the coordinates follow from the
+// counts after the loop.  A crossing with no move left on its axis leaves the
+// tile (state MOVE, into the neighbour tile's cell) or, at the grid's own
+// wall, the grid (state ESC, the cell unchanged).
+template <typename R, int K, bool NOISE>
 __device__ __forceinline__ void walk_tile(Packet<R>& s, const TransportParams<R>& P, int o0, int o1,
                                           int o2, int txy, int tz, const R* __restrict__ rho_t,
                                           R* __restrict__ acc_t, double* __restrict__ acc2_t,
                                           uint32_t* cnt, int& jl, R& rho) {
-    const int sx = s.d0 > (R)0 ? 1 : -1;
-    const int sy = s.d1 > (R)0 ? 1 : -1;
-    const int sz = s.d2 > (R)0 ? 1 : -1;
-    const int dyj = sy * txy, dzj = sz * txy * txy;
-    const int g0 = P.n[0], g1 = P.n[1], g2 = P.n[2];
-    bool act = true;   // still walking in this call
-    bool hit = false;  // the last segment ends in an interaction
+    const bool px = s.d0 > (R)0, py = s.d1 > (R)0, pz = s.d2 > (R)0;
+    const int sx = px ? 1 : -1;
+    const int sy = py ? 1 : -1;
+    const int sz = pz ? 1 : -1;
+    const int djy = sy * txy, djz = sz * txy * txy;
+    // one past the last cell of the tile that lies in the grid, per axis
+    const int h0 = min(o0 + txy, P.n[0]), h1 = min(o1 + txy, P.n[1]), h2 = min(o2 + tz, P.n[2]);
+    const int r0i = px ? h0 - 1 - s.c0 : s.c0 - o0;
+    const int r1i = py ? h1 - 1 - s.c1 : s.c1 - o1;
+    const int r2i = pz ? h2 - 1 - s.c2 : s.c2 - o2;
+    int r0 = r0i, r1 = r1i, r2 = r2i;  // moves left inside the tile per axis
+    bool act = true;    // still walking in this call
+    bool hit = false;   // the last segment ends in an interaction
+    bool left = false;  // the last segment crosses the tile's (or grid's) wall
+    int lax = 0;        // and on which axis
     R rc_h = (R)1, ts_h = (R)0;
     int jl_h = jl;
-    int st = ST_WALK;
     uint32_t nd = 0, ne = 0;
 #pragma unroll
     for (int i = 0; i < K; ++i) {
@@ -153,17 +166,10 @@ __device__ __forceinline__ void walk_tile(Packet<R>& s, const TransportParams<R>
         R tm = ax1 ? s.ty : s.tx;
         const bool ax2 = s.tz < tm;
         tm = ax2 ? s.tz : tm;
-        const bool ax0 = !ax1 && !ax2;
-        const bool by = ax1 && !ax2;
-        // the next cell along the moving axis, whether it leaves the grid or
-        // the tile (a cell past the grid inside a ragged tile holds 0)
-        const int na = ax0 ? s.c0 + sx : (by ? s.c1 + sy : s.c2 + sz);
-        const int oa = ax0 ? o0 : (by ? o1 : o2);
-        const int ga = ax0 ? g0 : (by ? g1 : g2);
-        const int la = ax2 ? tz : txy;
-        const bool out_grid = (unsigned)na >= (unsigned)ga;
-        const bool out_tile = (unsigned)(na - oa) >= (unsigned)la;
-        const int jn = out_tile ? jl : jl + (ax0 ? sx : (by ? dyj : dzj));
+        const int r = ax2 ? r2 : (ax1 ? r1 : r0);
+        const bool edge = r == 0;  // the next cell is outside the tile or the grid
+        const int dj = ax2 ? djz : (ax1 ? djy : sx);
+        const int jn = edge ? jl : jl + dj;
         const R rho_n = rho_t[jn];
         // this segment
         const R ts = s.t;
@@ -185,27 +191,56 @@ __device__ __forceinline__ void walk_tile(Packet<R>& s, const TransportParams<R>
             s.tau_acc += dtau;
             const R w = s.wgt * l * s.kap;
             atomicAdd(acc_t + jl, w);
-            if (acc2_t) atomicAdd(acc2_t + jl, (double)w * (double)w);  // w^2 may exceed FP32
+            if (NOISE) atomicAdd(acc2_t + jl, (double)w * (double)w);  // w^2 may exceed FP32
         }
         s.t = cross ? fmax(tm, s.t) : s.t;
-        const bool mv = cross && !out_grid;
-        s.c0 += (mv && ax0) ? sx : 0;
-        s.c1 += (mv && by) ? sy : 0;
-        s.c2 += (mv && ax2) ? sz : 0;
-        s.tx += (mv && ax0) ? s.dtx : (R)0;
-        s.ty += (mv && by) ? s.dty : (R)0;
-        s.tz += (mv && ax2) ? s.dtz : (R)0;
-        st = (cross && out_grid) ? ST_ESC : ((mv && out_tile) ? ST_MOVE : (h ? ST_EVENT : st));
-        act = mv && !out_tile;
-        jl = act ? jn : jl;
-        rho = act ? rho_n : rho;
+        const bool mv = cross && !edge;
+        const bool m0 = mv && !ax1 && !ax2, m1 = mv && ax1 && !ax2, m2 = mv && ax2;
+        r0 -= m0 ? 1 : 0;
+        r1 -= m1 ? 1 : 0;
+        r2 -= m2 ? 1 : 0;
+        s.tx += m0 ? s.dtx : (R)0;
+        s.ty += m1 ? s.dty : (R)0;
+        s.tz += m2 ? s.dtz : (R)0;
+        const bool lv = cross && edge;
+        left = left || lv;
+        lax = lv ? (ax2 ? 2 : (ax1 ? 1 : 0)) : lax;
+        act = mv;
+        jl = mv ? jn : jl;
+        rho = mv ? rho_n : rho;
     }
+    s.c0 += sx * (r0i - r0);
+    s.c1 += sy * (r1i - r1);
+    s.c2 += sz * (r2i - r2);
+    int st = ST_WALK;
     if (hit) {
         const R l = (s.tau - s.tau_acc) / rc_h;
         const R w = s.wgt * l * s.kap;
         atomicAdd(acc_t + jl_h, w);
-        if (acc2_t) atomicAdd(acc2_t + jl_h, (double)w * (double)w);
+        if (NOISE) atomicAdd(acc2_t + jl_h, (double)w * (double)w);
         s.t = ts_h + l;
+        st = ST_EVENT;
+    } else if (left) {
+        // past the tile's wall on axis lax: the neighbour tile's cell, or out
+        // of the grid if that wall is the grid's
+        const int c = lax == 0 ? s.c0 : (lax == 1 ? s.c1 : s.c2);
+        const int sg = lax == 0 ? sx : (lax == 1 ? sy : sz);
+        const int g = lax == 0 ? P.n[0] : (lax == 1 ? P.n[1] : P.n[2]);
+        if ((unsigned)(c + sg) >= (unsigned)g) {
+            st = ST_ESC;
+        } else {
+            st = ST_MOVE;
+            if (lax == 0) {
+                s.c0 += sx;
+                s.tx += s.dtx;
+            } else if (lax == 1) {
+                s.c1 += sy;
+                s.ty += s.dty;
+            } else {
+                s.c2 += sz;
+                s.tz += s.dtz;
+            }
+        }
     }
     s.st = st;
     cnt[C_CROSS_DUST] += nd;
@@ -346,9 +381,11 @@ __device__ __forceinline__ void flush_tile(const TransportParams<R>& P, const Sw
     if (threadIdx.x < 7) s_nb[threadIdx.x] = 0u;
 }
 
-// One sweep over the work items (persistent workgroups).
+// One sweep over the work items (persistent workgroups; in FP32 of up to 512
+// threads, so that one group of 8 waves can hold a 32x32x16 tile, 128 KB of
+// LDS; the FP64 walk keeps its registers at 256 threads).
 template <typename R, int K>
-__global__ void __launch_bounds__(256) k_sweep(TransportParams<R> P, SweepParams S) {
+__global__ void __launch_bounds__(sizeof(R) == 4 ? 512 : 256) k_sweep(TransportParams<R> P, SweepParams S) {
     extern __shared__ unsigned char smem_raw[];
     __shared__ unsigned s_item, s_next;
     __shared__ unsigned s_nb[7];  // records leaving for this tile, -x, +x, -y, +y, -z, +z
@@ -467,8 +504,13 @@ __global__ void __launch_bounds__(256) k_sweep(TransportParams<R> P, SweepParams
             if (__ballot(s.st != ST_DONE) == 0ull) break;
             drained = drained || __ballot(s.st == ST_DONE) != 0ull;
             for (;;) {
-                if (s.st == ST_WALK)
-                    walk_tile<R, K>(s, P, o0, o1, o2, txy, S.tz, rho_t, acc_t, acc2_t, cnt, jl, rho);
+                if (s.st == ST_WALK) {
+                    // Sum w^2 is kept (the tally's noise estimate) or not for the whole launch
+                    if (acc2_t)
+                        walk_tile<R, K, true>(s, P, o0, o1, o2, txy, S.tz, rho_t, acc_t, acc2_t, cnt, jl, rho);
+                    else
+                        walk_tile<R, K, false>(s, P, o0, o1, o2, txy, S.tz, rho_t, acc_t, nullptr, cnt, jl, rho);
+                }
                 if (__ballot(s.st == ST_WALK) == 0ull) break;
                 if (__popcll(__ballot(s.st != ST_WALK && s.st != ST_DONE)) >= defer) break;
             }

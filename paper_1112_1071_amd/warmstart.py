@@ -164,6 +164,25 @@ def test_clump(i: int, n: int = 128, n_packets: int = 250_000_000, n_iter: int =
     return synth.clump_config4(n=n, seed=SEED_TEST + i, n_packets=n_packets, n_iter=n_iter)
 
 
+def thick_holdout_disks(count: int, n: int = 64, packets_per_cell: float = 400.0,
+                        min_tau: float = 100.0, n_iter: int = 40) -> list:
+    """The first `count` disk members of the holdout family (seeds from
+    SEED_HOLDOUT, never trained on) with mid-plane tau(1 um) >= min_tau: the
+    optically thick disks where the Lucy iteration starts far from its fixed
+    point."""
+    out = []
+    for seed in range(SEED_HOLDOUT, SEED_HOLDOUT + 100000):
+        # the member kind and tau are the first draws of family_model's stream
+        rng = np.random.default_rng(seed)
+        kind = ("sphere", "disk", "clump")[int(rng.integers(3))]
+        if kind != "disk" or 10.0 ** rng.uniform(-1.0, 3.0) < min_tau:
+            continue
+        out.append(family_model(seed, n, packets_per_cell, n_iter))
+        if len(out) == count:
+            break
+    return out
+
+
 def converge(cfg: dict, sur=None, device: int = 0, **run) -> dict:
     """Lucy iterations until max dT/T < 1 % over the noise mask, from T = 10 K
     (sur None) or from the network's temperatures; wall times include the

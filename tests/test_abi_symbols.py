@@ -43,4 +43,4 @@ def test_no_device_is_reported_cleanly():
     h = ctypes.c_void_p()
     assert mcrt.lib().mcrt_create(ctypes.byref(h), 0) == -4  # MCRT_E_DEVICE
     cfg = mcrt.default_run_cfg()
-    assert cfg.n_packets == 100000 and cfg.conv_p == 0.999 and cfg.block_size == 256
+    assert cfg.n_packets == 100000 and cfg.conv_p == 0.999 and cfg.block_size == 0

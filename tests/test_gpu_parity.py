@@ -262,6 +262,12 @@ def test_abi_errors(M):
     assert L.mcrt_iterate(h3, C.byref(st)) == -2
     L.mcrt_destroy(h3)
     L.mcrt_destroy(None)
+    # 512-thread groups exist for the FP32 tiled sweeps only
+    for bad_run in (dict(precision=M.MCRT_FP64, transport_mode=1, block_size=512),
+                    dict(precision=M.MCRT_FP32_TRANSPORT, transport_mode=0, block_size=512),
+                    dict(precision=M.MCRT_FP32_TRANSPORT, transport_mode=1, block_size=576)):
+        with pytest.raises(M.MCRTError):
+            M.Model(cfg, **bad_run)
 
 
 @pytest.mark.parametrize("variant", [
@@ -299,8 +305,13 @@ def test_launch_variants_same_stream(M, variant):
     assert np.max(np.abs(ag[nz] / ao[nz] - 1)) < 1e-9
 
 
-@pytest.mark.parametrize("tile_z", [4, 32])
-def test_tiled_fp32_equals_persistent_fp32(M, tile_z):
+@pytest.mark.parametrize("tiles", [dict(tile_xy=16, tile_z=4, block_size=256),
+                                   dict(tile_xy=16, tile_z=32, block_size=256),
+                                   dict(tile_xy=32, tile_z=4, block_size=128),
+                                   # the FP32 default: one 8-wave group per 32x32x16
+                                   # tile (128 KB of LDS; 32x32x8 with Sum w^2 kept)
+                                   dict()])
+def test_tiled_fp32_equals_persistent_fp32(M, tiles):
     # FP32 transport: both modes follow identical packet histories in the first
     # iteration (same counters exactly); the tiled mode sums a tile's visits in
     # FP32 before the FP64 flush, so Adot agrees to a few FP32 roundings per
@@ -313,7 +324,7 @@ def test_tiled_fp32_equals_persistent_fp32(M, tile_z):
     cfg = synth.config2(n=48, n_packets=400000, n_iter=2, gen_seed=45777, n_src=12,
                         box=0.65 * synth.PC * 48 / 128)
     a = M.Model(cfg, precision=M.MCRT_FP32_TRANSPORT, want_noise=1, transport_mode=0)
-    b = M.Model(cfg, precision=M.MCRT_FP32_TRANSPORT, want_noise=1, transport_mode=1, tile_z=tile_z)
+    b = M.Model(cfg, precision=M.MCRT_FP32_TRANSPORT, want_noise=1, transport_mode=1, **tiles)
     for it in range(2):
         sa, sb = a.iterate(), b.iterate()
         for k in ["n_cross_dust", "n_cross_empty", "n_scatter", "n_absorb", "n_escape", "n_killed"]:
