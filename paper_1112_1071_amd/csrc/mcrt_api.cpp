@@ -669,7 +669,9 @@ mcrt_status run_sweeps(mcrt_model* m, TransportParams<R>& P, int64_t np, int64_t
     const size_t lds = tile_lds + (P.lds_tables ? tab_lds : 0);
     const int K = m->cfg.walk_batch == 1 || m->cfg.walk_batch == 2 ? m->cfg.walk_batch : 4;
     const int threads = m->cfg.block_size > 0 ? m->cfg.block_size : (f32 ? 512 : 256);
-    S.item = (unsigned)threads * 8u;
+    // records per work item: large enough that a group walks a tile's visits
+    // between two loads of its density (8192 at 512 threads)
+    S.item = (unsigned)threads * 16u;
     const int bpc =
         m->cfg.blocks_per_cu > 0 ? m->cfg.blocks_per_cu : sweep_max_blocks_per_cu<R>(K, threads, lds);
     const int blocks = m->n_cu * bpc;
