@@ -80,39 +80,60 @@ def bench_batch(args):
     print(f"# {args.models} models built in {time.time() - t0:.1f} s", file=sys.stderr, flush=True)
     prec = mcrt.MCRT_FP32_TRANSPORT if args.precision == "fp32" else mcrt.MCRT_FP64
     extra = {"mrw_gamma": args.mrw} if args.mrw > 0 else {}
+    if args.tally_copies:
+        extra["tally_copies"] = args.tally_copies
+    if args.max_events:
+        extra["max_events"] = args.max_events
     batch = [mcrt.Model(c, precision=prec, **extra) for c in cfgs]
     n_packets = sum(int(c["run"]["n_packets"]) for c in cfgs)
     cells = sum(int(np.prod(c["grid"]["n"])) for c in cfgs)
-    # iteration 0, which also tunes the launch shape (cached per workload class)
-    stw = mcrt.batch_run(batch, n_iter=1, final_pass=0, use_graph=0, autotune=1, verbose=1)
+    # launch shape: given in full, or tuned (cached per workload class)
+    shape = dict(autotune=1)
+    if args.block_size and args.walk_batch and args.defer:
+        shape = dict(autotune=0, block_size=args.block_size, walk_batch=args.walk_batch,
+                     defer_lanes=args.defer)
+    # iteration 0, which also tunes the launch shape
+    stw = mcrt.batch_run(batch, n_iter=1, final_pass=0, use_graph=0, verbose=1, **shape)
     print(f"# iteration 0 + tuning: {stw['ms_total']:.0f} ms (tune {stw['ms_tune']:.0f} ms) shape "
           f"bs={stw['block_size']} K={stw['walk_batch']} defer={stw['defer_lanes']}",
           file=sys.stderr, flush=True)
     torch.cuda.synchronize()
     tb = time.perf_counter()
-    st = mcrt.batch_run(batch, n_iter=args.steps, final_pass=0, use_graph=1, autotune=1, verbose=1)
+    st = mcrt.batch_run(batch, n_iter=args.steps, final_pass=0, use_graph=1, verbose=1, **shape)
     torch.cuda.synchronize()
     batch_s = time.perf_counter() - tb
     value = n_packets * args.steps / batch_s
     print(f"# batched: {1e3 * batch_s / args.steps:.1f} ms per iteration", file=sys.stderr, flush=True)
     del batch
-    # the same iterations, one model and one launch at a time
+    # the same iterations, one model at a time: with the batched launch's own
+    # walk (per-lane, transport_mode 0), and with the tiled sweeps (the
+    # single-model default)
     nseq = min(args.seq_models, args.models)
-    seq_s, seq_packets = 0.0, 0
-    for i, c in enumerate(cfgs[:nseq]):
-        m = mcrt.Model(c, precision=prec, **extra)
-        m.iterate()
-        torch.cuda.synchronize()
-        ts = time.perf_counter()
-        for _ in range(args.steps):
+    seq = {}
+    for mode in (0, 1):
+        seq_s, seq_packets = 0.0, 0
+        for i, c in enumerate(cfgs[:nseq]):
+            m = mcrt.Model(c, precision=prec, transport_mode=mode, **extra)
             m.iterate()
-        torch.cuda.synchronize()
-        seq_s += time.perf_counter() - ts
-        seq_packets += int(c["run"]["n_packets"]) * args.steps
-        m.close()
-        if (i + 1) % 8 == 0:
-            print(f"# sequential: {i + 1}/{nseq} models", file=sys.stderr, flush=True)
-    seq_value = seq_packets / seq_s
+            torch.cuda.synchronize()
+            ts = time.perf_counter()
+            for _ in range(args.steps):
+                m.iterate()
+            torch.cuda.synchronize()
+            seq_s += time.perf_counter() - ts
+            seq_packets += int(c["run"]["n_packets"]) * args.steps
+            m.close()
+            if (i + 1) % 8 == 0:
+                print(f"# sequential, transport_mode {mode}: {i + 1}/{nseq} models", file=sys.stderr,
+                      flush=True)
+        seq[mode] = {"value": seq_packets / seq_s if nseq else None, "unit": "packets/s",
+                     "models": nseq, "seconds": seq_s, "transport_mode": mode}
+    # the batched rate over the same models as the sequential legs, when they
+    # cover them all
+    for mode in (0, 1):
+        seq[mode]["speedup_batched"] = value / seq[mode]["value"] if nseq == args.models else None
+    print(f"# sequential: {seq[0]['value']} / {seq[1]['value']} packets/s (per-lane walk / tiled)",
+          file=sys.stderr, flush=True)
     ms_it = 1e3 * batch_s / args.steps
     out = {
         "metric": "packets/s, batched Lucy iterations of uneven models",
@@ -128,8 +149,7 @@ def bench_batch(args):
                   "block_size": st["block_size"], "walk_batch": st["walk_batch"],
                   "defer_lanes": st["defer_lanes"], "blocks_per_cu": st["blocks_per_cu"],
                   "ms_tune": stw["ms_tune"]},
-        "sequential": {"value": seq_value, "unit": "packets/s", "models": nseq,
-                       "seconds": seq_s, "speedup_batched": value / seq_value},
+        "sequential": seq[1], "sequential_per_lane_walk": seq[0],
     }
     print(json.dumps(out), flush=True)
 
@@ -256,6 +276,7 @@ def main():
     ap.add_argument("--tally-copies", type=int, default=0)
     ap.add_argument("--visit-events", type=int, default=0)
     ap.add_argument("--mrw", type=float, default=0.0, help="modified random walk gamma (0 = off)")
+    ap.add_argument("--max-events", type=int, default=0, help="batch: interactions before a kill")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this benchmark runs on one GPU only; --gpus must be 1"}))

@@ -46,6 +46,25 @@ def test_batch_equals_single_model_runs(M, graph):
         assert np.allclose(sb[0], ss[0], rtol=1e-12, atol=0), c["name"]
 
 
+def test_batch_fp32_equals_single_model_runs(M):
+    # FP32 transport: the batched launch and one per-lane-walk launch per
+    # model follow the same packets; the FP64 tallies differ only in
+    # summation order
+    cfgs = small_family(12)
+    run = dict(precision=M.MCRT_FP32_TRANSPORT, transport_mode=0)
+    batch = [M.Model(c, **run) for c in cfgs]
+    solo = [M.Model(c, **run) for c in cfgs]
+    st = M.batch_run(batch, n_iter=1, final_pass=0, use_graph=0, autotune=0)
+    assert st["block_size"] == 256
+    for b, s, c in zip(batch, solo, cfgs):
+        s.iterate()
+        ab, as_ = b.specific_energy(), s.specific_energy()
+        nz = as_ > 0
+        assert np.array_equal(nz, ab > 0), c["name"]
+        assert np.max(np.abs(ab[nz] / as_[nz] - 1)) < 1e-9, c["name"]
+        assert np.max(np.abs(b.temperature() / s.temperature() - 1)) < 1e-9, c["name"]
+
+
 def test_batch_sample_against_oracle(M):
     cfgs = small_family(6)
     batch = [M.Model(c, precision=M.MCRT_FP64) for c in cfgs]
