@@ -455,12 +455,15 @@ mcrt_status set_weights(mcrt_model* m, int64_t np) {
 // Device work before a transport pass: emission rows from T, zeroed tallies and
 // counters, event-log buffers.  graph_safe clears with fill kernels (a captured
 // graph records no memset nodes).
-mcrt_status prepare_pass(mcrt_model* m, int64_t np, bool graph_safe) {
+mcrt_status prepare_pass(mcrt_model* m, int64_t np, bool graph_safe, bool per_lane) {
     hipStream_t s = m->stream;
     const size_t nc = (size_t)m->ncell;
     const bool f32 = m->cfg.precision == MCRT_FP32_TRANSPORT;
     unsigned long long* misc = m->misc.p;
-    const int layout = m->cfg.grid_layout == 1 && m->cfg.transport_mode == 0 ? 1 : 0;
+    // the per-lane walk (transport_mode 0, and every batched launch) reads the
+    // grid in the model's layout and adds into per-XCD tally copies; the tiled
+    // sweeps read x-fastest and flush into one copy
+    const int layout = m->cfg.grid_layout == 1 && per_lane ? 1 : 0;
     {
         mcrt_status r = ensure_transport_grid(m, layout);
         if (r != MCRT_OK) return r;
@@ -468,8 +471,7 @@ mcrt_status prepare_pass(mcrt_model* m, int64_t np, bool graph_safe) {
     if (f32) HIPCHK(m->rowpos32.ensure(nc));
     else HIPCHK(m->rowpos64.ensure(nc));
     const size_t nt = (size_t)m->nt_cells;
-    m->acc_copies =
-        m->cfg.tally_copies == kMaxTallyCopies && m->cfg.transport_mode == 0 ? kMaxTallyCopies : 1;
+    m->acc_copies = m->cfg.tally_copies == kMaxTallyCopies && per_lane ? kMaxTallyCopies : 1;
     const size_t nacc = (m->acc_copies - 1) * m->acc_stride + nt;
     m->ev_packets = m->cfg.event_log_packets < np ? m->cfg.event_log_packets : np;
     m->ev_cap = m->cfg.event_log_cap > 0 ? m->cfg.event_log_cap : 256;
@@ -721,7 +723,7 @@ mcrt_status run_transport(mcrt_model* m, int64_t np, uint32_t key1, int binning,
     unsigned long long* misc = m->misc.p;
     mcrt_status r = set_weights(m, np);
     if (r != MCRT_OK) return r;
-    r = prepare_pass(m, np, false);
+    r = prepare_pass(m, np, false, m->cfg.transport_mode == 0);
     if (r != MCRT_OK) return r;
     const int threads = m->cfg.block_size > 0 ? m->cfg.block_size : 256;
     const int K = walk_batch_of(m);
@@ -1718,7 +1720,7 @@ mcrt_status batch_upload(Batch& B, double frac, int binning, const LaunchShape& 
         // tally copies prepare_pass selects
         mcrt_status r = set_weights(m, np);
         if (r != MCRT_OK) return r;
-        r = prepare_pass(m, np, false);
+        r = prepare_pass(m, np, false, true);
         if (r != MCRT_OK) return r;
         make_params(m, np, 0u, binning, P[i]);
         P[i].lds_tables = 0;
@@ -1740,7 +1742,7 @@ mcrt_status batch_pass_ops(Batch& B, double frac, const LaunchShape& sh, bool gr
         mcrt_model* m = B.ms[i];
         int64_t np = m->cfg.n_packets;  // the same count batch_upload gave the model
         if (frac < 1.0) np = std::max<int64_t>(64, (int64_t)(frac * (double)np));
-        mcrt_status r = prepare_pass(m, np, graph_safe);
+        mcrt_status r = prepare_pass(m, np, graph_safe, true);
         if (r != MCRT_OK) return r;
     }
     BCHK(launch_fill_u64(1, B.pool(), 0ull, 1, B.s));
@@ -1938,7 +1940,7 @@ mcrt_status batch_run(Batch& B, const mcrt_batch_cfg* c, mcrt_batch_stats* st) {
         if (r != MCRT_OK) return r;
         for (mcrt_model* m : B.ms) {
             const int64_t npf = m->cfg.n_packets_final > 0 ? m->cfg.n_packets_final : m->cfg.n_packets;
-            r = prepare_pass(m, npf, false);
+            r = prepare_pass(m, npf, false, true);
             if (r != MCRT_OK) return r;
         }
         BCHK(launch_fill_u64(1, B.pool(), 0ull, 1, B.s));
