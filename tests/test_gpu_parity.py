@@ -182,6 +182,7 @@ def test_fp32_same_seed_error_report(M):
             assert same.mean() > 0.9
     To, Tg = o.temperature(), g.temperature()
     a, s = o.specific_energy(with_sigma=True)
+    ag = g.specific_energy()
     rho = cfg["rho"].ravel()
     slope_m = (rho > 0) & (a > 0)
     sig_T = (s[slope_m] / a[slope_m]) / 4.5
@@ -189,6 +190,22 @@ def test_fp32_same_seed_error_report(M):
     rel = np.abs(Tg[slope_m][quiet] / To[slope_m][quiet] - 1)
     assert quiet.sum() > 1000
     assert np.all(rel < 0.01), rel.max()
+    # the final pass at these temperatures: SED bins
+    o.final_pass()
+    g.final_pass()
+    so, s2o, no = o.sed()
+    sg, _, ng = g.sed()
+    # a bin's sum over a random number of packets: variance sum of squares
+    full = no > 100
+    z = np.abs(sg[full] - so[full]) / np.sqrt(2.0 * s2o[full])
+    assert np.mean(z < 4) >= 0.999
+    za = np.abs(ag[slope_m] - a[slope_m]) / s[slope_m]
+    print(f"FP32 transport against the FP64 oracle, same stream: identical event sequences "
+          f"{same.mean():.4f} of {len(same)} packets; T in cells with sigma_T/T < 0.3 %: median "
+          f"{np.median(rel):.2e}, max {rel.max():.2e} ({quiet.sum()} cells); Adot |diff|/sigma: "
+          f"median {np.median(za):.2f}, p99.9 {np.quantile(za, 0.999):.2f}; SED bins with > 100 "
+          f"packets: |z| < 4 in {np.mean(z < 4):.4f} of {full.sum()}, median relative difference "
+          f"{np.median(np.abs(sg[full] / so[full] - 1)):.2e}", flush=True)
 
 
 def test_edge_cases_same_stream(M):
