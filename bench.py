@@ -346,6 +346,14 @@ def main():
     elapsed = time.perf_counter() - t_start
     ms_step = 1e3 * elapsed / args.steps
     value = n_packets * args.steps / elapsed
+    # every step transported every packet to an escape or a kill, and conserved
+    # the sources' energy (immediate re-emission, Sec. 1; dt = 1 s)
+    L = sum(float(s["lum"]) for s in cfg["sources"])
+    for i, st in enumerate(stats):
+        if st["n_escape"] + st["n_killed"] != n_packets:
+            raise SystemExit(f"step {i}: {st['n_escape']} escaped + {st['n_killed']} killed != {n_packets}")
+        if abs(st["e_escaped"] + st["e_killed"] - L) > 1e-9 * L:
+            raise SystemExit(f"step {i}: escaped + killed energy {st['e_escaped'] + st['e_killed']} != L {L}")
 
     ms_tr = float(np.mean([s["ms_transport"] for s in stats]))
     abytes = float(np.mean([algorithmic_bytes(s, prec) for s in stats]))
@@ -373,7 +381,7 @@ def main():
         },
         "roofline": {
             "bound": "hbm",
-            "kernel": "k_sweep (+ tile sort)" if model.run["transport_mode"] == 1 else "k_transport",
+            "kernel": "k_sweep (+ emission, scan, grouping)" if model.run["transport_mode"] == 1 else "k_transport",
             "achieved": achieved,
             "peak": HBM_PEAK_GBS,
             "unit": "GB/s",

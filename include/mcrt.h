@@ -93,9 +93,12 @@ typedef struct {
                                   256 (512 for FP32 tiled sweeps); 0: 512 for FP32 tiled
                                   sweeps, else 256 [0]                                    */
     int32_t blocks_per_cu;     /* persistent blocks per compute unit [0 = occupancy]      */
-    int32_t defer_lanes;       /* lanes of a wave that wait before events run; 0: 16 for
-                                  the per-lane walk, 64 for tiled sweeps [0]              */
-    int32_t walk_batch;        /* grid segments a lane gathers per walk step: 1,2,4,8 [4] */
+    int32_t defer_lanes;       /* lanes of a wave that wait before events run (tiled
+                                  sweeps: interactions, escapes, exits and free lanes with
+                                  a record to take); 0: 16 for the per-lane walk, 32 for
+                                  tiled sweeps [0]                                        */
+    int32_t walk_batch;        /* grid segments a lane gathers per walk step of the
+                                  per-lane walk: 1,2,4,8 [4]; tiled sweeps walk 4         */
     int32_t grid_layout;       /* device layout of the transport grid: 0 x-fastest,
                                   1 bricks of 4x4x4 cells [0]; results are identical     */
     int32_t tally_copies;      /* absorption tallies per device: 1, or 8 (one per XCD,
@@ -104,20 +107,26 @@ typedef struct {
                                   tallies with global FP64 atomics; 1: tiled sweeps --
                                   packets grouped by tile of tile_xy^2 x tile_z cells, each
                                   tile walked with density and tally in LDS, tally flushed
-                                  to FP64 once per work item [1]; same packet histories  */
-    int32_t tile_z;            /* tiled sweeps: tile extent in z, 4, 8, 16 or 32, halved
-                                  while the tile does not fit in LDS; 0: 16 in FP32, 32
-                                  in FP64 [0]                                             */
+                                  to FP64 when a workgroup leaves the tile [1]; same packet
+                                  histories.  Tiled sweeps hold at most 1024 cells per
+                                  axis (MCRT_E_UNSUPPORTED beyond)                        */
+    int32_t tile_z;            /* tiled sweeps: tile extent in z, 1..64, halved while the
+                                  tile does not fit in LDS; 0: 20 in FP32, 32 in FP64 [0] */
     int32_t visit_events;      /* tiled sweeps: interactions per tile visit before a
                                   packet waits for the next sweep [256]                   */
-    int32_t tile_xy;           /* tiled sweeps: tile extent in x and y, 16 or 32; 0: 32
-                                  in FP32, 16 in FP64 [0]                                 */
+    int32_t tile_xy;           /* tiled sweeps: tile extent in x and y, a multiple of 4 in
+                                  [4, 64]; 0: 24 in FP32, 16 in FP64 [0].  A tile holds its
+                                  density (transport precision) and its FP64 tally in LDS */
     double mrw_gamma;          /* modified random walk (Sec. 2.2): at the start of a flight,
                                   while the sphere to the nearest wall of the cell holds at
                                   least mrw_gamma Rosseland mean free paths, one diffusion
                                   step to its surface (path length from the first-passage
                                   distribution, tally with the Planck-mean absorption,
                                   re-emission from the cell); 0 = off [0]                 */
+    int64_t sweep_batch;       /* tiled sweeps: packets emitted at a time; whenever fewer
+                                  records than this are in flight after a sweep, the next
+                                  sweep_batch packets are emitted into the pool (refill);
+                                  0: 2^25 [0]                                             */
 } mcrt_run_cfg;
 
 /* Statistics of one pass (a Lucy iteration or the final pass). */
@@ -163,9 +172,15 @@ typedef struct {
 } mcrt_run_stats;
 
 /* ---- lifetime ------------------------------------------------------------ */
+/* A model holds one problem of Sec. 2.1 (grid, density, dust, sources) and its
+ * state on HIP device hip_device.  *out receives the handle (NULL on failure:
+ * MCRT_E_DEVICE for a bad device, MCRT_E_NOMEM).  Plumbing, not a passage of
+ * the paper. */
 mcrt_status mcrt_create(mcrt_model** out, int hip_device);
-void mcrt_destroy(mcrt_model* m);                      /* NULL-safe                   */
-const char* mcrt_last_error(const mcrt_model* m);      /* valid until the next call  */
+/* Frees every device and host allocation of m.  NULL-safe. */
+void mcrt_destroy(mcrt_model* m);
+/* Message of the last failing call on m; valid until the next call on m. */
+const char* mcrt_last_error(const mcrt_model* m);
 /* Run all work of m on this HIP stream (e.g. a PyTorch stream handle); NULL =
  * the library's own stream.  The stream must outlive the model's use of it. */
 mcrt_status mcrt_set_stream(mcrt_model* m, void* hip_stream);
@@ -174,11 +189,18 @@ mcrt_status mcrt_set_stream(mcrt_model* m, void* hip_stream);
 /* Cartesian grid of nx*ny*nz cells over [lo, hi] (Sec. 2.1.2). */
 mcrt_status mcrt_set_grid(mcrt_model* m, int nx, int ny, int nz, const double lo[3],
                           const double hi[3]);
-/* Dust density per cell, g cm^-3, finite and >= 0 (host array, n = ncell). */
+/* Dust density per cell (Sec. 2.1.2: cells of constant density), g cm^-3,
+ * finite and >= 0, host array of n = ncell values in the cell order above,
+ * copied during the call.  MCRT_E_STATE before mcrt_set_grid, MCRT_E_SIZE for
+ * another n, MCRT_E_ARG for a negative or non-finite value. */
 mcrt_status mcrt_set_density(mcrt_model* m, const double* rho, size_t n);
-/* Same from device memory (FP64 if is_fp64 else FP32), read during the call. */
+/* Same from device memory (FP64 if is_fp64 else FP32), read during the call
+ * (Sec. 2.1.2). */
 mcrt_status mcrt_set_density_device(mcrt_model* m, const void* d_rho, int is_fp64, size_t n);
-/* n_nu+1 increasing frequency edges, Hz. */
+/* n_nu+1 strictly increasing frequency edges, Hz (host array, copied).  The
+ * bins carry the source spectra (Sec. 2.1.1) and the dust properties
+ * (Sec. 2.1.3): a packet keeps the index of its bin.  MCRT_E_ARG for edges
+ * that are not positive and increasing. */
 mcrt_status mcrt_set_frequencies(mcrt_model* m, const double* nu_edges, int n_nu);
 /* Mass extinction chi_nu (cm^2/g, >= 0), albedo in [0,1] and HG asymmetry g,
  * |g| < 1, per bin (Sec. 2.1.3).  kappa = chi (1 - albedo). */
@@ -252,10 +274,16 @@ mcrt_status mcrt_get_raytraced_sed(mcrt_model* m, double* sed, size_t n);
  * mcrt_raytrace or mcrt_destroy). */
 mcrt_status mcrt_get_raytraced_cube(mcrt_model* m, double* cube, size_t n);
 mcrt_status mcrt_get_raytraced_cube_device(mcrt_model* m, const double** d_cube);
+/* Fill cfg with the defaults in brackets above. */
 mcrt_status mcrt_run_cfg_default(mcrt_run_cfg* cfg);
+/* Photon counts, iterations and convergence thresholds (Sec. 2.2, 2.4) and
+ * launch options; copied.  MCRT_E_ARG for an out-of-range field. */
 mcrt_status mcrt_set_run(mcrt_model* m, const mcrt_run_cfg* cfg);
-/* Temperatures (K, > 0) that the next iteration re-emits from (warm start). */
+/* Temperatures (K, > 0; n = ncell, host, copied) that the next Lucy iteration
+ * re-emits from (Sec. 2.3-2.4: the emissivity of an iteration follows from the
+ * previous one's absorption rate; here from T, the start of the iteration). */
 mcrt_status mcrt_set_temperature(mcrt_model* m, const double* T, size_t n);
+/* Same from device memory (FP64 if is_fp64 else FP32), read during the call. */
 mcrt_status mcrt_set_temperature_device(mcrt_model* m, const void* d_T, int is_fp64, size_t n);
 
 /* ---- running ------------------------------------------------------------- */
@@ -264,23 +292,44 @@ mcrt_status mcrt_set_temperature_device(mcrt_model* m, const void* d_T, int is_f
 mcrt_status mcrt_iterate(mcrt_model* m, mcrt_iter_stats* st);
 /* Final binning pass at fixed temperatures (Sec. 2.6.1); Ȧ is not updated. */
 mcrt_status mcrt_final_pass(mcrt_model* m, mcrt_iter_stats* st);
-/* Iterations until n_iter or the stopping criterion, then the final pass. */
+/* Lucy iterations (Sec. 2.3) until n_iter or the stopping criterion of
+ * Sec. 2.4 (Eqs. 4-6, or max dT/T), then the final binning pass (Sec. 2.6.1). */
 mcrt_status mcrt_run(mcrt_model* m, mcrt_run_stats* st);
 
 /* ---- results ------------------------------------------------------------- */
+/* Specific energy absorption rate of every cell after the last Lucy
+ * iteration, Eq. 2: Adot = eps sum(l kappa) / (dt V), dt = 1 s, erg/s/g;
+ * adot_sigma (may be NULL) its Monte-Carlo standard error from the sum of
+ * squared path-length weights (needs want_noise, else zeros).  n = ncell. */
 mcrt_status mcrt_get_specific_energy(mcrt_model* m, double* adot, double* adot_sigma, size_t n);
+/* LTE temperature of every cell, K: the root of 4 pi sum_k kappa_k B_k(T) = Adot
+ * (Eq. 3 over the model's bins); dust cells with Adot = 0 hold 1 K.  n = ncell. */
 mcrt_status mcrt_get_temperature(mcrt_model* m, double* T, size_t n);
 /* Device pointer to the FP64 temperature field (valid until the next call). */
 mcrt_status mcrt_get_temperature_device(mcrt_model* m, const double** d_T);
-/* SED [n_incl][n_nu]: sum of energies, sum of squares, packet counts. */
+/* Binned SED of the last binning pass (Sec. 2.6.1; uncertainties from the
+ * sums of squares, Sec. 2.7.1) [n_incl][n_nu]: sum of escaped energies (erg,
+ * dt = 1 s), sum of their squares, packet counts; n = n_incl*n_nu. */
 mcrt_status mcrt_get_sed(mcrt_model* m, double* sum, double* sum2, int64_t* count, size_t n);
-/* Images [n_img_nu][n_incl][npix][npix]: sum of energies and of squares. */
+/* Binned images (Sec. 2.6.1) [n_img_nu][n_incl][npix][npix]: the escape point
+ * projected on e_x = norm(z x d), e_y = d x e_x (row index from Y, column from
+ * X); sum of energies and of squares. */
 mcrt_status mcrt_get_images(mcrt_model* m, double* sum, double* sum2, size_t n);
-/* Event log of the last pass: ev[p*cap + i], counts[p] events of packet p
- * (may exceed cap: later events were dropped).  Returns MCRT_OK. */
+/* Event log of the last pass (the packet history of Sec. 2.2: emission,
+ * scatterings, absorptions, escape): ev[p*cap + i], counts[p] events of
+ * packet p (may exceed cap: later events were dropped).  Returns MCRT_OK. */
 mcrt_status mcrt_get_event_log(mcrt_model* m, mcrt_event* ev, size_t cap_total, int32_t* counts,
                                size_t n_counts);
-/* Number of compute units of the model's device. */
+/* The direction update of a scattering (Sec. 2.2 with the Henyey-Greenstein
+ * phase function): for i < n, out[3i..3i+2] = the unit vector at angle acos(mu[i])
+ * from the unit vector d[3i..3i+2], azimuth phi[i] about it, computed on m's
+ * device by the device function every transport kernel uses, in precision
+ * MCRT_FP64 or MCRT_FP32_TRANSPORT (inputs rounded to FP32 first).  Host
+ * arrays, copied; MCRT_E_ARG for mu outside [-1, 1] or non-finite values. */
+mcrt_status mcrt_scatter_directions(mcrt_model* m, int precision, const double* d, const double* mu,
+                                    const double* phi, double* out, int n);
+/* Number of compute units and the wavefront width of the model's device
+ * (plumbing, not a passage of the paper). */
 mcrt_status mcrt_device_info(mcrt_model* m, int* n_cu, int* wave_size);
 
 /* ---- batching: many independent models in one launch ---------------------

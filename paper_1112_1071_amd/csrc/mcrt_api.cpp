@@ -47,15 +47,15 @@ hipError_t launch_fill_u64(int64_t n, unsigned long long* p, unsigned long long 
                            hipStream_t st);
 size_t sweep_record_bytes(int fp32);
 template <typename R>
-hipError_t launch_sweep_emit(const TransportParams<R>& P, const SweepParams& S, uint64_t first,
-                             uint64_t count, unsigned base, int blocks, hipStream_t st);
-template <typename R>
-hipError_t launch_sweep(const TransportParams<R>& P, const SweepParams& S, int K, int blocks,
-                        int threads, size_t lds, hipStream_t st);
-template <typename R> int sweep_max_blocks_per_cu(int K, int threads, size_t lds);
-hipError_t launch_tile_sort(const SweepParams& S, unsigned* order, unsigned* tile_off,
-                            unsigned* item_off, unsigned* cursor, int blocks, hipStream_t st);
+hipError_t launch_sweep_step(const TransportParams<R>& P, const SweepParams& S, int b, bool full,
+                             int emit_blocks, int group_blocks, int blocks, int threads, size_t lds,
+                             hipStream_t st);
+template <typename R> hipError_t sweep_prepare(bool noise, bool full, size_t lds);
+template <typename R> int sweep_max_blocks_per_cu(bool noise, bool full, int threads, size_t lds);
+int sweep_emit_step();
 hipError_t launch_fill_u32(unsigned* p, int n, unsigned v, hipStream_t st);
+hipError_t launch_rotate(int fp32, const double* d, const double* mu, const double* phi, double* out,
+                         int n, hipStream_t st);
 hipError_t launch_raytrace(const RayParams& R, hipStream_t st);
 hipError_t launch_pda_coefficients(const PdaParams& P, int select, hipStream_t st);
 hipError_t launch_pda_connect(const PdaParams& P, hipStream_t st);
@@ -167,10 +167,17 @@ struct mcrt_model {
     DBuf<unsigned long long> misc;  // pool, counters[C_COUNT], stats[8], sel[3], scratch
     DBuf<double> energies;
     DBuf<unsigned int> hist;
-    // tiled sweeps: packet records (two buffers), record tiles, tile counts and
-    // offsets, work-item offsets, scatter cursors, [item_next, out_count]
-    DBuf<unsigned char> sw_a, sw_b;
-    DBuf<unsigned> sw_tile, sw_counts, sw_tile_off, sw_item_off, sw_cursor, sw_ctr, sw_order;
+    // tiled sweeps: packet records (two buffers), registered entries (two
+    // lists), entries grouped by tile, per-tile counts, offsets and cursors,
+    // control words; pinned host copies of the termination flag and events
+    // for the lagged check of the host loop
+    DBuf<uint4> sw_rec[2];
+    DBuf<unsigned> sw_ent_tile[2];
+    DBuf<uint2> sw_ent[2], sw_sent;
+    DBuf<unsigned> sw_tile_rec, sw_tile_ent, sw_ent_off, sw_item_off, sw_cursor;
+    DBuf<SweepCtl> sw_ctl;
+    unsigned* sw_host = nullptr;   // [kSweepLag] done flags
+    hipEvent_t sw_ev[4] = {nullptr, nullptr, nullptr, nullptr};
     size_t lds_max = 65536 - 1024;  // dynamic LDS a transport kernel may take
     int64_t ev_packets = 0;
     int ev_cap = 0;
@@ -611,106 +618,140 @@ int persistent_blocks(const mcrt_model* m, int bpc, int64_t np, int threads) {
     return (int)(blocks < 1 ? 1 : blocks);
 }
 
-// Tiled sweeps (transport_mode 1): emission writes packets as records with
-// their tiles, then sort-by-tile and sweep alternate until no record is left.
-// The pool is refilled: whenever fewer than kSweepBatch records are in flight
-// after a sweep, the next kSweepBatch packets are emitted into the same output,
-// so only the end of the pass drains (one tail of short sweeps, not one per
-// batch).  The host reads the record count after each sweep.
-constexpr int64_t kSweepBatch = 1ll << 25;  // packets emitted at once
+// Tiled sweeps (transport_mode 1).  Each step: the refill decision and the
+// emission (device side), the scan of the per-tile counts, the grouping of
+// the entries by tile, and one sweep, which writes the records still in
+// flight into the other buffer.  The pool is refilled whenever fewer than
+// `batch` records remain after a sweep, so only the end of the pass drains.
+// The host never waits for a step: it copies each step's termination flag
+// into pinned memory and checks the flag of the step kSweepLag-1 steps back,
+// so that at most that many empty steps run after the last record.
+constexpr int64_t kSweepBatch = 1ll << 25;  // default packets emitted at once
 constexpr int64_t kMaxSweeps = 1ll << 20;    // every visit advances a packet; this is a backstop
+constexpr int kSweepLag = 4;
+constexpr int64_t kChunkSlots = 64;     // record slots of a chunk (as in the sweep kernels)
 
 template <typename R>
 mcrt_status run_sweeps(mcrt_model* m, TransportParams<R>& P, int64_t np, int64_t* n_sweeps,
                        int64_t* n_visits) {
     hipStream_t s = m->stream;
     constexpr bool f32 = std::is_same<R, float>::value;
+    for (int a = 0; a < 3; ++a)
+        if (m->n[a] > 1024)
+            return fail(m, MCRT_E_UNSUPPORTED,
+                        "tiled sweeps hold at most 1024 cells per axis; use transport_mode 0");
     SweepParams S{};
-    // tile shape and group size, 0 = by precision: FP32 32x32x16 tiles (128 KB
-    // of LDS) walked by one group of 512 threads per compute unit; FP64
-    // 16x16x32 tiles and 256 threads (its register budget)
-    S.txy = m->cfg.tile_xy == 0 ? (f32 ? 32 : 16) : m->cfg.tile_xy;
-    S.tz = m->cfg.tile_z == 0 ? (f32 ? 16 : 32) : m->cfg.tile_z;
-    // LDS: tile density and tally (and sum of squares), bin opacities, then the
-    // staged tables; a tile too deep for LDS is halved in z
+    // tile shape and group size, 0 = by precision: FP32 24x24x20 tiles (FP32
+    // density and FP64 tally, 135 KB of LDS) walked by one group of 512
+    // threads per compute unit; FP64 16x16x32 tiles and 256 threads (its
+    // register budget)
+    S.txy = m->cfg.tile_xy == 0 ? (f32 ? 24 : 16) : m->cfg.tile_xy;
+    S.tz = m->cfg.tile_z == 0 ? (f32 ? 20 : 32) : m->cfg.tile_z;
+    const bool noise = P.acc2 != nullptr;
+    // logging, binning, peeling and the modified random walk need the full
+    // event code; a plain Lucy iteration runs the lean kernels
+    const bool full = P.binning || P.mrw_gamma > 0.0 || P.ev_packets > 0;
+    // LDS: tile density and tally (and sum of squares), the bins' chi, kappa,
+    // albedo and g, and the staged tables; a tile too deep for LDS is halved in z
+    const size_t tab_lds = (size_t)(m->src.size() + (kRows + m->src.size()) * m->ngroup) * sizeof(R);
     auto tile_bytes = [&](int tz) {
-        return (size_t)S.txy * S.txy * tz * (2 * sizeof(R) + (P.acc2 ? sizeof(double) : 0)) +
-               2 * m->kap.size() * sizeof(R);
+        return (size_t)S.txy * S.txy * tz * (sizeof(R) + (noise ? 2 : 1) * sizeof(double)) +
+               4 * m->kap.size() * sizeof(R) + tab_lds;
     };
-    while (tile_bytes(S.tz) > m->lds_max && S.tz > 4) S.tz /= 2;
+    while (tile_bytes(S.tz) > m->lds_max && S.tz > 1) S.tz /= 2;
     S.ntx = (m->n[0] + S.txy - 1) / S.txy;
     S.nty = (m->n[1] + S.txy - 1) / S.txy;
     S.ntz = (m->n[2] + S.tz - 1) / S.tz;
     S.ntiles = S.ntx * S.nty * S.ntz;
     S.visit_events = m->cfg.visit_events > 0 ? m->cfg.visit_events : 256;
-    const int64_t batch = np < kSweepBatch ? np : kSweepBatch;
-    const int64_t cap = np < 2 * batch ? np : 2 * batch;  // records in flight: < batch + batch
-    const size_t rb = sweep_record_bytes(f32 ? 1 : 0);
-    HIPCHK(m->sw_a.ensure((size_t)cap * rb));
-    HIPCHK(m->sw_b.ensure((size_t)cap * rb));
-    HIPCHK(m->sw_tile.ensure((size_t)cap));
-    HIPCHK(m->sw_order.ensure((size_t)cap));
-    HIPCHK(m->sw_counts.ensure((size_t)S.ntiles));
-    HIPCHK(m->sw_tile_off.ensure((size_t)S.ntiles + 1));
+    const size_t lds = tile_bytes(S.tz);
+    if (lds > m->lds_max)
+        return fail(m, MCRT_E_UNSUPPORTED, "tile and tables do not fit in LDS; use smaller tiles or fewer sources");
+    const int threads = m->cfg.block_size > 0 ? m->cfg.block_size : (f32 ? 512 : 256);
+    // a work item: entries of one tile, about 16 records per thread when full
+    S.item_ent = threads * 16 / (int)64 > 0 ? threads * 16 / 64 : 1;
+    // lanes of a wave that wait (events, escapes, exits, free lanes with a
+    // record to take) before the wave handles them
+    S.service = m->cfg.defer_lanes > 0 ? m->cfg.defer_lanes : 32;
+    const int64_t batch = m->cfg.sweep_batch > 0 ? std::min<int64_t>(m->cfg.sweep_batch, np)
+                                                 : std::min<int64_t>(kSweepBatch, np);
+    S.batch = (unsigned long long)batch;
+    S.n_packets = (unsigned long long)np;
+    HIPCHK(sweep_prepare<R>(noise, full, lds));
+    const int bpc = m->cfg.blocks_per_cu > 0 ? m->cfg.blocks_per_cu
+                                             : sweep_max_blocks_per_cu<R>(noise, full, threads, lds);
+    const int blocks = m->n_cu * bpc;
+    // record slots per buffer: the records in flight (< 2 batch after a refill)
+    // plus the slots left empty in chunks that a wave registers partly filled:
+    // at most 7 chunks per wave and tile change, a group changes tile at most
+    // once per work item, and a sweep has about (records / 64) / item_ent work
+    // items (full chunks) plus one per tile.  A pass that still runs out of
+    // slots stops with MCRT_E_NOMEM.
+    // Each wave also holds up to one run of 1024 slots and 32 entry slots.
+    const int64_t waves = (int64_t)blocks * (threads / 64);
+    const int64_t items = 2 * batch / ((int64_t)S.item_ent * kChunkSlots) + S.ntiles;
+    const int64_t slack = kChunkSlots * 7 * (threads / 64) * (items + blocks);
+    int64_t cap = 2 * batch + std::max<int64_t>(2 * batch / 3, slack) + 1024 * waves;
+    cap = (cap + 63) / 64 * 64;
+    if (cap > (int64_t)0xffff0000ll) return fail(m, MCRT_E_UNSUPPORTED, "sweep_batch too large for the record buffers");
+    S.cap = (unsigned)cap;
+    S.max_ent = (unsigned)std::min<int64_t>(cap / 4 + 65536 + 32 * waves, 0xffff0000ll);
+    const size_t rq = sweep_record_bytes(f32 ? 1 : 0) / 16;
+    for (int b = 0; b < 2; ++b) {
+        HIPCHK(m->sw_rec[b].ensure((size_t)cap * rq));
+        HIPCHK(m->sw_ent_tile[b].ensure(S.max_ent));
+        HIPCHK(m->sw_ent[b].ensure(S.max_ent));
+        S.recs[b] = m->sw_rec[b].p;
+        S.ent_tile[b] = m->sw_ent_tile[b].p;
+        S.ent[b] = m->sw_ent[b].p;
+    }
+    HIPCHK(m->sw_sent.ensure(S.max_ent));
+    HIPCHK(m->sw_tile_rec.ensure((size_t)S.ntiles));
+    HIPCHK(m->sw_tile_ent.ensure((size_t)S.ntiles));
+    HIPCHK(m->sw_ent_off.ensure((size_t)S.ntiles + 1));
     HIPCHK(m->sw_item_off.ensure((size_t)S.ntiles + 1));
     HIPCHK(m->sw_cursor.ensure((size_t)S.ntiles));
-    HIPCHK(m->sw_ctr.ensure(2));
-    HIPCHK(launch_fill_u32(m->sw_counts.p, S.ntiles, 0u, s));
-    HIPCHK(launch_fill_u32(m->sw_ctr.p, 2, 0u, s));
-    S.item_next = m->sw_ctr.p;
-    S.out_count = m->sw_ctr.p + 1;
-    S.out_tile = m->sw_tile.p;
-    S.counts = m->sw_counts.p;
-    S.order = m->sw_order.p;
-    S.tile_off = m->sw_tile_off.p;
+    HIPCHK(m->sw_ctl.ensure(1));
+    if (!m->sw_host) HIPCHK(hipHostMalloc((void**)&m->sw_host, kSweepLag * sizeof(unsigned), hipHostMallocDefault));
+    for (int i = 0; i < kSweepLag; ++i)
+        if (!m->sw_ev[i]) HIPCHK(hipEventCreateWithFlags(&m->sw_ev[i], hipEventDisableTiming));
+    S.sent = m->sw_sent.p;
+    S.tile_rec = m->sw_tile_rec.p;
+    S.tile_ent = m->sw_tile_ent.p;
+    S.ent_off = m->sw_ent_off.p;
     S.item_off = m->sw_item_off.p;
-    const size_t tile_lds = tile_bytes(S.tz);
-    const size_t tab_lds = (size_t)(m->src.size() + (kRows + m->src.size()) * m->ngroup) * sizeof(R);
-    if (tile_lds > m->lds_max) return fail(m, MCRT_E_UNSUPPORTED, "tile does not fit in LDS; use smaller tiles");
-    P.lds_tables = tile_lds + tab_lds <= m->lds_max ? 1 : 0;
-    const size_t lds = tile_lds + (P.lds_tables ? tab_lds : 0);
-    const int K = m->cfg.walk_batch == 1 || m->cfg.walk_batch == 2 ? m->cfg.walk_batch : 4;
-    const int threads = m->cfg.block_size > 0 ? m->cfg.block_size : (f32 ? 512 : 256);
-    // records per work item: large enough that a group walks a tile's visits
-    // between two loads of its density (8192 at 512 threads)
-    S.item = (unsigned)threads * 16u;
-    const int bpc =
-        m->cfg.blocks_per_cu > 0 ? m->cfg.blocks_per_cu : sweep_max_blocks_per_cu<R>(K, threads, lds);
-    const int blocks = m->n_cu * bpc;
+    S.cursor = m->sw_cursor.p;
+    S.ctl = m->sw_ctl.p;
+    HIPCHK(launch_fill_u32(S.tile_rec, S.ntiles, 0u, s));
+    HIPCHK(launch_fill_u32(S.tile_ent, S.ntiles, 0u, s));
+    HIPCHK(launch_fill_u32(reinterpret_cast<unsigned*>(S.ctl), (int)(sizeof(SweepCtl) / 4), 0u, s));
+    const int64_t eb = (batch + sweep_emit_step() - 1) / sweep_emit_step();
+    const int emit_blocks = (int)std::min<int64_t>(eb, (int64_t)m->n_cu * 4);
+    const int group_blocks = m->n_cu * 4;
     P.packet_base = 0;
-    int64_t sweeps = 0, visits = 0;
-    unsigned char* bufs[2] = {m->sw_a.p, m->sw_b.p};
-    int w = 0;  // buffer the next records are written to
-    S.out = bufs[w];
-    int64_t emitted = 0;
-    for (;;) {
-        unsigned nout = 0;
-        HIPCHK(hipMemcpyAsync(&nout, S.out_count, sizeof nout, hipMemcpyDeviceToHost, s));
-        HIPCHK(hipStreamSynchronize(s));
-        if ((int64_t)nout < batch && emitted < np) {
-            // refill: appended after the records the last sweep wrote, counted per tile
-            const int64_t cnt = np - emitted < batch ? np - emitted : batch;
-            const int64_t eb = (cnt + 255) / 256;
-            HIPCHK(launch_sweep_emit<R>(P, S, (uint64_t)emitted, (uint64_t)cnt, nout,
-                                        (int)(eb < (int64_t)m->n_cu * 8 ? eb : (int64_t)m->n_cu * 8), s));
-            HIPCHK(launch_fill_u32(S.out_count, 1, nout + (unsigned)cnt, s));
-            emitted += cnt;
-            continue;
+    int b = 0;  // the buffer the step's refill and sweep read
+    bool done = false;
+    for (int64_t step = 0; !done; ++step) {
+        if (step > kMaxSweeps) return fail(m, MCRT_E_DEVICE, "tiled sweeps did not finish");
+        HIPCHK(launch_sweep_step<R>(P, S, b, full, emit_blocks, group_blocks, blocks, threads, lds, s));
+        const int slot = (int)(step % kSweepLag);
+        HIPCHK(hipMemcpyAsync(m->sw_host + slot, &S.ctl->done, sizeof(unsigned), hipMemcpyDeviceToHost, s));
+        HIPCHK(hipEventRecord(m->sw_ev[slot], s));
+        b ^= 1;
+        if (step >= kSweepLag - 1) {
+            const int k = (int)((step - (kSweepLag - 1)) % kSweepLag);
+            HIPCHK(hipEventSynchronize(m->sw_ev[k]));
+            done = m->sw_host[k] != 0u;
         }
-        if (nout == 0) break;
-        if (++sweeps > kMaxSweeps) return fail(m, MCRT_E_DEVICE, "tiled sweeps did not finish");
-        visits += nout;
-        const int64_t sb = ((int64_t)nout + 4095) / 4096;  // one chunk of 4096 records per block
-        HIPCHK(launch_tile_sort(S, m->sw_order.p, m->sw_tile_off.p, m->sw_item_off.p, m->sw_cursor.p,
-                                (int)(sb < (int64_t)m->n_cu * 8 ? sb : (int64_t)m->n_cu * 8), s));
-        HIPCHK(launch_fill_u32(S.out_count, 1, 0u, s));
-        S.in = bufs[w];
-        w ^= 1;
-        S.out = bufs[w];
-        HIPCHK(launch_sweep<R>(P, S, K, blocks, threads, lds, s));
     }
-    *n_sweeps = sweeps;
-    *n_visits = visits;
+    SweepCtl c;
+    HIPCHK(hipMemcpyAsync(&c, S.ctl, sizeof c, hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    if (c.overflow & 2u) return fail(m, MCRT_E_DEVICE, "tiled sweeps: a record was not in its tile");
+    if (c.overflow)
+        return fail(m, MCRT_E_NOMEM, "tiled sweep record buffers overflowed; lower sweep_batch");
+    *n_sweeps = (int64_t)c.sweeps;
+    *n_visits = (int64_t)c.visits;
     return MCRT_OK;
 }
 
@@ -978,9 +1019,16 @@ void mcrt_destroy(mcrt_model* m) {
     m->mrw_tab.release();
     m->pda_flag.release(); m->pda_vec.release(); m->pda_red.release(); m->pda_count.release();
     m->misc.release(); m->energies.release(); m->hist.release();
-    m->sw_a.release(); m->sw_b.release(); m->sw_tile.release(); m->sw_counts.release();
-    m->sw_tile_off.release(); m->sw_item_off.release(); m->sw_cursor.release(); m->sw_ctr.release();
-    m->sw_order.release();
+    for (int b = 0; b < 2; ++b) {
+        m->sw_rec[b].release();
+        m->sw_ent_tile[b].release();
+        m->sw_ent[b].release();
+    }
+    m->sw_sent.release(); m->sw_tile_rec.release(); m->sw_tile_ent.release(); m->sw_ent_off.release();
+    m->sw_item_off.release(); m->sw_cursor.release(); m->sw_ctl.release();
+    if (m->sw_host) hipHostFree(m->sw_host);
+    for (int i = 0; i < 4; ++i)
+        if (m->sw_ev[i]) hipEventDestroy(m->sw_ev[i]);
     if (m->own_stream && m->stream) hipStreamDestroy(m->stream);
     delete m;
 }
@@ -1440,13 +1488,13 @@ mcrt_status mcrt_set_run(mcrt_model* m, const mcrt_run_cfg* c) {
     if (c->blocks_per_cu < 0) return fail(m, MCRT_E_ARG, "blocks_per_cu must be >= 0");
     if (c->transport_mode != 0 && c->transport_mode != 1)
         return fail(m, MCRT_E_ARG, "transport_mode must be 0 or 1");
-    if (c->transport_mode == 1 && c->tile_z != 0 && c->tile_z != 4 && c->tile_z != 8 && c->tile_z != 16 &&
-        c->tile_z != 32)
-        return fail(m, MCRT_E_ARG, "tile_z must be 4, 8, 16 or 32");
+    if (c->tile_z < 0 || c->tile_z > 64) return fail(m, MCRT_E_ARG, "tile_z must be in [1, 64] (0: default)");
     if (c->visit_events < 0) return fail(m, MCRT_E_ARG, "visit_events must be >= 0");
-    if (c->tile_xy != 0 && c->tile_xy != 16 && c->tile_xy != 32)
-        return fail(m, MCRT_E_ARG, "tile_xy must be 16 or 32");
+    if (c->tile_xy != 0 && (c->tile_xy < 4 || c->tile_xy > 64 || c->tile_xy % 4 != 0))
+        return fail(m, MCRT_E_ARG, "tile_xy must be a multiple of 4 in [4, 64] (0: default)");
     if (!(c->mrw_gamma >= 0.0) || !isfinite(c->mrw_gamma)) return fail(m, MCRT_E_ARG, "mrw_gamma must be >= 0");
+    if (c->sweep_batch < 0 || c->sweep_batch > ((int64_t)1 << 30))
+        return fail(m, MCRT_E_ARG, "sweep_batch must be in [0, 2^30]");
     const bool reset = !m->have_run || c->t_init != m->cfg.t_init;
     m->cfg = *c;
     if (m->cfg.mrw_gamma > 0.0 && !m->mrw_tab_built) m->tables_dirty = true;
@@ -1635,6 +1683,37 @@ mcrt_status mcrt_get_event_log(mcrt_model* m, mcrt_event* ev, size_t cap_total, 
     HIPCHK(hipMemcpyAsync(ev, m->evlog.p, need * sizeof(mcrt_event), hipMemcpyDeviceToHost, m->stream));
     HIPCHK(hipMemcpyAsync(counts, m->evcount.p, n_counts * sizeof(int32_t), hipMemcpyDeviceToHost, m->stream));
     HIPCHK(hipStreamSynchronize(m->stream));
+    return MCRT_OK;
+}
+
+mcrt_status mcrt_scatter_directions(mcrt_model* m, int precision, const double* d, const double* mu,
+                                    const double* phi, double* out, int n) {
+    if (!m) return MCRT_E_ARG;
+    if (precision != MCRT_FP64 && precision != MCRT_FP32_TRANSPORT)
+        return fail(m, MCRT_E_ARG, "unknown precision");
+    if (n < 0 || (n > 0 && (!d || !mu || !phi || !out))) return fail(m, MCRT_E_ARG, "bad direction arrays");
+    if (n == 0) return MCRT_OK;
+    for (int i = 0; i < n; ++i)
+        if (!(mu[i] >= -1.0 && mu[i] <= 1.0) || !isfinite(phi[i]) || !isfinite(d[3 * i]) ||
+            !isfinite(d[3 * i + 1]) || !isfinite(d[3 * i + 2]))
+            return fail(m, MCRT_E_ARG, "mu must lie in [-1,1]; directions and phi finite");
+    hipStream_t s = m->stream;
+    struct Guard {
+        DBuf<double> b;
+        ~Guard() { b.release(); }
+    } g;
+    DBuf<double>& buf = g.b;
+    HIPCHK(buf.ensure((size_t)9 * n));
+    double* dd = buf.p;
+    double* dm = dd + 3 * (size_t)n;
+    double* dp = dm + n;
+    double* dout = dp + n;
+    HIPCHK(hipMemcpyAsync(dd, d, 3 * sizeof(double) * n, hipMemcpyHostToDevice, s));
+    HIPCHK(hipMemcpyAsync(dm, mu, sizeof(double) * n, hipMemcpyHostToDevice, s));
+    HIPCHK(hipMemcpyAsync(dp, phi, sizeof(double) * n, hipMemcpyHostToDevice, s));
+    HIPCHK(launch_rotate(precision == MCRT_FP32_TRANSPORT ? 1 : 0, dd, dm, dp, dout, n, s));
+    HIPCHK(hipMemcpyAsync(out, dout, 3 * sizeof(double) * n, hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
     return MCRT_OK;
 }
 

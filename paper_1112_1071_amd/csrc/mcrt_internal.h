@@ -150,22 +150,49 @@ struct PdaParams {
     unsigned char* valid;
 };
 
-// Tiled sweeps: the tiling and the buffers of one sweep.
+// Tiled sweeps: control words of a pass, in device memory.  Buffer b (0, 1)
+// holds packet records; a sweep reads one buffer and writes the other.
+struct SweepCtl {
+    unsigned rec_alloc[2];        // record slots handed out in buffer b
+    unsigned n_ent[2];            // entry slots handed out for buffer b
+    unsigned item_next;           // work items taken in the current sweep
+    unsigned n_items;             // work items of the current sweep
+    unsigned overflow;            // a buffer or the entry list ran out of room
+    unsigned done;                // no record left and every packet emitted
+    unsigned sweeps;              // sweeps that walked records
+    unsigned pad;
+    unsigned long long emitted;   // packets emitted so far in this pass
+    unsigned long long emit_first, emit_count;  // the refill of the current step
+    unsigned long long visits;    // records walked (tile visits) so far
+};
+
+// Tiled sweeps: the tiling and the buffers of a pass.  A record's state is
+// five (FP32) or nine (FP64) 16-byte quads; quad q of record i is at
+// recs[b][q * cap + i].  Records are written in chunks of 64 slots per
+// destination tile; every chunk (and every block of emitted packets of one
+// tile) is registered as an entry (first record, count) of its tile, and the
+// entries, grouped by tile, are the next sweep's work.
 struct SweepParams {
     int txy;                    // tile extent in x and y (cells): 16 or 32
     int tz;                     // tile extent in z (cells)
     int ntx, nty, ntz, ntiles;  // tiles per axis, total
     int visit_events;           // interactions per visit before a packet yields
-    unsigned item;              // records per work item
-    const void* in;             // records of this sweep (in the order they were written)
-    const unsigned* order;      // record indices grouped by tile
-    const unsigned* tile_off;   // [ntiles+1] first entry of each tile in order
-    const unsigned* item_off;   // [ntiles+1] first work item of each tile
-    unsigned* item_next;        // work items handed out
-    void* out;                  // records written in this sweep
-    unsigned* out_tile;         // tile of each written record
-    unsigned* out_count;
-    unsigned* counts;           // [ntiles] records written per tile (for the next sort)
+    int item_ent;               // entries per work item
+    int service;                // lanes of a wave that wait before its events and exits run
+    unsigned cap;               // record slots per buffer
+    unsigned max_ent;           // entries per buffer
+    uint4* recs[2];
+    unsigned* ent_tile[2];      // tile of each registered entry
+    uint2* ent[2];              // (first record, count) of each registered entry
+    uint2* sent;                // the entries of the buffer being read, grouped by tile
+    unsigned* tile_rec;         // [ntiles] records registered per tile
+    unsigned* tile_ent;         // [ntiles] entries registered per tile
+    unsigned* ent_off;          // [ntiles+1] first grouped entry of each tile
+    unsigned* item_off;         // [ntiles+1] first work item of each tile
+    unsigned* cursor;           // [ntiles] grouping cursors
+    SweepCtl* ctl;
+    unsigned long long n_packets;  // packets of the pass
+    unsigned long long batch;      // refill batch
 };
 
 // Cell-update parameters (always FP64).

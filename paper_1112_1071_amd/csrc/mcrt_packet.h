@@ -220,27 +220,49 @@ template <typename R> __device__ __forceinline__ R hg_mu(R g, R u) {
     return fmin((R)1, fmax((R)-1, mu));
 }
 
-// new direction at angle acos(mu) from d, azimuth phi about d; renormalised
-template <typename R> __device__ __forceinline__ void rotate(Packet<R>& s, R mu, R phi) {
+// New direction at angle acos(mu) from d, azimuth phi about d; renormalised.
+// q = |d_perp| = sin(theta_d).  In FP64 q = sqrt(1 - d_z^2) with the pole
+// branch for |d_z| > 1 - 1e-10 (the oracle's arithmetic).  In FP32 that test
+// cannot work (1 - 1e-10 rounds to 1, and a direction within ~2.4e-4 rad of
+// the pole stores d_z = +-1 exactly, giving q = 0), so q is taken from the
+// transverse components themselves, sqrt(d_x^2 + d_y^2), which stays accurate
+// down to the pole; only d_x = d_y = 0 takes the pole branch.  Packet
+// histories must not depend on which kernel walks a packet, so each FP32 sum
+// of products here is written as one explicit fused multiply-add.
+template <typename R>
+__device__ __forceinline__ void rotate_dir(R& d0, R& d1, R& d2, R mu, R phi) {
     const R st = sqrt(fmax((R)0, (R)1 - mu * mu));
     R sp, cp;
     sin_cos(phi, &sp, &cp);
+    R q;
+    bool pole;
+    if constexpr (sizeof(R) == 8) {
+        pole = fabs(d2) > (R)1 - (R)1e-10;
+        q = pole ? (R)1 : sqrt((R)1 - d2 * d2);
+    } else {
+        // one explicit fused multiply-add, so that every kernel rounds alike
+        q = sqrt(fmaf(d0, d0, d1 * d1));
+        pole = !(q > (R)1e-30);
+    }
     R o0, o1, o2;
-    if (fabs(s.d2) > (R)1 - (R)1e-10) {
-        const R sgn = s.d2 > (R)0 ? (R)1 : (R)-1;
+    if (pole) {
+        const R sgn = d2 > (R)0 ? (R)1 : (R)-1;
         o0 = st * cp;
         o1 = st * sp;
         o2 = sgn * mu;
     } else {
-        const R q = sqrt((R)1 - s.d2 * s.d2);
-        o0 = st * (s.d0 * s.d2 * cp - s.d1 * sp) / q + s.d0 * mu;
-        o1 = st * (s.d1 * s.d2 * cp + s.d0 * sp) / q + s.d1 * mu;
-        o2 = -st * cp * q + s.d2 * mu;
+        o0 = st * (d0 * d2 * cp - d1 * sp) / q + d0 * mu;
+        o1 = st * (d1 * d2 * cp + d0 * sp) / q + d1 * mu;
+        o2 = -st * cp * q + d2 * mu;
     }
     const R nrm = sqrt(o0 * o0 + o1 * o1 + o2 * o2);
-    s.d0 = o0 / nrm;
-    s.d1 = o1 / nrm;
-    s.d2 = o2 / nrm;
+    d0 = o0 / nrm;
+    d1 = o1 / nrm;
+    d2 = o2 / nrm;
+}
+
+template <typename R> __device__ __forceinline__ void rotate(Packet<R>& s, R mu, R phi) {
+    rotate_dir(s.d0, s.d1, s.d2, mu, phi);
 }
 
 template <typename R>
@@ -263,12 +285,22 @@ __device__ __forceinline__ void log_event(Packet<R>& s, const TransportParams<R>
     P.evcount[s.id] = (int32_t)(i + 1);
 }
 
-// Tables the event code searches: from LDS when they were staged there.
+// Tables the event code reads (from LDS where a kernel staged them): the
+// luminosity CDF, the coarse indices of the emission and source-spectrum CDFs,
+// and the dust properties per bin.
 template <typename R> struct Tables {
     const R* lcdf;
     const R* ecoarse;
     const R* scoarse;
+    const R* chi;
+    const R* kap;
+    const R* alb;
+    const R* g;
 };
+
+template <typename R> __device__ __forceinline__ Tables<R> global_tables(const TransportParams<R>& P) {
+    return Tables<R>{P.lcdf, P.ecoarse, P.scoarse, P.chi, P.kap, P.alb, P.g};
+}
 
 // Optical depth in bin k from the point (cell c, in-cell offsets f) to the
 // grid boundary along the unit vector o: the walk of a flight, without
@@ -380,13 +412,14 @@ __device__ __forceinline__ GlobalDeposit<BRICK> global_deposit(const TransportPa
     return GlobalDeposit<BRICK>{acc, P.acc2, {P.n[0], P.n[1], P.n[2]}, P.bx, P.bxy};
 }
 
+// The tile's LDS tally: FP64 sums of the (transport-precision) weights.
 template <typename R> struct TileDeposit {
-    R* acc;
+    double* acc;
     double* acc2;
     int o0, o1, o2, txy;
     __device__ void operator()(int c0, int c1, int c2, R w) const {
         const int jl = (c0 - o0) + txy * ((c1 - o1) + txy * (c2 - o2));
-        atomicAdd(acc + jl, w);
+        atomicAdd(acc + jl, (double)w);
         if (acc2) atomicAdd(acc2 + jl, (double)w * (double)w);
     }
 };
@@ -503,24 +536,31 @@ __device__ bool mrw_steps(Packet<R>& s, Stream<R>& rs, const TransportParams<R>&
         f2 = (R)fmin(1.0, fmax(0.0, (g2 + R0 * mu) / P.dx[2]));
         s.k = reemission_bin(P, tb, j, u_mix, u_nu);
         isotropic(s, u_mu2, u_phi2);
-        s.chi = P.chi[s.k];
-        s.kap = P.kap[s.k];
+        s.chi = tb.chi[s.k];
+        s.kap = tb.kap[s.k];
         ++cnt[C_MRW];
         log_event(s, P, MCRT_EV_MRW, -1);
         if (P.binning && P.n_peel > 0) peel(s, P, f0, f1, f2, 1, false, 0.0, 0.0, 0.0);
     }
 }
 
-template <typename R, typename Dep>
-__device__ __forceinline__ void emit(Packet<R>& s, Stream<R>& rs, const TransportParams<R>& P,
-                                     const Tables<R>& tb, uint64_t id, uint32_t* cnt, double& e_killed,
-                                     const Dep& dep) {
+// First part of an emission (Sec. 2.1.1, 2.2): the packet's stream, its four
+// draws u_src u_nu u_mu u_phi, the source (luminosity CDF, or packet id mod
+// the number of sources), its weight and isotropic direction, and the start
+// cell with the in-cell offsets f: the floor of the position in cell units;
+// a position exactly on a wall belongs to the lower cell when the direction is
+// negative on that axis.  Returns the source; u_nu is left for the bin.
+template <typename R>
+__device__ __forceinline__ int emit_start(Packet<R>& s, Stream<R>& rs, const TransportParams<R>& P,
+                                          const Tables<R>& tb, uint64_t id, R& u_nu, R f[3]) {
     s.id = id;
     const uint64_t gid = P.packet_base + id;
     rs.p0 = (uint32_t)gid;
     rs.p1 = (uint32_t)(gid >> 32);
     rs.n = 0;
-    const R u_src = rs.next(), u_nu = rs.next(), u_mu = rs.next(), u_phi = rs.next();
+    const R u_src = rs.next();
+    u_nu = rs.next();
+    const R u_mu = rs.next(), u_phi = rs.next();
     int src;
     if (P.sampling == 0) {
         src = cdf_search(tb.lcdf, P.nsrc, u_src);
@@ -529,13 +569,8 @@ __device__ __forceinline__ void emit(Packet<R>& s, Stream<R>& rs, const Transpor
         src = (int)(gid % (uint64_t)P.nsrc);
         s.wgt = (R)P.sweight[src];
     }
-    s.k = cdf_search2(P.scdf + (size_t)src * P.npad, tb.scoarse + (size_t)src * P.ngroup, P.ngroup,
-                      u_nu);
     isotropic(s, u_mu, u_phi);
-    // start cell: floor of the position in cell units; a position exactly on a
-    // wall belongs to the lower cell when the direction is negative on that axis
     const double* x = P.spos + 3 * src;
-    R f[3];
     int c[3];
     const R dd[3] = {s.d0, s.d1, s.d2};
 #pragma unroll
@@ -552,15 +587,37 @@ __device__ __forceinline__ void emit(Packet<R>& s, Stream<R>& rs, const Transpor
     s.c0 = c[0];
     s.c1 = c[1];
     s.c2 = c[2];
-    s.chi = P.chi[s.k];
-    s.kap = P.kap[s.k];
+    return src;
+}
+
+template <typename R>
+__device__ __forceinline__ bool in_grid(const TransportParams<R>& P, int c0, int c1, int c2) {
+    return (unsigned)c0 < (unsigned)P.n[0] && (unsigned)c1 < (unsigned)P.n[1] &&
+           (unsigned)c2 < (unsigned)P.n[2];
+}
+
+// Emission of packet id: emit_start, the frequency bin from the source's
+// spectrum, the log, peeling-off of a binning pass, the modified random walk,
+// and the first flight (state WALK inside the grid, ESC outside it; EMPTY if
+// the walk killed it).  FULL = false leaves out logging, peeling and the walk
+// (a pass that uses none of them).
+template <typename R, typename Dep, bool FULL = true>
+__device__ __forceinline__ void emit(Packet<R>& s, Stream<R>& rs, const TransportParams<R>& P,
+                                     const Tables<R>& tb, uint64_t id, uint32_t* cnt, double& e_killed,
+                                     const Dep& dep) {
+    R u_nu;
+    R f[3];
+    const int src = emit_start(s, rs, P, tb, id, u_nu, f);
+    s.k = cdf_search2(P.scdf + (size_t)src * P.npad, tb.scoarse + (size_t)src * P.ngroup, P.ngroup,
+                      u_nu);
+    s.chi = tb.chi[s.k];
+    s.kap = tb.kap[s.k];
     s.nev = 0;
     s.nlog = 0;
-    log_event(s, P, MCRT_EV_EMIT, -1);
-    if (P.binning && P.n_peel > 0) peel(s, P, f[0], f[1], f[2], 0, false, 0.0, 0.0, 0.0);
-    const bool inside = (unsigned)s.c0 < (unsigned)P.n[0] && (unsigned)s.c1 < (unsigned)P.n[1] &&
-                        (unsigned)s.c2 < (unsigned)P.n[2];
-    if (inside && P.mrw_gamma > 0.0 && !mrw_steps(s, rs, P, tb, f[0], f[1], f[2], cnt, e_killed, dep))
+    if (FULL) log_event(s, P, MCRT_EV_EMIT, -1);
+    if (FULL && P.binning && P.n_peel > 0) peel(s, P, f[0], f[1], f[2], 0, false, 0.0, 0.0, 0.0);
+    const bool inside = in_grid(P, s.c0, s.c1, s.c2);
+    if (FULL && inside && P.mrw_gamma > 0.0 && !mrw_steps(s, rs, P, tb, f[0], f[1], f[2], cnt, e_killed, dep))
         return;  // killed (s.st = ST_EMPTY)
     begin_flight(s, P, rs, f[0], f[1], f[2]);
     s.st = inside ? ST_WALK : ST_ESC;
@@ -665,7 +722,7 @@ __device__ __forceinline__ void walk(Packet<R>& s, const G& P, double* acc, uint
 }
 
 // Scatter (u <= albedo) or absorb and re-emit (Sec. 2.2), then a new flight.
-template <typename R, typename Dep>
+template <typename R, typename Dep, bool FULL = true>
 __device__ __forceinline__ void interact(Packet<R>& s, Stream<R>& rs, const TransportParams<R>& P,
                                          const Tables<R>& tb, uint32_t* cnt, double& e_killed,
                                          const Dep& dep) {
@@ -673,37 +730,37 @@ __device__ __forceinline__ void interact(Packet<R>& s, Stream<R>& rs, const Tran
     if ((int64_t)s.nev > P.max_events) {
         ++cnt[C_KILLED];
         e_killed += P.eps0 * (double)s.wgt;
-        log_event(s, P, MCRT_EV_KILLED, -1);
+        if (FULL) log_event(s, P, MCRT_EV_KILLED, -1);
         s.st = ST_EMPTY;
         return;
     }
     R f0, f1, f2;
     offsets_at(s, P, s.t, f0, f1, f2);
     const R u_int = rs.next();
-    if (u_int > P.alb[s.k]) {
+    if (u_int > tb.alb[s.k]) {
         const R u_mix = rs.next(), u_nu = rs.next(), u_mu = rs.next(), u_phi = rs.next();
         const int64_t j = s.c0 + (int64_t)P.n[0] * (s.c1 + (int64_t)P.n[1] * s.c2);
         s.k = reemission_bin(P, tb, j, u_mix, u_nu);
         isotropic(s, u_mu, u_phi);
         ++cnt[C_ABSORB];
-        log_event(s, P, MCRT_EV_ABSORB, -1);
-        s.chi = P.chi[s.k];
-        s.kap = P.kap[s.k];
-        if (P.binning && P.n_peel > 0) peel(s, P, f0, f1, f2, 1, false, 0.0, 0.0, 0.0);
+        if (FULL) log_event(s, P, MCRT_EV_ABSORB, -1);
+        s.chi = tb.chi[s.k];
+        s.kap = tb.kap[s.k];
+        if (FULL && P.binning && P.n_peel > 0) peel(s, P, f0, f1, f2, 1, false, 0.0, 0.0, 0.0);
     } else {
         const R u_mu = rs.next(), u_phi = rs.next();
-        const R mu = hg_mu(P.g[s.k], u_mu);
-        if (P.binning && P.n_peel > 0) peel(s, P, f0, f1, f2, 1, true, s.d0, s.d1, s.d2);
+        const R mu = hg_mu(tb.g[s.k], u_mu);
+        if (FULL && P.binning && P.n_peel > 0) peel(s, P, f0, f1, f2, 1, true, s.d0, s.d1, s.d2);
         rotate(s, mu, Const<R>::two_pi * u_phi);
         ++cnt[C_SCATTER];
-        log_event(s, P, MCRT_EV_SCATTER, -1);
+        if (FULL) log_event(s, P, MCRT_EV_SCATTER, -1);
     }
-    if (P.mrw_gamma > 0.0 && !mrw_steps(s, rs, P, tb, f0, f1, f2, cnt, e_killed, dep)) return;
+    if (FULL && P.mrw_gamma > 0.0 && !mrw_steps(s, rs, P, tb, f0, f1, f2, cnt, e_killed, dep)) return;
     begin_flight(s, P, rs, f0, f1, f2);
     s.st = ST_WALK;
 }
 
-template <typename R>
+template <typename R, bool FULL = true>
 __device__ __forceinline__ void escape(Packet<R>& s, const TransportParams<R>& P, uint32_t* cnt,
                                        double& e_escaped) {
     const R fz = fmin((R)P.n_incl, fmax((R)0, fabs(s.d2) * (R)P.n_incl));  // NaN -> 0
@@ -712,7 +769,7 @@ __device__ __forceinline__ void escape(Packet<R>& s, const TransportParams<R>& P
     const double eps = P.eps0 * (double)s.wgt;
     ++cnt[C_ESCAPE];
     e_escaped += eps;
-    if (P.binning) {
+    if (FULL && P.binning) {
         const size_t q = (size_t)incl * P.nnu + s.k;
         unsafeAtomicAdd(P.sed_sum + q, eps);
         unsafeAtomicAdd(P.sed_sum2 + q, eps * eps);
@@ -745,7 +802,7 @@ __device__ __forceinline__ void escape(Packet<R>& s, const TransportParams<R>& P
             }
         }
     }
-    log_event(s, P, MCRT_EV_ESCAPE, incl);
+    if (FULL) log_event(s, P, MCRT_EV_ESCAPE, incl);
     s.st = ST_EMPTY;
 }
 

@@ -2,20 +2,36 @@
 // walked with its density and absorption tally staged in LDS.
 //
 // The grid is cut into tiles of txy x txy x tz cells.  A pass runs in sweeps.
-// Between sweeps every packet in flight is a record in global memory (its
-// full state: cell, direction, flight origin, wall distances, ray distance,
-// sampled and used optical depth, weight, bin, event counts and the position
-// in its random stream), and the records are grouped by the tile the packet
-// is in.  In a sweep, a workgroup takes work items (each up to S.item
-// records of one tile); for each new tile it loads the tile's density into
-// LDS and clears an LDS tally, and its lanes walk the item's packets
-// (Sec. 2.2; Lucy's path-length estimator, Sec. 2.3 Eq. 2, added into the
-// LDS tally) until each leaves the tile, escapes the grid, is
-// killed, or has had visit_events interactions in this visit; a packet that
-// leaves (or yields) is written out with the tile it is now in.  When the
-// workgroup moves on to another tile (or ends), it adds the LDS tally into
-// the FP64 global tally, one atomic per touched cell of the tile.  Sweeps
-// repeat until no packet is left.
+// Between sweeps every packet in flight is a record in one of two buffers:
+// its full state (cell, direction, flight origin, wall distances, ray
+// distance, sampled and used optical depth, weight, bin, event counts, the
+// position in its random stream), stored as 16-byte quads in planes, so that
+// the 64 lanes of a wave that read consecutive records load 1 KB contiguous
+// per quad.  Records are written in chunks of 64 slots per destination tile
+// (each wave keeps one open chunk per neighbour of the tile it walks); a
+// full chunk, and the rest of a chunk when the wave moves to another tile, is
+// registered as an entry (first record, count) of its tile.  Between sweeps
+// the entries are grouped by tile (a counting sort of the entries, not of the
+// records) and cut into work items.
+//
+// In a sweep a workgroup takes work items (up to item_ent entries of one
+// tile); for each new tile it loads the tile's density into LDS and clears an
+// LDS tally.  Its waves take the item's entries one at a time and hand their
+// records to lanes; each lane holds the packet it walks and the record of the
+// packet it walks next, loaded while the current one walks.  A lane walks its
+// packet (Sec. 2.2; Lucy's path-length estimator, Sec. 2.3 Eq. 2, added into
+// the LDS tally) until it leaves the tile, escapes the grid, is killed, or has
+// had visit_events interactions in this visit; interactions, escapes and
+// exits of a wave are handled together once `service` of its lanes wait.  A
+// packet that leaves (or yields) is written to the chunk of the tile it is
+// now in.  When the workgroup moves to another tile (or ends), it adds the LDS
+// tally into the FP64 global tally, one atomic per touched cell.
+//
+// The sweeps of a pass run without a host round trip: a one-thread kernel
+// decides on the device whether to refill the pool (emit the next batch of
+// packets when fewer than `batch` records are in flight), the emission writes
+// its packets as records of their start tiles, a one-block kernel scans the
+// per-tile counts, and the entries are grouped before the sweep reads them.
 //
 // Every packet follows the same arithmetic, random numbers and decisions as
 // in the per-lane persistent kernel (the walk is the same segment by segment,
@@ -24,83 +40,126 @@
 // flush).
 #include <math.h>
 
+#include <type_traits>
+
 #include "mcrt_internal.h"
 #include "mcrt_packet.h"
 
 namespace mcrt {
 
 constexpr int kDrainEvents = 32;     // interactions per visit once an item is drained
-constexpr unsigned kNoTile = 0xffffffffu;  // tile of a hole in the records (no packet)
-constexpr int kEmitHistTiles = 16384;      // tiles counted in LDS by the emission (64 KB)
+constexpr unsigned kChunk = 64;      // record slots per chunk
+constexpr unsigned kNone = 0xffffffffu;
+constexpr int kEmitPer = 16;         // packets per thread of an emission step
+constexpr int kEmitThreads = 256;
+constexpr int kEmitStep = kEmitPer * kEmitThreads;  // packets per block and step
+constexpr int kEmitHash = 1024;      // tiles an emission block counts in LDS
+constexpr int kMaxItemEnt = 128;     // entries of a work item (the host keeps item_ent below)
 enum : int { ST_MOVE = 5, ST_YIELD = 6 };
+enum : unsigned { RS_WALK = 0u, RS_EVENT = 1u, RS_HOLE = 2u };  // record states
 
-// State of a packet between visits (the Packet fields that are not
-// recomputed from the direction, the bin and the stream position).
-template <typename R> struct __attribute__((aligned(16))) PacketRec {
-    int c0, c1, c2, k;
-    R d0, d1, d2, u0, u1, u2, tx, ty, tz, t, tau, tau_acc, wgt;
-    uint32_t nev, nlog, n, st;
-    uint64_t id;
-};
+// ---- records ----------------------------------------------------------------
+template <typename R> struct Rec;
+template <> struct Rec<float> { static constexpr int NQ = 5; };
+template <> struct Rec<double> { static constexpr int NQ = 9; };
+template <typename R> struct Raw { uint4 q[Rec<R>::NQ]; };
 
-__device__ __forceinline__ int tile_of(const SweepParams& S, int c0, int c1, int c2) {
-    return (c0 / S.txy) + S.ntx * ((c1 / S.txy) + S.nty * (c2 / S.tz));
+__device__ __forceinline__ uint32_t pack_cell(int c0, int c1, int c2, unsigned rs) {
+    return (uint32_t)c0 | ((uint32_t)c1 << 10) | ((uint32_t)c2 << 20) | (rs << 30);
+}
+__device__ __forceinline__ uint32_t f2u(float x) { return __float_as_uint(x); }
+__device__ __forceinline__ float u2f(uint32_t x) { return __uint_as_float(x); }
+__device__ __forceinline__ uint2 d2u(double x) {
+    const unsigned long long b = (unsigned long long)__double_as_longlong(x);
+    return make_uint2((uint32_t)b, (uint32_t)(b >> 32));
+}
+__device__ __forceinline__ double u2d(uint32_t lo, uint32_t hi) {
+    return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
+}
+__device__ __forceinline__ uint4 dd2q(double a, double b) {
+    const uint2 x = d2u(a), y = d2u(b);
+    return make_uint4(x.x, x.y, y.x, y.y);
+}
+
+__device__ __forceinline__ void pack_rec(Raw<float>& r, const Packet<float>& s, const Stream<float>& rs,
+                                         unsigned state) {
+    r.q[0] = make_uint4(pack_cell(s.c0, s.c1, s.c2, state), (uint32_t)s.k, s.nev, rs.n);
+    r.q[1] = make_uint4(f2u(s.d0), f2u(s.d1), f2u(s.d2), f2u(s.t));
+    r.q[2] = make_uint4(f2u(s.u0), f2u(s.u1), f2u(s.u2), f2u(s.tau));
+    r.q[3] = make_uint4(f2u(s.tx), f2u(s.ty), f2u(s.tz), f2u(s.tau_acc));
+    r.q[4] = make_uint4((uint32_t)s.id, (uint32_t)(s.id >> 32), f2u(s.wgt), s.nlog);
+}
+__device__ __forceinline__ void pack_rec(Raw<double>& r, const Packet<double>& s, const Stream<double>& rs,
+                                         unsigned state) {
+    r.q[0] = make_uint4(pack_cell(s.c0, s.c1, s.c2, state), (uint32_t)s.k, s.nev, rs.n);
+    r.q[1] = dd2q(s.d0, s.d1);
+    r.q[2] = dd2q(s.d2, s.t);
+    r.q[3] = dd2q(s.u0, s.u1);
+    r.q[4] = dd2q(s.u2, s.tau);
+    r.q[5] = dd2q(s.tx, s.ty);
+    r.q[6] = dd2q(s.tz, s.tau_acc);
+    r.q[7] = make_uint4((uint32_t)s.id, (uint32_t)(s.id >> 32), s.nlog, 0u);
+    r.q[8] = dd2q(s.wgt, 0.0);
+}
+
+// record state RS_* of a raw record
+template <typename R> __device__ __forceinline__ unsigned rec_state(const Raw<R>& r) { return r.q[0].x >> 30; }
+
+__device__ __forceinline__ void unpack_fields(Packet<float>& s, uint32_t& n, const Raw<float>& r) {
+    s.k = (int)r.q[0].y;
+    s.nev = r.q[0].z;
+    n = r.q[0].w;
+    s.d0 = u2f(r.q[1].x); s.d1 = u2f(r.q[1].y); s.d2 = u2f(r.q[1].z); s.t = u2f(r.q[1].w);
+    s.u0 = u2f(r.q[2].x); s.u1 = u2f(r.q[2].y); s.u2 = u2f(r.q[2].z); s.tau = u2f(r.q[2].w);
+    s.tx = u2f(r.q[3].x); s.ty = u2f(r.q[3].y); s.tz = u2f(r.q[3].z); s.tau_acc = u2f(r.q[3].w);
+    s.id = (uint64_t)r.q[4].x | ((uint64_t)r.q[4].y << 32);
+    s.wgt = u2f(r.q[4].z);
+    s.nlog = r.q[4].w;
+}
+__device__ __forceinline__ void unpack_fields(Packet<double>& s, uint32_t& n, const Raw<double>& r) {
+    s.k = (int)r.q[0].y;
+    s.nev = r.q[0].z;
+    n = r.q[0].w;
+    s.d0 = u2d(r.q[1].x, r.q[1].y); s.d1 = u2d(r.q[1].z, r.q[1].w);
+    s.d2 = u2d(r.q[2].x, r.q[2].y); s.t = u2d(r.q[2].z, r.q[2].w);
+    s.u0 = u2d(r.q[3].x, r.q[3].y); s.u1 = u2d(r.q[3].z, r.q[3].w);
+    s.u2 = u2d(r.q[4].x, r.q[4].y); s.tau = u2d(r.q[4].z, r.q[4].w);
+    s.tx = u2d(r.q[5].x, r.q[5].y); s.ty = u2d(r.q[5].z, r.q[5].w);
+    s.tz = u2d(r.q[6].x, r.q[6].y); s.tau_acc = u2d(r.q[6].z, r.q[6].w);
+    s.id = (uint64_t)r.q[7].x | ((uint64_t)r.q[7].y << 32);
+    s.nlog = r.q[7].z;
+    s.wgt = u2d(r.q[8].x, r.q[8].y);
 }
 
 template <typename R>
-__device__ __forceinline__ void store_rec(PacketRec<R>* r, const Packet<R>& s, const Stream<R>& rs,
-                                          int st) {
-    PacketRec<R> q;
-    q.c0 = s.c0;
-    q.c1 = s.c1;
-    q.c2 = s.c2;
-    q.k = s.k;
-    q.d0 = s.d0;
-    q.d1 = s.d1;
-    q.d2 = s.d2;
-    q.u0 = s.u0;
-    q.u1 = s.u1;
-    q.u2 = s.u2;
-    q.tx = s.tx;
-    q.ty = s.ty;
-    q.tz = s.tz;
-    q.t = s.t;
-    q.tau = s.tau;
-    q.tau_acc = s.tau_acc;
-    q.wgt = s.wgt;
-    q.nev = s.nev;
-    q.nlog = s.nlog;
-    q.n = rs.n;
-    q.st = (uint32_t)st;
-    q.id = s.id;
-    *r = q;
+__device__ __forceinline__ void store_raw(const SweepParams& S, uint4* recs, unsigned idx, const Raw<R>& r) {
+#pragma unroll
+    for (int q = 0; q < Rec<R>::NQ; ++q) recs[(size_t)q * S.cap + idx] = r.q[q];
 }
 
+template <typename R>
+__device__ __forceinline__ void load_raw(const SweepParams& S, const uint4* recs, unsigned idx, Raw<R>& r) {
+#pragma unroll
+    for (int q = 0; q < Rec<R>::NQ; ++q) r.q[q] = recs[(size_t)q * S.cap + idx];
+}
+
+// The packet of a record: the state fields, then what begin_flight derived
+// from them (wall spacings along the ray, the bin's opacities) and the random
+// stream (the second uniform of the last Philox call when the position is odd).
 template <typename R>
 __device__ __forceinline__ void unpack_rec(Packet<R>& s, Stream<R>& rs, const TransportParams<R>& P,
-                                           const PacketRec<R>& q, const R* chi_t, const R* kap_t) {
-    s.c0 = q.c0;
-    s.c1 = q.c1;
-    s.c2 = q.c2;
-    s.k = q.k;
-    s.d0 = q.d0;
-    s.d1 = q.d1;
-    s.d2 = q.d2;
-    s.u0 = q.u0;
-    s.u1 = q.u1;
-    s.u2 = q.u2;
-    s.tx = q.tx;
-    s.ty = q.ty;
-    s.tz = q.tz;
-    s.t = q.t;
-    s.tau = q.tau;
-    s.tau_acc = q.tau_acc;
-    s.wgt = q.wgt;
-    s.nev = q.nev;
-    s.nlog = q.nlog;
-    s.id = q.id;
-    s.st = (int)q.st;
-    // the same quotients begin_flight computed for this flight
+                                           const Raw<R>& r, const R* chi_t, const R* kap_t) {
+    const uint32_t cw = r.q[0].x;
+    s.c0 = (int)(cw & 1023u);
+    s.c1 = (int)((cw >> 10) & 1023u);
+    s.c2 = (int)((cw >> 20) & 1023u);
+    const unsigned state = cw >> 30;
+    if (state == RS_HOLE) {
+        s.st = ST_EMPTY;
+        return;
+    }
+    uint32_t n;
+    unpack_fields(s, n, r);
     s.dtx = P.dxr[0] / fabs(s.d0);
     s.dty = P.dxr[1] / fabs(s.d1);
     s.dtz = P.dxr[2] / fabs(s.d2);
@@ -109,13 +168,43 @@ __device__ __forceinline__ void unpack_rec(Packet<R>& s, Stream<R>& rs, const Tr
     const uint64_t gid = P.packet_base + s.id;
     rs.p0 = (uint32_t)gid;
     rs.p1 = (uint32_t)(gid >> 32);
-    rs.n = q.n;
-    if (rs.n & 1u) {  // the second uniform of the last Philox call is still unused
+    rs.n = n;
+    if (rs.n & 1u) {
         uint32_t c0 = rs.n >> 1, c1 = 0u, c2 = rs.p0, c3 = rs.p1;
         philox4x32_10(c0, c1, c2, c3, rs.k0, rs.k1);
         rs.s0 = c2;
         rs.s1 = c3;
     }
+    s.st = state == RS_WALK ? ST_WALK : ST_EVENT;
+}
+
+// ---- tiles --------------------------------------------------------------------
+__device__ __forceinline__ int tile_of(const SweepParams& S, int c0, int c1, int c2) {
+    return (c0 / S.txy) + S.ntx * ((c1 / S.txy) + S.nty * (c2 / S.tz));
+}
+
+// the tile of destination slot d of tile t: itself, then -x, +x, -y, +y, -z, +z
+__device__ __forceinline__ int slot_tile(const SweepParams& S, int t, int d) {
+    const int nxy = S.ntx * S.nty;
+    switch (d) {
+        case 1: return t - 1;
+        case 2: return t + 1;
+        case 3: return t - S.ntx;
+        case 4: return t + S.ntx;
+        case 5: return t - nxy;
+        case 6: return t + nxy;
+        default: return t;
+    }
+}
+__device__ __forceinline__ int slot_of(const SweepParams& S, int t, int dest) {
+    const int dt = dest - t, nxy = S.ntx * S.nty;
+    if (dt == 0) return 0;
+    if (dt == -1) return 1;
+    if (dt == 1) return 2;
+    if (dt == -S.ntx) return 3;
+    if (dt == S.ntx) return 4;
+    if (dt == -nxy) return 5;
+    return 6;  // dt == nxy: a packet moves at most one cell per crossing
 }
 
 // Local LDS index of the packet's cell in the tile with origin (o0, o1, o2).
@@ -140,7 +229,7 @@ __device__ __forceinline__ int tile_index(int c0, int c1, int c2, int o0, int o1
 template <typename R, int K, bool NOISE>
 __device__ __forceinline__ void walk_tile(Packet<R>& s, const TransportParams<R>& P, int o0, int o1,
                                           int o2, int txy, int tz, const R* __restrict__ rho_t,
-                                          R* __restrict__ acc_t, double* __restrict__ acc2_t,
+                                          double* __restrict__ acc_t, double* __restrict__ acc2_t,
                                           uint32_t* cnt, int& jl, R& rho) {
     const bool px = s.d0 > (R)0, py = s.d1 > (R)0, pz = s.d2 > (R)0;
     const int sx = px ? 1 : -1;
@@ -190,7 +279,7 @@ __device__ __forceinline__ void walk_tile(Packet<R>& s, const TransportParams<R>
         if (cross && dust) {
             s.tau_acc += dtau;
             const R w = s.wgt * l * s.kap;
-            atomicAdd(acc_t + jl, w);
+            atomicAdd(acc_t + jl, (double)w);
             if (NOISE) atomicAdd(acc2_t + jl, (double)w * (double)w);  // w^2 may exceed FP32
         }
         s.t = cross ? fmax(tm, s.t) : s.t;
@@ -216,7 +305,7 @@ __device__ __forceinline__ void walk_tile(Packet<R>& s, const TransportParams<R>
     if (hit) {
         const R l = (s.tau - s.tau_acc) / rc_h;
         const R w = s.wgt * l * s.kap;
-        atomicAdd(acc_t + jl_h, w);
+        atomicAdd(acc_t + jl_h, (double)w);
         if (NOISE) atomicAdd(acc2_t + jl_h, (double)w * (double)w);
         s.t = ts_h + l;
         st = ST_EVENT;
@@ -247,42 +336,182 @@ __device__ __forceinline__ void walk_tile(Packet<R>& s, const TransportParams<R>
     cnt[C_CROSS_EMPTY] += ne;
 }
 
-// Append the lanes' records whose state is ST_MOVE or ST_YIELD (one atomic per
-// wave) and free those lanes.  Returns the record's tile in dest (or -1).
-template <typename R>
-__device__ __forceinline__ void append_moves(const SweepParams& S, Packet<R>& s, const Stream<R>& rs,
-                                             int lane, int& dest) {
-    dest = -1;
-    const bool mine = s.st == ST_MOVE || s.st == ST_YIELD;
-    const unsigned long long mv = __ballot(mine);
-    if (!mv) return;
-    const int leader = __ffsll((long long)mv) - 1;
-    unsigned base = 0;
-    if (lane == leader) base = atomicAdd(S.out_count, (unsigned)__popcll(mv));
-    base = __shfl(base, leader);
-    if (mine) {
-        const unsigned idx = base + (unsigned)__popcll(mv & __lanemask_lt());
-        store_rec(reinterpret_cast<PacketRec<R>*>(S.out) + idx, s, rs,
-                  s.st == ST_YIELD ? ST_EVENT : ST_WALK);
-        dest = tile_of(S, s.c0, s.c1, s.c2);
-        S.out_tile[idx] = (unsigned)dest;
-        s.st = ST_EMPTY;
+// ---- entries and record slots -------------------------------------------------
+// A sweep's records and entries are handed out from two counters per buffer.
+// To keep atomics on those two addresses rare, a wave takes record slots
+// kArenaSlots at a time and entry slots kArenaEnt at a time and hands them
+// out itself; the per-tile record and entry counts of a workgroup's
+// registrations are summed in LDS and added to the global counts when the
+// workgroup leaves the tile.  Entry slots a wave still holds when the sweep
+// ends are marked empty (count 0).
+constexpr unsigned kArenaSlots = 1024;  // record slots a wave takes at a time (a multiple of kChunk)
+constexpr unsigned kArenaEnt = 32;      // entry slots a wave takes at a time
+
+// One wave's output state: its open chunk per destination slot of the tile it
+// walks, and the record and entry slots it holds.
+struct WaveOut {
+    unsigned base[7];
+    unsigned fill[7];
+    unsigned rb, rl;  // record slots [rb, rb + rl)
+    unsigned eb, el;  // entry slots [eb, eb + el)
+};
+
+__device__ __forceinline__ void wave_out_init(WaveOut& w) {
+#pragma unroll
+    for (int d = 0; d < 7; ++d) {
+        w.base[d] = kNone;
+        w.fill[d] = 0u;
+    }
+    w.rb = w.rl = w.eb = w.el = 0u;
+}
+
+// kChunk record slots of buffer b (kNone when the buffer is full); wave-uniform
+__device__ __forceinline__ unsigned take_chunk(const SweepParams& S, int b, WaveOut& w, int lane) {
+    if (w.rl < kChunk) {
+        unsigned f = 0u;
+        if (lane == 0) {
+            f = atomicAdd(&S.ctl->rec_alloc[b], kArenaSlots);
+            if (f > S.cap || S.cap - f < kArenaSlots) {
+                atomicOr(&S.ctl->overflow, 1u);
+                f = kNone;
+            }
+        }
+        f = (unsigned)__shfl((int)f, 0);
+        if (f == kNone) return kNone;
+        w.rb = f;
+        w.rl = kArenaSlots;
+    }
+    const unsigned c = w.rb;
+    w.rb += kChunk;
+    w.rl -= kChunk;
+    return c;
+}
+
+// Register records [first, first + count) as an entry of the tile in
+// destination slot d; s_tc holds the workgroup's per-slot record and entry
+// counts of the current tile.  Wave-uniform arguments.
+__device__ __forceinline__ void wave_register(const SweepParams& S, int b, WaveOut& w, int tile, int d,
+                                              unsigned first, unsigned count, unsigned* s_tc, int lane) {
+    if (w.el == 0u) {
+        unsigned e = 0u;
+        if (lane == 0) {
+            e = atomicAdd(&S.ctl->n_ent[b], kArenaEnt);
+            if (e > S.max_ent || S.max_ent - e < kArenaEnt) {
+                atomicOr(&S.ctl->overflow, 1u);
+                e = kNone;
+            }
+        }
+        e = (unsigned)__shfl((int)e, 0);
+        if (e == kNone) return;
+        w.eb = e;
+        w.el = kArenaEnt;
+    }
+    if (lane == 0) {
+        S.ent_tile[b][w.eb] = (unsigned)tile;
+        S.ent[b][w.eb] = make_uint2(first, count);
+        atomicAdd(&s_tc[2 * d], count);
+        atomicAdd(&s_tc[2 * d + 1], 1u);
+    }
+    w.eb += 1u;
+    w.el -= 1u;
+}
+
+// Emission: registration of a run of records of one tile in entry slot e.
+__device__ __forceinline__ void emit_register(const SweepParams& S, int b, unsigned e, int tile, unsigned first,
+                                              unsigned count) {
+    S.ent_tile[b][e] = (unsigned)tile;
+    S.ent[b][e] = make_uint2(first, count);
+    atomicAdd(S.tile_rec + tile, count);
+    atomicAdd(S.tile_ent + tile, 1u);
+}
+
+// Emission: n record slots (or entry slots, ent = true) of buffer b from the
+// buffer's counter, kNone when the buffer is full.
+__device__ __forceinline__ unsigned emit_take(const SweepParams& S, int b, unsigned n, bool ent) {
+    unsigned* ctr = ent ? &S.ctl->n_ent[b] : &S.ctl->rec_alloc[b];
+    const unsigned lim = ent ? S.max_ent : S.cap;
+    const unsigned f = atomicAdd(ctr, n);
+    if (f > lim || lim - f < n) {
+        atomicOr(&S.ctl->overflow, 1u);
+        return kNone;
+    }
+    return f;
+}
+
+// The entry slots a wave still holds are marked empty.
+__device__ __forceinline__ void wave_out_release(const SweepParams& S, int b, WaveOut& w, int lane) {
+    if ((unsigned)lane < w.el) S.ent[b][w.eb + lane] = make_uint2(0u, 0u);
+    w.el = 0u;
+}
+
+// Register the wave's partly filled chunks (the wave leaves tile t).
+__device__ __forceinline__ void chunks_close(const SweepParams& S, int b, int t, WaveOut& w, unsigned* s_tc,
+                                             int lane) {
+#pragma unroll
+    for (int d = 0; d < 7; ++d) {
+        if (w.base[d] != kNone && w.fill[d] > 0u)
+            wave_register(S, b, w, slot_tile(S, t, d), d, w.base[d], w.fill[d], s_tc, lane);
+        w.base[d] = kNone;
+        w.fill[d] = 0u;
     }
 }
 
-// count records per destination tile: one global atomic per distinct tile of
-// the wave
-__device__ __forceinline__ void count_tiles(unsigned* counts, int dest) {
-    bool pending = dest >= 0;
-    for (;;) {
-        const unsigned long long act = __ballot(pending);
-        if (!act) break;
-        const int leader = __ffsll((long long)act) - 1;
-        const int lt = __shfl(dest, leader);
-        const bool mine = pending && dest == lt;
-        const unsigned long long same = __ballot(mine);
-        if (__lane_id() == leader) atomicAdd(counts + lt, (unsigned)__popcll(same));
-        if (mine) pending = false;
+// The workgroup's per-slot counts of tile t into the global per-tile counts
+// (threads 0..6, after a barrier that follows the last registration).
+__device__ __forceinline__ void flush_tile_counts(const SweepParams& S, int t, unsigned* s_tc) {
+    if (threadIdx.x < 7) {
+        const int d = threadIdx.x;
+        if (s_tc[2 * d]) atomicAdd(S.tile_rec + slot_tile(S, t, d), s_tc[2 * d]);
+        if (s_tc[2 * d + 1]) atomicAdd(S.tile_ent + slot_tile(S, t, d), s_tc[2 * d + 1]);
+        s_tc[2 * d] = 0u;
+        s_tc[2 * d + 1] = 0u;
+    }
+}
+
+// Write the records of the lanes whose packets leave the tile or yield
+// (state MOVE / YIELD) into the open chunks of their destination tiles, and
+// free those lanes.  Per destination: the wave's lanes take consecutive slots
+// (their rank among the lanes of that destination); a chunk that fills is
+// registered and the rest goes to a new chunk.
+template <typename R>
+__device__ __forceinline__ void write_exits(const SweepParams& S, int b, int tile, Packet<R>& s,
+                                            const Stream<R>& rs, WaveOut& w, unsigned* s_tc, int lane) {
+    const bool out = s.st == ST_MOVE || s.st == ST_YIELD;
+    if (__ballot(out) == 0ull) return;
+    const int slot = out ? slot_of(S, tile, tile_of(S, s.c0, s.c1, s.c2)) : -1;
+    unsigned idx = kNone;
+#pragma unroll
+    for (int d = 0; d < 7; ++d) {
+        const unsigned long long m = __ballot(slot == d);
+        if (m == 0ull) continue;
+        const unsigned n = (unsigned)__popcll(m);
+        const unsigned room = w.base[d] == kNone ? 0u : kChunk - w.fill[d];
+        const unsigned k1 = n < room ? n : room;
+        const unsigned nb = n > k1 ? take_chunk(S, b, w, lane) : kNone;
+        if (slot == d) {
+            const unsigned rank = (unsigned)__popcll(m & __lanemask_lt());
+            if (rank < k1) idx = w.base[d] + w.fill[d] + rank;
+            else idx = nb == kNone ? kNone : nb + (rank - k1);
+        }
+        if (w.base[d] != kNone && w.fill[d] + k1 == kChunk) {
+            wave_register(S, b, w, slot_tile(S, tile, d), d, w.base[d], kChunk, s_tc, lane);
+            w.base[d] = kNone;
+            w.fill[d] = 0u;
+        } else {
+            w.fill[d] += k1;
+        }
+        if (n > k1) {
+            w.base[d] = nb;
+            w.fill[d] = nb == kNone ? 0u : n - k1;
+        }
+    }
+    if (out) {
+        if (idx != kNone) {
+            Raw<R> r;
+            pack_rec(r, s, rs, s.st == ST_YIELD ? RS_EVENT : RS_WALK);
+            store_raw(S, S.recs[b], idx, r);
+        }
+        s.st = ST_EMPTY;
     }
 }
 
@@ -299,145 +528,349 @@ __device__ __forceinline__ void flush_block_counters(const TransportParams<R>& P
     if (threadIdx.x < 2) unsafeAtomicAdd(P.energies + threadIdx.x, s_energy[threadIdx.x]);
 }
 
-// Emission of packets [first, first+count): each starts its first flight
-// (exactly as in the per-lane kernel) and is written as record base+i with its
-// tile; a packet that starts outside the grid escapes at once (or is killed by
-// the modified random walk at the event limit) and leaves a hole
-// (tile kNoTile, skipped by the ordering).  Positions need no atomics; the
-// per-tile counts are gathered in an LDS histogram per block when the tiles
-// fit (hist), else per wave.
-template <typename R>
-__global__ void __launch_bounds__(256) k_sweep_emit(TransportParams<R> P, SweepParams S,
-                                                     uint64_t first, uint64_t count, unsigned base,
-                                                     int hist) {
-    extern __shared__ unsigned s_hist[];
+// ---- sweep control --------------------------------------------------------------
+// The refill of this step: when fewer than batch records were registered for
+// buffer b (summed over the tiles) and packets remain, the next batch is
+// emitted into b.  One block.
+__global__ void __launch_bounds__(1024) k_refill_plan(SweepParams S, int b) {
+    __shared__ unsigned long long s_sum[1024];
+    unsigned long long v = 0ull;
+    for (int t = threadIdx.x; t < S.ntiles; t += blockDim.x) v += S.tile_rec[t];
+    s_sum[threadIdx.x] = v;
+    __syncthreads();
+    for (int o = (int)blockDim.x / 2; o > 0; o >>= 1) {
+        if ((int)threadIdx.x < o) s_sum[threadIdx.x] += s_sum[threadIdx.x + o];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        SweepCtl* c = S.ctl;
+        unsigned long long cnt = 0ull;
+        if (s_sum[0] < S.batch && c->emitted < S.n_packets) {
+            const unsigned long long left = S.n_packets - c->emitted;
+            cnt = left < S.batch ? left : S.batch;
+        }
+        c->emit_first = c->emitted;
+        c->emit_count = cnt;
+        c->emitted += cnt;
+    }
+}
+
+// Emission of the step's refill into buffer b.  A block takes kEmitStep
+// packets at a time: it first finds every packet's start tile (the first
+// part of an emission: the same draws and arithmetic), counts them per tile in
+// an LDS hash table, reserves one run of slots per tile and registers it as an
+// entry; then it emits the packets in full and writes each at its tile's run
+// plus its rank.  A packet that starts outside the grid escapes at once; one
+// the modified random walk kills at emission leaves a hole in its run.  A tile
+// that finds no free hash slot takes one slot and one entry per packet.
+template <typename R, bool FULL>
+__global__ void __launch_bounds__(kEmitThreads) k_sweep_emit(TransportParams<R> P, SweepParams S, int b) {
+    __shared__ unsigned h_key[kEmitHash], h_cnt[kEmitHash], h_base[kEmitHash], h_ent[kEmitHash];
+    __shared__ unsigned s_rtot, s_etot, s_rbase, s_ebase;
+    __shared__ int s_slot[kEmitStep];  // per packet: hash slot, -1 own entry, -2 outside / none
     __shared__ unsigned long long s_cnt[C_COUNT];
     __shared__ double s_energy[2];
+    const unsigned long long first = S.ctl->emit_first, count = S.ctl->emit_count;
+    if (count == 0ull) return;
     if (threadIdx.x < C_COUNT) s_cnt[threadIdx.x] = 0ull;
     if (threadIdx.x < 2) s_energy[threadIdx.x] = 0.0;
-    if (hist)
-        for (int t = threadIdx.x; t < S.ntiles; t += blockDim.x) s_hist[t] = 0u;
-    __syncthreads();
-    uint32_t cnt[C_COUNT] = {0, 0, 0, 0, 0, 0};
+    uint32_t cnt[C_COUNT] = {0, 0, 0, 0, 0, 0, 0};
     double e_escaped = 0.0, e_killed = 0.0;
-    const Tables<R> tb{P.lcdf, P.ecoarse, P.scoarse};
+    const Tables<R> tb = global_tables(P);
     Stream<R> rs;
     rs.k0 = P.key0;
     rs.k1 = P.key1;
     rs.n = 0;
     rs.p0 = rs.p1 = rs.s0 = rs.s1 = 0;
-    PacketRec<R>* out = reinterpret_cast<PacketRec<R>*>(S.out);
-    const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
-    for (uint64_t b0 = (uint64_t)blockIdx.x * blockDim.x; b0 < count; b0 += stride) {
-        const uint64_t i = b0 + threadIdx.x;
-        int dest = -1;
-        if (i < count) {
-            Packet<R> s;
-            emit(s, rs, P, tb, first + i, cnt, e_killed, global_deposit<0>(P, P.acc));
-            const unsigned idx = base + (unsigned)i;
-            if (s.st == ST_ESC || s.st == ST_EMPTY) {  // escaped at once, or killed by the walk
-                if (s.st == ST_ESC) escape(s, P, cnt, e_escaped);
-                S.out_tile[idx] = kNoTile;
-            } else {
-                store_rec(out + idx, s, rs, ST_WALK);
-                dest = tile_of(S, s.c0, s.c1, s.c2);
-                S.out_tile[idx] = (unsigned)dest;
-                if (hist) atomicAdd(&s_hist[dest], 1u);
+    for (unsigned long long c0 = (unsigned long long)blockIdx.x * kEmitStep; c0 < count;
+         c0 += (unsigned long long)gridDim.x * kEmitStep) {
+        for (int i = threadIdx.x; i < kEmitHash; i += blockDim.x) {
+            h_key[i] = kNone;
+            h_cnt[i] = 0u;
+        }
+        __syncthreads();
+#pragma unroll 1
+        for (int j = 0; j < kEmitPer; ++j) {
+            const unsigned long long i = c0 + (unsigned long long)(j * kEmitThreads) + threadIdx.x;
+            int& slot = s_slot[j * kEmitThreads + threadIdx.x];
+            slot = -2;  // no packet, or it starts outside the grid
+            if (i < count) {
+                Packet<R> s;
+                R u_nu, f[3];
+                emit_start(s, rs, P, tb, first + i, u_nu, f);
+                if (in_grid(P, s.c0, s.c1, s.c2)) {
+                    const unsigned t = (unsigned)tile_of(S, s.c0, s.c1, s.c2);
+                    unsigned h = (t * 2654435761u) >> 22;
+                    slot = -1;  // no hash slot: one entry of its own
+                    for (int probe = 0; probe < kEmitHash; ++probe) {
+                        const unsigned k = atomicCAS(&h_key[h], kNone, t);
+                        if (k == kNone || k == t) {
+                            slot = (int)h;
+                            atomicAdd(&h_cnt[h], 1u);
+                            break;
+                        }
+                        h = (h + 1u) & (kEmitHash - 1);
+                    }
+                }
             }
         }
-        if (!hist) count_tiles(S.counts, dest);
-    }
-    if (hist) {
+        // one run of slots per tile, one entry per run: the block's records and
+        // entries are taken from the buffer's counters at once
+        if (threadIdx.x == 0) {
+            s_rtot = 0u;
+            s_etot = 0u;
+        }
         __syncthreads();
-        for (int t = threadIdx.x; t < S.ntiles; t += blockDim.x)
-            if (s_hist[t]) atomicAdd(S.counts + t, s_hist[t]);
+        for (int e = threadIdx.x; e < kEmitHash; e += blockDim.x) {
+            h_base[e] = kNone;
+            if (h_cnt[e]) {
+                h_base[e] = atomicAdd(&s_rtot, h_cnt[e]);  // offset within the block's run
+                h_ent[e] = atomicAdd(&s_etot, 1u);
+            }
+        }
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            s_rbase = s_rtot ? emit_take(S, b, s_rtot, false) : kNone;
+            s_ebase = s_etot ? emit_take(S, b, s_etot, true) : kNone;
+        }
+        __syncthreads();
+        for (int e = threadIdx.x; e < kEmitHash; e += blockDim.x) {
+            if (h_cnt[e]) {
+                if (s_rbase == kNone || s_ebase == kNone) {
+                    h_base[e] = kNone;
+                } else {
+                    h_base[e] += s_rbase;
+                    emit_register(S, b, s_ebase + h_ent[e], (int)h_key[e], h_base[e], h_cnt[e]);
+                }
+                h_cnt[e] = 0u;  // ranks from here on
+            }
+        }
+        __syncthreads();
+#pragma unroll 1
+        for (int j = 0; j < kEmitPer; ++j) {
+            const unsigned long long i = c0 + (unsigned long long)(j * kEmitThreads) + threadIdx.x;
+            if (i >= count) continue;
+            const int slot = s_slot[j * kEmitThreads + threadIdx.x];
+            Packet<R> s;
+            emit<R, GlobalDeposit<0>, FULL>(s, rs, P, tb, first + i, cnt, e_killed,
+                                            global_deposit<0>(P, P.acc));
+            if (slot == -2) {  // outside the grid: escapes at once
+                if (s.st == ST_ESC) escape<R, FULL>(s, P, cnt, e_escaped);
+                continue;
+            }
+            unsigned idx;
+            if (slot >= 0) {
+                const unsigned rank = atomicAdd(&h_cnt[slot], 1u);
+                idx = h_base[slot] == kNone ? kNone : h_base[slot] + rank;
+            } else {
+                idx = emit_take(S, b, 1u, false);
+                const unsigned e = idx == kNone ? kNone : emit_take(S, b, 1u, true);
+                if (e != kNone) emit_register(S, b, e, tile_of(S, s.c0, s.c1, s.c2), idx, 1u);
+                else idx = kNone;
+            }
+            if (idx == kNone) continue;
+            Raw<R> r;
+            pack_rec(r, s, rs, s.st == ST_WALK ? RS_WALK : RS_HOLE);
+            store_raw(S, S.recs[b], idx, r);
+        }
+        __syncthreads();
     }
     flush_block_counters(P, cnt, e_escaped, e_killed, s_cnt, s_energy);
 }
 
-// The tile's counts of records written for it and its face neighbours, and its
-// LDS partial sums into the FP64 tally (cells of this tile only); the LDS is
-// free again on return.
-template <typename R>
-__device__ __forceinline__ void flush_tile(const TransportParams<R>& P, const SweepParams& S, int tile,
-                                           int o0, int o1, int o2, int txy, int tcells,
-                                           const R* acc_t, const double* acc2_t, unsigned* s_nb) {
-    __syncthreads();
-    if (threadIdx.x < 7 && s_nb[threadIdx.x]) {
-        const int off[7] = {0, -1, 1, -S.ntx, S.ntx, -S.ntx * S.nty, S.ntx * S.nty};
-        atomicAdd(S.counts + tile + off[threadIdx.x], s_nb[threadIdx.x]);
+// Exclusive scans of the per-tile entry counts (grouped entry offsets, and work
+// items of item_ent entries), the grouping cursors, the statistics of the
+// sweep about to run, and the reset of the counters of the buffer that sweep
+// writes; one block.
+__global__ void __launch_bounds__(1024) k_sweep_scan(SweepParams S, int b) {
+    __shared__ unsigned s_a[1024], s_b[1024], s_r[1024];
+    const int n = S.ntiles;
+    const unsigned ie = (unsigned)S.item_ent;
+    const int per = (n + (int)blockDim.x - 1) / (int)blockDim.x;
+    const int t0 = threadIdx.x * per;
+    unsigned ra = 0, rb = 0, rr = 0;
+    for (int t = t0; t < t0 + per && t < n; ++t) {
+        const unsigned e = S.tile_ent[t];
+        ra += e;
+        rb += (e + ie - 1) / ie;
+        rr += S.tile_rec[t];
     }
+    s_a[threadIdx.x] = ra;
+    s_b[threadIdx.x] = rb;
+    s_r[threadIdx.x] = rr;
+    __syncthreads();
+    for (int o = 1; o < (int)blockDim.x; o <<= 1) {
+        const unsigned va = threadIdx.x >= (unsigned)o ? s_a[threadIdx.x - o] : 0u;
+        const unsigned vb = threadIdx.x >= (unsigned)o ? s_b[threadIdx.x - o] : 0u;
+        const unsigned vr = threadIdx.x >= (unsigned)o ? s_r[threadIdx.x - o] : 0u;
+        __syncthreads();
+        s_a[threadIdx.x] += va;
+        s_b[threadIdx.x] += vb;
+        s_r[threadIdx.x] += vr;
+        __syncthreads();
+    }
+    unsigned pa = s_a[threadIdx.x] - ra, pb = s_b[threadIdx.x] - rb;  // exclusive
+    for (int t = t0; t < t0 + per && t < n; ++t) {
+        const unsigned e = S.tile_ent[t];
+        S.ent_off[t] = pa;
+        S.cursor[t] = pa;
+        S.item_off[t] = pb;
+        pa += e;
+        pb += (e + ie - 1) / ie;
+        S.tile_ent[t] = 0u;
+        S.tile_rec[t] = 0u;
+    }
+    if (threadIdx.x == blockDim.x - 1) {
+        const unsigned recs = s_r[threadIdx.x];
+        SweepCtl* c = S.ctl;
+        S.ent_off[n] = s_a[threadIdx.x];
+        S.item_off[n] = s_b[threadIdx.x];
+        c->n_items = s_b[threadIdx.x];
+        c->item_next = 0u;
+        c->visits += recs;
+        if (recs) c->sweeps += 1u;
+        c->done = (recs == 0u && c->emitted >= S.n_packets) ? 1u : 0u;
+        c->rec_alloc[b ^ 1] = 0u;
+        c->n_ent[b ^ 1] = 0u;
+    }
+}
+
+// Entries of buffer b grouped by tile.
+__global__ void k_sweep_group(SweepParams S, int b) {
+    const unsigned n = S.ctl->n_ent[b] < S.max_ent ? S.ctl->n_ent[b] : S.max_ent;
+    for (unsigned e = blockIdx.x * blockDim.x + threadIdx.x; e < n; e += gridDim.x * blockDim.x) {
+        const uint2 en = S.ent[b][e];
+        if (en.y == 0u) continue;  // a slot a wave held but did not use
+        S.sent[atomicAdd(S.cursor + S.ent_tile[b][e], 1u)] = en;
+    }
+}
+
+// ---- the sweep ------------------------------------------------------------------
+// The tile's density into LDS and its tally cleared: 16-byte loads, eight in
+// flight per thread, when the tile lies inside the grid and its rows are
+// aligned; otherwise cell by cell.
+template <typename R>
+__device__ __forceinline__ void load_tile(const TransportParams<R>& P, int o0, int o1, int o2, int txy,
+                                          int tz, R* rho_t, double* acc_t, double* acc2_t) {
+    constexpr int VW = 16 / (int)sizeof(R);
+    using V = typename std::conditional<sizeof(R) == 4, float4, double2>::type;
+    const int tcells = txy * txy * tz;
+    const bool vec = o0 + txy <= P.n[0] && o1 + txy <= P.n[1] && o2 + tz <= P.n[2] && P.n[0] % VW == 0 &&
+                     txy % VW == 0;
+    if (vec) {
+        const int nv = tcells / VW, per_row = txy / VW;
+        const int bd = (int)blockDim.x;
+        auto src = [&](int q) {
+            const int row = q / per_row, part = q - row * per_row;
+            const int ly = row % txy, lz = row / txy;
+            return reinterpret_cast<const V*>(
+                P.rho + ((o0 + part * VW) + (int64_t)P.n[0] * ((o1 + ly) + (int64_t)P.n[1] * (o2 + lz))));
+        };
+        int q0 = threadIdx.x;
+        // batches of eight loads in flight, then the rest one at a time
+        for (; q0 + 7 * bd < nv; q0 += 8 * bd) {
+            V v0 = *src(q0), v1 = *src(q0 + bd), v2 = *src(q0 + 2 * bd), v3 = *src(q0 + 3 * bd);
+            V v4 = *src(q0 + 4 * bd), v5 = *src(q0 + 5 * bd), v6 = *src(q0 + 6 * bd), v7 = *src(q0 + 7 * bd);
+            V* r = reinterpret_cast<V*>(rho_t);
+            r[q0] = v0; r[q0 + bd] = v1; r[q0 + 2 * bd] = v2; r[q0 + 3 * bd] = v3;
+            r[q0 + 4 * bd] = v4; r[q0 + 5 * bd] = v5; r[q0 + 6 * bd] = v6; r[q0 + 7 * bd] = v7;
+        }
+        for (; q0 < nv; q0 += bd) reinterpret_cast<V*>(rho_t)[q0] = *src(q0);
+    } else {
+        for (int i = threadIdx.x; i < tcells; i += blockDim.x) {
+            const int lx = i % txy, ly = (i / txy) % txy, lz = i / (txy * txy);
+            const int gx = o0 + lx, gy = o1 + ly, gz = o2 + lz;
+            R r = (R)0;
+            if (gx < P.n[0] && gy < P.n[1] && gz < P.n[2])
+                r = P.rho[gx + (int64_t)P.n[0] * (gy + (int64_t)P.n[1] * gz)];
+            rho_t[i] = r;
+        }
+    }
+    // the FP64 tally (and sum of squares) cleared, 16 bytes at a time
+    const int nd = (acc2_t ? 2 : 1) * tcells;  // doubles; the two arrays are adjacent
+    const double2 z2 = make_double2(0.0, 0.0);
+    for (int i = threadIdx.x; i < nd / 2; i += blockDim.x) reinterpret_cast<double2*>(acc_t)[i] = z2;
+    if ((nd & 1) && threadIdx.x == 0) acc_t[nd - 1] = 0.0;
+}
+
+// The tile's LDS partial sums into the FP64 tally (cells of this tile only).
+template <typename R>
+__device__ __forceinline__ void flush_tile(const TransportParams<R>& P, int o0, int o1, int o2, int txy,
+                                           int tcells, const double* acc_t, const double* acc2_t) {
     for (int i = threadIdx.x; i < tcells; i += blockDim.x) {
-        const R a = acc_t[i];
+        const double a = acc_t[i];
         const double a2 = acc2_t ? acc2_t[i] : 0.0;
-        if (a != (R)0 || a2 != 0.0) {
+        if (a != 0.0 || a2 != 0.0) {
             const int lx = i % txy, ly = (i / txy) % txy, lz = i / (txy * txy);
             const int64_t j = (o0 + lx) + (int64_t)P.n[0] * ((o1 + ly) + (int64_t)P.n[1] * (o2 + lz));
-            if (a != (R)0) unsafeAtomicAdd(P.acc + j, (double)a);
+            if (a != 0.0) unsafeAtomicAdd(P.acc + j, a);
             if (a2 != 0.0) unsafeAtomicAdd(P.acc2 + j, a2);
         }
     }
-    __syncthreads();
-    if (threadIdx.x < 7) s_nb[threadIdx.x] = 0u;
 }
 
-// One sweep over the work items (persistent workgroups; in FP32 of up to 512
-// threads, so that one group of 8 waves can hold a 32x32x16 tile, 128 KB of
-// LDS; the FP64 walk keeps its registers at 256 threads).
-template <typename R, int K>
-__global__ void __launch_bounds__(sizeof(R) == 4 ? 512 : 256) k_sweep(TransportParams<R> P, SweepParams S) {
-    extern __shared__ unsigned char smem_raw[];
-    __shared__ unsigned s_item, s_next;
-    __shared__ unsigned s_nb[7];  // records leaving for this tile, -x, +x, -y, +y, -z, +z
+// One sweep: reads the records of buffer b (entries grouped in S.sent),
+// writes the records that stay in flight into buffer b^1.  Persistent
+// workgroups; in FP32 of up to 512 threads, so that one group of 8 waves can
+// hold a 32x32x16 tile (128 KB of LDS); the FP64 walk keeps 256 threads.
+template <typename R, bool NOISE, bool FULL>
+__global__ void __launch_bounds__(sizeof(R) == 4 ? 512 : 256) k_sweep(TransportParams<R> P, SweepParams S,
+                                                                      int b) {
+    constexpr int K = 4;
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    __shared__ unsigned s_item, s_enext, s_eend;
+    __shared__ uint2 s_ents[kMaxItemEnt];  // the item's entries
+    __shared__ unsigned s_tc[14];          // records, entries registered per destination slot
     __shared__ unsigned long long s_cnt[C_COUNT];
     __shared__ double s_energy[2];
+    const int bo = b ^ 1;  // the buffer this sweep writes
     const int txy = S.txy;
     const int tcells = txy * txy * S.tz;
-    // LDS: Sum w^2 (FP64, when kept), density, tally, staged tables
-    double* acc2_t = P.acc2 ? reinterpret_cast<double*>(smem_raw) : nullptr;
-    R* rho_t = reinterpret_cast<R*>(smem_raw + (P.acc2 ? tcells * sizeof(double) : 0));
-    R* acc_t = rho_t + tcells;
-    R* chi_t = acc_t + tcells;  // bin opacities
+    // LDS: Sum w^2 (FP64, when kept), density, tally, the bins' chi, kappa,
+    // albedo and g, the luminosity CDF and the coarse CDF indices (the host
+    // sizes the tile so that all of it fits): everything the walk and the
+    // events read per packet, so that no global load feeds the walk
+    double* acc_t = reinterpret_cast<double*>(smem_raw);
+    double* acc2_t = NOISE ? acc_t + tcells : nullptr;
+    R* rho_t = reinterpret_cast<R*>(acc_t + (NOISE ? 2 : 1) * tcells);
+    R* chi_t = rho_t + tcells;
     R* kap_t = chi_t + P.nnu;
-    R* sm_tab = kap_t + P.nnu;
+    R* alb_t = kap_t + P.nnu;
+    R* g_t = alb_t + P.nnu;
+    R* sm_tab = g_t + P.nnu;
     for (int i = threadIdx.x; i < P.nnu; i += blockDim.x) {
         chi_t[i] = P.chi[i];
         kap_t[i] = P.kap[i];
+        alb_t[i] = P.alb[i];
+        g_t[i] = P.g[i];
     }
     if (threadIdx.x < C_COUNT) s_cnt[threadIdx.x] = 0ull;
     if (threadIdx.x < 2) s_energy[threadIdx.x] = 0.0;
-    Tables<R> tb;
-    if (P.lds_tables) {
-        const int ne = kRows * P.ngroup, ns = P.nsrc * P.ngroup;
-        for (int i = threadIdx.x; i < P.nsrc; i += blockDim.x) sm_tab[i] = P.lcdf[i];
-        for (int i = threadIdx.x; i < ne; i += blockDim.x) sm_tab[P.nsrc + i] = P.ecoarse[i];
-        for (int i = threadIdx.x; i < ns; i += blockDim.x) sm_tab[P.nsrc + ne + i] = P.scoarse[i];
-        tb.lcdf = sm_tab;
-        tb.ecoarse = sm_tab + P.nsrc;
-        tb.scoarse = sm_tab + P.nsrc + ne;
-    } else {
-        tb.lcdf = P.lcdf;
-        tb.ecoarse = P.ecoarse;
-        tb.scoarse = P.scoarse;
-    }
-    uint32_t cnt[C_COUNT] = {0, 0, 0, 0, 0, 0};
+    const int ne = kRows * P.ngroup, ns = P.nsrc * P.ngroup;
+    for (int i = threadIdx.x; i < P.nsrc; i += blockDim.x) sm_tab[i] = P.lcdf[i];
+    for (int i = threadIdx.x; i < ne; i += blockDim.x) sm_tab[P.nsrc + i] = P.ecoarse[i];
+    for (int i = threadIdx.x; i < ns; i += blockDim.x) sm_tab[P.nsrc + ne + i] = P.scoarse[i];
+    const Tables<R> tb{sm_tab, sm_tab + P.nsrc, sm_tab + P.nsrc + ne, chi_t, kap_t, alb_t, g_t};
+    uint32_t cnt[C_COUNT] = {0, 0, 0, 0, 0, 0, 0};
     double e_escaped = 0.0, e_killed = 0.0;
     const int lane = __lane_id();
-    const int defer = P.defer_lanes;
-    const PacketRec<R>* in = reinterpret_cast<const PacketRec<R>*>(S.in);
+    const int service = S.service;
+    const uint4* in = S.recs[b];
     Stream<R> rs;
     rs.k0 = P.key0;
     rs.k1 = P.key1;
     rs.n = 0;
     rs.p0 = rs.p1 = rs.s0 = rs.s1 = 0;
-    const unsigned n_items = S.item_off[S.ntiles];
-    if (threadIdx.x < 7) s_nb[threadIdx.x] = 0u;
+    const unsigned n_items = S.ctl->n_items;
     int tile = -1;  // the tile held in LDS (block-uniform)
     int o0 = 0, o1 = 0, o2 = 0;
+    WaveOut wo;
+    wave_out_init(wo);
+    if (threadIdx.x < 14) s_tc[threadIdx.x] = 0u;
 
     for (;;) {
         __syncthreads();
-        if (threadIdx.x == 0) s_item = atomicAdd(S.item_next, 1u);
+        if (threadIdx.x == 0) s_item = atomicAdd(&S.ctl->item_next, 1u);
         __syncthreads();
         const unsigned item = s_item;
         if (item >= n_items) break;
@@ -450,7 +883,13 @@ __global__ void __launch_bounds__(sizeof(R) == 4 ? 512 : 256) k_sweep(TransportP
         if (lo != tile) {
             // an item of the tile already in LDS keeps it; otherwise the tile
             // in LDS goes out before the item's tile comes in
-            if (tile >= 0) flush_tile(P, S, tile, o0, o1, o2, txy, tcells, acc_t, acc2_t, s_nb);
+            if (tile >= 0) {
+                chunks_close(S, bo, tile, wo, s_tc, lane);
+                __syncthreads();
+                flush_tile_counts(S, tile, s_tc);
+                flush_tile(P, o0, o1, o2, txy, tcells, acc_t, acc2_t);
+                __syncthreads();
+            }
             tile = lo;
             const int tzi = tile / (S.ntx * S.nty);
             const int trem = tile - tzi * S.ntx * S.nty;
@@ -458,62 +897,31 @@ __global__ void __launch_bounds__(sizeof(R) == 4 ? 512 : 256) k_sweep(TransportP
             o0 = txi * txy;
             o1 = tyi * txy;
             o2 = tzi * S.tz;
-            for (int i = threadIdx.x; i < tcells; i += blockDim.x) {
-                const int lx = i % txy, ly = (i / txy) % txy, lz = i / (txy * txy);
-                const int gx = o0 + lx, gy = o1 + ly, gz = o2 + lz;
-                R r = (R)0;
-                if (gx < P.n[0] && gy < P.n[1] && gz < P.n[2])
-                    r = P.rho[gx + (int64_t)P.n[0] * (gy + (int64_t)P.n[1] * gz)];
-                rho_t[i] = r;
-                acc_t[i] = (R)0;
-                if (acc2_t) acc2_t[i] = 0.0;
+            load_tile(P, o0, o1, o2, txy, S.tz, rho_t, acc_t, acc2_t);
+        }
+        {
+            const unsigned e0 = S.ent_off[tile] + (item - S.item_off[tile]) * (unsigned)S.item_ent;
+            const unsigned e1 = min(e0 + (unsigned)S.item_ent, S.ent_off[tile + 1]);
+            if (threadIdx.x < e1 - e0) s_ents[threadIdx.x] = S.sent[e0 + threadIdx.x];
+            if (threadIdx.x == 0) {
+                s_enext = 0u;
+                s_eend = e1 - e0;
             }
         }
-        if (threadIdx.x == 0) s_next = 0u;
         __syncthreads();
-        const unsigned first = S.tile_off[tile] + (item - S.item_off[tile]) * S.item;
-        const unsigned end = min(first + S.item, S.tile_off[tile + 1]);
 
+        // the wave's current entry: records [eb + ep, eb + ec) not yet handed out
+        unsigned eb = 0u, ec = 0u, ep = 0u;
+        bool drained = false;  // the item has no entry left for this wave (wave-uniform)
         Packet<R> s;
         s.st = ST_EMPTY;
-        int jl = 0;       // the packet's cell in LDS
-        R rho = (R)0;     // and its density
+        Raw<R> nx;             // the record this lane walks next
+        bool hn = false;       // nx holds one
+        int jl = 0;            // the packet's cell in LDS
+        R rho = (R)0;          // and its density
         int visit = 0;
-        bool drained = false;  // this item's records are all taken (wave-uniform)
         for (;;) {
-            const unsigned long long need = __ballot(s.st == ST_EMPTY);
-            if (need) {
-                const int leader = __ffsll((long long)need) - 1;
-                unsigned base = 0;
-                if (lane == leader) base = atomicAdd(&s_next, (unsigned)__popcll(need));
-                base = __shfl(base, leader);
-                if (s.st == ST_EMPTY) {
-                    const unsigned slot = first + base + (unsigned)__popcll(need & __lanemask_lt());
-                    if (slot < end) {
-                        unpack_rec(s, rs, P, in[S.order[slot]], chi_t, kap_t);
-                        jl = tile_index(s.c0, s.c1, s.c2, o0, o1, o2, txy);
-                        rho = rho_t[jl];
-                        visit = 0;
-                        // a record is always mid-walk or at a pending event
-                        if (s.st != ST_WALK && s.st != ST_EVENT) s.st = ST_DONE;
-                    } else {
-                        s.st = ST_DONE;
-                    }
-                }
-            }
-            if (__ballot(s.st != ST_DONE) == 0ull) break;
-            drained = drained || __ballot(s.st == ST_DONE) != 0ull;
-            for (;;) {
-                if (s.st == ST_WALK) {
-                    // Sum w^2 is kept (the tally's noise estimate) or not for the whole launch
-                    if (acc2_t)
-                        walk_tile<R, K, true>(s, P, o0, o1, o2, txy, S.tz, rho_t, acc_t, acc2_t, cnt, jl, rho);
-                    else
-                        walk_tile<R, K, false>(s, P, o0, o1, o2, txy, S.tz, rho_t, acc_t, nullptr, cnt, jl, rho);
-                }
-                if (__ballot(s.st == ST_WALK) == 0ull) break;
-                if (__popcll(__ballot(s.st != ST_WALK && s.st != ST_DONE)) >= defer) break;
-            }
+            // events, escapes, exits
             if (s.st == ST_EVENT) {
                 // a packet yields (back to this tile's queue for the next sweep)
                 // after visit_events interactions in this visit, or after
@@ -525,133 +933,76 @@ __global__ void __launch_bounds__(sizeof(R) == 4 ? 512 : 256) k_sweep(TransportP
                     s.st = ST_YIELD;
                 } else {
                     ++visit;
-                    interact(s, rs, P, tb, cnt, e_killed, TileDeposit<R>{acc_t, acc2_t, o0, o1, o2, txy});
+                    interact<R, TileDeposit<R>, FULL>(s, rs, P, tb, cnt, e_killed,
+                                                      TileDeposit<R>{acc_t, acc2_t, o0, o1, o2, txy});
                 }
             }
-            if (s.st == ST_ESC) escape(s, P, cnt, e_escaped);
-            int dest;
-            append_moves(S, s, rs, lane, dest);
-            if (dest >= 0) {
-                int nb = 0;  // a packet moves at most one cell: this tile or a face neighbour
-                const int dt = dest - tile;
-                if (dt == -1) nb = 1;
-                else if (dt == 1) nb = 2;
-                else if (dt == -S.ntx) nb = 3;
-                else if (dt == S.ntx) nb = 4;
-                else if (dt == -S.ntx * S.nty) nb = 5;
-                else if (dt == S.ntx * S.nty) nb = 6;
-                atomicAdd(&s_nb[nb], 1u);
+            if (s.st == ST_ESC) escape<R, FULL>(s, P, cnt, e_escaped);
+            write_exits(S, bo, tile, s, rs, wo, s_tc, lane);
+            // free lanes take their next record
+            if (s.st == ST_EMPTY && hn) {
+                unpack_rec(s, rs, P, nx, tb.chi, tb.kap);
+                hn = false;
+                if (s.st != ST_EMPTY) {
+                    // a record always lies in the tile it was registered for;
+                    // anything else is dropped and reported
+                    if ((unsigned)(s.c0 - o0) >= (unsigned)txy || (unsigned)(s.c1 - o1) >= (unsigned)txy ||
+                        (unsigned)(s.c2 - o2) >= (unsigned)S.tz || !in_grid(P, s.c0, s.c1, s.c2)) {
+                        atomicOr(&S.ctl->overflow, 2u);
+                        s.st = ST_EMPTY;
+                    } else {
+                        jl = tile_index(s.c0, s.c1, s.c2, o0, o1, o2, txy);
+                        rho = rho_t[jl];
+                        visit = 0;
+                    }
+                }
             }
-        }
-    }
-    if (tile >= 0) flush_tile(P, S, tile, o0, o1, o2, txy, tcells, acc_t, acc2_t, s_nb);
-    flush_block_counters(P, cnt, e_escaped, e_killed, s_cnt, s_energy);
-}
-
-// ---- grouping the written records by tile ---------------------------------
-// (the counts per tile were taken while the records were written)
-
-// exclusive scans of the counts (records and work items), cursors, and the
-// counters of the next sweep; one block
-__global__ void __launch_bounds__(1024) k_tile_scan(unsigned* __restrict__ counts, int ntiles,
-                                                    unsigned kItem,
-                                                    unsigned* __restrict__ tile_off,
-                                                    unsigned* __restrict__ item_off,
-                                                    unsigned* __restrict__ cursor,
-                                                    unsigned* __restrict__ item_next) {
-    __shared__ unsigned s_a[1024], s_b[1024];
-    const int per = (ntiles + (int)blockDim.x - 1) / (int)blockDim.x;
-    const int t0 = threadIdx.x * per;
-    unsigned ra = 0, rb = 0;
-    for (int t = t0; t < t0 + per && t < ntiles; ++t) {
-        ra += counts[t];
-        rb += (counts[t] + kItem - 1) / kItem;
-    }
-    s_a[threadIdx.x] = ra;
-    s_b[threadIdx.x] = rb;
-    __syncthreads();
-    for (int o = 1; o < (int)blockDim.x; o <<= 1) {
-        const unsigned va = threadIdx.x >= (unsigned)o ? s_a[threadIdx.x - o] : 0u;
-        const unsigned vb = threadIdx.x >= (unsigned)o ? s_b[threadIdx.x - o] : 0u;
-        __syncthreads();
-        s_a[threadIdx.x] += va;
-        s_b[threadIdx.x] += vb;
-        __syncthreads();
-    }
-    unsigned pa = s_a[threadIdx.x] - ra, pb = s_b[threadIdx.x] - rb;  // exclusive
-    for (int t = t0; t < t0 + per && t < ntiles; ++t) {
-        const unsigned c = counts[t];
-        tile_off[t] = pa;
-        cursor[t] = pa;
-        item_off[t] = pb;
-        pa += c;
-        pb += (c + kItem - 1) / kItem;
-        counts[t] = 0u;
-    }
-    if (threadIdx.x == blockDim.x - 1) {
-        tile_off[ntiles] = s_a[threadIdx.x];
-        item_off[ntiles] = s_b[threadIdx.x];
-        *item_next = 0u;
-    }
-}
-
-// order[cursor[tile]++] = record index.  A block takes kOrderChunk consecutive
-// records (written by a few hundred waves, so they fall into few tiles), counts
-// them per tile in an LDS hash table, reserves each tile's range with one global
-// atomic, and places every record at its reserved base + its rank in the block.
-// A record whose tile finds no free hash slot takes its position directly.
-constexpr int kOrderChunk = 4096;
-constexpr int kOrderHash = 1024;
-
-__global__ void __launch_bounds__(256) k_tile_order(const unsigned* __restrict__ out_tile,
-                                                    const unsigned* __restrict__ n_out,
-                                                    unsigned* __restrict__ cursor,
-                                                    unsigned* __restrict__ order) {
-    __shared__ unsigned h_key[kOrderHash], h_cnt[kOrderHash];
-    constexpr int per = kOrderChunk / 256;
-    const unsigned n = *n_out;
-    for (unsigned c0 = blockIdx.x * (unsigned)kOrderChunk; c0 < n; c0 += gridDim.x * (unsigned)kOrderChunk) {
-        for (int i = threadIdx.x; i < kOrderHash; i += blockDim.x) {
-            h_key[i] = 0xffffffffu;
-            h_cnt[i] = 0u;
-        }
-        __syncthreads();
-        int slot[per];
-        unsigned rank[per];
-#pragma unroll
-        for (int j = 0; j < per; ++j) {
-            const unsigned i = c0 + (unsigned)(j * 256) + threadIdx.x;
-            slot[j] = -1;
-            rank[j] = 0u;
-            const unsigned t = i < n ? out_tile[i] : kNoTile;
-            if (t != kNoTile) {
-                unsigned h = (t * 2654435761u) >> 22;
-                int found = -1;
-                for (int probe = 0; probe < kOrderHash; ++probe) {
-                    const unsigned k = atomicCAS(&h_key[h], 0xffffffffu, t);
-                    if (k == 0xffffffffu || k == t) {
-                        found = (int)h;
+            // and lanes without a next record claim one from the wave's entry
+            for (;;) {
+                const unsigned long long need = __ballot(!hn);
+                if (need == 0ull || drained) break;
+                if (ep == ec) {
+                    unsigned e = 0u;
+                    if (lane == 0) e = atomicAdd(&s_enext, 1u);
+                    e = (unsigned)__shfl((int)e, 0);
+                    if (e >= s_eend) {
+                        drained = true;
                         break;
                     }
-                    h = (h + 1u) & (kOrderHash - 1);
+                    const uint2 en = s_ents[e];
+                    eb = (unsigned)__builtin_amdgcn_readfirstlane(en.x);
+                    ec = (unsigned)__builtin_amdgcn_readfirstlane(en.y);
+                    ep = 0u;
+                    continue;
                 }
-                if (found >= 0) {
-                    slot[j] = found;
-                    rank[j] = atomicAdd(&h_cnt[found], 1u);
-                } else {
-                    order[atomicAdd(cursor + t, 1u)] = i;  // table full
+                const unsigned avail = ec - ep;
+                const unsigned rank = (unsigned)__popcll(need & __lanemask_lt());
+                if (!hn && rank < avail) {
+                    load_raw(S, in, eb + ep + rank, nx);
+                    hn = true;
                 }
+                const unsigned n = (unsigned)__popcll(need);
+                ep += n < avail ? n : avail;
+            }
+            if (__ballot(s.st != ST_EMPTY || hn) == 0ull && drained) break;
+            // walk until `service` lanes wait (or none walks)
+            for (;;) {
+                if (s.st == ST_WALK) walk_tile<R, K, NOISE>(s, P, o0, o1, o2, txy, S.tz, rho_t, acc_t, acc2_t,
+                                                              cnt, jl, rho);
+                if (__ballot(s.st == ST_WALK) == 0ull) break;
+                const bool wait = s.st != ST_WALK && (s.st != ST_EMPTY || hn || !drained);
+                if (__popcll(__ballot(wait)) >= service) break;
             }
         }
-        __syncthreads();
-        for (int e = threadIdx.x; e < kOrderHash; e += blockDim.x)
-            if (h_cnt[e]) h_cnt[e] = atomicAdd(cursor + h_key[e], h_cnt[e]);  // count -> base
-        __syncthreads();
-#pragma unroll
-        for (int j = 0; j < per; ++j)
-            if (slot[j] >= 0) order[h_cnt[slot[j]] + rank[j]] = c0 + (unsigned)(j * 256) + threadIdx.x;
-        __syncthreads();
     }
+    if (tile >= 0) {
+        chunks_close(S, bo, tile, wo, s_tc, lane);
+        __syncthreads();
+        flush_tile_counts(S, tile, s_tc);
+        flush_tile(P, o0, o1, o2, txy, tcells, acc_t, acc2_t);
+    }
+    wave_out_release(S, bo, wo, lane);
+    flush_block_counters(P, cnt, e_escaped, e_killed, s_cnt, s_energy);
 }
 
 __global__ void k_fill_u32(unsigned* p, int n, unsigned v) {
@@ -659,59 +1010,44 @@ __global__ void k_fill_u32(unsigned* p, int n, unsigned v) {
 }
 
 // ---------------------------------------------------------------------------
-size_t sweep_record_bytes(int fp32) {
-    return fp32 ? sizeof(PacketRec<float>) : sizeof(PacketRec<double>);
-}
+size_t sweep_record_bytes(int fp32) { return 16u * (fp32 ? Rec<float>::NQ : Rec<double>::NQ); }
 
-template <typename R> using SweepFn = void (*)(TransportParams<R>, SweepParams);
+template <typename R> using SweepFn = void (*)(TransportParams<R>, SweepParams, int);
 
-template <typename R> SweepFn<R> pick_sweep(int K) {
-    switch (K) {
-        case 1: return k_sweep<R, 1>;
-        case 2: return k_sweep<R, 2>;
-        default: return k_sweep<R, 4>;
-    }
+template <typename R> SweepFn<R> pick_sweep(bool noise, bool full) {
+    if (noise) return full ? k_sweep<R, true, true> : k_sweep<R, true, false>;
+    return full ? k_sweep<R, false, true> : k_sweep<R, false, false>;
 }
 
 template <typename R>
-hipError_t launch_sweep_emit(const TransportParams<R>& P, const SweepParams& S, uint64_t first,
-                             uint64_t count, unsigned base, int blocks, hipStream_t st) {
-    const int hist = S.ntiles <= kEmitHistTiles ? 1 : 0;
-    hipLaunchKernelGGL(k_sweep_emit<R>, dim3(blocks), dim3(256), hist ? S.ntiles * sizeof(unsigned) : 0, st,
-                       P, S, first, count, base, hist);
+hipError_t launch_sweep_step(const TransportParams<R>& P, const SweepParams& S, int b, bool full,
+                             int emit_blocks, int group_blocks, int blocks, int threads, size_t lds,
+                             hipStream_t st) {
+    hipLaunchKernelGGL(k_refill_plan, dim3(1), dim3(1024), 0, st, S, b);
+    if (full) hipLaunchKernelGGL((k_sweep_emit<R, true>), dim3(emit_blocks), dim3(kEmitThreads), 0, st, P, S, b);
+    else hipLaunchKernelGGL((k_sweep_emit<R, false>), dim3(emit_blocks), dim3(kEmitThreads), 0, st, P, S, b);
+    hipLaunchKernelGGL(k_sweep_scan, dim3(1), dim3(1024), 0, st, S, b);
+    hipLaunchKernelGGL(k_sweep_group, dim3(group_blocks), dim3(256), 0, st, S, b);
+    hipLaunchKernelGGL(pick_sweep<R>(P.acc2 != nullptr, full), dim3(blocks), dim3(threads), lds, st, P, S, b);
     return hipGetLastError();
 }
 
-template <typename R>
-hipError_t launch_sweep(const TransportParams<R>& P, const SweepParams& S, int K, int blocks,
-                        int threads, size_t lds, hipStream_t st) {
-    if (lds > 65536) {
-        hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(pick_sweep<R>(K)),
-                                           hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-        if (e != hipSuccess) return e;
-    }
-    hipLaunchKernelGGL(pick_sweep<R>(K), dim3(blocks), dim3(threads), lds, st, P, S);
-    return hipGetLastError();
+template <typename R> hipError_t sweep_prepare(bool noise, bool full, size_t lds) {
+    if (lds <= 65536) return hipSuccess;
+    return hipFuncSetAttribute(reinterpret_cast<const void*>(pick_sweep<R>(noise, full)),
+                               hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
 }
 
-template <typename R> int sweep_max_blocks_per_cu(int K, int threads, size_t lds) {
+template <typename R> int sweep_max_blocks_per_cu(bool noise, bool full, int threads, size_t lds) {
     int nb = 0;
-    if (lds > 65536)
-        hipFuncSetAttribute(reinterpret_cast<const void*>(pick_sweep<R>(K)),
-                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, pick_sweep<R>(K), threads, lds) != hipSuccess)
+    if (sweep_prepare<R>(noise, full, lds) != hipSuccess) return 1;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, pick_sweep<R>(noise, full), threads, lds) !=
+        hipSuccess)
         return 1;
     return nb > 0 ? nb : 1;
 }
 
-hipError_t launch_tile_sort(const SweepParams& S, unsigned* order, unsigned* tile_off,
-                            unsigned* item_off, unsigned* cursor, int blocks, hipStream_t st) {
-    hipLaunchKernelGGL(k_tile_scan, dim3(1), dim3(1024), 0, st, S.counts, S.ntiles, S.item, tile_off,
-                       item_off, cursor, S.item_next);
-    hipLaunchKernelGGL(k_tile_order, dim3(blocks), dim3(256), 0, st, S.out_tile, S.out_count, cursor,
-                       order);
-    return hipGetLastError();
-}
+int sweep_emit_step() { return kEmitStep; }
 
 hipError_t launch_fill_u32(unsigned* p, int n, unsigned v, hipStream_t st) {
     hipLaunchKernelGGL(k_fill_u32, dim3((n + 255) / 256 < 1024 ? (n + 255) / 256 : 1024), dim3(256), 0,
@@ -719,15 +1055,13 @@ hipError_t launch_fill_u32(unsigned* p, int n, unsigned v, hipStream_t st) {
     return hipGetLastError();
 }
 
-template hipError_t launch_sweep_emit<float>(const TransportParams<float>&, const SweepParams&,
-                                             uint64_t, uint64_t, unsigned, int, hipStream_t);
-template hipError_t launch_sweep_emit<double>(const TransportParams<double>&, const SweepParams&,
-                                              uint64_t, uint64_t, unsigned, int, hipStream_t);
-template hipError_t launch_sweep<float>(const TransportParams<float>&, const SweepParams&, int, int,
-                                        int, size_t, hipStream_t);
-template hipError_t launch_sweep<double>(const TransportParams<double>&, const SweepParams&, int,
-                                         int, int, size_t, hipStream_t);
-template int sweep_max_blocks_per_cu<float>(int, int, size_t);
-template int sweep_max_blocks_per_cu<double>(int, int, size_t);
+template hipError_t launch_sweep_step<float>(const TransportParams<float>&, const SweepParams&, int, bool,
+                                             int, int, int, int, size_t, hipStream_t);
+template hipError_t launch_sweep_step<double>(const TransportParams<double>&, const SweepParams&, int, bool,
+                                              int, int, int, int, size_t, hipStream_t);
+template hipError_t sweep_prepare<float>(bool, bool, size_t);
+template hipError_t sweep_prepare<double>(bool, bool, size_t);
+template int sweep_max_blocks_per_cu<float>(bool, bool, int, size_t);
+template int sweep_max_blocks_per_cu<double>(bool, bool, int, size_t);
 
 }  // namespace mcrt

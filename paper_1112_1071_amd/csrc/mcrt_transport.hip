@@ -38,7 +38,7 @@ __global__ void __launch_bounds__(256) k_transport(TransportParams<R> P) {
     __shared__ double s_energy[2];
     if (threadIdx.x < C_COUNT) s_cnt[threadIdx.x] = 0ull;
     if (threadIdx.x < 2) s_energy[threadIdx.x] = 0.0;
-    Tables<R> tb;
+    Tables<R> tb = global_tables(P);
     if (P.lds_tables) {
         R* sm = reinterpret_cast<R*>(smem_raw);
         const int ne = kRows * P.ngroup, ns = P.nsrc * P.ngroup;
@@ -253,7 +253,7 @@ k_transport_batch(const TransportParams<R>* __restrict__ Ps,
                     lm = wm;
                 }
                 const TransportParams<R>& P = Ps[lm];
-                const Tables<R> tb{P.lcdf, P.ecoarse, P.scoarse};
+                const Tables<R> tb = global_tables(P);
                 rs.k0 = P.key0;
                 rs.k1 = keys[lm];
                 emit(s, rs, P, tb, wbase + (uint64_t)rank, cnt, e_killed, global_deposit<BRICK>(P, P.acc));
@@ -280,7 +280,7 @@ k_transport_batch(const TransportParams<R>* __restrict__ Ps,
             if (__ballot(s.st == ST_WALK) == 0ull) break;
             if (__popcll(__ballot(s.st == ST_EVENT || s.st == ST_ESC)) >= defer) break;
         }
-        const Tables<R> tb{P.lcdf, P.ecoarse, P.scoarse};
+        const Tables<R> tb = global_tables(P);
         if (s.st == ST_EVENT) interact(s, rs, P, tb, cnt, e_killed, global_deposit<BRICK>(P, acc));
         if (s.st == ST_ESC) escape(s, P, cnt, e_escaped);
     }
@@ -332,5 +332,30 @@ template hipError_t launch_transport_batch<float>(const TransportParams<float>*,
                                                   int, int, hipStream_t);
 template int batch_max_blocks_per_cu<double>(int, int, int);
 template int batch_max_blocks_per_cu<float>(int, int, int);
+
+// ---------------------------------------------------------------------------
+// The direction update of a scattering (Sec. 2.2, Henyey-Greenstein angle mu
+// and azimuth phi about the incoming direction), n directions at a time, in
+// the transport precision R: the device function every transport kernel uses.
+// ---------------------------------------------------------------------------
+template <typename R>
+__global__ void k_rotate(const double* __restrict__ d, const double* __restrict__ mu,
+                         const double* __restrict__ phi, double* __restrict__ out, int n) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    R d0 = (R)d[3 * i], d1 = (R)d[3 * i + 1], d2 = (R)d[3 * i + 2];
+    rotate_dir<R>(d0, d1, d2, (R)mu[i], (R)phi[i]);
+    out[3 * i] = (double)d0;
+    out[3 * i + 1] = (double)d1;
+    out[3 * i + 2] = (double)d2;
+}
+
+hipError_t launch_rotate(int fp32, const double* d, const double* mu, const double* phi, double* out,
+                         int n, hipStream_t st) {
+    const int blocks = (n + 255) / 256;
+    if (fp32) hipLaunchKernelGGL(k_rotate<float>, dim3(blocks), dim3(256), 0, st, d, mu, phi, out, n);
+    else hipLaunchKernelGGL(k_rotate<double>, dim3(blocks), dim3(256), 0, st, d, mu, phi, out, n);
+    return hipGetLastError();
+}
 
 }  // namespace mcrt

@@ -40,7 +40,7 @@ class RunCfg(C.Structure):
         ("blocks_per_cu", C.c_int32), ("defer_lanes", C.c_int32), ("walk_batch", C.c_int32),
         ("grid_layout", C.c_int32), ("tally_copies", C.c_int32),
         ("transport_mode", C.c_int32), ("tile_z", C.c_int32), ("visit_events", C.c_int32),
-        ("tile_xy", C.c_int32), ("mrw_gamma", C.c_double),
+        ("tile_xy", C.c_int32), ("mrw_gamma", C.c_double), ("sweep_batch", C.c_int64),
     ]
 
 
@@ -152,6 +152,7 @@ def lib():
         "mcrt_get_images": ([vp, vp, vp, sz], i32),
         "mcrt_get_event_log": ([vp, vp, sz, vp, sz], i32),
         "mcrt_device_info": ([vp, C.POINTER(i32), C.POINTER(i32)], i32),
+        "mcrt_scatter_directions": ([vp, i32, vp, vp, vp, vp, i32], i32),
         "mcrt_raytrace": ([vp, i32, dbl], i32),
         "mcrt_apply_pda": ([vp, dbl, i32, C.POINTER(PdaStats)], i32),
         "mcrt_get_raytraced_sed": ([vp, vp, sz], i32),
@@ -368,6 +369,17 @@ class Model:
         n, w = C.c_int(), C.c_int()
         self._check(self.L.mcrt_device_info(self.h, C.byref(n), C.byref(w)))
         return n.value, w.value
+
+    def scatter_directions(self, d, mu, phi, precision=MCRT_FP64):
+        """Directions after scatterings (unit vectors d [n,3], cos angle mu,
+        azimuth phi) computed by the transport's device function."""
+        d = np.ascontiguousarray(d, dtype=np.float64).reshape(-1, 3)
+        mu = np.ascontiguousarray(mu, dtype=np.float64).ravel()
+        phi = np.ascontiguousarray(phi, dtype=np.float64).ravel()
+        out = np.zeros_like(d)
+        self._check(self.L.mcrt_scatter_directions(self.h, int(precision), _ptr(d), _ptr(mu),
+                                                   _ptr(phi), _ptr(out), d.shape[0]))
+        return out
 
     # -- learned warm start ----------------------------------------------------
     def apply_pda(self, noise: float, passes: int = 3) -> dict:

@@ -22,7 +22,7 @@ import sys
 from collections import defaultdict
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-TRANSPORT_KERNELS = ("k_transport", "k_sweep", "k_tile_order", "k_tile_scan", "k_fill_u32")
+TRANSPORT_KERNELS = ("k_transport", "k_sweep", "k_refill_plan", "k_fill_u32")
 TRANSPORT_SOURCES = ("mcrt_transport.hip", "mcrt_sweep.hip", "mcrt_packet.h", "mcrt_internal.h", "mcrt_api.cpp")
 
 

@@ -330,14 +330,14 @@ def test_launch_variants_same_stream(M, variant):
                                    dict()])
 def test_tiled_fp32_equals_persistent_fp32(M, tiles):
     # FP32 transport: both modes follow identical packet histories in the first
-    # iteration (same counters exactly); the tiled mode sums a tile's visits in
-    # FP32 before the FP64 flush, so Adot agrees to a few FP32 roundings per
-    # cell.  The second iteration re-emits from temperatures that already
-    # differ at that level, which can flip a rare emission-row choice; a
-    # flipped packet takes another path from there on, which moves the cells
-    # it crosses by about one packet's contribution, within their Monte-Carlo
-    # error: counters agree to 1e-4, Adot to 1e-4 in 99 % of the cells and
-    # within 3 sigma in 99.9 %.
+    # iteration (same counters exactly) and add the same FP32 products w l kappa
+    # into FP64 sums (the tiled mode in LDS, flushed to the FP64 tally), so
+    # Adot and its noise estimate agree to FP64 summation order (1e-9).  The
+    # second iteration re-emits from temperatures that differ at that level,
+    # which could flip a rare emission-row choice; a flipped packet takes
+    # another path from there on, moving the cells it crosses by about one
+    # packet's contribution, within their Monte-Carlo error: counters agree to
+    # 1e-4, Adot to 1e-4 in 99 % of the cells and within 3 sigma in 99.9 %.
     cfg = synth.config2(n=48, n_packets=400000, n_iter=2, gen_seed=45777, n_src=12,
                         box=0.65 * synth.PC * 48 / 128)
     a = M.Model(cfg, precision=M.MCRT_FP32_TRANSPORT, want_noise=1, transport_mode=0)
@@ -357,8 +357,8 @@ def test_tiled_fp32_equals_persistent_fp32(M, tiles):
         srel = np.abs(sgb[nz] - sga[nz]) / sga[nz]
         if it == 0:
             assert np.array_equal(aa > 0, ab > 0)
-            assert rel.max() < 1e-4 and srel.max() < 1e-3, it
-            np.testing.assert_allclose(b.temperature(), a.temperature(), rtol=1e-4)
+            assert rel.max() < 1e-9 and srel.max() < 1e-9, it
+            np.testing.assert_allclose(b.temperature(), a.temperature(), rtol=1e-9)
         else:
             z = np.abs(ab[nz] - aa[nz]) / np.sqrt(sga[nz] ** 2 + sgb[nz] ** 2)
             print(f"iteration {it}: rel q99 {np.quantile(rel, 0.99):.2e} q999 {np.quantile(rel, 0.999):.2e} "
