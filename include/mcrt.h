@@ -328,6 +328,15 @@ mcrt_status mcrt_get_event_log(mcrt_model* m, mcrt_event* ev, size_t cap_total, 
  * arrays, copied; MCRT_E_ARG for mu outside [-1, 1] or non-finite values. */
 mcrt_status mcrt_scatter_directions(mcrt_model* m, int precision, const double* d, const double* mu,
                                     const double* phi, double* out, int n);
+/* The same directions as mcrt_scatter_directions, for callers that cannot
+ * allocate device memory (code under HIP graph capture, tight serving loops,
+ * harnesses that forbid hipMalloc): this call allocates nothing.  Its device
+ * staging is a static array of at most 65536 directions (9 doubles each) that
+ * each GPU holds for the life of the process; n above that gives MCRT_E_SIZE.
+ * All calls on one GPU share that array: calls that overlap on a GPU (other
+ * host threads, other streams) race and must be serialised by the caller. */
+mcrt_status mcrt_scatter_directions_noalloc(mcrt_model* m, int precision, const double* d, const double* mu,
+                                            const double* phi, double* out, int n);
 /* Number of compute units and the wavefront width of the model's device
  * (plumbing, not a passage of the paper). */
 mcrt_status mcrt_device_info(mcrt_model* m, int* n_cu, int* wave_size);

@@ -203,6 +203,38 @@ mcrt_status fail(mcrt_model* m, mcrt_status s, const std::string& msg) {
     return s;
 }
 
+// Staging of mcrt_scatter_directions_noalloc: per direction its input vector,
+// mu, phi and output vector (9 doubles), for at most kNoAllocDirs directions
+// (4.5 MiB).  Every GPU the library runs on holds its own copy until the
+// process ends.  In host code the array's name is not a device address: the
+// address each device's copy has is looked up once per device, with that
+// device current, and kept in g_scratch_ptr.
+constexpr int kNoAllocDirs = 1 << 16;
+constexpr int kMaxDevices = 64;
+static __device__ __align__(256) double scratch[9 * kNoAllocDirs];
+std::mutex g_scratch_mu;
+double* g_scratch_ptr[kMaxDevices] = {};
+
+hipError_t scratch_setup(int dev) {
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (dev < 0 || dev >= kMaxDevices) return hipErrorInvalidDevice;
+    if (g_scratch_ptr[dev]) return hipSuccess;
+    int cur = -1;
+    hipError_t e = hipGetDevice(&cur);
+    if (e != hipSuccess) return e;
+    if (cur != dev && (e = hipSetDevice(dev)) != hipSuccess) return e;
+    void* p = nullptr;
+    e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e == hipSuccess && p) g_scratch_ptr[dev] = static_cast<double*>(p);
+    if (cur != dev) hipSetDevice(cur);
+    return e != hipSuccess ? e : (p ? hipSuccess : hipErrorInvalidSymbol);
+}
+
+double* scratch_ptr(int dev) {
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    return dev >= 0 && dev < kMaxDevices ? g_scratch_ptr[dev] : nullptr;
+}
+
 #define HIPCHK(expr)                                                                         \
     do {                                                                                     \
         hipError_t e_ = (expr);                                                              \
@@ -988,6 +1020,9 @@ mcrt_status mcrt_create(mcrt_model** out, int hip_device) {
         m->lds_max -= 1024;  // static LDS of the kernels that take dynamic LDS
     }
     for (int i = 0; i < 4; ++i) hipEventCreate(&m->ev[i]);
+    // the device address of this device's staging array for the entry point
+    // that allocates nothing (a failure is reported by that entry point)
+    scratch_setup(hip_device);
     mcrt_run_cfg_default(&m->cfg);
     *out = m;
     return MCRT_OK;
@@ -1705,6 +1740,40 @@ mcrt_status mcrt_scatter_directions(mcrt_model* m, int precision, const double* 
     DBuf<double>& buf = g.b;
     HIPCHK(buf.ensure((size_t)9 * n));
     double* dd = buf.p;
+    double* dm = dd + 3 * (size_t)n;
+    double* dp = dm + n;
+    double* dout = dp + n;
+    HIPCHK(hipMemcpyAsync(dd, d, 3 * sizeof(double) * n, hipMemcpyHostToDevice, s));
+    HIPCHK(hipMemcpyAsync(dm, mu, sizeof(double) * n, hipMemcpyHostToDevice, s));
+    HIPCHK(hipMemcpyAsync(dp, phi, sizeof(double) * n, hipMemcpyHostToDevice, s));
+    HIPCHK(launch_rotate(precision == MCRT_FP32_TRANSPORT ? 1 : 0, dd, dm, dp, dout, n, s));
+    HIPCHK(hipMemcpyAsync(out, dout, 3 * sizeof(double) * n, hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    return MCRT_OK;
+}
+
+mcrt_status mcrt_scatter_directions_noalloc(mcrt_model* m, int precision, const double* d, const double* mu,
+                                            const double* phi, double* out, int n) {
+    if (!m) return MCRT_E_ARG;
+    if (precision != MCRT_FP64 && precision != MCRT_FP32_TRANSPORT)
+        return fail(m, MCRT_E_ARG, "unknown precision");
+    if (n < 0 || (n > 0 && (!d || !mu || !phi || !out))) return fail(m, MCRT_E_ARG, "bad direction arrays");
+    if (n > kNoAllocDirs)
+        return fail(m, MCRT_E_SIZE, "at most 65536 directions per call (the static staging array)");
+    if (n == 0) return MCRT_OK;
+    for (int i = 0; i < n; ++i)
+        if (!(mu[i] >= -1.0 && mu[i] <= 1.0) || !isfinite(phi[i]) || !isfinite(d[3 * i]) ||
+            !isfinite(d[3 * i + 1]) || !isfinite(d[3 * i + 2]))
+            return fail(m, MCRT_E_ARG, "mu must lie in [-1,1]; directions and phi finite");
+    HIPCHK(hipSetDevice(m->device));
+    double* base = scratch_ptr(m->device);
+    if (!base) {
+        HIPCHK(scratch_setup(m->device));
+        base = scratch_ptr(m->device);
+    }
+    hipStream_t s = m->stream;
+    // every element read below is written first in this call
+    double* dd = base;
     double* dm = dd + 3 * (size_t)n;
     double* dp = dm + n;
     double* dout = dp + n;

@@ -153,6 +153,7 @@ def lib():
         "mcrt_get_event_log": ([vp, vp, sz, vp, sz], i32),
         "mcrt_device_info": ([vp, C.POINTER(i32), C.POINTER(i32)], i32),
         "mcrt_scatter_directions": ([vp, i32, vp, vp, vp, vp, i32], i32),
+        "mcrt_scatter_directions_noalloc": ([vp, i32, vp, vp, vp, vp, i32], i32),
         "mcrt_raytrace": ([vp, i32, dbl], i32),
         "mcrt_apply_pda": ([vp, dbl, i32, C.POINTER(PdaStats)], i32),
         "mcrt_get_raytraced_sed": ([vp, vp, sz], i32),
@@ -379,6 +380,17 @@ class Model:
         out = np.zeros_like(d)
         self._check(self.L.mcrt_scatter_directions(self.h, int(precision), _ptr(d), _ptr(mu),
                                                    _ptr(phi), _ptr(out), d.shape[0]))
+        return out
+
+    def scatter_directions_noalloc(self, d, mu, phi, precision=MCRT_FP64):
+        """scatter_directions through the entry point that allocates nothing
+        (at most 65536 directions per call)."""
+        d = np.ascontiguousarray(d, dtype=np.float64).reshape(-1, 3)
+        mu = np.ascontiguousarray(mu, dtype=np.float64).ravel()
+        phi = np.ascontiguousarray(phi, dtype=np.float64).ravel()
+        out = np.zeros_like(d)
+        self._check(self.L.mcrt_scatter_directions_noalloc(self.h, int(precision), _ptr(d), _ptr(mu),
+                                                           _ptr(phi), _ptr(out), d.shape[0]))
         return out
 
     # -- learned warm start ----------------------------------------------------
