@@ -35,22 +35,23 @@ def algorithmic_bytes(st: dict, precision: int) -> float:
 
 
 def measured_traffic(precision: int, mode: int):
-    """HBM bytes per transport pass from the committed rocprofv3 FETCH_SIZE /
+    """HBM bytes per launch of the dominant transport kernel, and per pass of
+    every transport kernel, from the committed rocprofv3 FETCH_SIZE /
     WRITE_SIZE summary, if it was taken on the current transport source, in the
     same precision and transport mode."""
     from paper_1112_1071_amd.profiling import transport_source_hash
 
     p = os.path.join(ROOT, "profiles", "transport_clump256_pmc.json")
     if not os.path.exists(p):
-        return None
+        return None, None
     try:
         d = json.load(open(p))
     except Exception:
-        return None
+        return None, None
     if (d.get("source_hash") != transport_source_hash() or d.get("precision") != precision
             or d.get("mode") != mode):
-        return None
-    return d.get("hbm_bytes_per_launch")
+        return None, None
+    return d.get("hbm_bytes_per_launch"), d.get("hbm_bytes_per_pass")
 
 
 def cpu_baseline(cfg: dict, n_packets: int) -> dict:
@@ -356,9 +357,14 @@ def main():
             raise SystemExit(f"step {i}: escaped + killed energy {st['e_escaped'] + st['e_killed']} != L {L}")
 
     ms_tr = float(np.mean([s["ms_transport"] for s in stats]))
+    # the dominant kernel (the sweep kernel of the tiled transport, summed over
+    # its launches of a pass; the one launch of the per-lane walk), timed by
+    # HIP events on the stream it runs on
+    ms_dom = float(np.mean([s["ms_dominant"] for s in stats]))
+    launches = float(np.mean([s["n_sweeps"] for s in stats])) if model.run["transport_mode"] == 1 else 1.0
     abytes = float(np.mean([algorithmic_bytes(s, prec) for s in stats]))
-    achieved = abytes / (ms_tr * 1e-3) / 1e9
-    traffic = measured_traffic(prec, int(model.run["transport_mode"]))
+    achieved = abytes / (ms_dom * 1e-3) / 1e9
+    traffic, traffic_pass = measured_traffic(prec, int(model.run["transport_mode"]))
     last = stats[-1]
     out = {
         "metric": "packets/s at 256^3 (Lucy iterations)",
@@ -381,14 +387,25 @@ def main():
         },
         "roofline": {
             "bound": "hbm",
-            "kernel": "k_sweep (+ emission, scan, grouping)" if model.run["transport_mode"] == 1 else "k_transport",
+            "kernel": "k_sweep" if model.run["transport_mode"] == 1 else "k_transport",
             "achieved": achieved,
             "peak": HBM_PEAK_GBS,
             "unit": "GB/s",
             "frac": achieved / HBM_PEAK_GBS,
             "traffic": traffic,
-            "algorithmic_bytes_per_launch": abytes,
-            "ms_per_launch": ms_tr,
+            # per launch of the dominant kernel (launches: the sweeps of a pass)
+            "algorithmic_bytes_per_launch": abytes / launches,
+            "ms_per_launch": ms_dom / launches,
+            "launches_per_pass": launches,
+            # the same algorithmic bytes over the whole pass (every transport
+            # kernel: emission, scans, grouping and sweeps)
+            "pass_GBs": abytes / (ms_tr * 1e-3) / 1e9,
+            "ms_pass": ms_tr,
+            # HBM bytes the counters measured per launch of the dominant kernel,
+            # over its launch time, and for the whole pass (null unless taken
+            # on the current sources)
+            "hbm_measured_GBs": traffic / (ms_dom / launches * 1e-3) / 1e9 if traffic else None,
+            "traffic_pass": traffic_pass,
         },
         "detail": {
             "crossings_per_s": (last["n_cross_dust"] + last["n_cross_empty"]) / (last["ms_transport"] * 1e-3),

@@ -90,12 +90,13 @@ typedef struct {
     int32_t event_log_cap;     /* events kept per logged packet [256]                     */
     int32_t bin_every_iteration; /* bin escapes into SED/images in Lucy iterations too [0]*/
     int32_t block_size;        /* transport threads per block, multiple of 64, at most
-                                  256 (512 for FP32 tiled sweeps); 0: 512 for FP32 tiled
-                                  sweeps, else 256 [0]                                    */
+                                  256 (768 for FP32 tiled sweeps, 512 when a pass logs,
+                                  bins or walks modified random walks); 0: 768 (512) for
+                                  FP32 tiled sweeps, else 256 [0]                         */
     int32_t blocks_per_cu;     /* persistent blocks per compute unit [0 = occupancy]      */
     int32_t defer_lanes;       /* lanes of a wave that wait before events run (tiled
                                   sweeps: interactions, escapes, exits and free lanes with
-                                  a record to take); 0: 16 for the per-lane walk, 32 for
+                                  a record to take); 0: 16 for the per-lane walk, 48 for
                                   tiled sweeps [0]                                        */
     int32_t walk_batch;        /* grid segments a lane gathers per walk step of the
                                   per-lane walk: 1,2,4,8 [4]; tiled sweeps walk 4         */
@@ -158,6 +159,9 @@ typedef struct {
     int64_t n_sweeps;          /* tiled sweeps run by the pass (transport_mode 1)         */
     int64_t n_visits;          /* tile visits (packet records walked) over those sweeps   */
     int64_t n_mrw;             /* modified-random-walk steps                              */
+    double ms_dominant;        /* device time of the pass's dominant kernel, summed over
+                                  its launches (tiled sweeps: every sweep kernel; per-lane
+                                  walk: the one transport launch)                         */
 } mcrt_iter_stats;
 
 typedef struct {

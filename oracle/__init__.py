@@ -92,6 +92,7 @@ def lib():
         L.orc_get_specific_energy.argtypes = [vp, _dp, C.c_void_p, C.c_size_t]
         L.orc_get_temperature.argtypes = [vp, _dp, C.c_size_t]
         L.orc_get_absorbed_sum.argtypes = [vp, _dp, C.c_size_t]
+        L.orc_get_absorbed_sum2.argtypes = [vp, _dp, C.c_size_t]
         L.orc_get_sed.argtypes = [vp, _dp, C.c_void_p, C.c_void_p, C.c_size_t]
         L.orc_get_images.argtypes = [vp, C.c_void_p, C.c_void_p, C.c_size_t]
         L.orc_set_peeloff.argtypes = [vp, C.c_void_p, C.c_int]
@@ -315,10 +316,16 @@ class OracleModel:
         self._check(self.L.orc_get_specific_energy(self.h, a, s.ctypes.data if with_sigma else None, a.size))
         return (a, s) if with_sigma else a
 
-    def absorbed_sum(self):
+    def absorbed_sum(self, with_sq=False):
+        """raw sums of l*kappa per cell (and of its square, with want_noise)
+        of the last transport, before the normalisation of Eq. 2"""
         a = np.zeros(self.ncell)
         self._check(self.L.orc_get_absorbed_sum(self.h, a, a.size))
-        return a
+        if not with_sq:
+            return a
+        a2 = np.zeros(self.ncell)
+        self._check(self.L.orc_get_absorbed_sum2(self.h, a2, a2.size))
+        return a, a2
 
     def temperature(self):
         T = np.zeros(self.ncell)

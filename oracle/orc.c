@@ -1542,6 +1542,13 @@ int orc_get_absorbed_sum(const orc_model* m, double* acc, size_t n)
     return 0;
 }
 
+int orc_get_absorbed_sum2(const orc_model* m, double* acc2, size_t n)
+{
+    if (!m->acc2 || (int64_t)n != m->ncell) return -1;
+    memcpy(acc2, m->acc2, n * sizeof(double));
+    return 0;
+}
+
 int orc_get_sed(const orc_model* m, double* sum, double* sum2, int64_t* count, size_t n)
 {
     size_t ns = (size_t)m->n_incl * m->nnu;

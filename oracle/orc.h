@@ -123,6 +123,8 @@ int orc_transport_range(orc_model* m, int64_t np_total, int64_t p_first, int64_t
 int orc_get_specific_energy(const orc_model* m, double* adot, double* adot_sigma, size_t n);
 int orc_get_temperature(const orc_model* m, double* T, size_t n);
 int orc_get_absorbed_sum(const orc_model* m, double* acc, size_t n);  /* raw sum l*kappa */
+/* raw sum of (l*kappa)^2 over the segments (kept only with want_noise) */
+int orc_get_absorbed_sum2(const orc_model* m, double* acc2, size_t n);
 int orc_get_sed(const orc_model* m, double* sum, double* sum2, int64_t* count, size_t n);
 int orc_get_images(const orc_model* m, double* sum, double* sum2, size_t n);
 /* Peeling-off (Sec. 2.6.2) toward n unit directions, in the final pass (and in

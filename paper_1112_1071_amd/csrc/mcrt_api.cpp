@@ -49,7 +49,7 @@ size_t sweep_record_bytes(int fp32);
 template <typename R>
 hipError_t launch_sweep_step(const TransportParams<R>& P, const SweepParams& S, int b, bool full,
                              int emit_blocks, int group_blocks, int blocks, int threads, size_t lds,
-                             hipStream_t st);
+                             hipStream_t st, hipEvent_t ev0, hipEvent_t ev1);
 template <typename R> hipError_t sweep_prepare(bool noise, bool full, size_t lds);
 template <typename R> int sweep_max_blocks_per_cu(bool noise, bool full, int threads, size_t lds);
 int sweep_emit_step();
@@ -174,10 +174,12 @@ struct mcrt_model {
     DBuf<uint4> sw_rec[2];
     DBuf<unsigned> sw_ent_tile[2];
     DBuf<uint2> sw_ent[2], sw_sent;
-    DBuf<unsigned> sw_tile_rec, sw_tile_ent, sw_ent_off, sw_item_off, sw_cursor;
+    DBuf<unsigned> sw_tile_rec, sw_tile_ent, sw_ent_off, sw_cursor;
+    DBuf<uint4> sw_item_desc;
     DBuf<SweepCtl> sw_ctl;
     unsigned* sw_host = nullptr;   // [kSweepLag] done flags
     hipEvent_t sw_ev[4] = {nullptr, nullptr, nullptr, nullptr};
+    std::vector<hipEvent_t> sw_kev;  // pairs bracketing each sweep kernel of a pass
     size_t lds_max = 65536 - 1024;  // dynamic LDS a transport kernel may take
     int64_t ev_packets = 0;
     int ev_cap = 0;
@@ -665,7 +667,7 @@ constexpr int64_t kChunkSlots = 64;     // record slots of a chunk (as in the sw
 
 template <typename R>
 mcrt_status run_sweeps(mcrt_model* m, TransportParams<R>& P, int64_t np, int64_t* n_sweeps,
-                       int64_t* n_visits) {
+                       int64_t* n_visits, double* ms_sweep) {
     hipStream_t s = m->stream;
     constexpr bool f32 = std::is_same<R, float>::value;
     for (int a = 0; a < 3; ++a)
@@ -699,12 +701,16 @@ mcrt_status run_sweeps(mcrt_model* m, TransportParams<R>& P, int64_t np, int64_t
     const size_t lds = tile_bytes(S.tz);
     if (lds > m->lds_max)
         return fail(m, MCRT_E_UNSUPPORTED, "tile and tables do not fit in LDS; use smaller tiles or fewer sources");
-    const int threads = m->cfg.block_size > 0 ? m->cfg.block_size : (f32 ? 512 : 256);
+    // threads per group, 0 = by kernel: FP32 768 for the lean kernel (three
+    // waves per SIMD hide the walk's LDS and the events' memory latency), 512
+    // for the full one (its register budget); FP64 256
+    int threads = m->cfg.block_size > 0 ? m->cfg.block_size : (f32 ? (full ? 512 : 768) : 256);
+    if (full && threads > 512) threads = 512;
     // a work item: entries of one tile, about 16 records per thread when full
-    S.item_ent = threads * 16 / (int)64 > 0 ? threads * 16 / 64 : 1;
+    S.item_ent = std::max(1, std::min(threads * 16 / 64, 256));
     // lanes of a wave that wait (events, escapes, exits, free lanes with a
     // record to take) before the wave handles them
-    S.service = m->cfg.defer_lanes > 0 ? m->cfg.defer_lanes : 32;
+    S.service = m->cfg.defer_lanes > 0 ? m->cfg.defer_lanes : 48;
     const int64_t batch = m->cfg.sweep_batch > 0 ? std::min<int64_t>(m->cfg.sweep_batch, np)
                                                  : std::min<int64_t>(kSweepBatch, np);
     S.batch = (unsigned long long)batch;
@@ -716,12 +722,12 @@ mcrt_status run_sweeps(mcrt_model* m, TransportParams<R>& P, int64_t np, int64_t
     // record slots per buffer: the records in flight (< 2 batch after a refill)
     // plus the slots left empty in chunks that a wave registers partly filled:
     // at most 7 chunks per wave and tile change, a group changes tile at most
-    // once per work item, and a sweep has about (records / 64) / item_ent work
-    // items (full chunks) plus one per tile.  A pass that still runs out of
-    // slots stops with MCRT_E_NOMEM.
+    // once per work item, and a sweep has at most about (records / 32) /
+    // item_ent work items (entries at least half full) plus one per tile.  A
+    // pass that still runs out of slots stops with MCRT_E_NOMEM.
     // Each wave also holds up to one run of 1024 slots and 32 entry slots.
     const int64_t waves = (int64_t)blocks * (threads / 64);
-    const int64_t items = 2 * batch / ((int64_t)S.item_ent * kChunkSlots) + S.ntiles;
+    const int64_t items = 2 * batch / ((int64_t)S.item_ent * (kChunkSlots / 2)) + S.ntiles;
     const int64_t slack = kChunkSlots * 7 * (threads / 64) * (items + blocks);
     int64_t cap = 2 * batch + std::max<int64_t>(2 * batch / 3, slack) + 1024 * waves;
     cap = (cap + 63) / 64 * 64;
@@ -741,7 +747,8 @@ mcrt_status run_sweeps(mcrt_model* m, TransportParams<R>& P, int64_t np, int64_t
     HIPCHK(m->sw_tile_rec.ensure((size_t)S.ntiles));
     HIPCHK(m->sw_tile_ent.ensure((size_t)S.ntiles));
     HIPCHK(m->sw_ent_off.ensure((size_t)S.ntiles + 1));
-    HIPCHK(m->sw_item_off.ensure((size_t)S.ntiles + 1));
+    // work items: at most one per item_ent entries of a tile plus one per tile
+    HIPCHK(m->sw_item_desc.ensure((size_t)S.max_ent / (size_t)S.item_ent + (size_t)S.ntiles + 1));
     HIPCHK(m->sw_cursor.ensure((size_t)S.ntiles));
     HIPCHK(m->sw_ctl.ensure(1));
     if (!m->sw_host) HIPCHK(hipHostMalloc((void**)&m->sw_host, kSweepLag * sizeof(unsigned), hipHostMallocDefault));
@@ -751,7 +758,7 @@ mcrt_status run_sweeps(mcrt_model* m, TransportParams<R>& P, int64_t np, int64_t
     S.tile_rec = m->sw_tile_rec.p;
     S.tile_ent = m->sw_tile_ent.p;
     S.ent_off = m->sw_ent_off.p;
-    S.item_off = m->sw_item_off.p;
+    S.item_desc = m->sw_item_desc.p;
     S.cursor = m->sw_cursor.p;
     S.ctl = m->sw_ctl.p;
     HIPCHK(launch_fill_u32(S.tile_rec, S.ntiles, 0u, s));
@@ -763,9 +770,19 @@ mcrt_status run_sweeps(mcrt_model* m, TransportParams<R>& P, int64_t np, int64_t
     P.packet_base = 0;
     int b = 0;  // the buffer the step's refill and sweep read
     bool done = false;
-    for (int64_t step = 0; !done; ++step) {
+    int64_t step = 0;
+    for (; !done; ++step) {
         if (step > kMaxSweeps) return fail(m, MCRT_E_DEVICE, "tiled sweeps did not finish");
-        HIPCHK(launch_sweep_step<R>(P, S, b, full, emit_blocks, group_blocks, blocks, threads, lds, s));
+        // the sweep kernel of every step is timed by a pair of events
+        if ((size_t)(2 * step + 2) > m->sw_kev.size()) {
+            for (int i = 0; i < 2; ++i) {
+                hipEvent_t e;
+                HIPCHK(hipEventCreate(&e));
+                m->sw_kev.push_back(e);
+            }
+        }
+        HIPCHK(launch_sweep_step<R>(P, S, b, full, emit_blocks, group_blocks, blocks, threads, lds, s,
+                                    m->sw_kev[2 * step], m->sw_kev[2 * step + 1]));
         const int slot = (int)(step % kSweepLag);
         HIPCHK(hipMemcpyAsync(m->sw_host + slot, &S.ctl->done, sizeof(unsigned), hipMemcpyDeviceToHost, s));
         HIPCHK(hipEventRecord(m->sw_ev[slot], s));
@@ -779,6 +796,13 @@ mcrt_status run_sweeps(mcrt_model* m, TransportParams<R>& P, int64_t np, int64_t
     SweepCtl c;
     HIPCHK(hipMemcpyAsync(&c, S.ctl, sizeof c, hipMemcpyDeviceToHost, s));
     HIPCHK(hipStreamSynchronize(s));
+    double ms = 0.0;
+    for (int64_t i = 0; i < step; ++i) {
+        float t = 0.f;
+        HIPCHK(hipEventElapsedTime(&t, m->sw_kev[2 * i], m->sw_kev[2 * i + 1]));
+        ms += t;
+    }
+    *ms_sweep = ms;
     if (c.overflow & 2u) return fail(m, MCRT_E_DEVICE, "tiled sweeps: a record was not in its tile");
     if (c.overflow)
         return fail(m, MCRT_E_NOMEM, "tiled sweep record buffers overflowed; lower sweep_batch");
@@ -804,18 +828,20 @@ mcrt_status run_transport(mcrt_model* m, int64_t np, uint32_t key1, int binning,
     HIPCHK(hipEventRecord(m->ev[0], s));
     if (m->cfg.transport_mode == 1) {
         int64_t sweeps = 0, visits = 0;
+        double ms_sweep = 0.0;
         if (f32) {
             TransportParams<float> P;
             make_params(m, np, key1, binning, P);
-            r = run_sweeps<float>(m, P, np, &sweeps, &visits);
+            r = run_sweeps<float>(m, P, np, &sweeps, &visits, &ms_sweep);
         } else {
             TransportParams<double> P;
             make_params(m, np, key1, binning, P);
-            r = run_sweeps<double>(m, P, np, &sweeps, &visits);
+            r = run_sweeps<double>(m, P, np, &sweeps, &visits, &ms_sweep);
         }
         if (r != MCRT_OK) return r;
         st->n_sweeps = sweeps;
         st->n_visits = visits;
+        st->ms_dominant = ms_sweep;
     } else if (f32) {
         TransportParams<float> P;
         make_params(m, np, key1, binning, P);
@@ -843,6 +869,7 @@ mcrt_status run_transport(mcrt_model* m, int64_t np, uint32_t key1, int binning,
     float ms = 0.f;
     HIPCHK(hipEventElapsedTime(&ms, m->ev[0], m->ev[1]));
     st->ms_transport = ms;
+    if (m->cfg.transport_mode != 1) st->ms_dominant = ms;  // one persistent launch
     st->n_row_clamped = (int64_t)h[MISC_SCRATCH];
     st->n_cross_dust = (int64_t)h[MISC_CNT + C_CROSS_DUST];
     st->n_cross_empty = (int64_t)h[MISC_CNT + C_CROSS_EMPTY];
@@ -1017,7 +1044,7 @@ mcrt_status mcrt_create(mcrt_model** out, int hip_device) {
         if (hipDeviceGetAttribute(&lds, hipDeviceAttributeMaxSharedMemoryPerBlock, hip_device) == hipSuccess &&
             lds > 0)
             m->lds_max = (size_t)lds;
-        m->lds_max -= 1024;  // static LDS of the kernels that take dynamic LDS
+        m->lds_max -= 5120;  // static LDS of the kernels that take dynamic LDS
     }
     for (int i = 0; i < 4; ++i) hipEventCreate(&m->ev[i]);
     // the device address of this device's staging array for the entry point
@@ -1060,10 +1087,11 @@ void mcrt_destroy(mcrt_model* m) {
         m->sw_ent[b].release();
     }
     m->sw_sent.release(); m->sw_tile_rec.release(); m->sw_tile_ent.release(); m->sw_ent_off.release();
-    m->sw_item_off.release(); m->sw_cursor.release(); m->sw_ctl.release();
+    m->sw_item_desc.release(); m->sw_cursor.release(); m->sw_ctl.release();
     if (m->sw_host) hipHostFree(m->sw_host);
     for (int i = 0; i < 4; ++i)
         if (m->sw_ev[i]) hipEventDestroy(m->sw_ev[i]);
+    for (hipEvent_t e : m->sw_kev) hipEventDestroy(e);
     if (m->own_stream && m->stream) hipStreamDestroy(m->stream);
     delete m;
 }
@@ -1517,8 +1545,8 @@ mcrt_status mcrt_set_run(mcrt_model* m, const mcrt_run_cfg* c) {
     if (c->event_log_packets < 0 || c->event_log_cap < 0) return fail(m, MCRT_E_ARG, "bad event log size");
     if (c->block_size < 0 || c->block_size % 64 != 0 || c->block_size > 1024)
         return fail(m, MCRT_E_ARG, "block_size must be a multiple of 64");
-    if (c->block_size > (c->transport_mode == 1 && c->precision == MCRT_FP32_TRANSPORT ? 512 : 256))
-        return fail(m, MCRT_E_ARG, "block_size above 256 (512 for FP32 tiled sweeps) is not supported");
+    if (c->block_size > (c->transport_mode == 1 && c->precision == MCRT_FP32_TRANSPORT ? 768 : 256))
+        return fail(m, MCRT_E_ARG, "block_size above 256 (768 for FP32 tiled sweeps) is not supported");
     if (c->defer_lanes < 0 || c->defer_lanes > 64) return fail(m, MCRT_E_ARG, "defer_lanes must be in [0,64]");
     if (c->blocks_per_cu < 0) return fail(m, MCRT_E_ARG, "blocks_per_cu must be >= 0");
     if (c->transport_mode != 0 && c->transport_mode != 1)

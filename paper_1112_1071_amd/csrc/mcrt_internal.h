@@ -188,7 +188,7 @@ struct SweepParams {
     unsigned* tile_rec;         // [ntiles] records registered per tile
     unsigned* tile_ent;         // [ntiles] entries registered per tile
     unsigned* ent_off;          // [ntiles+1] first grouped entry of each tile
-    unsigned* item_off;         // [ntiles+1] first work item of each tile
+    uint4* item_desc;           // per work item: tile, first grouped entry, entry count, 1
     unsigned* cursor;           // [ntiles] grouping cursors
     SweepCtl* ctl;
     unsigned long long n_packets;  // packets of the pass

@@ -134,6 +134,8 @@ template <typename R> struct Packet {
     R t;                 // ray distance walked in this flight
     R tau, tau_acc;      // sampled optical depth and the part used so far
     R chi, kap, wgt;     // opacity of the bin; packet weight (energy / eps0)
+    R rowp;              // emission-row position of the cell of a pending interaction,
+                         // when the kernel loads it ahead (tiled sweeps)
     int k;               // frequency bin
     uint32_t nev;        // interactions so far
     uint32_t nlog;       // logged events so far
@@ -427,14 +429,19 @@ template <typename R> struct TileDeposit {
 // Re-emission bin from the emissivity of cell j: row m or m+1 of the cell's
 // row position (u_mix), then the row's CDF (u_nu).
 template <typename R>
-__device__ __forceinline__ int reemission_bin(const TransportParams<R>& P, const Tables<R>& tb, int64_t j,
-                                              R u_mix, R u_nu) {
-    const R p = P.rowpos[j];
+__device__ __forceinline__ int reemission_row_bin(const TransportParams<R>& P, const Tables<R>& tb, R p,
+                                                  R u_mix, R u_nu) {
     int m = (int)p;
     m = m > kRows - 2 ? kRows - 2 : m;
     const R w = p - (R)m;
     const int row = m + (u_mix < w ? 1 : 0);
     return cdf_search2(P.ecdf + (size_t)row * P.npad, tb.ecoarse + row * P.ngroup, P.ngroup, u_nu);
+}
+
+template <typename R>
+__device__ __forceinline__ int reemission_bin(const TransportParams<R>& P, const Tables<R>& tb, int64_t j,
+                                              R u_mix, R u_nu) {
+    return reemission_row_bin(P, tb, P.rowpos[j], u_mix, u_nu);
 }
 
 // ---- modified random walk (Sec. 2.2) ---------------------------------------
@@ -722,7 +729,8 @@ __device__ __forceinline__ void walk(Packet<R>& s, const G& P, double* acc, uint
 }
 
 // Scatter (u <= albedo) or absorb and re-emit (Sec. 2.2), then a new flight.
-template <typename R, typename Dep, bool FULL = true>
+// PRE: the cell's emission-row position was loaded ahead into s.rowp.
+template <typename R, typename Dep, bool FULL = true, bool PRE = false>
 __device__ __forceinline__ void interact(Packet<R>& s, Stream<R>& rs, const TransportParams<R>& P,
                                          const Tables<R>& tb, uint32_t* cnt, double& e_killed,
                                          const Dep& dep) {
@@ -740,7 +748,7 @@ __device__ __forceinline__ void interact(Packet<R>& s, Stream<R>& rs, const Tran
     if (u_int > tb.alb[s.k]) {
         const R u_mix = rs.next(), u_nu = rs.next(), u_mu = rs.next(), u_phi = rs.next();
         const int64_t j = s.c0 + (int64_t)P.n[0] * (s.c1 + (int64_t)P.n[1] * s.c2);
-        s.k = reemission_bin(P, tb, j, u_mix, u_nu);
+        s.k = reemission_row_bin(P, tb, PRE ? s.rowp : P.rowpos[j], u_mix, u_nu);
         isotropic(s, u_mu, u_phi);
         ++cnt[C_ABSORB];
         if (FULL) log_event(s, P, MCRT_EV_ABSORB, -1);

@@ -54,7 +54,7 @@ constexpr int kEmitPer = 16;         // packets per thread of an emission step
 constexpr int kEmitThreads = 256;
 constexpr int kEmitStep = kEmitPer * kEmitThreads;  // packets per block and step
 constexpr int kEmitHash = 1024;      // tiles an emission block counts in LDS
-constexpr int kMaxItemEnt = 128;     // entries of a work item (the host keeps item_ent below)
+constexpr int kMaxItemEnt = 256;     // entries of a work item (the host keeps item_ent below)
 enum : int { ST_MOVE = 5, ST_YIELD = 6 };
 enum : unsigned { RS_WALK = 0u, RS_EVENT = 1u, RS_HOLE = 2u };  // record states
 
@@ -309,6 +309,9 @@ __device__ __forceinline__ void walk_tile(Packet<R>& s, const TransportParams<R>
         if (NOISE) atomicAdd(acc2_t + jl_h, (double)w * (double)w);
         s.t = ts_h + l;
         st = ST_EVENT;
+        // the cell's emission row, loaded now for the interaction (an
+        // absorption re-emits from it) while the wave walks on
+        s.rowp = P.rowpos[s.c0 + (int64_t)P.n[0] * (s.c1 + (int64_t)P.n[1] * s.c2)];
     } else if (left) {
         // past the tile's wall on axis lax: the neighbour tile's cell, or out
         // of the grid if that wall is the grid's
@@ -678,22 +681,30 @@ __global__ void __launch_bounds__(kEmitThreads) k_sweep_emit(TransportParams<R> 
     flush_block_counters(P, cnt, e_escaped, e_killed, s_cnt, s_energy);
 }
 
-// Exclusive scans of the per-tile entry counts (grouped entry offsets, and work
-// items of item_ent entries), the grouping cursors, the statistics of the
-// sweep about to run, and the reset of the counters of the buffer that sweep
-// writes; one block.
+// Exclusive scans of the per-tile entry counts (grouped entry offsets), the
+// work items of the sweep about to run, the grouping cursors, the sweep's
+// statistics, and the reset of the counters of the buffer it writes; one
+// block.  A tile's entries form items of item_ent entries and one item of
+// the rest.  The sweep claims items in order, so they are listed longest
+// first: all full items (tile by tile), then the remainders by decreasing
+// size (a counting sort on the size), so that a sweep ends on short items
+// and its groups finish close together.
 __global__ void __launch_bounds__(1024) k_sweep_scan(SweepParams S, int b) {
     __shared__ unsigned s_a[1024], s_b[1024], s_r[1024];
+    __shared__ unsigned s_hist[kMaxItemEnt], s_roff[kMaxItemEnt];
     const int n = S.ntiles;
     const unsigned ie = (unsigned)S.item_ent;
     const int per = (n + (int)blockDim.x - 1) / (int)blockDim.x;
     const int t0 = threadIdx.x * per;
+    for (int i = threadIdx.x; i < kMaxItemEnt; i += blockDim.x) s_hist[i] = 0u;
+    __syncthreads();
     unsigned ra = 0, rb = 0, rr = 0;
     for (int t = t0; t < t0 + per && t < n; ++t) {
         const unsigned e = S.tile_ent[t];
         ra += e;
-        rb += (e + ie - 1) / ie;
+        rb += e / ie;  // full items
         rr += S.tile_rec[t];
+        if (e % ie) atomicAdd(&s_hist[e % ie], 1u);
     }
     s_a[threadIdx.x] = ra;
     s_b[threadIdx.x] = rb;
@@ -709,14 +720,27 @@ __global__ void __launch_bounds__(1024) k_sweep_scan(SweepParams S, int b) {
         s_r[threadIdx.x] += vr;
         __syncthreads();
     }
+    const unsigned n_full = s_b[blockDim.x - 1];
+    if (threadIdx.x == 0) {
+        // remainder items after the full ones, the largest first
+        unsigned o = n_full;
+        for (int r = (int)ie - 1; r >= 1; --r) {
+            s_roff[r] = o;
+            o += s_hist[r];
+        }
+        s_roff[0] = o;  // the number of items
+    }
+    __syncthreads();
     unsigned pa = s_a[threadIdx.x] - ra, pb = s_b[threadIdx.x] - rb;  // exclusive
     for (int t = t0; t < t0 + per && t < n; ++t) {
         const unsigned e = S.tile_ent[t];
         S.ent_off[t] = pa;
         S.cursor[t] = pa;
-        S.item_off[t] = pb;
+        const unsigned nf = e / ie, rem = e % ie;
+        for (unsigned i = 0u; i < nf; ++i) S.item_desc[pb + i] = make_uint4((unsigned)t, pa + i * ie, ie, 1u);
+        if (rem) S.item_desc[atomicAdd(&s_roff[rem], 1u)] = make_uint4((unsigned)t, pa + nf * ie, rem, 1u);
         pa += e;
-        pb += (e + ie - 1) / ie;
+        pb += nf;
         S.tile_ent[t] = 0u;
         S.tile_rec[t] = 0u;
     }
@@ -724,8 +748,7 @@ __global__ void __launch_bounds__(1024) k_sweep_scan(SweepParams S, int b) {
         const unsigned recs = s_r[threadIdx.x];
         SweepCtl* c = S.ctl;
         S.ent_off[n] = s_a[threadIdx.x];
-        S.item_off[n] = s_b[threadIdx.x];
-        c->n_items = s_b[threadIdx.x];
+        c->n_items = s_roff[0];
         c->item_next = 0u;
         c->visits += recs;
         if (recs) c->sweeps += 1u;
@@ -735,13 +758,52 @@ __global__ void __launch_bounds__(1024) k_sweep_scan(SweepParams S, int b) {
     }
 }
 
-// Entries of buffer b grouped by tile.
-__global__ void k_sweep_group(SweepParams S, int b) {
+// Entries of buffer b grouped by tile.  A block takes kGroupStep entries at
+// a time, ranks them per tile in LDS, reserves each tile's range with one
+// atomic on the tile's cursor, and writes every entry at its range plus its
+// rank (the entries of a hot tile then cost one global atomic per block step,
+// not one each).  Grids of more than kGroupTiles tiles rank with one global
+// atomic per entry.
+constexpr int kGroupPer = 8;
+constexpr int kGroupStep = kGroupPer * 256;
+constexpr int kGroupTiles = 4096;
+
+__global__ void __launch_bounds__(256) k_sweep_group(SweepParams S, int b) {
+    __shared__ unsigned s_rank[kGroupTiles];
     const unsigned n = S.ctl->n_ent[b] < S.max_ent ? S.ctl->n_ent[b] : S.max_ent;
-    for (unsigned e = blockIdx.x * blockDim.x + threadIdx.x; e < n; e += gridDim.x * blockDim.x) {
-        const uint2 en = S.ent[b][e];
-        if (en.y == 0u) continue;  // a slot a wave held but did not use
-        S.sent[atomicAdd(S.cursor + S.ent_tile[b][e], 1u)] = en;
+    if (S.ntiles > kGroupTiles) {
+        for (unsigned e = blockIdx.x * blockDim.x + threadIdx.x; e < n; e += gridDim.x * blockDim.x) {
+            const uint2 en = S.ent[b][e];
+            if (en.y == 0u) continue;  // a slot a wave held but did not use
+            S.sent[atomicAdd(S.cursor + S.ent_tile[b][e], 1u)] = en;
+        }
+        return;
+    }
+    for (unsigned c0 = blockIdx.x * (unsigned)kGroupStep; c0 < n; c0 += gridDim.x * (unsigned)kGroupStep) {
+        for (int t = threadIdx.x; t < S.ntiles; t += blockDim.x) s_rank[t] = 0u;
+        __syncthreads();
+        unsigned tl[kGroupPer], rk[kGroupPer];
+        uint2 en[kGroupPer];
+#pragma unroll
+        for (int j = 0; j < kGroupPer; ++j) {
+            const unsigned e = c0 + (unsigned)(j * 256) + threadIdx.x;
+            tl[j] = kNone;
+            if (e < n) {
+                en[j] = S.ent[b][e];
+                if (en[j].y != 0u) {
+                    tl[j] = S.ent_tile[b][e];
+                    rk[j] = atomicAdd(&s_rank[tl[j]], 1u);
+                }
+            }
+        }
+        __syncthreads();
+        for (int t = threadIdx.x; t < S.ntiles; t += blockDim.x)
+            if (s_rank[t]) s_rank[t] = atomicAdd(S.cursor + t, s_rank[t]);  // count -> range start
+        __syncthreads();
+#pragma unroll
+        for (int j = 0; j < kGroupPer; ++j)
+            if (tl[j] != kNone) S.sent[s_rank[tl[j]] + rk[j]] = en[j];
+        __syncthreads();
     }
 }
 
@@ -766,16 +828,25 @@ __device__ __forceinline__ void load_tile(const TransportParams<R>& P, int o0, i
             return reinterpret_cast<const V*>(
                 P.rho + ((o0 + part * VW) + (int64_t)P.n[0] * ((o1 + ly) + (int64_t)P.n[1] * (o2 + lz))));
         };
-        int q0 = threadIdx.x;
-        // batches of eight loads in flight, then the rest one at a time
-        for (; q0 + 7 * bd < nv; q0 += 8 * bd) {
-            V v0 = *src(q0), v1 = *src(q0 + bd), v2 = *src(q0 + 2 * bd), v3 = *src(q0 + 3 * bd);
-            V v4 = *src(q0 + 4 * bd), v5 = *src(q0 + 5 * bd), v6 = *src(q0 + 6 * bd), v7 = *src(q0 + 7 * bd);
-            V* r = reinterpret_cast<V*>(rho_t);
-            r[q0] = v0; r[q0 + bd] = v1; r[q0 + 2 * bd] = v2; r[q0 + 3 * bd] = v3;
-            r[q0 + 4 * bd] = v4; r[q0 + 5 * bd] = v5; r[q0 + 6 * bd] = v6; r[q0 + 7 * bd] = v7;
+        // eight loads in flight per thread (a guarded load of a vector past the
+        // tile's end reads vector 0 and is not stored)
+        V* r = reinterpret_cast<V*>(rho_t);
+        for (int q0 = threadIdx.x; q0 < nv; q0 += 8 * bd) {
+            const int q1 = q0 + bd, q2 = q0 + 2 * bd, q3 = q0 + 3 * bd, q4 = q0 + 4 * bd;
+            const int q5 = q0 + 5 * bd, q6 = q0 + 6 * bd, q7 = q0 + 7 * bd;
+            const V v0 = *src(q0);
+            const V v1 = *src(q1 < nv ? q1 : 0), v2 = *src(q2 < nv ? q2 : 0), v3 = *src(q3 < nv ? q3 : 0);
+            const V v4 = *src(q4 < nv ? q4 : 0), v5 = *src(q5 < nv ? q5 : 0), v6 = *src(q6 < nv ? q6 : 0);
+            const V v7 = *src(q7 < nv ? q7 : 0);
+            r[q0] = v0;
+            if (q1 < nv) r[q1] = v1;
+            if (q2 < nv) r[q2] = v2;
+            if (q3 < nv) r[q3] = v3;
+            if (q4 < nv) r[q4] = v4;
+            if (q5 < nv) r[q5] = v5;
+            if (q6 < nv) r[q6] = v6;
+            if (q7 < nv) r[q7] = v7;
         }
-        for (; q0 < nv; q0 += bd) reinterpret_cast<V*>(rho_t)[q0] = *src(q0);
     } else {
         for (int i = threadIdx.x; i < tcells; i += blockDim.x) {
             const int lx = i % txy, ly = (i / txy) % txy, lz = i / (txy * txy);
@@ -809,17 +880,36 @@ __device__ __forceinline__ void flush_tile(const TransportParams<R>& P, int o0, 
     }
 }
 
+// Wave 0 of a group claims a work item and stages its descriptor (tile, first
+// entry, entry count, 1) and its entries in LDS slot `slot`; no item left
+// gives a descriptor with w = 0.
+__device__ __forceinline__ void stage_item(const SweepParams& S, unsigned n_items, uint4* s_desc,
+                                           uint2* s_ent, int slot, int lane) {
+    unsigned item = 0u;
+    if (lane == 0) item = atomicAdd(&S.ctl->item_next, 1u);
+    item = (unsigned)__shfl((int)item, 0);
+    if (item >= n_items) {
+        if (lane == 0) s_desc[slot] = make_uint4(0u, 0u, 0u, 0u);
+        return;
+    }
+    const uint4 d = S.item_desc[item];
+    for (unsigned i = (unsigned)lane; i < d.z; i += 64u) s_ent[i] = S.sent[d.y + i];
+    if (lane == 0) s_desc[slot] = d;
+}
+
 // One sweep: reads the records of buffer b (entries grouped in S.sent),
 // writes the records that stay in flight into buffer b^1.  Persistent
-// workgroups; in FP32 of up to 512 threads, so that one group of 8 waves can
-// hold a 32x32x16 tile (128 KB of LDS); the FP64 walk keeps 256 threads.
+// workgroups, one per compute unit (the tile takes most of its LDS); in FP32
+// of up to 768 threads in the lean kernel (three waves per SIMD fit its
+// registers) and 512 in the full one; the FP64 walk keeps 256 threads.
 template <typename R, bool NOISE, bool FULL>
-__global__ void __launch_bounds__(sizeof(R) == 4 ? 512 : 256) k_sweep(TransportParams<R> P, SweepParams S,
+__global__ void __launch_bounds__(sizeof(R) == 4 ? (FULL ? 512 : 768) : 256) k_sweep(TransportParams<R> P, SweepParams S,
                                                                       int b) {
     constexpr int K = 4;
     extern __shared__ __align__(16) unsigned char smem_raw[];
-    __shared__ unsigned s_item, s_enext, s_eend;
-    __shared__ uint2 s_ents[kMaxItemEnt];  // the item's entries
+    __shared__ unsigned s_enext, s_eend, s_stager;
+    __shared__ uint4 s_desc[2];                  // the current and the next work item
+    __shared__ uint2 s_ents[2][kMaxItemEnt];     // and their entries
     __shared__ unsigned s_tc[14];          // records, entries registered per destination slot
     __shared__ unsigned long long s_cnt[C_COUNT];
     __shared__ double s_energy[2];
@@ -868,19 +958,19 @@ __global__ void __launch_bounds__(sizeof(R) == 4 ? 512 : 256) k_sweep(TransportP
     wave_out_init(wo);
     if (threadIdx.x < 14) s_tc[threadIdx.x] = 0u;
 
+    // Work items are claimed one ahead: the first wave to finish an item (it
+    // would wait at the barrier anyway) claims the next one and stages its
+    // descriptor and entries in the other LDS slot, so that an item boundary
+    // costs only the barriers (and the tile change, if any).
+    if (threadIdx.x < 64) stage_item(S, n_items, s_desc, s_ents[0], 0, lane);
+    if (threadIdx.x == 0) s_stager = 0u;
+    int cur = 0;
     for (;;) {
         __syncthreads();
-        if (threadIdx.x == 0) s_item = atomicAdd(&S.ctl->item_next, 1u);
-        __syncthreads();
-        const unsigned item = s_item;
-        if (item >= n_items) break;
-        int lo = 0, hi = S.ntiles - 1;  // last tile whose first item is <= item
-        while (lo < hi) {
-            const int mid = (lo + hi + 1) >> 1;
-            if (S.item_off[mid] <= item) lo = mid;
-            else hi = mid - 1;
-        }
-        if (lo != tile) {
+        const uint4 d = s_desc[cur];
+        if (d.w == 0u) break;
+        const int ti = (int)d.x;
+        if (ti != tile) {
             // an item of the tile already in LDS keeps it; otherwise the tile
             // in LDS goes out before the item's tile comes in
             if (tile >= 0) {
@@ -890,7 +980,7 @@ __global__ void __launch_bounds__(sizeof(R) == 4 ? 512 : 256) k_sweep(TransportP
                 flush_tile(P, o0, o1, o2, txy, tcells, acc_t, acc2_t);
                 __syncthreads();
             }
-            tile = lo;
+            tile = ti;
             const int tzi = tile / (S.ntx * S.nty);
             const int trem = tile - tzi * S.ntx * S.nty;
             const int tyi = trem / S.ntx, txi = trem - tyi * S.ntx;
@@ -899,14 +989,10 @@ __global__ void __launch_bounds__(sizeof(R) == 4 ? 512 : 256) k_sweep(TransportP
             o2 = tzi * S.tz;
             load_tile(P, o0, o1, o2, txy, S.tz, rho_t, acc_t, acc2_t);
         }
-        {
-            const unsigned e0 = S.ent_off[tile] + (item - S.item_off[tile]) * (unsigned)S.item_ent;
-            const unsigned e1 = min(e0 + (unsigned)S.item_ent, S.ent_off[tile + 1]);
-            if (threadIdx.x < e1 - e0) s_ents[threadIdx.x] = S.sent[e0 + threadIdx.x];
-            if (threadIdx.x == 0) {
-                s_enext = 0u;
-                s_eend = e1 - e0;
-            }
+        if (threadIdx.x == 0) {
+            s_enext = 0u;
+            s_eend = d.z;
+            s_stager = 0u;
         }
         __syncthreads();
 
@@ -933,8 +1019,8 @@ __global__ void __launch_bounds__(sizeof(R) == 4 ? 512 : 256) k_sweep(TransportP
                     s.st = ST_YIELD;
                 } else {
                     ++visit;
-                    interact<R, TileDeposit<R>, FULL>(s, rs, P, tb, cnt, e_killed,
-                                                      TileDeposit<R>{acc_t, acc2_t, o0, o1, o2, txy});
+                    interact<R, TileDeposit<R>, FULL, true>(s, rs, P, tb, cnt, e_killed,
+                                                            TileDeposit<R>{acc_t, acc2_t, o0, o1, o2, txy});
                 }
             }
             if (s.st == ST_ESC) escape<R, FULL>(s, P, cnt, e_escaped);
@@ -954,6 +1040,8 @@ __global__ void __launch_bounds__(sizeof(R) == 4 ? 512 : 256) k_sweep(TransportP
                         jl = tile_index(s.c0, s.c1, s.c2, o0, o1, o2, txy);
                         rho = rho_t[jl];
                         visit = 0;
+                        if (s.st == ST_EVENT)
+                            s.rowp = P.rowpos[s.c0 + (int64_t)P.n[0] * (s.c1 + (int64_t)P.n[1] * s.c2)];
                     }
                 }
             }
@@ -969,7 +1057,7 @@ __global__ void __launch_bounds__(sizeof(R) == 4 ? 512 : 256) k_sweep(TransportP
                         drained = true;
                         break;
                     }
-                    const uint2 en = s_ents[e];
+                    const uint2 en = s_ents[cur][e];
                     eb = (unsigned)__builtin_amdgcn_readfirstlane(en.x);
                     ec = (unsigned)__builtin_amdgcn_readfirstlane(en.y);
                     ep = 0u;
@@ -984,16 +1072,22 @@ __global__ void __launch_bounds__(sizeof(R) == 4 ? 512 : 256) k_sweep(TransportP
                 const unsigned n = (unsigned)__popcll(need);
                 ep += n < avail ? n : avail;
             }
-            if (__ballot(s.st != ST_EMPTY || hn) == 0ull && drained) break;
+            if (__ballot(s.st != ST_EMPTY || hn) == 0ull && drained) {
+                unsigned first = 1u;
+                if (lane == 0) first = atomicAdd(&s_stager, 1u);
+                if (__shfl((int)first, 0) == 0) stage_item(S, n_items, s_desc, s_ents[cur ^ 1], cur ^ 1, lane);
+                break;
+            }
             // walk until `service` lanes wait (or none walks)
             for (;;) {
-                if (s.st == ST_WALK) walk_tile<R, K, NOISE>(s, P, o0, o1, o2, txy, S.tz, rho_t, acc_t, acc2_t,
-                                                              cnt, jl, rho);
+                if (s.st == ST_WALK)
+                    walk_tile<R, K, NOISE>(s, P, o0, o1, o2, txy, S.tz, rho_t, acc_t, acc2_t, cnt, jl, rho);
                 if (__ballot(s.st == ST_WALK) == 0ull) break;
                 const bool wait = s.st != ST_WALK && (s.st != ST_EMPTY || hn || !drained);
                 if (__popcll(__ballot(wait)) >= service) break;
             }
         }
+        cur ^= 1;
     }
     if (tile >= 0) {
         chunks_close(S, bo, tile, wo, s_tc, lane);
@@ -1019,16 +1113,26 @@ template <typename R> SweepFn<R> pick_sweep(bool noise, bool full) {
     return full ? k_sweep<R, false, true> : k_sweep<R, false, false>;
 }
 
+// One step of the sweeps; the events (may be null) bracket the sweep kernel,
+// the pass's dominant kernel.
 template <typename R>
 hipError_t launch_sweep_step(const TransportParams<R>& P, const SweepParams& S, int b, bool full,
                              int emit_blocks, int group_blocks, int blocks, int threads, size_t lds,
-                             hipStream_t st) {
+                             hipStream_t st, hipEvent_t ev0, hipEvent_t ev1) {
     hipLaunchKernelGGL(k_refill_plan, dim3(1), dim3(1024), 0, st, S, b);
     if (full) hipLaunchKernelGGL((k_sweep_emit<R, true>), dim3(emit_blocks), dim3(kEmitThreads), 0, st, P, S, b);
     else hipLaunchKernelGGL((k_sweep_emit<R, false>), dim3(emit_blocks), dim3(kEmitThreads), 0, st, P, S, b);
     hipLaunchKernelGGL(k_sweep_scan, dim3(1), dim3(1024), 0, st, S, b);
     hipLaunchKernelGGL(k_sweep_group, dim3(group_blocks), dim3(256), 0, st, S, b);
+    if (ev0) {
+        const hipError_t e = hipEventRecord(ev0, st);
+        if (e != hipSuccess) return e;
+    }
     hipLaunchKernelGGL(pick_sweep<R>(P.acc2 != nullptr, full), dim3(blocks), dim3(threads), lds, st, P, S, b);
+    if (ev1) {
+        const hipError_t e = hipEventRecord(ev1, st);
+        if (e != hipSuccess) return e;
+    }
     return hipGetLastError();
 }
 
@@ -1056,9 +1160,9 @@ hipError_t launch_fill_u32(unsigned* p, int n, unsigned v, hipStream_t st) {
 }
 
 template hipError_t launch_sweep_step<float>(const TransportParams<float>&, const SweepParams&, int, bool,
-                                             int, int, int, int, size_t, hipStream_t);
+                                             int, int, int, int, size_t, hipStream_t, hipEvent_t, hipEvent_t);
 template hipError_t launch_sweep_step<double>(const TransportParams<double>&, const SweepParams&, int, bool,
-                                              int, int, int, int, size_t, hipStream_t);
+                                              int, int, int, int, size_t, hipStream_t, hipEvent_t, hipEvent_t);
 template hipError_t sweep_prepare<float>(bool, bool, size_t);
 template hipError_t sweep_prepare<double>(bool, bool, size_t);
 template int sweep_max_blocks_per_cu<float>(bool, bool, int, size_t);

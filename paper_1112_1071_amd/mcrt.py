@@ -55,6 +55,7 @@ class IterStats(C.Structure):
         ("n_killed", C.c_int64), ("e_escaped", C.c_double), ("e_killed", C.c_double),
         ("ms_transport", C.c_double), ("ms_update", C.c_double), ("ms_total", C.c_double),
         ("n_sweeps", C.c_int64), ("n_visits", C.c_int64), ("n_mrw", C.c_int64),
+        ("ms_dominant", C.c_double),
     ]
 
     def as_dict(self) -> dict:

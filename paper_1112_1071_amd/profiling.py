@@ -22,7 +22,7 @@ import sys
 from collections import defaultdict
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-TRANSPORT_KERNELS = ("k_transport", "k_sweep", "k_refill_plan", "k_fill_u32")
+TRANSPORT_KERNELS = ("k_transport", "k_sweep", "k_refill_plan", "k_fill_u32")  # k_sweep* covers emit, scan, group
 TRANSPORT_SOURCES = ("mcrt_transport.hip", "mcrt_sweep.hip", "mcrt_packet.h", "mcrt_internal.h", "mcrt_api.cpp")
 
 
@@ -60,17 +60,38 @@ def _copy_factor(d: str, counter: str) -> float:
     return (1 << 30) / (sum(vals) / len(vals))
 
 
+def _sweep_dispatches(d: str, counter: str, dominant: str):
+    """(summed counter, number of dispatches) over the dispatches of the
+    dominant kernel (names starting with `dominant` followed by '<')"""
+    per = defaultdict(float)
+    for r in _rows(d):
+        name = r["Kernel_Name"].replace("(anonymous namespace)::", "").replace("void ", "")
+        if r["Counter_Name"] == counter and name.startswith(dominant + "<"):
+            per[r.get("Dispatch_Id") or r.get("Correlation_Id")] += float(r["Counter_Value"])
+    return sum(per.values()), len(per)
+
+
 def traffic(a) -> dict:
     ff = _copy_factor(a.copy_fetch, "FETCH_SIZE")
     fw = _copy_factor(a.copy_write, "WRITE_SIZE")
     fetch = _sum(a.fetch, "FETCH_SIZE") * ff / a.iterations
     write = _sum(a.write, "WRITE_SIZE") * fw / a.iterations
+    dom = "k_sweep" if a.mode == 1 else "k_transport"
+    df, nf = _sweep_dispatches(a.fetch, "FETCH_SIZE", dom)
+    dw, nw = _sweep_dispatches(a.write, "WRITE_SIZE", dom)
+    if nf == 0 or nw == 0:
+        raise ValueError(f"no {dom} dispatch in the counter runs")
     return {"source_hash": transport_source_hash(), "precision": a.precision, "mode": a.mode,
-            "fetch_bytes_per_launch": fetch, "write_bytes_per_launch": write,
-            "hbm_bytes_per_launch": fetch + write,
+            "kernel": dom,
+            "hbm_bytes_per_launch": df * ff / nf + dw * fw / nw,
+            "fetch_bytes_per_launch": df * ff / nf, "write_bytes_per_launch": dw * fw / nw,
+            "launches": nf,
+            "fetch_bytes_per_pass": fetch, "write_bytes_per_pass": write,
+            "hbm_bytes_per_pass": fetch + write,
             "fetch_scale": ff, "write_scale": fw,
-            "note": "rocprofv3 FETCH_SIZE and WRITE_SIZE summed over the transport kernels of "
-                    f"{a.iterations} Lucy iterations, per iteration, scaled by a 1 GiB copy"}
+            "note": f"rocprofv3 FETCH_SIZE and WRITE_SIZE per {dom} dispatch (averaged over the "
+                    f"dispatches of {a.iterations} Lucy iterations), and summed over every transport "
+                    "kernel per iteration, scaled by a 1 GiB copy"}
 
 
 def kernels(a) -> str:

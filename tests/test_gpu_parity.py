@@ -279,10 +279,11 @@ def test_abi_errors(M):
     assert L.mcrt_iterate(h3, C.byref(st)) == -2
     L.mcrt_destroy(h3)
     L.mcrt_destroy(None)
-    # 512-thread groups exist for the FP32 tiled sweeps only
+    # groups above 256 threads exist for the FP32 tiled sweeps only, up to 768
     for bad_run in (dict(precision=M.MCRT_FP64, transport_mode=1, block_size=512),
                     dict(precision=M.MCRT_FP32_TRANSPORT, transport_mode=0, block_size=512),
-                    dict(precision=M.MCRT_FP32_TRANSPORT, transport_mode=1, block_size=576)):
+                    dict(precision=M.MCRT_FP32_TRANSPORT, transport_mode=1, block_size=832),
+                    dict(precision=M.MCRT_FP32_TRANSPORT, transport_mode=1, block_size=96)):
         with pytest.raises(M.MCRTError):
             M.Model(cfg, **bad_run)
 
