@@ -18,6 +18,7 @@ import glob
 import hashlib
 import json
 import os
+import re
 import sys
 from collections import defaultdict
 
@@ -64,9 +65,9 @@ def _sweep_dispatches(d: str, counter: str, dominant: str):
     """(summed counter, number of dispatches) over the dispatches of the
     dominant kernel (names starting with `dominant` followed by '<')"""
     per = defaultdict(float)
+    pat = re.compile(r"(^|[\s:])" + re.escape(dominant) + "<")
     for r in _rows(d):
-        name = r["Kernel_Name"].replace("(anonymous namespace)::", "").replace("void ", "")
-        if r["Counter_Name"] == counter and name.startswith(dominant + "<"):
+        if r["Counter_Name"] == counter and pat.search(r["Kernel_Name"]):
             per[r.get("Dispatch_Id") or r.get("Correlation_Id")] += float(r["Counter_Value"])
     return sum(per.values()), len(per)
 

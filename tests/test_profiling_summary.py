@@ -21,8 +21,8 @@ def _write(d, rows):
 
 
 def test_traffic_per_sweep_launch_and_per_pass(tmp_path):
-    sweep = "void (anonymous namespace)::k_sweep<float, false, false>(SweepParams)"
-    emit = "void (anonymous namespace)::k_sweep_emit<float>(SweepParams)"
+    sweep = "void mcrt::k_sweep<float, false, false>(mcrt::SweepParams)"
+    emit = "void mcrt::k_sweep_emit<float, false>(mcrt::SweepParams)"
     other = "void (anonymous namespace)::k_update(Foo)"
     # two sweeps (100 and 300 KiB read), one emission (50), one unrelated kernel
     _write(tmp_path / "f", [(1, sweep, "FETCH_SIZE", 100), (2, sweep, "FETCH_SIZE", 300),
