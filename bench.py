@@ -23,6 +23,7 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, published
+BF16_PEAK_TFLOPS = 2500.0  # MI355X dense BF16 MFMA, published
 
 
 def algorithmic_bytes(st: dict, precision: int) -> float:
@@ -197,48 +198,126 @@ def bench_raytrace(args):
     print(json.dumps(out), flush=True)
 
 
-def bench_warmstart(args):
-    """Time to a converged temperature (max dT/T < 1 % over the noise mask) on
-    unseen 128^3 clumps, from T = 10 K and from the learned warm start; the
-    warm-start time includes feature computation and network inference."""
+def surrogate_flops(N: int, D: int, C0: int = 16) -> dict:
+    """Multiply-add FLOPs (2 per MAC) of one forward pass and of one training
+    step of the warm-start network on N cubes of side D: every convolution is a
+    GEMM of rows x taps*Cin x Cout (the first layer's 3 features padded to 16
+    channels, as the kernels run it); a step is the forward pass, the
+    backward-data pass (all layers but the first) and the weight gradients."""
+    # (mode, Cin, Cout, level of the GEMM rows): CONV3 27 taps over output
+    # voxels, DOWN 8 taps over output voxels, UP 8 taps over input voxels
+    c = C0
+    L = [("c", 16, c, 0), ("c", c, c, 0), ("d", c, 2 * c, 1), ("c", 2 * c, 2 * c, 1), ("c", 2 * c, 2 * c, 1),
+         ("d", 2 * c, 4 * c, 2), ("c", 4 * c, 4 * c, 2), ("c", 4 * c, 4 * c, 2), ("d", 4 * c, 8 * c, 3),
+         ("c", 8 * c, 8 * c, 3), ("c", 8 * c, 8 * c, 3), ("u", 8 * c, 4 * c, 3), ("c", 8 * c, 4 * c, 2),
+         ("c", 4 * c, 4 * c, 2), ("u", 4 * c, 2 * c, 2), ("c", 4 * c, 2 * c, 1), ("c", 2 * c, 2 * c, 1),
+         ("u", 2 * c, c, 1), ("c", 2 * c, c, 0), ("c", c, c, 0)]
+    fwd = []
+    for mode, ci, co, lev in L:
+        rows = N * (D >> lev) ** 3
+        fwd.append(2.0 * rows * (27 if mode == "c" else 8) * ci * co)
+    f = sum(fwd)
+    return {"forward": f, "train_step": 3.0 * f - fwd[0]}
+
+
+def bench_surrogate(args):
+    """Training steps of the warm-start network (BF16 MFMA kernels, FP32
+    accumulation, Adam) on a batch of N = 8 random 64^3 samples."""
+    import torch
+
+    from paper_1112_1071_amd import mcrt
+
+    N, D = 8, 64
+    g = torch.Generator(device="cuda").manual_seed(5)
+    x = torch.randn((N * D ** 3, 3), generator=g, device="cuda") * 2.0
+    x[:, 1] -= 25.0
+    x[:, 2] += 4.0
+    y = torch.randn(N * D ** 3, generator=g, device="cuda") * 0.3 + 1.5
+    k = torch.ones(N * D ** 3, device="cuda")
+    sur = mcrt.Surrogate(0, 16, seed=1)
+    for _ in range(args.warmup):
+        sur.train_step(x, y, k, N, D, lr=1e-4, mask_count=float(N * D ** 3))
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        sur.train_step(x, y, k, N, D, lr=1e-4, mask_count=float(N * D ** 3))
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t0) * 1e3 / args.steps
+    t1 = time.perf_counter()
+    for _ in range(args.steps):
+        sur.forward(x, N, D)
+    torch.cuda.synchronize()
+    ms_fwd = (time.perf_counter() - t1) * 1e3 / args.steps
+    fl = surrogate_flops(N, D)
+    tf = fl["train_step"] / (ms * 1e-3) / 1e12
+    out = {
+        "metric": "warm-start network training steps per second (8 x 64^3 samples)",
+        "value": 1e3 / ms, "unit": "steps/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": ms, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "bf16", "data": "synthetic",
+        "config": {"workload": "warm-start network: 4-level 3-D conv encoder-decoder, 16 base channels, "
+                               "batch 8 x 64^3, forward + backward + Adam", "batch": N, "side": D},
+        "roofline": {"bound": "mfma", "kernel": "whole training step", "achieved": tf,
+                     "peak": BF16_PEAK_TFLOPS, "unit": "TFLOP/s", "frac": tf / BF16_PEAK_TFLOPS,
+                     "traffic": None, "flops_per_step": fl["train_step"]},
+        "forward": {"ms": ms_fwd, "tflops": fl["forward"] / (ms_fwd * 1e-3) / 1e12},
+    }
+    print(json.dumps(out), flush=True)
+
+
+def warmstart_runs(family: str, count: int, packets: float, ppc: float, weights: str) -> dict:
+    """Time to a converged temperature (max dT/T < 1 % over the noise mask),
+    from T = 10 K and from the learned warm start, on `count` unseen models:
+    128^3 clumps built like the 256^3 clump, or thick disks of the training
+    family's holdout; the warm-start time includes feature computation and
+    network inference."""
     from paper_1112_1071_amd import mcrt, warmstart
 
     sur = mcrt.Surrogate(0, 16, seed=0)
-    sur.load(args.weights)
+    sur.load(weights)
     runs = []
-    if args.family == "disk":
-        cfgs = warmstart.thick_holdout_disks(args.clumps, packets_per_cell=args.ppc)
+    if family == "disk":
+        cfgs = warmstart.thick_holdout_disks(count, packets_per_cell=ppc)
         n_packets = int(cfgs[0]["run"]["n_packets"])
-        workload = (f"{args.clumps} thick holdout disks of the training family (64^3, mid-plane "
-                    f"tau(1 um) >= 100), {args.ppc:g} packets per cell per iteration")
+        workload = (f"{count} thick holdout disks of the training family (64^3, mid-plane "
+                    f"tau(1 um) >= {warmstart.THICK_DISK_TAU:g}), {ppc:g} packets per cell per iteration")
     else:
-        cfgs = [warmstart.test_clump(i, n_packets=int(args.packets)) for i in range(args.clumps)]
-        n_packets = int(args.packets)
-        workload = (f"{args.clumps} unseen 128^3 clumps built like the 256^3 clump (0.65 pc, "
-                    f"50 sources, mean tau(1 um) 50), {args.packets:.2e} packets per iteration")
+        cfgs = [warmstart.test_clump(i, n_packets=int(packets)) for i in range(count)]
+        n_packets = int(packets)
+        workload = (f"{count} unseen 128^3 clumps built like the 256^3 clump (0.65 pc, "
+                    f"50 sources, mean tau(1 um) 50), {packets:.2e} packets per iteration")
     for i, cfg in enumerate(cfgs):
         cold = warmstart.converge(cfg, None)
         warm = warmstart.converge(cfg, sur)
-        runs.append({"clump": i, "cold": cold, "warm": warm})
-        print(f"# model {i}: cold {cold['iterations']} it {cold['ms_to_converged']:.0f} ms, warm "
-              f"{warm['iterations']} it {warm['ms_to_converged']:.0f} ms, pre-MC median |dlnT| "
-              f"{warm['pre_mc_error']['median_abs_dlnT']:.3f}", file=sys.stderr, flush=True)
+        runs.append({"model": i, "cold": cold, "warm": warm})
+        print(f"# {family} {i}: cold {cold['iterations']} it {cold['ms_to_converged'] or -1:.0f} ms, "
+              f"warm {warm['iterations']} it {warm['ms_to_converged'] or -1:.0f} ms, pre-MC median "
+              f"|dlnT| {warm['pre_mc_error']['median_abs_dlnT']:.3f}", file=sys.stderr, flush=True)
     ok = all(r["cold"]["converged"] and r["warm"]["converged"] for r in runs)
     t_cold = float(np.mean([r["cold"]["ms_to_converged"] or np.nan for r in runs]))
     t_warm = float(np.mean([r["warm"]["ms_to_converged"] or np.nan for r in runs]))
-    out = {
-        "metric": "time to converged T (max dT/T < 1%), learned warm start",
-        "value": t_warm, "unit": "ms", "n_gpus": 1, "steps": len(runs), "warmup": 0,
-        "ms_per_step": t_warm, "higher_is_better": False, "scaling": "weak", "vs_baseline": None,
-        "dtype": "fp32 transport, bf16 network", "data": "synthetic",
-        "config": {"workload": workload, "models": args.clumps, "packets_per_step": n_packets},
-        "cold": {"ms_to_converged": t_cold,
-                 "iterations": [r["cold"]["iterations"] for r in runs]},
-        "warm": {"ms_to_converged": t_warm,
-                 "iterations": [r["warm"]["iterations"] for r in runs],
+    return {
+        "workload": workload, "models": count, "packets_per_iteration": n_packets,
+        "cold": {"ms_to_converged": t_cold, "iterations": [r["cold"]["iterations"] for r in runs]},
+        "warm": {"ms_to_converged": t_warm, "iterations": [r["warm"]["iterations"] for r in runs],
                  "ms_inference": [r["warm"]["ms_warm_start"] for r in runs],
                  "pre_mc_error": [r["warm"]["pre_mc_error"] for r in runs]},
         "speedup": t_cold / t_warm if ok else None, "all_converged": ok,
+    }
+
+
+def bench_warmstart(args):
+    w = warmstart_runs(args.family, args.clumps, args.packets, args.ppc, args.weights)
+    out = {
+        "metric": "time to converged T (max dT/T < 1%), learned warm start",
+        "value": w["warm"]["ms_to_converged"], "unit": "ms", "n_gpus": 1, "steps": w["models"],
+        "warmup": 0, "ms_per_step": w["warm"]["ms_to_converged"], "higher_is_better": False,
+        "scaling": "weak", "vs_baseline": None, "dtype": "fp32 transport, bf16 network",
+        "data": "synthetic",
+        "config": {"workload": w["workload"], "models": w["models"],
+                   "packets_per_step": w["packets_per_iteration"]},
+        "cold": w["cold"], "warm": w["warm"], "speedup": w["speedup"],
+        "all_converged": w["all_converged"],
     }
     print(json.dumps(out), flush=True)
 
@@ -246,7 +325,8 @@ def bench_warmstart(args):
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--workload", choices=["clump256", "batch", "warmstart", "raytrace"], default="clump256")
+    ap.add_argument("--workload", choices=["clump256", "batch", "warmstart", "raytrace", "surrogate"],
+                    default="clump256")
     ap.add_argument("--npix", type=int, default=256, help="raytrace: image pixels per side")
     ap.add_argument("--clumps", type=int, default=2, help="warmstart: test models")
     ap.add_argument("--family", choices=["clump", "disk"], default="clump",
@@ -264,6 +344,8 @@ def main():
     ap.add_argument("--precision", choices=["fp32", "fp64"], default="fp32")
     ap.add_argument("--cpu-packets", type=int, default=10_000_000)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-warmstart", action="store_true",
+                    help="skip the warm-start vs cold-start runs of the default line")
     ap.add_argument("--defer", type=int, default=0)
     ap.add_argument("--blocks-per-cu", type=int, default=0)
     ap.add_argument("--walk-batch", type=int, default=0)
@@ -288,6 +370,9 @@ def main():
         return
     if args.workload == "raytrace":
         bench_raytrace(args)
+        return
+    if args.workload == "surrogate":
+        bench_surrogate(args)
         return
     if args.workload == "warmstart":
         if args.packets == 1e8:
@@ -417,9 +502,18 @@ def main():
             "max_dT": last["max_dT"], "q": last["q"],
         },
     }
+    model.close()
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(cfg, args.cpu_packets)
         out["cpu_baseline"]["gpu_over_cpu"] = value / out["cpu_baseline"]["value"]
+    if not args.no_warmstart:
+        # the metric's second half: time to a converged T, warm start vs cold
+        # start, on one unseen 128^3 clump and one thick holdout disk
+        del cfg
+        out["warmstart"] = {
+            "clump128": warmstart_runs("clump", 1, 2.5e8, 0, args.weights),
+            "disk64": warmstart_runs("disk", 1, 0, 400, args.weights),
+        }
     print(json.dumps(out), flush=True)
 
 

@@ -420,7 +420,10 @@ void mcrt_surrogate_destroy(mcrt_surrogate* s);            /* NULL-safe         
 const char* mcrt_surrogate_last_error(const mcrt_surrogate* s);
 mcrt_status mcrt_surrogate_set_stream(mcrt_surrogate* s, void* hip_stream);
 int64_t mcrt_surrogate_param_count(const mcrt_surrogate* s);
-/* Host copies of the FP32 parameters / of the gradients of the last train step. */
+/* Host copies of the FP32 parameters / of the gradients of the last train step.
+ * Saving and loading a trained network is host file I/O over these two calls
+ * (the Python binding writes the parameter vector as a .npy file); the
+ * library itself reads and writes no files. */
 mcrt_status mcrt_surrogate_get_params(mcrt_surrogate* s, float* host, size_t n);
 mcrt_status mcrt_surrogate_set_params(mcrt_surrogate* s, const float* host, size_t n);
 mcrt_status mcrt_surrogate_get_grads(mcrt_surrogate* s, float* host, size_t n);

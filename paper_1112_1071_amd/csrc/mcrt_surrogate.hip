@@ -1,6 +1,10 @@
 // mcrt_surrogate.hip -- gfx950 kernels of the learned warm start: a 3-D
 // convolutional encoder-decoder evaluated and trained with BF16 operands on
-// the matrix cores (MFMA 16x16x16, FP32 accumulation).
+// the matrix cores (FP32 accumulation).  The 3x3x3 convolutions, which carry
+// nearly all of the work, stage a brick of their input with its one-voxel
+// halo in LDS and run on v_mfma_f32_16x16x32_bf16 (forward, backward data and
+// weight gradients); the stride-2 down and up convolutions use a plain
+// per-lane gather on v_mfma_f32_16x16x16_bf16.
 //
 // Tensors are channels-last (voxel-major, channel fastest) BF16.  Every
 // convolution is an implicit GEMM: rows = voxels, columns = output channels,
@@ -22,7 +26,17 @@ namespace mcrt {
 namespace nn {
 
 typedef short bf16x4 __attribute__((ext_vector_type(4)));
+typedef short s16x8 __attribute__((ext_vector_type(8)));
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef float f32x4 __attribute__((ext_vector_type(4)));
+
+// D += A B with A 16x32, B 32x16 (BF16), D 16x16 (FP32).  Lane l holds
+// A[l % 16][8 (l / 16) + j] and B[8 (l / 16) + j][l % 16] for j = 0..7, and
+// D[4 (l / 16) + i][l % 16] for i = 0..3.
+__device__ __forceinline__ f32x4 mfma32(const uint4& a, const uint4& b, f32x4 c) {
+    return __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8, a), __builtin_bit_cast(bf16x8, b),
+                                                   c, 0, 0, 0);
+}
 
 enum Mode : int { CONV3 = 0, DOWN = 1, UP = 2 };
 
@@ -155,6 +169,108 @@ __global__ void __launch_bounds__(256) k_conv(ConvArgs A, int64_t rows) {
     }
 }
 
+// 3x3x3 convolution (stride 1, zero padding) as an implicit GEMM with its
+// input staged in LDS.  A workgroup of 4 waves owns an output brick of 8x8x4
+// voxels of one sample and 16 NT output channels (blockIdx.y); wave w owns the
+// brick's z-plane w: 64 rows in 4 MFMA row tiles (row = 8 y + x).  The
+// reduction runs over taps x input channels in chunks of CC = min(Cin, 32)
+// channels: the chunk's 10x10x6 halo brick is loaded once (zero outside the
+// grid) and every tap reads it from LDS; one K = 32 step covers one tap of a
+// 32-channel chunk or two taps of a 16-channel chunk (tap 27 is zero).  A
+// lane's 8 K values are 8 consecutive channels of one voxel: one 16-byte LDS
+// read.  The weights' B fragments (8 consecutive input channels of one tap and
+// output channel) come from global memory, shared by the 4 row tiles.
+constexpr int kHalo3 = 10 * 10 * 6;
+
+template <int NT>
+__global__ void __launch_bounds__(256) k_conv3(ConvArgs A, int nbx, int nbz) {
+    extern __shared__ uint4 hal[];  // [kHalo3][CC / 8]
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int D = A.Dout;
+    int b = blockIdx.x;
+    const int bx = b % nbx;
+    b /= nbx;
+    const int by = b % nbx;
+    b /= nbx;
+    const int bz = b % nbz;
+    const int n = b / nbz;
+    const int x0 = 8 * bx, y0 = 8 * by, z0 = 4 * bz;
+    const int co0 = blockIdx.y * 16 * NT;
+    const int Cin = A.C1 + A.C2;
+    const int CC = Cin < 32 ? Cin : 32;
+    const int oct = CC >> 3;
+    const int m = lane & 15, kq = lane >> 4;
+    f32x4 acc[4][NT];
+#pragma unroll
+    for (int r = 0; r < 4; ++r)
+#pragma unroll
+        for (int t = 0; t < NT; ++t) acc[r][t] = (f32x4){0.f, 0.f, 0.f, 0.f};
+    const int ksteps = (27 * CC + 31) / 32;
+    for (int c0 = 0; c0 < Cin; c0 += CC) {
+        __syncthreads();
+        for (int i = threadIdx.x; i < kHalo3 * oct; i += 256) {
+            const int o = i % oct, hv = i / oct;
+            const int hx = hv % 10, hy = (hv / 10) % 10, hz = hv / 100;
+            const int gx = x0 + hx - 1, gy = y0 + hy - 1, gz = z0 + hz - 1;
+            uint4 v = {0u, 0u, 0u, 0u};
+            if ((unsigned)gx < (unsigned)D && (unsigned)gy < (unsigned)D && (unsigned)gz < (unsigned)D) {
+                const int64_t sv = (((int64_t)n * D + gz) * D + gy) * D + gx;
+                const int c = c0 + 8 * o;
+                const uint16_t* src = c < A.C1 ? A.in1 + sv * A.C1 + c : A.in2 + sv * A.C2 + (c - A.C1);
+                v = *reinterpret_cast<const uint4*>(src);
+            }
+            hal[i] = v;
+        }
+        __syncthreads();
+        for (int s = 0; s < ksteps; ++s) {
+            const int k = 32 * s + 8 * kq;
+            const int t = k / CC, c = k - t * CC;
+            const bool tap_ok = t < 27;
+            uint4 bw[NT];
+#pragma unroll
+            for (int tt = 0; tt < NT; ++tt) {
+                bw[tt] = (uint4){0u, 0u, 0u, 0u};
+                if (tap_ok)
+                    bw[tt] = *reinterpret_cast<const uint4*>(A.w + ((size_t)t * A.Cout + co0 + 16 * tt + m) * Cin +
+                                                             c0 + c);
+            }
+            const int dz = t / 9, dy = (t / 3) % 3, dx = t % 3;  // offsets + 1
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                uint4 a = {0u, 0u, 0u, 0u};
+                if (tap_ok) {
+                    const int hx = (m & 7) + dx, hy = 2 * r + (m >> 3) + dy, hz = wave + dz;
+                    a = hal[((hz * 10 + hy) * 10 + hx) * oct + (c >> 3)];
+                }
+#pragma unroll
+                for (int tt = 0; tt < NT; ++tt) acc[r][tt] = mfma32(a, bw[tt], acc[r][tt]);
+            }
+        }
+    }
+#pragma unroll
+    for (int tt = 0; tt < NT; ++tt) {
+        const int co = co0 + 16 * tt + m;
+        const float bias = A.bias ? A.bias[co] : 0.f;
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                const int rr = 4 * kq + i;  // row within the tile: x = rr % 8, y = 2 r + rr / 8
+                const int64_t dv = (((int64_t)n * D + z0 + wave) * D + y0 + 2 * r + (rr >> 3)) * D + x0 + (rr & 7);
+                float v = acc[r][tt][i] + bias;
+                if (A.out_bf) {
+                    if (A.act) v = v > 0.f ? v : A.slope * v;
+                    A.out_bf[dv * A.Cout + co] = f2bf(v);
+                } else {
+                    float* dst = co < A.Csplit ? A.out_f + dv * A.Csplit + co
+                                               : A.out_f2 + dv * (A.Cout - A.Csplit) + (co - A.Csplit);
+                    *dst = A.accumulate ? *dst + v : v;
+                }
+            }
+        }
+    }
+}
+
 struct WgradArgs {
     const uint16_t* x1;   // layer input(s) [N][Din^3][C1], [N][Din^3][C2]
     const uint16_t* x2;
@@ -221,6 +337,99 @@ __global__ void __launch_bounds__(256) k_wgrad(WgradArgs W, int64_t rows, int ch
     for (int i = 0; i < 4; ++i) {
         const int coo = cot * 16 + 4 * kq + i;
         atomicAdd(W.dw + ((size_t)t * W.Cout + coo) * Cin + ci, acc[i]);
+    }
+}
+
+// Weight gradients of a 3x3x3 convolution with LDS-staged operands:
+// dW[t][co][ci] += sum over output voxels v of dz[v][co] x[v + delta_t][ci].
+// A workgroup owns a column of 8x8x8 bricks of one sample (all z), a
+// 16-channel slice of the input (blockIdx.y) and 16 NCO output channels
+// (blockIdx.z).  Per brick, dz is staged transposed ([co][voxel], so that a
+// lane's 8 K values, 8 consecutive voxels of one x-line, are one 16-byte
+// read) and x with its halo channels-last.  MFMA 16x16x32: M = output channel,
+// N = input channel, K = 32 voxels (four x-lines); wave w owns taps w, w + 4,
+// ... and keeps their tiles in registers across the column; one FP32 atomic
+// add per weight and workgroup at the end.
+constexpr int kDzStride = 520;  // 512 voxels + 8: consecutive channels 16 B apart in bank order
+
+template <int NCO>
+__global__ void __launch_bounds__(256) k_wgrad3(WgradArgs W, int nbx) {
+    __shared__ __align__(16) uint16_t dzT[16 * NCO][kDzStride];
+    __shared__ __align__(16) uint16_t xh[1000 * 16];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int D = W.Dout;
+    int b = blockIdx.x;
+    const int bx = b % nbx;
+    b /= nbx;
+    const int by = b % nbx;
+    const int n = b / nbx;
+    const int x0 = 8 * bx, y0 = 8 * by;
+    const int ci0 = blockIdx.y * 16, co0 = blockIdx.z * 16 * NCO;
+    const int Cin = W.C1 + W.C2;
+    const int m = lane & 15, kq = lane >> 4;
+    f32x4 acc[7][NCO];
+#pragma unroll
+    for (int j = 0; j < 7; ++j)
+#pragma unroll
+        for (int t = 0; t < NCO; ++t) acc[j][t] = (f32x4){0.f, 0.f, 0.f, 0.f};
+    for (int z0 = 0; z0 < D; z0 += 8) {
+        __syncthreads();
+        // dz of the brick: 512 voxels x 2 NCO octets, written transposed
+        for (int i = threadIdx.x; i < 512 * 2 * NCO; i += 256) {
+            const int o = i % (2 * NCO), v = i / (2 * NCO);
+            const int64_t gv = (((int64_t)n * D + z0 + (v >> 6)) * D + y0 + ((v >> 3) & 7)) * D + x0 + (v & 7);
+            const s16x8 q = *reinterpret_cast<const s16x8*>(W.dz + gv * W.Cout + co0 + 8 * o);
+#pragma unroll
+            for (int j = 0; j < 8; ++j) dzT[8 * o + j][v] = (uint16_t)q[j];
+        }
+        // x slice with its halo: 10x10x10 voxels x 2 octets
+        for (int i = threadIdx.x; i < 2000; i += 256) {
+            const int o = i & 1, hv = i >> 1;
+            const int hx = hv % 10, hy = (hv / 10) % 10, hz = hv / 100;
+            const int gx = x0 + hx - 1, gy = y0 + hy - 1, gz = z0 + hz - 1;
+            uint4 v = {0u, 0u, 0u, 0u};
+            if ((unsigned)gx < (unsigned)D && (unsigned)gy < (unsigned)D && (unsigned)gz < (unsigned)D) {
+                const int64_t sv = (((int64_t)n * D + gz) * D + gy) * D + gx;
+                const int c = ci0 + 8 * o;
+                const uint16_t* src = c < W.C1 ? W.x1 + sv * W.C1 + c : W.x2 + sv * W.C2 + (c - W.C1);
+                v = *reinterpret_cast<const uint4*>(src);
+            }
+            *reinterpret_cast<uint4*>(xh + hv * 16 + 8 * o) = v;
+        }
+        __syncthreads();
+        for (int kg = 0; kg < 16; ++kg) {
+            const int z = kg >> 1, y = 4 * (kg & 1) + kq;  // this lane's x-line
+            uint4 a[NCO];
+#pragma unroll
+            for (int tt = 0; tt < NCO; ++tt)
+                a[tt] = *reinterpret_cast<const uint4*>(&dzT[16 * tt + m][z * 64 + y * 8]);
+#pragma unroll
+            for (int j = 0; j < 7; ++j) {
+                const int t = wave + 4 * j;
+                if (t < 27) {
+                    const int dz = t / 9, dy = (t / 3) % 3, dx = t % 3;  // offsets + 1
+                    const uint16_t* xs = xh + (((z + dz) * 10 + y + dy) * 10 + dx) * 16 + m;
+                    s16x8 q;
+#pragma unroll
+                    for (int i = 0; i < 8; ++i) q[i] = (short)xs[16 * i];
+                    const uint4 bq = __builtin_bit_cast(uint4, q);
+#pragma unroll
+                    for (int tt = 0; tt < NCO; ++tt) acc[j][tt] = mfma32(a[tt], bq, acc[j][tt]);
+                }
+            }
+        }
+    }
+#pragma unroll
+    for (int j = 0; j < 7; ++j) {
+        const int t = wave + 4 * j;
+        if (t >= 27) continue;
+#pragma unroll
+        for (int tt = 0; tt < NCO; ++tt)
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                const int co = co0 + 16 * tt + 4 * kq + i;
+                atomicAdd(W.dw + ((size_t)t * W.Cout + co) * Cin + ci0 + m, acc[j][tt][i]);
+            }
     }
 }
 
@@ -420,6 +629,21 @@ static int blocks_for(int64_t n) {
 }
 
 hipError_t launch_conv(const ConvArgs& A, hipStream_t st) {
+    if (A.mode == CONV3 && A.Din == A.Dout && A.Dout % 8 == 0 && A.Cout % 16 == 0 &&
+        (A.C1 + A.C2) % 16 == 0 && A.C1 % 16 == 0) {
+        const int nbx = A.Dout / 8, nbz = A.Dout / 4;
+        const int cin = A.C1 + A.C2;
+        const size_t lds = (size_t)kHalo3 * (cin < 32 ? cin : 32) * 2;
+        const int nt = A.Cout % 64 == 0 ? 4 : (A.Cout % 32 == 0 ? 2 : 1);
+        dim3 grid((unsigned)(nbx * nbx * nbz * A.N), (unsigned)(A.Cout / (16 * nt)));
+        if (nt == 4)
+            hipLaunchKernelGGL(k_conv3<4>, grid, dim3(256), lds, st, A, nbx, nbz);
+        else if (nt == 2)
+            hipLaunchKernelGGL(k_conv3<2>, grid, dim3(256), lds, st, A, nbx, nbz);
+        else
+            hipLaunchKernelGGL(k_conv3<1>, grid, dim3(256), lds, st, A, nbx, nbz);
+        return hipGetLastError();
+    }
     // rows of the GEMM: output voxels (CONV3, DOWN) or input voxels (UP)
     const int Dg = A.mode == UP ? A.Din : A.Dout;
     const int64_t rows = (int64_t)A.N * Dg * Dg * Dg;
@@ -429,6 +653,17 @@ hipError_t launch_conv(const ConvArgs& A, hipStream_t st) {
 }
 
 hipError_t launch_wgrad(const WgradArgs& W, hipStream_t st) {
+    if (W.mode == CONV3 && W.Din == W.Dout && W.Dout % 8 == 0 && W.Cout % 16 == 0 &&
+        W.C1 % 16 == 0 && W.C2 % 16 == 0) {
+        const int nbx = W.Dout / 8;
+        const int nco = W.Cout % 32 == 0 ? 2 : 1;
+        dim3 grid((unsigned)(nbx * nbx * W.N), (unsigned)((W.C1 + W.C2) / 16), (unsigned)(W.Cout / (16 * nco)));
+        if (nco == 2)
+            hipLaunchKernelGGL(k_wgrad3<2>, grid, dim3(256), 0, st, W, nbx);
+        else
+            hipLaunchKernelGGL(k_wgrad3<1>, grid, dim3(256), 0, st, W, nbx);
+        return hipGetLastError();
+    }
     const int Dg = W.mode == UP ? W.Din : W.Dout;
     const int64_t rows = (int64_t)W.N * Dg * Dg * Dg;
     const int taps = W.mode == CONV3 ? 27 : 8;

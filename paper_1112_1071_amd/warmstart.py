@@ -28,31 +28,49 @@ DEFAULT_WEIGHTS = os.path.join(HERE, "weights", "warmstart_c16.npy")
 SEED_TRAIN, SEED_HOLDOUT, SEED_TEST = 40000, 42000, 45000
 
 
-def family_model(seed: int, n: int = 64, packets_per_cell: float = 5.0, n_iter: int = 5,
-                 members=("sphere", "disk", "clump")) -> dict:
+# the training family: member kinds (drawn uniformly from this tuple) and the
+# range of log10 of the mid-plane (disk) or radial (sphere) tau(1 um)
+MEMBERS = ("sphere", "disk", "clump", "clump")
+SPHERE_LOG_TAU = (-1.0, 3.0)
+DISK_LOG_TAU = (-1.0, 4.3)
+# the thick holdout disks the warm start is scored on: mid-plane tau(1 um) at
+# least this (a cold start needs 5 or more Lucy iterations there)
+THICK_DISK_TAU = 3000.0
+
+
+def _family_draw(seed: int, members=MEMBERS, disk_log_tau=DISK_LOG_TAU) -> dict:
+    """The random parameters of family member `seed` (kind first, so that a
+    selection by kind and tau reads the same draws the member is built from)."""
+    rng = np.random.default_rng(seed)
+    kind = members[int(rng.integers(len(members)))]
+    if kind == "clump":
+        return {"kind": kind, "n_src": int(rng.integers(2, 17)), "tau": 10.0 ** rng.uniform(1.0, 2.0),
+                "sigma_ln": float(rng.uniform(1.0, 2.0))}
+    lo, hi = SPHERE_LOG_TAU if kind == "sphere" else disk_log_tau
+    return {"kind": kind, "tau": 10.0 ** rng.uniform(lo, hi), "teff": float(rng.uniform(3000.0, 10000.0)),
+            "g": float(rng.uniform(0.0, 0.8))}
+
+
+def family_model(seed: int, n: int = 64, packets_per_cell: float = 10.0, n_iter: int = 10,
+                 members=MEMBERS, disk_log_tau=DISK_LOG_TAU) -> dict:
     """One member of the training family at side n: a randomly parameterised
     sphere or disk (as in the batched family of uneven models) or a clump
     built with the star-forming-clump recipe at the cell size of the 128^3
     test clumps."""
-    rng = np.random.default_rng(seed)
-    kind = members[int(rng.integers(len(members)))]
+    d = _family_draw(seed, members, disk_log_tau)
+    kind = d["kind"]
     npk = int(packets_per_cell * n ** 3)
     if kind == "clump":
-        n_src = int(rng.integers(2, 17))
-        tau = 10.0 ** rng.uniform(1.0, 2.0)
-        sig = float(rng.uniform(1.0, 2.0))
         cfg = synth.config2(n=n, n_packets=npk, n_iter=n_iter, seed=seed, gen_seed=seed,
-                            n_src=n_src, tau_mean=tau, sigma_ln=sig, box=0.65 * synth.PC * n / 128)
+                            n_src=d["n_src"], tau_mean=d["tau"], sigma_ln=d["sigma_ln"],
+                            box=0.65 * synth.PC * n / 128)
+    elif kind == "sphere":
+        cfg = synth.config0(n=n, tau=d["tau"], n_packets=npk, n_iter=n_iter, seed=seed, g=d["g"],
+                            teff=d["teff"])
     else:
-        tau = 10.0 ** rng.uniform(-1.0, 3.0)
-        teff = float(rng.uniform(3000.0, 10000.0))
-        g = float(rng.uniform(0.0, 0.8))
-        if kind == "sphere":
-            cfg = synth.config0(n=n, tau=tau, n_packets=npk, n_iter=n_iter, seed=seed, g=g, teff=teff)
-        else:
-            cfg = synth.config1(n=n, tau=tau, n_packets=npk, n_iter=n_iter, seed=seed, teff=teff,
-                                g=g, npix=1)
-            cfg["observers"] = {"n_incl": 10}
+        cfg = synth.config1(n=n, tau=d["tau"], n_packets=npk, n_iter=n_iter, seed=seed,
+                            teff=d["teff"], g=d["g"], npix=1)
+        cfg["observers"] = {"n_incl": 10}
     cfg["name"] = f"train{seed}-{kind}{n}"
     cfg["meta"]["family"] = kind
     return cfg
@@ -62,14 +80,14 @@ def _log(msg: str):
     print(msg, file=sys.stderr, flush=True)
 
 
-def generate(seeds, n: int = 64, packets_per_cell: float = 5.0, n_iter: int = 5, device: int = 0,
-             members=("sphere", "disk", "clump"), group: int = 64):
-    """Run n_iter Lucy iterations of the Monte-Carlo method from T = 10 K for
-    each member (groups of models share one batched launch per iteration) and
-    return device tensors X [M, n^3, 3] (features), Y [M, n^3] (log10 T) and
-    MASK [M, n^3] (1 where the cell holds dust and was sampled in the last
-    iteration).  Member configs are built on host threads while the GPU runs
-    the previous group."""
+def generate(seeds, n: int = 64, packets_per_cell: float = 10.0, max_iter: int = 10, device: int = 0,
+             members=MEMBERS, disk_log_tau=DISK_LOG_TAU):
+    """Run the Monte-Carlo method on each member from T = 10 K until the
+    convergence criterion of Sec. 2.4 (max dT/T < 1 % over the noise mask) or
+    max_iter Lucy iterations, and return device tensors X [M, n^3, 3]
+    (features), Y [M, n^3] (log10 T), MASK [M, n^3] (1 where the cell holds
+    dust and was sampled) and the per-member iteration counts and convergence
+    flags.  Member configs are built on host threads while the GPU runs."""
     import torch
     from concurrent.futures import ThreadPoolExecutor
 
@@ -80,26 +98,33 @@ def generate(seeds, n: int = 64, packets_per_cell: float = 5.0, n_iter: int = 5,
     X = torch.empty((M, n ** 3, 3), dtype=torch.float32, device=dev)
     Y = torch.empty((M, n ** 3), dtype=torch.float32, device=dev)
     K = torch.empty((M, n ** 3), dtype=torch.float32, device=dev)
+    iters = np.zeros(M, dtype=np.int32)
+    conv = np.zeros(M, dtype=bool)
     t0 = time.time()
     pool = ThreadPoolExecutor(max_workers=8)
-    futs = [pool.submit(family_model, s, n, packets_per_cell, n_iter, members) for s in seeds]
-    for g0 in range(0, M, group):
-        idx = list(range(g0, min(M, g0 + group)))
-        cfgs = [futs[i].result() for i in idx]
-        for i in idx:
-            futs[i] = None
-        models = [mcrt.Model(c, device=device, precision=mcrt.MCRT_FP32_TRANSPORT) for c in cfgs]
-        mcrt.batch_run(models, n_iter=n_iter, final_pass=0, use_graph=1, autotune=0)
-        for i, m, cfg in zip(idx, models, cfgs):
-            X[i] = m.features()
-            T = torch.as_tensor(m.temperature(), device=dev)
-            rho = torch.as_tensor(np.asarray(cfg["rho"]).reshape(-1), device=dev)
-            Y[i] = torch.log10(T).float()
-            K[i] = ((rho > 0) & (T > 1.0)).float()
-            m.close()
-        _log(f"# generated {idx[-1] + 1}/{M} models in {time.time() - t0:.0f} s")
+    futs = [pool.submit(family_model, s, n, packets_per_cell, max_iter, members, disk_log_tau)
+            for s in seeds[:64]]
+    for i in range(M):
+        cfg = futs[i].result()
+        futs[i] = None
+        if i + 64 < M:
+            futs.append(pool.submit(family_model, seeds[i + 64], n, packets_per_cell, max_iter, members,
+                                    disk_log_tau))
+        m = mcrt.Model(cfg, device=device, precision=mcrt.MCRT_FP32_TRANSPORT, stop_on_convergence=1,
+                       want_noise=1, n_packets_final=1000)
+        rs = m.run_all()
+        iters[i], conv[i] = rs["n_iterations"], bool(rs["converged"])
+        X[i] = m.features()
+        T = torch.as_tensor(m.temperature(), device=dev)
+        rho = torch.as_tensor(np.asarray(cfg["rho"]).reshape(-1), device=dev)
+        Y[i] = torch.log10(T).float()
+        K[i] = ((rho > 0) & (T > 1.0)).float()
+        m.close()
+        if (i + 1) % 100 == 0 or i + 1 == M:
+            _log(f"# generated {i + 1}/{M} models in {time.time() - t0:.0f} s; iterations mean "
+                 f"{iters[:i + 1].mean():.2f} max {iters[:i + 1].max()}, converged {conv[:i + 1].mean():.3f}")
     pool.shutdown()
-    return X, Y, K
+    return X, Y, K, iters, conv
 
 
 def train(sur, X, Y, K, epochs: int = 30, batch: int = 8, lr: float = 2e-3, holdout=None,
@@ -165,19 +190,18 @@ def test_clump(i: int, n: int = 128, n_packets: int = 250_000_000, n_iter: int =
 
 
 def thick_holdout_disks(count: int, n: int = 64, packets_per_cell: float = 400.0,
-                        min_tau: float = 100.0, n_iter: int = 40) -> list:
+                        min_tau: float = THICK_DISK_TAU, n_iter: int = 40, members=MEMBERS,
+                        disk_log_tau=DISK_LOG_TAU) -> list:
     """The first `count` disk members of the holdout family (seeds from
     SEED_HOLDOUT, never trained on) with mid-plane tau(1 um) >= min_tau: the
     optically thick disks where the Lucy iteration starts far from its fixed
     point."""
     out = []
-    for seed in range(SEED_HOLDOUT, SEED_HOLDOUT + 100000):
-        # the member kind and tau are the first draws of family_model's stream
-        rng = np.random.default_rng(seed)
-        kind = ("sphere", "disk", "clump")[int(rng.integers(3))]
-        if kind != "disk" or 10.0 ** rng.uniform(-1.0, 3.0) < min_tau:
+    for seed in range(SEED_HOLDOUT, SEED_TEST):
+        d = _family_draw(seed, members, disk_log_tau)
+        if d["kind"] != "disk" or d["tau"] < min_tau:
             continue
-        out.append(family_model(seed, n, packets_per_cell, n_iter))
+        out.append(family_model(seed, n, packets_per_cell, n_iter, members, disk_log_tau))
         if len(out) == count:
             break
     return out
@@ -223,14 +247,15 @@ def main():
     t.add_argument("--n-train", type=int, default=2000)
     t.add_argument("--n-holdout", type=int, default=200)
     t.add_argument("--side", type=int, default=64)
-    t.add_argument("--ppc", type=float, default=5.0)
-    t.add_argument("--mc-iter", type=int, default=5)
-    t.add_argument("--epochs", type=int, default=30)
+    t.add_argument("--ppc", type=float, default=10.0)
+    t.add_argument("--max-iter", type=int, default=10)
+    t.add_argument("--epochs", type=int, default=25)
     t.add_argument("--batch", type=int, default=8)
     t.add_argument("--lr", type=float, default=3e-4)
     t.add_argument("--clip", type=float, default=1.0)
     t.add_argument("--channels", type=int, default=16)
-    t.add_argument("--members", default="sphere,disk,clump")
+    t.add_argument("--members", default=",".join(MEMBERS))
+    t.add_argument("--disk-log-tau", default=",".join(str(v) for v in DISK_LOG_TAU))
     t.add_argument("--history", default="")
     e = sub.add_parser("evaluate")
     e.add_argument("--weights", default=DEFAULT_WEIGHTS)
@@ -244,10 +269,12 @@ def main():
 
     if args.cmd == "train":
         members = tuple(args.members.split(","))
-        X, Y, K = generate([SEED_TRAIN + i for i in range(args.n_train)], args.side, args.ppc,
-                           args.mc_iter, members=members)
-        H = generate([SEED_HOLDOUT + i for i in range(args.n_holdout)], args.side, args.ppc,
-                     args.mc_iter, members=members)
+        dlt = tuple(float(v) for v in args.disk_log_tau.split(","))
+        X, Y, K, it_x, cv_x = generate([SEED_TRAIN + i for i in range(args.n_train)], args.side, args.ppc,
+                                       args.max_iter, members=members, disk_log_tau=dlt)
+        Hx, Hy, Hk, it_h, cv_h = generate([SEED_HOLDOUT + i for i in range(args.n_holdout)], args.side,
+                                          args.ppc, args.max_iter, members=members, disk_log_tau=dlt)
+        H = (Hx, Hy, Hk)
         sur = mcrt.Surrogate(0, args.channels, seed=1)
         sur.set_grad_clip(args.clip)
         hist = train(sur, X, Y, K, args.epochs, args.batch, args.lr, holdout=H)
@@ -255,7 +282,10 @@ def main():
         sur.save(args.out)
         if args.history:
             with open(args.history, "w") as f:
-                json.dump({"args": vars(args), "history": hist}, f, indent=1)
+                json.dump({"args": vars(args), "history": hist,
+                           "targets": {"train_iterations": it_x.tolist(), "train_converged": cv_x.tolist(),
+                                       "holdout_iterations": it_h.tolist(),
+                                       "holdout_converged": cv_h.tolist()}}, f)
         print(json.dumps({"final": hist[-1]}), flush=True)
     else:
         sur = mcrt.Surrogate(0, args.channels, seed=0)
