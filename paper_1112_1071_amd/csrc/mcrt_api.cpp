@@ -277,6 +277,47 @@ void pad_rows(const std::vector<double>& rows, size_t nrow, size_t nb, size_t np
     }
 }
 
+// The emissivity rows and the T-solve table depend on the frequency edges and
+// kappa alone and take most of a model's set-up time (thousands of Planck bin
+// integrals); the last few sets built in the process are kept and reused for
+// models with identical frequency edges and kappa (a family of models sharing
+// one dust, set up one after another).
+struct DustTables {
+    std::vector<double> nu, kap, ecdf, lnA, slope;
+    double dy = 0.0;
+};
+std::mutex g_dust_mu;
+std::vector<DustTables> g_dust;  // most recent last
+constexpr size_t kDustCache = 4;
+
+void dust_tables(const std::vector<double>& nu, const std::vector<double>& kap, std::vector<double>& ecdf,
+                 std::vector<double>& lnA, std::vector<double>& slope, double* dy) {
+    {
+        std::lock_guard<std::mutex> lk(g_dust_mu);
+        for (size_t i = 0; i < g_dust.size(); ++i) {
+            if (g_dust[i].nu == nu && g_dust[i].kap == kap) {
+                ecdf = g_dust[i].ecdf;
+                lnA = g_dust[i].lnA;
+                slope = g_dust[i].slope;
+                *dy = g_dust[i].dy;
+                return;
+            }
+        }
+    }
+    DustTables t;
+    t.nu = nu;
+    t.kap = kap;
+    emission_rows(nu, kap, t.ecdf);
+    tsolve_table(nu, kap, t.lnA, t.slope, &t.dy);
+    ecdf = t.ecdf;
+    lnA = t.lnA;
+    slope = t.slope;
+    *dy = t.dy;
+    std::lock_guard<std::mutex> lk(g_dust_mu);
+    if (g_dust.size() == kDustCache) g_dust.erase(g_dust.begin());
+    g_dust.push_back(std::move(t));
+}
+
 mcrt_status build_tables(mcrt_model* m) {
     const size_t nb = m->kap.size();
     const size_t ns = m->src.size();
@@ -298,8 +339,7 @@ mcrt_status build_tables(mcrt_model* m) {
     }
     lcdf.back() = 1.0;
     std::vector<double> ecdf, lnA, slope;
-    emission_rows(m->nu, m->kap, ecdf);
-    tsolve_table(m->nu, m->kap, lnA, slope, &m->dy);
+    dust_tables(m->nu, m->kap, ecdf, lnA, slope, &m->dy);
     std::vector<double> scdf_p, scoarse, ecdf_p, ecoarse;
     pad_rows(scdf, ns, nb, npad, ng, scdf_p, scoarse);
     pad_rows(ecdf, kRows, nb, npad, ng, ecdf_p, ecoarse);

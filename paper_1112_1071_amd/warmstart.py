@@ -31,7 +31,7 @@ SEED_TRAIN, SEED_HOLDOUT, SEED_TEST = 40000, 42000, 45000
 # the training family: member kinds (drawn uniformly from this tuple) and the
 # range of log10 of the mid-plane (disk) or radial (sphere) tau(1 um)
 MEMBERS = ("sphere", "disk", "clump", "clump")
-SPHERE_LOG_TAU = (-1.0, 3.0)
+SPHERE_LOG_TAU = (-1.0, 2.0)
 DISK_LOG_TAU = (-1.0, 4.3)
 # the thick holdout disks the warm start is scored on: mid-plane tau(1 um) at
 # least this (a cold start needs 5 or more Lucy iterations there)

@@ -29,3 +29,27 @@ def test_thick_disk_threshold():
     thick = warmstart.thick_holdout_disks(2, n=16, packets_per_cell=1.0, min_tau=500.0)
     assert all(c["meta"]["tau_1um"] >= 500.0 for c in thick)
     assert thin[0]["name"] != thick[0]["name"]
+
+
+def test_committed_network_was_trained_on_this_family():
+    # the committed weights' training run used the family and target settings
+    # the module builds by default, so the holdout disks the warm start is
+    # scored on are members of the holdout family the network never saw
+    import json
+    import os
+
+    h = json.load(open(os.path.join(os.path.dirname(warmstart.__file__), "weights",
+                                    "warmstart_c16_history.json")))
+    a = h["args"]
+    assert tuple(a["members"].split(",")) == warmstart.MEMBERS
+    assert tuple(float(v) for v in a["disk_log_tau"].split(",")) == warmstart.DISK_LOG_TAU
+    assert a["n_train"] == 2000 and a["n_holdout"] == 200 and a["side"] == 64
+    # targets: every member iterated to the convergence criterion
+    t = h["targets"]
+    assert len(t["train_iterations"]) == 2000 and all(t["train_converged"])
+    assert all(t["holdout_converged"])
+    # the thick holdout disks come from the holdout seed range
+    for c in warmstart.thick_holdout_disks(2, n=16, packets_per_cell=1.0):
+        seed = int(c["name"].split("-")[0].replace("train", ""))
+        assert warmstart.SEED_HOLDOUT <= seed < warmstart.SEED_TEST
+        assert c["meta"]["tau_1um"] >= warmstart.THICK_DISK_TAU
