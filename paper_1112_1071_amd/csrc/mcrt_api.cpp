@@ -152,6 +152,8 @@ struct mcrt_model {
     DBuf<double> peel_dir, psed_sum, psed_sum2, pimg_sum, pimg_sum2;
     // raytracing: spectral cube and SED of the last mcrt_raytrace, its image
     DBuf<double> ray_cube, ray_sed, ray_nu, ray_lsrc;
+    DBuf<double> ray_btab;          // raytracing table of ln B_k(ln T), built on first use
+    bool ray_btab_ok = false;
     // modified random walk: Planck/Rosseland mean table (built when mrw_gamma > 0
     // or for the partial diffusion approximation)
     DBuf<double> mrw_tab;
@@ -318,7 +320,28 @@ void dust_tables(const std::vector<double>& nu, const std::vector<double>& kap, 
     g_dust.push_back(std::move(t));
 }
 
+// The raytracing table of ln B_k(ln T) depends on the frequency edges alone;
+// the last few built in the process are reused.
+std::mutex g_btab_mu;
+std::vector<std::pair<std::vector<double>, std::vector<double>>> g_btab;  // (nu, table), most recent last
+
+void ray_planck_table(const std::vector<double>& nu, std::vector<double>& tab) {
+    {
+        std::lock_guard<std::mutex> lk(g_btab_mu);
+        for (const auto& e : g_btab)
+            if (e.first == nu) {
+                tab = e.second;
+                return;
+            }
+    }
+    planck_ln_table(nu, tab);
+    std::lock_guard<std::mutex> lk(g_btab_mu);
+    if (g_btab.size() == kDustCache) g_btab.erase(g_btab.begin());
+    g_btab.emplace_back(nu, tab);
+}
+
 mcrt_status build_tables(mcrt_model* m) {
+    m->ray_btab_ok = false;
     const size_t nb = m->kap.size();
     const size_t ns = m->src.size();
     const size_t ng = (nb + kGroup - 1) / kGroup, npad = ng * kGroup;
@@ -1118,6 +1141,7 @@ void mcrt_destroy(mcrt_model* m) {
     m->peel_dir.release(); m->psed_sum.release(); m->psed_sum2.release();
     m->pimg_sum.release(); m->pimg_sum2.release();
     m->ray_cube.release(); m->ray_sed.release(); m->ray_nu.release(); m->ray_lsrc.release();
+    m->ray_btab.release();
     m->mrw_tab.release();
     m->pda_flag.release(); m->pda_vec.release(); m->pda_red.release(); m->pda_count.release();
     m->misc.release(); m->energies.release(); m->hist.release();
@@ -1405,6 +1429,13 @@ mcrt_status mcrt_raytrace(mcrt_model* m, int npix, double half_width) {
     HIPCHK(m->ray_sed.ensure((size_t)m->n_peel * 2 * nnu));
     HIPCHK(m->ray_nu.ensure(nnu + 1));
     HIPCHK(m->ray_lsrc.ensure(ns * nnu));
+    if (!m->ray_btab_ok) {
+        std::vector<double> tab;
+        ray_planck_table(m->nu, tab);
+        HIPCHK(m->ray_btab.ensure(tab.size()));
+        HIPCHK(hipMemcpy(m->ray_btab.p, tab.data(), tab.size() * sizeof(double), hipMemcpyHostToDevice));
+        m->ray_btab_ok = true;
+    }
     std::vector<double> lsrc(ns * nnu);
     for (size_t i = 0; i < ns; ++i) {
         double tot = 0.0;
@@ -1437,6 +1468,8 @@ mcrt_status mcrt_raytrace(mcrt_model* m, int npix, double half_width) {
     R.lsrc = m->ray_lsrc.p;
     R.cube = m->ray_cube.p;
     R.sed = m->ray_sed.p;
+    R.btab = reinterpret_cast<const double2*>(m->ray_btab.p);
+    R.dlnT = (log(kTHi) - log(kTLo)) / (kRayTRows - 1);
     HIPCHK(launch_raytrace(R, s));
     HIPCHK(hipStreamSynchronize(s));
     m->ray_npix = npix;

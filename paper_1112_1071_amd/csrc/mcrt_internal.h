@@ -12,6 +12,8 @@ namespace mcrt {
 constexpr int kRows = 128;          // emissivity rows, log-spaced in T over [1 K, 1e4 K]
 constexpr double kTLo = 1.0;        // K
 constexpr double kTHi = 1.0e4;      // K
+constexpr int kRayTRows = 2048;     // rows of the raytracing table of ln B_k(ln T)
+constexpr double kLnBFloor = -690.0; // ln B of a bin whose Planck integral underflows
 constexpr double kTFloor = 1.0;     // K, temperature of cells that absorbed nothing
 constexpr int kTSolveRows = 2048;   // rows of the ln Adot(ln T) table of the T solve
 constexpr int kMrwRows = 2048;      // rows of the Planck/Rosseland mean table, log-spaced in T
@@ -125,6 +127,10 @@ struct RayParams {
     const double* lsrc;     // [nsrc*nnu] source luminosity per bin, erg/s
     double* cube;           // [n_obs][npix][npix][nnu], erg/s/sr per pixel
     double* sed;            // [n_obs][2][nnu] (0 sources, 1 dust), erg/s/sr
+    // ln B_k and d ln B_k / d ln T at ln T = ln kTLo + i dlnT (i < kRayTRows),
+    // [row][bin] pairs; temperatures outside [kTLo, kTHi] use quadrature
+    const double2* btab;
+    double dlnT;
 };
 
 // Partial diffusion approximation: the grid, the selection inputs and the

@@ -63,6 +63,7 @@ inline double planck_integrand(double x) {
     if (x <= 0.0) return 0.0;
     if (x > 745.0) return 0.0;
     if (x < 1e-8) return x * x * (1.0 - 0.5 * x);
+    if (x > 700.0) return x * x * x * exp(-x);  // expm1 overflows past 709.78
     return x * x * x / expm1(x);
 }
 }  // namespace
@@ -148,6 +149,30 @@ void adot_of_T(const std::vector<double>& nu, const std::vector<double>& kappa, 
     }
     *adot = 4.0 * kPi * pref * s;
     *dlnA_dlnT = s > 0.0 ? ds / s : 4.0;
+}
+
+void planck_ln_table(const std::vector<double>& nu, std::vector<double>& tab) {
+    const size_t nb = nu.size() - 1;
+    tab.assign((size_t)kRayTRows * nb * 2, 0.0);
+    const double dl = (log(kTHi) - log(kTLo)) / (kRayTRows - 1);
+    for (int i = 0; i < kRayTRows; ++i) {
+        const double T = exp(log(kTLo) + i * dl);
+        const double kT = kK * T;
+        const double pref = 2.0 * kT * kT * kT * kT / (kH * kH * kH * kC * kC);
+        for (size_t k = 0; k < nb; ++k) {
+            const double a = kH * nu[k] / kT, b = kH * nu[k + 1] / kT;
+            const double I = planck_x_integral(a, b);
+            double* e = &tab[2 * ((size_t)i * nb + k)];
+            if (!(pref * I > 1e-300)) {
+                e[0] = kLnBFloor;
+                e[1] = 0.0;
+            } else {
+                // B = pref(T) I(a(T), b(T)) with pref ~ T^4 and a, b ~ 1/T
+                e[0] = log(pref * I);
+                e[1] = (4.0 * I + a * planck_integrand(a) - b * planck_integrand(b)) / I;
+            }
+        }
+    }
 }
 
 void tsolve_table(const std::vector<double>& nu, const std::vector<double>& kappa,

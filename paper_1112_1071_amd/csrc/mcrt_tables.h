@@ -18,6 +18,9 @@ void adot_of_T(const std::vector<double>& nu, const std::vector<double>& kappa, 
                double* adot, double* dlnA_dlnT);
 void tsolve_table(const std::vector<double>& nu, const std::vector<double>& kappa,
                   std::vector<double>& lnA, std::vector<double>& slope, double* dy);
+// raytracing: ln B_k(T) and d ln B_k / d ln T per bin on kRayTRows rows of ln T
+// over [kTLo, kTHi], interleaved per (row, bin); underflowing bins hold kLnBFloor
+void planck_ln_table(const std::vector<double>& nu, std::vector<double>& tab);
 // modified random walk: Planck-mean kappa and Rosseland-mean chi against ln T
 void mrw_table(const std::vector<double>& nu, const std::vector<double>& kappa,
                const std::vector<double>& chi, std::vector<double>& tab);
