@@ -1047,6 +1047,11 @@ static int mrw(const orc_model* m, orc_stream* rs, int64_t p, double x[3], doubl
         double u[3];
         isotropic(u_mu, u_phi, u);
         for (int a = 0; a < 3; ++a) x[a] += R0 * u[a];
+#ifdef ORC_MRW_NUDGE
+        /* sensitivity experiment only (a separate test build): move the point
+         * by one unit in the last place after every step */
+        for (int a = 0; a < 3; ++a) x[a] = nextafter(x[a], INFINITY);
+#endif
         int row = m->row_m[j] + (u_mix < m->row_w[j] ? 1 : 0);
         *k = cdf_search(m->ecdf + (size_t)row * m->nnu, m->nnu, u_nu);
         isotropic(u_mu2, u_phi2, d);

@@ -6,9 +6,16 @@ tally agree as for the plain walk.  The GPU reads the Planck- and
 Rosseland-mean opacities from a table (cubic Hermite in ln T, ~1e-11), the
 oracle evaluates them at T.  In thick cells a packet takes hundreds of
 steps; a rare packet's history parts from the oracle's after thousands of
-events (at a step's threshold rho chi_R R0 >= gamma or a wall crossing
-decided the other way: in a tau = 30 cube about 3 packets in 1000), where
-the plain walk's histories stay identical.  The bar: at least 99 % of the packets with identical event
+events, always first at a step/no-step decision (rho chi_R R0 >= gamma
+decided the other way after hundreds of identical steps): in the grey
+tau = 30 cube 6 of 2000 packets, in both transport modes, the same packets;
+with power-law dust none.  The cause is the walk's own sensitivity, not the
+table: each step's radius is the distance from the previous step's end point
+to the nearest wall, so last-bit differences in position are carried and
+occasionally amplified until a threshold decision flips.  The oracle parts
+from itself in the same way (3 of 2000 packets after a one-ulp nudge per
+step: test_oracle_mrw_sensitivity.py), and grey dust, where both sides use
+the same opacity, shows it.  The bar: at least 99 % of the packets with identical event
 sequences (98 % in the second iteration, at non-uniform temperatures),
 counters to 1e-3, and Adot differences (the few parted packets cross most
 cells of the small cube) well below those between two seeds of the oracle.
