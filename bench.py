@@ -35,7 +35,7 @@ def algorithmic_bytes(st: dict, precision: int) -> float:
     return (st["n_cross_dust"] * (rb + 16) + st["n_cross_empty"] * rb + st["n_absorb"] * rb)
 
 
-def measured_traffic(precision: int, mode: int):
+def measured_traffic(precision: int, mode: int, workload: str = "clump256"):
     """HBM bytes per launch of the dominant transport kernel, and per pass of
     every transport kernel, from the committed rocprofv3 FETCH_SIZE /
     WRITE_SIZE summary, if it was taken on the current transport source, in the
@@ -50,22 +50,31 @@ def measured_traffic(precision: int, mode: int):
     except Exception:
         return None, None
     if (d.get("source_hash") != transport_source_hash() or d.get("precision") != precision
-            or d.get("mode") != mode):
+            or d.get("mode") != mode or d.get("workload", "clump256") != workload):
         return None, None
     return d.get("hbm_bytes_per_launch"), d.get("hbm_bytes_per_pass")
 
 
-def cpu_baseline(cfg: dict, n_packets: int) -> dict:
+def cpu_baseline(cfg: dict, n_packets: int, what: str, one_thread_packets: int = 0) -> dict:
+    """The oracle's transport on the host cores: a bounded sample of a first
+    Lucy iteration of the same model, on all cores (and, when asked, on one)."""
     import oracle
 
     threads = int(os.environ.get("OMP_NUM_THREADS", "0")) or len(os.sched_getaffinity(0))
     o = oracle.OracleModel(cfg, n_threads=threads)
     st = o.transport_sample(n_packets)
     o.close()
-    return {"value": n_packets / st["seconds"], "unit": "packets/s", "cores": threads,
-            "kind": "oracle",
-            "sample": f"{n_packets} packets of a first Lucy iteration of the same 256^3 clump "
-                      f"(FP64 oracle transport only, {st['seconds']:.1f} s)"}
+    out = {"value": n_packets / st["seconds"], "unit": "packets/s", "cores": threads,
+           "kind": "oracle",
+           "sample": f"{n_packets} packets of a first Lucy iteration of the same {what} "
+                     f"(FP64 oracle transport only, {st['seconds']:.1f} s)"}
+    if one_thread_packets:
+        o = oracle.OracleModel(cfg, n_threads=1)
+        s1 = o.transport_sample(one_thread_packets)
+        o.close()
+        out["one_thread"] = {"value": one_thread_packets / s1["seconds"], "packets": one_thread_packets,
+                             "seconds": s1["seconds"]}
+    return out
 
 
 def bench_batch(args):
@@ -80,7 +89,7 @@ def bench_batch(args):
     cfgs = [synth.config3_model(m, packets_per_cell=args.ppc, n_iter=args.steps + 1)
             for m in range(args.models)]
     print(f"# {args.models} models built in {time.time() - t0:.1f} s", file=sys.stderr, flush=True)
-    prec = mcrt.MCRT_FP32_TRANSPORT if args.precision == "fp32" else mcrt.MCRT_FP64
+    prec = mcrt.MCRT_FP32_TRANSPORT if args.precision != "fp64" else mcrt.MCRT_FP64
     extra = {"mrw_gamma": args.mrw} if args.mrw > 0 else {}
     if args.tally_copies:
         extra["tally_copies"] = args.tally_copies
@@ -325,8 +334,8 @@ def bench_warmstart(args):
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--workload", choices=["clump256", "batch", "warmstart", "raytrace", "surrogate"],
-                    default="clump256")
+    ap.add_argument("--workload", choices=["clump256", "sphere32", "disk128", "batch", "warmstart", "raytrace",
+                                           "surrogate"], default="clump256")
     ap.add_argument("--npix", type=int, default=256, help="raytrace: image pixels per side")
     ap.add_argument("--clumps", type=int, default=2, help="warmstart: test models")
     ap.add_argument("--family", choices=["clump", "disk"], default="clump",
@@ -341,7 +350,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--packets", type=float, default=1e8)
     ap.add_argument("--grid", type=int, default=256)
-    ap.add_argument("--precision", choices=["fp32", "fp64"], default="fp32")
+    ap.add_argument("--precision", choices=["fp32", "fp64"], default=None,
+                    help="transport precision (default: fp64 for sphere32, fp32 otherwise)")
     ap.add_argument("--cpu-packets", type=int, default=10_000_000)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-warmstart", action="store_true",
@@ -385,9 +395,35 @@ def main():
 
     t0 = time.time()
     n_packets = int(args.packets)
-    cfg = synth.config2(n=args.grid, n_packets=n_packets, n_iter=args.warmup + args.steps)
+    n_iter = args.warmup + args.steps
+    if args.workload == "sphere32":
+        # the small FP64 case: 32^3 sphere, one star, 100 bins, 1e5 packets
+        n_packets = int(args.packets) if args.packets != 1e8 else 100_000
+        cfg = synth.config0(n=32, n_packets=n_packets, n_iter=n_iter)
+        what, cpu_n, cpu_1 = "32^3 sphere", n_packets, n_packets
+        workload = (f"sphere32: 32^3 uniform sphere (tau(1 um) = 1), 5800 K star, 100 frequency bins, "
+                    f"{n_packets:.0e} packets per Lucy iteration")
+        prec_default = "fp64"
+        mode_default = 0
+    elif args.workload == "disk128":
+        # the flared disk: 128^3, mid-plane tau(1 um) = 1e3, 200 bins, 1e7 packets
+        n_packets = int(args.packets) if args.packets != 1e8 else 10_000_000
+        cfg = synth.config1(n=128, n_packets=n_packets, n_iter=n_iter)
+        what, cpu_n, cpu_1 = "128^3 disk", 2_000_000, 200_000
+        workload = (f"disk128: 128^3 flared disk (mid-plane tau(1 um) = 1e3), 4000 K star, 200 frequency "
+                    f"bins, {n_packets:.0e} packets per Lucy iteration")
+        prec_default = "fp32"
+        mode_default = 0
+    else:
+        cfg = synth.config2(n=args.grid, n_packets=n_packets, n_iter=n_iter)
+        what, cpu_n, cpu_1 = f"{args.grid}^3 clump", args.cpu_packets, 200_000
+        workload = (f"clump{args.grid}: {args.grid}^3 log-normal star-forming clump, 50 point "
+                    f"sources, 200 frequency bins, {n_packets:.0e} packets per Lucy iteration")
+        prec_default = "fp32"
+        mode_default = -1
     gen_s = time.time() - t0
-    prec = mcrt.MCRT_FP32_TRANSPORT if args.precision == "fp32" else mcrt.MCRT_FP64
+    precision = args.precision or prec_default
+    prec = mcrt.MCRT_FP32_TRANSPORT if precision == "fp32" else mcrt.MCRT_FP64
     run = dict(precision=prec)
     if args.defer:
         run["defer_lanes"] = args.defer
@@ -403,8 +439,11 @@ def main():
         run["source_sampling"] = args.sampling
     if args.mrw > 0:
         run["mrw_gamma"] = args.mrw
-    if args.mode >= 0:
-        run["transport_mode"] = args.mode
+    # the per-lane walk is the faster transport on the small sphere (6.8x) and
+    # on the mostly empty disk (1.7x); the tiled sweeps on the dense clumps
+    mode = args.mode if args.mode >= 0 else mode_default
+    if mode >= 0:
+        run["transport_mode"] = mode
     if args.tile_z:
         run["tile_z"] = args.tile_z
     if args.tile_xy:
@@ -449,10 +488,10 @@ def main():
     launches = float(np.mean([s["n_sweeps"] for s in stats])) if model.run["transport_mode"] == 1 else 1.0
     abytes = float(np.mean([algorithmic_bytes(s, prec) for s in stats]))
     achieved = abytes / (ms_dom * 1e-3) / 1e9
-    traffic, traffic_pass = measured_traffic(prec, int(model.run["transport_mode"]))
+    traffic, traffic_pass = measured_traffic(prec, int(model.run["transport_mode"]), args.workload)
     last = stats[-1]
     out = {
-        "metric": "packets/s at 256^3 (Lucy iterations)",
+        "metric": f"packets/s at {int(cfg['grid']['n'][0])}^3 (Lucy iterations)",
         "value": value,
         "unit": "packets/s",
         "n_gpus": 1,
@@ -465,10 +504,8 @@ def main():
         "dtype": "fp32" if prec == 1 else "fp64",
         "data": "synthetic",
         "config": {
-            "workload": f"clump{args.grid}: {args.grid}^3 log-normal star-forming clump, 50 point "
-                        f"sources, 200 frequency bins, {n_packets:.0e} packets per Lucy iteration, "
-                        f"{'FP32' if prec == 1 else 'FP64'} transport with FP64 reductions",
-            "grid": args.grid, "packets_per_step": n_packets, "precision": args.precision,
+            "workload": f"{workload}, {'FP32' if prec == 1 else 'FP64'} transport with FP64 reductions",
+            "grid": int(cfg["grid"]["n"][0]), "packets_per_step": n_packets, "precision": precision,
         },
         "roofline": {
             "bound": "hbm",
@@ -504,9 +541,9 @@ def main():
     }
     model.close()
     if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(cfg, args.cpu_packets)
+        out["cpu_baseline"] = cpu_baseline(cfg, cpu_n, what, cpu_1)
         out["cpu_baseline"]["gpu_over_cpu"] = value / out["cpu_baseline"]["value"]
-    if not args.no_warmstart:
+    if not args.no_warmstart and args.workload == "clump256":
         # the metric's second half: time to a converged T, warm start vs cold
         # start, on one unseen 128^3 clump and one thick holdout disk
         del cfg

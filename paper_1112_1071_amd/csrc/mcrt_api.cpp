@@ -340,6 +340,31 @@ void ray_planck_table(const std::vector<double>& nu, std::vector<double>& tab) {
     g_btab.emplace_back(nu, tab);
 }
 
+// The Planck- and Rosseland-mean table of the modified random walk and the
+// diffusion approximation depends on the frequency edges, kappa and chi; the
+// last few built in the process are reused.
+struct MeanTables {
+    std::vector<double> nu, kap, chi, tab;
+};
+std::mutex g_mean_mu;
+std::vector<MeanTables> g_mean;  // most recent last
+
+void mean_opacity_table(const std::vector<double>& nu, const std::vector<double>& kap,
+                        const std::vector<double>& chi, std::vector<double>& tab) {
+    {
+        std::lock_guard<std::mutex> lk(g_mean_mu);
+        for (const MeanTables& e : g_mean)
+            if (e.nu == nu && e.kap == kap && e.chi == chi) {
+                tab = e.tab;
+                return;
+            }
+    }
+    mrw_table(nu, kap, chi, tab);
+    std::lock_guard<std::mutex> lk(g_mean_mu);
+    if (g_mean.size() == kDustCache) g_mean.erase(g_mean.begin());
+    g_mean.push_back(MeanTables{nu, kap, chi, tab});
+}
+
 mcrt_status build_tables(mcrt_model* m) {
     m->ray_btab_ok = false;
     const size_t nb = m->kap.size();
@@ -406,7 +431,7 @@ mcrt_status build_tables(mcrt_model* m) {
     HIPCHK(upload(m->img_of_bin, iob, st));
     std::vector<double> mrw;
     if (m->cfg.mrw_gamma > 0.0) {
-        mrw_table(m->nu, m->kap, m->chi, mrw);
+        mean_opacity_table(m->nu, m->kap, m->chi, mrw);
         HIPCHK(upload(m->mrw_tab, mrw, st));
     }
     m->mrw_tab_built = m->cfg.mrw_gamma > 0.0;
@@ -1488,7 +1513,7 @@ mcrt_status mcrt_apply_pda(mcrt_model* m, double noise, int passes, mcrt_pda_sta
     hipStream_t s = m->stream;
     if (!m->mrw_tab_built) {
         std::vector<double> tab;
-        mrw_table(m->nu, m->kap, m->chi, tab);
+        mean_opacity_table(m->nu, m->kap, m->chi, tab);
         HIPCHK(upload(m->mrw_tab, tab, s));
         HIPCHK(hipStreamSynchronize(s));
         m->mrw_tab_built = true;

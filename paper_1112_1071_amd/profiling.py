@@ -83,7 +83,7 @@ def traffic(a) -> dict:
     if nf == 0 or nw == 0:
         raise ValueError(f"no {dom} dispatch in the counter runs")
     return {"source_hash": transport_source_hash(), "precision": a.precision, "mode": a.mode,
-            "kernel": dom,
+            "workload": a.workload, "kernel": dom,
             "hbm_bytes_per_launch": df * ff / nf + dw * fw / nw,
             "fetch_bytes_per_launch": df * ff / nf, "write_bytes_per_launch": dw * fw / nw,
             "launches": nf,
@@ -166,6 +166,7 @@ def main():
     t.add_argument("--iterations", type=int, default=2)
     t.add_argument("--precision", type=int, default=1)
     t.add_argument("--mode", type=int, default=1)
+    t.add_argument("--workload", default="clump256")
     t.add_argument("--out", required=True)
     k = sub.add_parser("kernels")
     k.add_argument("--trace", required=True)

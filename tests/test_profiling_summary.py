@@ -35,7 +35,7 @@ def test_traffic_per_sweep_launch_and_per_pass(tmp_path):
     _write(tmp_path / "cw", [(1, copy, "WRITE_SIZE", 1 << 30)])
     a = SimpleNamespace(fetch=str(tmp_path / "f"), write=str(tmp_path / "w"),
                         copy_fetch=str(tmp_path / "cf"), copy_write=str(tmp_path / "cw"),
-                        iterations=1, precision=1, mode=1)
+                        iterations=1, precision=1, mode=1, workload="clump256")
     r = profiling.traffic(a)
     assert r["fetch_scale"] == pytest.approx(2.0) and r["write_scale"] == pytest.approx(1.0)
     assert r["launches"] == 2
