@@ -711,7 +711,7 @@ __device__ __forceinline__ void walk(Packet<R>& s, const G& P, double* acc, uint
                 } else {
                     s.tau_acc += dtau;
                 }
-                const R w = s.wgt * l * s.kap;
+                const R w = s.wgt * s.kap * l;  // the tiled walk's order: (wgt kappa) l
                 unsafeAtomicAdd(acc + jj[i], (double)w);
                 if (P.acc2) unsafeAtomicAdd(P.acc2 + jj[i], (double)w * (double)w);
             } else {

@@ -249,6 +249,7 @@ __device__ __forceinline__ void walk_tile(Packet<R>& s, const TransportParams<R>
     R rc_h = (R)1, ts_h = (R)0;
     int jl_h = jl;
     uint32_t nd = 0, ne = 0;
+    const R wk = s.wgt * s.kap;  // tally weight per unit path length
 #pragma unroll
     for (int i = 0; i < K; ++i) {
         const bool ax1 = s.ty < s.tx;
@@ -278,11 +279,13 @@ __device__ __forceinline__ void walk_tile(Packet<R>& s, const TransportParams<R>
         }
         if (cross && dust) {
             s.tau_acc += dtau;
-            const R w = s.wgt * l * s.kap;
+            const R w = wk * l;
             atomicAdd(acc_t + jl, (double)w);
             if (NOISE) atomicAdd(acc2_t + jl, (double)w * (double)w);  // w^2 may exceed FP32
         }
-        s.t = cross ? fmax(tm, s.t) : s.t;
+        // the ray parameter never decreases (a select: fmax would canonicalise
+        // both operands on every segment)
+        s.t = (cross && tm > s.t) ? tm : s.t;
         const bool mv = cross && !edge;
         const bool m0 = mv && !ax1 && !ax2, m1 = mv && ax1 && !ax2, m2 = mv && ax2;
         r0 -= m0 ? 1 : 0;
@@ -304,7 +307,7 @@ __device__ __forceinline__ void walk_tile(Packet<R>& s, const TransportParams<R>
     int st = ST_WALK;
     if (hit) {
         const R l = (s.tau - s.tau_acc) / rc_h;
-        const R w = s.wgt * l * s.kap;
+        const R w = wk * l;
         atomicAdd(acc_t + jl_h, (double)w);
         if (NOISE) atomicAdd(acc2_t + jl_h, (double)w * (double)w);
         s.t = ts_h + l;

@@ -21,7 +21,7 @@ def test_help_lists_the_workloads():
     r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--help"],
                        capture_output=True, text=True, timeout=120)
     assert r.returncode == 0
-    for w in ("clump256", "batch", "warmstart", "raytrace", "surrogate"):
+    for w in ("clump256", "sphere32", "disk128", "batch", "warmstart", "raytrace", "surrogate", "pda"):
         assert w in r.stdout
 
 
