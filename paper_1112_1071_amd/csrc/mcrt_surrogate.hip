@@ -434,20 +434,25 @@ __global__ void __launch_bounds__(256) k_wgrad3(WgradArgs W, int nbx) {
 }
 
 // dz = dy * LeakyReLU'(y) as BF16 (y is the layer's post-activation output,
-// whose sign equals the pre-activation's), plus the bias gradient.
+// whose sign equals the pre-activation's), plus the bias gradient.  C divides
+// the block size and the grid stride (C a power of two <= 256, blocks of 256
+// threads), so a thread only ever sees channel threadIdx.x % C: it sums its
+// channel in a register and adds it once.
 __global__ void k_act_back(int64_t n, int C, const float* __restrict__ dy,
                            const uint16_t* __restrict__ y, float slope, int act,
                            uint16_t* __restrict__ dz, float* __restrict__ dbias) {
     __shared__ float sb[256];
     for (int i = threadIdx.x; i < 256; i += blockDim.x) sb[i] = 0.f;
     __syncthreads();
+    float acc = 0.f;
     for (int64_t j = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; j < n;
          j += (int64_t)gridDim.x * blockDim.x) {
         float g = dy[j];
         if (act && !(bf2f(y[j]) > 0.f)) g *= slope;
         dz[j] = f2bf(g);
-        atomicAdd(&sb[j % C], g);
+        acc += g;
     }
+    atomicAdd(&sb[threadIdx.x % C], acc);
     __syncthreads();
     for (int c = threadIdx.x; c < C; c += blockDim.x) atomicAdd(dbias + c, sb[c]);
 }
@@ -683,6 +688,7 @@ hipError_t launch_wgrad(const WgradArgs& W, hipStream_t st) {
 
 hipError_t launch_act_back(int64_t n, int C, const float* dy, const uint16_t* y, float slope, int act,
                            uint16_t* dz, float* dbias, hipStream_t st) {
+    if (C < 1 || C > 256 || (C & (C - 1)) != 0) return hipErrorInvalidValue;
     hipLaunchKernelGGL(k_act_back, dim3(blocks_for(n)), dim3(256), 0, st, n, C, dy, y, slope, act, dz,
                        dbias);
     return hipGetLastError();
