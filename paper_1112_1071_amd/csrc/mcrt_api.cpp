@@ -157,6 +157,7 @@ struct mcrt_model {
     // modified random walk: Planck/Rosseland mean table (built when mrw_gamma > 0
     // or for the partial diffusion approximation)
     DBuf<double> mrw_tab;
+    DBuf<double> mrw_ytab;          // the walk's first-passage inverse (the same for every model)
     bool mrw_tab_built = false;
     // partial diffusion approximation: flags, CG vectors (8 x ncell), reductions
     DBuf<unsigned char> pda_flag;
@@ -365,6 +366,15 @@ void mean_opacity_table(const std::vector<double>& nu, const std::vector<double>
     g_mean.push_back(MeanTables{nu, kap, chi, tab});
 }
 
+// The walk's first-passage inverse depends on nothing of a model: built once
+// per process.
+const std::vector<double>& escape_table() {
+    static std::once_flag once;
+    static std::vector<double> tab;
+    std::call_once(once, [] { mrw_escape_table(tab); });
+    return tab;
+}
+
 mcrt_status build_tables(mcrt_model* m) {
     m->ray_btab_ok = false;
     const size_t nb = m->kap.size();
@@ -433,6 +443,7 @@ mcrt_status build_tables(mcrt_model* m) {
     if (m->cfg.mrw_gamma > 0.0) {
         mean_opacity_table(m->nu, m->kap, m->chi, mrw);
         HIPCHK(upload(m->mrw_tab, mrw, st));
+        HIPCHK(upload(m->mrw_ytab, escape_table(), st));
     }
     m->mrw_tab_built = m->cfg.mrw_gamma > 0.0;
     HIPCHK(hipStreamSynchronize(st));
@@ -720,6 +731,7 @@ void make_params(mcrt_model* m, int64_t np, uint32_t key1, int binning, Transpor
         P.mrw_gamma = m->cfg.mrw_gamma;
         P.Tcell = m->T.p;
         P.mrw_tab = m->mrw_tab.p;
+        P.mrw_ytab = m->mrw_ytab.p;
         P.psed_sum = m->psed_sum.p;
         P.psed_sum2 = m->psed_sum2.p;
         P.pimg_sum = m->pimg_sum.p;
@@ -1168,6 +1180,7 @@ void mcrt_destroy(mcrt_model* m) {
     m->ray_cube.release(); m->ray_sed.release(); m->ray_nu.release(); m->ray_lsrc.release();
     m->ray_btab.release();
     m->mrw_tab.release();
+    m->mrw_ytab.release();
     m->pda_flag.release(); m->pda_vec.release(); m->pda_red.release(); m->pda_count.release();
     m->misc.release(); m->energies.release(); m->hist.release();
     for (int b = 0; b < 2; ++b) {
@@ -1515,6 +1528,7 @@ mcrt_status mcrt_apply_pda(mcrt_model* m, double noise, int passes, mcrt_pda_sta
         std::vector<double> tab;
         mean_opacity_table(m->nu, m->kap, m->chi, tab);
         HIPCHK(upload(m->mrw_tab, tab, s));
+        HIPCHK(upload(m->mrw_ytab, escape_table(), s));
         HIPCHK(hipStreamSynchronize(s));
         m->mrw_tab_built = true;
     }

@@ -17,6 +17,8 @@ constexpr double kLnBFloor = -690.0; // ln B of a bin whose Planck integral unde
 constexpr double kTFloor = 1.0;     // K, temperature of cells that absorbed nothing
 constexpr int kTSolveRows = 2048;   // rows of the ln Adot(ln T) table of the T solve
 constexpr int kMrwRows = 2048;      // rows of the Planck/Rosseland mean table, log-spaced in T
+constexpr int kMrwYRows = 8192;     // rows of the walk's first-passage inverse y(w), w = ln(u/(1-u))
+constexpr double kMrwW0 = -37.5, kMrwW1 = 37.5;  // its range of w (|w| <= 36.8 for FP64 uniforms)
 constexpr int kWave = 64;
 
 // Per-lane counters flushed once per wave at the end of a transport launch.
@@ -94,6 +96,7 @@ struct TransportParams {
     double mrw_gamma;
     const double* Tcell;
     const double* mrw_tab;   // [kMrwRows * 4]
+    const double* mrw_ytab;  // [kMrwYRows * 2]: y and dy/dw of the first-passage inverse against w = logit(u)
     double* psed_sum;
     double* psed_sum2;
     double* pimg_sum;

@@ -486,6 +486,22 @@ __device__ inline double mrw_escape_y(double u) {
     return 0.5 * (lo + hi);
 }
 
+// y with F(y) = u from the table of y against w = ln(u / (1 - u)) (values and
+// slopes, cubic Hermite; relative error below 1e-10), by bisection outside it
+template <typename R>
+__device__ inline double mrw_escape_y_tab(const TransportParams<R>& P, double u) {
+    const double w = log(u) - log1p(-u);
+    const double h = (kMrwW1 - kMrwW0) / (kMrwYRows - 1);
+    const double p = (w - kMrwW0) / h;
+    if (!(p >= 0.0 && p <= (double)(kMrwYRows - 1))) return mrw_escape_y(u);
+    int i = (int)p;
+    i = i > kMrwYRows - 2 ? kMrwYRows - 2 : i;
+    const double t = p - i, t2 = t * t, t3 = t2 * t;
+    const double* a = P.mrw_ytab + 2 * (size_t)i;
+    return (2 * t3 - 3 * t2 + 1) * a[0] + (t3 - 2 * t2 + t) * h * a[1] + (-2 * t3 + 3 * t2) * a[2] +
+           (t3 - t2) * h * a[3];
+}
+
 // Planck-mean kappa and Rosseland-mean chi of cell j at its temperature:
 // cubic Hermite interpolation in ln T of the table
 template <typename R>
@@ -533,7 +549,7 @@ __device__ bool mrw_steps(Packet<R>& s, Stream<R>& rs, const TransportParams<R>&
         }
         const R u_y = rs.next(), u_mu = rs.next(), u_phi = rs.next(), u_mix = rs.next(), u_nu = rs.next();
         const R u_mu2 = rs.next(), u_phi2 = rs.next();
-        const double y = mrw_escape_y((double)u_y);
+        const double y = mrw_escape_y_tab(P, (double)u_y);
         const double sp = 3.0 * r * chir * R0 * R0 * y / (pi * pi);
         dep(s.c0, s.c1, s.c2, (R)((double)s.wgt * kp * sp));
         const double mu = 2.0 * (double)u_mu - 1.0, phi = 2.0 * pi * (double)u_phi;

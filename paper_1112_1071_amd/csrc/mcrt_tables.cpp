@@ -151,6 +151,69 @@ void adot_of_T(const std::vector<double>& nu, const std::vector<double>& kappa, 
     *dlnA_dlnT = s > 0.0 ? ds / s : 4.0;
 }
 
+// F(y) = 1 + 2 sum_{n>=1} (-1)^n exp(-n^2 y), the probability that diffusion
+// from the centre of a sphere has reached its surface by the scaled time y,
+// its complement G = 1 - F without cancellation, and dF/dy; for y < 2 the
+// same functions after Jacobi's transformation,
+// F = 2 sqrt(pi / y) sum_{m>=0} exp(-a_m^2 / (4 y)), a_m = (2m + 1) pi.
+static void escape_cdf(double y, double* F, double* G, double* dF) {
+    double f = 0.0, d = 0.0;
+    if (y < 2.0) {
+        for (int m = 0; m < 60; ++m) {
+            const double a = (2.0 * m + 1.0) * kPi, q = a * a / (4.0 * y);
+            const double t = exp(-q);
+            f += t;
+            d += t * (q / y - 0.5 / y);
+            if (t < 1e-300) break;
+        }
+        const double c = 2.0 * sqrt(kPi / y);
+        *F = c * f;
+        *G = 1.0 - *F;
+        *dF = c * d;
+        return;
+    }
+    double sg = -1.0;
+    for (int n = 1; n < 60; ++n) {
+        const double t = exp(-(double)n * n * y);
+        f += sg * t;
+        d -= sg * (double)n * n * t;
+        sg = -sg;
+        if (t < 1e-300) break;
+    }
+    *F = 1.0 + 2.0 * f;
+    *G = -2.0 * f;
+    *dF = 2.0 * d;
+}
+
+void mrw_escape_table(std::vector<double>& tab) {
+    tab.assign((size_t)kMrwYRows * 2, 0.0);
+    const double h = (kMrwW1 - kMrwW0) / (kMrwYRows - 1);
+    for (int i = 0; i < kMrwYRows; ++i) {
+        const double w = kMrwW0 + i * h;
+        // u and 1 - u without cancellation
+        const double u = w < 0.0 ? exp(w) / (1.0 + exp(w)) : 1.0 / (1.0 + exp(-w));
+        const double v = w < 0.0 ? 1.0 / (1.0 + exp(w)) : exp(-w) / (1.0 + exp(-w));
+        // F(y) = u by bisection to the last bit, in the variable that keeps
+        // both tails resolved: F < 1/2 compares F with u, F > 1/2 compares
+        // 1 - F with v
+        double lo = 1e-3, hi = 120.0;
+        for (int it = 0; it < 400; ++it) {
+            const double mid = 0.5 * (lo + hi);
+            if (mid <= lo || mid >= hi) break;
+            double F, G, dF;
+            escape_cdf(mid, &F, &G, &dF);
+            const bool below = u <= 0.5 ? F < u : G > v;
+            if (below) lo = mid;
+            else hi = mid;
+        }
+        const double y = 0.5 * (lo + hi);
+        double F, G, dF;
+        escape_cdf(y, &F, &G, &dF);
+        tab[2 * (size_t)i] = y;
+        tab[2 * (size_t)i + 1] = dF > 0.0 ? u * v / dF : 0.0;  // dy/dw = (du/dw) / F'(y)
+    }
+}
+
 void planck_ln_table(const std::vector<double>& nu, std::vector<double>& tab) {
     const size_t nb = nu.size() - 1;
     tab.assign((size_t)kRayTRows * nb * 2, 0.0);

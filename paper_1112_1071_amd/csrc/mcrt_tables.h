@@ -21,6 +21,10 @@ void tsolve_table(const std::vector<double>& nu, const std::vector<double>& kapp
 // raytracing: ln B_k(T) and d ln B_k / d ln T per bin on kRayTRows rows of ln T
 // over [kTLo, kTHi], interleaved per (row, bin); underflowing bins hold kLnBFloor
 void planck_ln_table(const std::vector<double>& nu, std::vector<double>& tab);
+// modified random walk: the inverse of the first-passage distribution F of
+// diffusion from the centre of a sphere, y(w) and dy/dw at kMrwYRows points of
+// w = ln(u / (1 - u)) over [kMrwW0, kMrwW1], interleaved
+void mrw_escape_table(std::vector<double>& tab);
 // modified random walk: Planck-mean kappa and Rosseland-mean chi against ln T
 void mrw_table(const std::vector<double>& nu, const std::vector<double>& kappa,
                const std::vector<double>& chi, std::vector<double>& tab);
