@@ -110,7 +110,12 @@ typedef struct {
                                   tile walked with density and tally in LDS, tally flushed
                                   to FP64 when a workgroup leaves the tile [1]; same packet
                                   histories.  Tiled sweeps hold at most 1024 cells per
-                                  axis (MCRT_E_UNSUPPORTED beyond)                        */
+                                  axis (MCRT_E_UNSUPPORTED beyond).  The tiled sweeps win
+                                  on grids where most cells hold dust and packets cross
+                                  many of them (5-6x on 128^3-256^3 clumps); the per-lane
+                                  walk on small or mostly empty grids (6.8x on a 32^3
+                                  sphere, 1.7x on a 128^3 disk), where a tile's load and
+                                  flush serve few records                                 */
     int32_t tile_z;            /* tiled sweeps: tile extent in z, 1..64, halved while the
                                   tile does not fit in LDS; 0: 20 in FP32, 32 in FP64 [0] */
     int32_t visit_events;      /* tiled sweeps: interactions per tile visit before a
