@@ -411,6 +411,8 @@ def main():
     ap.add_argument("--tile-xy", type=int, default=0)
     ap.add_argument("--tally-copies", type=int, default=0)
     ap.add_argument("--visit-events", type=int, default=0)
+    ap.add_argument("--drain", type=int, default=0,
+                    help="tiled sweeps: records left for the per-lane finish (-1 never, 0 default)")
     ap.add_argument("--mrw", type=float, default=0.0, help="modified random walk gamma (0 = off)")
     ap.add_argument("--max-events", type=int, default=0, help="batch: interactions before a kill")
     args = ap.parse_args()
@@ -498,6 +500,8 @@ def main():
         run["tally_copies"] = args.tally_copies
     if args.visit_events:
         run["visit_events"] = args.visit_events
+    if args.drain:
+        run["sweep_drain"] = args.drain
     model = mcrt.Model(cfg, **run)
     print(f"# workload built in {gen_s:.1f} s; warmup {args.warmup}", file=sys.stderr, flush=True)
     for i in range(args.warmup):
@@ -531,7 +535,10 @@ def main():
     # its launches of a pass; the one launch of the per-lane walk), timed by
     # HIP events on the stream it runs on
     ms_dom = float(np.mean([s["ms_dominant"] for s in stats]))
-    launches = float(np.mean([s["n_sweeps"] for s in stats])) if model.run["transport_mode"] == 1 else 1.0
+    # launches of the dominant kernel: the sweeps, plus the per-lane finish of
+    # the tail when the pass used it
+    launches = (float(np.mean([s["n_sweeps"] + (1 if s["n_drained"] else 0) for s in stats]))
+                if model.run["transport_mode"] == 1 else 1.0)
     abytes = float(np.mean([algorithmic_bytes(s, prec) for s in stats]))
     achieved = abytes / (ms_dom * 1e-3) / 1e9
     traffic, traffic_pass = measured_traffic(prec, int(model.run["transport_mode"]), args.workload)
@@ -555,7 +562,7 @@ def main():
         },
         "roofline": {
             "bound": "hbm",
-            "kernel": "k_sweep" if model.run["transport_mode"] == 1 else "k_transport",
+            "kernel": "k_sweep (+ k_sweep_drain)" if model.run["transport_mode"] == 1 else "k_transport",
             "achieved": achieved,
             "peak": HBM_PEAK_GBS,
             "unit": "GB/s",
@@ -581,7 +588,7 @@ def main():
             "scatters": last["n_scatter"], "absorptions": last["n_absorb"],
             "killed": last["n_killed"], "ms_update": last["ms_update"],
             "transport_mode": model.run["transport_mode"], "sweeps": last["n_sweeps"],
-            "tile_visits": last["n_visits"],
+            "tile_visits": last["n_visits"], "drained_records": last["n_drained"],
             "max_dT": last["max_dT"], "q": last["q"],
         },
     }

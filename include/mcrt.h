@@ -133,6 +133,11 @@ typedef struct {
                                   records than this are in flight after a sweep, the next
                                   sweep_batch packets are emitted into the pool (refill);
                                   0: 2^25 [0]                                             */
+    int64_t sweep_drain;       /* tiled sweeps: once every packet is emitted and at most
+                                  this many records remain, the per-lane walk finishes
+                                  them in one launch instead of further sweeps (same
+                                  histories); 0: the smaller of 2^18 and 1/64 of the
+                                  pass's packets, -1: never [0]                           */
 } mcrt_run_cfg;
 
 /* Statistics of one pass (a Lucy iteration or the final pass). */
@@ -165,8 +170,10 @@ typedef struct {
     int64_t n_visits;          /* tile visits (packet records walked) over those sweeps   */
     int64_t n_mrw;             /* modified-random-walk steps                              */
     double ms_dominant;        /* device time of the pass's dominant kernel, summed over
-                                  its launches (tiled sweeps: every sweep kernel; per-lane
-                                  walk: the one transport launch)                         */
+                                  its launches (tiled sweeps: every sweep kernel and the
+                                  per-lane finish of the tail; per-lane walk: the one
+                                  transport launch)                                       */
+    int64_t n_drained;         /* tiled sweeps: records of the tail finished per lane     */
 } mcrt_iter_stats;
 
 typedef struct {

@@ -50,6 +50,9 @@ template <typename R>
 hipError_t launch_sweep_step(const TransportParams<R>& P, const SweepParams& S, int b, bool full,
                              int emit_blocks, int group_blocks, int blocks, int threads, size_t lds,
                              hipStream_t st, hipEvent_t ev0, hipEvent_t ev1);
+template <typename R>
+hipError_t launch_sweep_drain(const TransportParams<R>& P, const SweepParams& S, int b, int blocks,
+                              hipStream_t st);
 template <typename R> hipError_t sweep_prepare(bool noise, bool full, size_t lds);
 template <typename R> int sweep_max_blocks_per_cu(bool noise, bool full, int threads, size_t lds);
 int sweep_emit_step();
@@ -761,13 +764,14 @@ int persistent_blocks(const mcrt_model* m, int bpc, int64_t np, int threads) {
 // into pinned memory and checks the flag of the step kSweepLag-1 steps back,
 // so that at most that many empty steps run after the last record.
 constexpr int64_t kSweepBatch = 1ll << 25;  // default packets emitted at once
+constexpr int64_t kSweepDrain = 1ll << 18;  // default records left for the per-lane finish
 constexpr int64_t kMaxSweeps = 1ll << 20;    // every visit advances a packet; this is a backstop
 constexpr int kSweepLag = 4;
 constexpr int64_t kChunkSlots = 64;     // record slots of a chunk (as in the sweep kernels)
 
 template <typename R>
 mcrt_status run_sweeps(mcrt_model* m, TransportParams<R>& P, int64_t np, int64_t* n_sweeps,
-                       int64_t* n_visits, double* ms_sweep) {
+                       int64_t* n_visits, double* ms_sweep, int64_t* n_drained) {
     hipStream_t s = m->stream;
     constexpr bool f32 = std::is_same<R, float>::value;
     for (int a = 0; a < 3; ++a)
@@ -815,6 +819,12 @@ mcrt_status run_sweeps(mcrt_model* m, TransportParams<R>& P, int64_t np, int64_t
                                                  : std::min<int64_t>(kSweepBatch, np);
     S.batch = (unsigned long long)batch;
     S.n_packets = (unsigned long long)np;
+    // the tail: records left once every packet is emitted, finished per lane
+    // (default: 2^18, at most 1/64 of the pass, so that small passes still
+    // walk nearly all of their packets through the tiles)
+    S.drain_below = m->cfg.sweep_drain < 0 ? 0ull
+                    : m->cfg.sweep_drain == 0 ? (unsigned long long)std::min<int64_t>(kSweepDrain, np / 64)
+                                              : (unsigned long long)m->cfg.sweep_drain;
     HIPCHK(sweep_prepare<R>(noise, full, lds));
     const int bpc = m->cfg.blocks_per_cu > 0 ? m->cfg.blocks_per_cu
                                              : sweep_max_blocks_per_cu<R>(noise, full, threads, lds);
@@ -902,12 +912,24 @@ mcrt_status run_sweeps(mcrt_model* m, TransportParams<R>& P, int64_t np, int64_t
         HIPCHK(hipEventElapsedTime(&t, m->sw_kev[2 * i], m->sw_kev[2 * i + 1]));
         ms += t;
     }
+    if (c.drain) {
+        // the per-lane finish of the tail, timed with the sweeps (its packets'
+        // crossings count in the pass's algorithmic bytes)
+        HIPCHK(hipEventRecord(m->sw_kev[0], s));
+        HIPCHK(launch_sweep_drain<R>(P, S, (int)c.drain_buf, m->n_cu * 8, s));
+        HIPCHK(hipEventRecord(m->sw_kev[1], s));
+        HIPCHK(hipEventSynchronize(m->sw_kev[1]));
+        float t = 0.f;
+        HIPCHK(hipEventElapsedTime(&t, m->sw_kev[0], m->sw_kev[1]));
+        ms += t;
+    }
     *ms_sweep = ms;
     if (c.overflow & 2u) return fail(m, MCRT_E_DEVICE, "tiled sweeps: a record was not in its tile");
     if (c.overflow)
         return fail(m, MCRT_E_NOMEM, "tiled sweep record buffers overflowed; lower sweep_batch");
     *n_sweeps = (int64_t)c.sweeps;
     *n_visits = (int64_t)c.visits;
+    *n_drained = c.drain ? (int64_t)c.drain_recs : 0;
     return MCRT_OK;
 }
 
@@ -927,20 +949,21 @@ mcrt_status run_transport(mcrt_model* m, int64_t np, uint32_t key1, int binning,
     const int layout = m->t_layout;
     HIPCHK(hipEventRecord(m->ev[0], s));
     if (m->cfg.transport_mode == 1) {
-        int64_t sweeps = 0, visits = 0;
+        int64_t sweeps = 0, visits = 0, drained = 0;
         double ms_sweep = 0.0;
         if (f32) {
             TransportParams<float> P;
             make_params(m, np, key1, binning, P);
-            r = run_sweeps<float>(m, P, np, &sweeps, &visits, &ms_sweep);
+            r = run_sweeps<float>(m, P, np, &sweeps, &visits, &ms_sweep, &drained);
         } else {
             TransportParams<double> P;
             make_params(m, np, key1, binning, P);
-            r = run_sweeps<double>(m, P, np, &sweeps, &visits, &ms_sweep);
+            r = run_sweeps<double>(m, P, np, &sweeps, &visits, &ms_sweep, &drained);
         }
         if (r != MCRT_OK) return r;
         st->n_sweeps = sweeps;
         st->n_visits = visits;
+        st->n_drained = drained;
         st->ms_dominant = ms_sweep;
     } else if (f32) {
         TransportParams<float> P;
@@ -1670,6 +1693,8 @@ mcrt_status mcrt_set_run(mcrt_model* m, const mcrt_run_cfg* c) {
     if (!(c->mrw_gamma >= 0.0) || !isfinite(c->mrw_gamma)) return fail(m, MCRT_E_ARG, "mrw_gamma must be >= 0");
     if (c->sweep_batch < 0 || c->sweep_batch > ((int64_t)1 << 30))
         return fail(m, MCRT_E_ARG, "sweep_batch must be in [0, 2^30]");
+    if (c->sweep_drain < -1 || c->sweep_drain > ((int64_t)1 << 30))
+        return fail(m, MCRT_E_ARG, "sweep_drain must be -1 or in [0, 2^30]");
     const bool reset = !m->have_run || c->t_init != m->cfg.t_init;
     m->cfg = *c;
     if (m->cfg.mrw_gamma > 0.0 && !m->mrw_tab_built) m->tables_dirty = true;

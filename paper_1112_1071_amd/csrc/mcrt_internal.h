@@ -173,6 +173,10 @@ struct SweepCtl {
     unsigned long long emitted;   // packets emitted so far in this pass
     unsigned long long emit_first, emit_count;  // the refill of the current step
     unsigned long long visits;    // records walked (tile visits) so far
+    unsigned drain;               // the pass's tail goes to the per-lane finish
+    unsigned drain_buf;           // the buffer whose records it finishes
+    unsigned drain_next;          // entries taken by the finish
+    unsigned drain_recs;          // records it finishes
 };
 
 // Tiled sweeps: the tiling and the buffers of a pass.  A record's state is
@@ -202,6 +206,7 @@ struct SweepParams {
     SweepCtl* ctl;
     unsigned long long n_packets;  // packets of the pass
     unsigned long long batch;      // refill batch
+    unsigned long long drain_below;  // finish per lane once at most this many records remain (0: never)
 };
 
 // Cell-update parameters (always FP64).

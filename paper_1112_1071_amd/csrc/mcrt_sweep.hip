@@ -695,6 +695,7 @@ __global__ void __launch_bounds__(kEmitThreads) k_sweep_emit(TransportParams<R> 
 __global__ void __launch_bounds__(1024) k_sweep_scan(SweepParams S, int b) {
     __shared__ unsigned s_a[1024], s_b[1024], s_r[1024];
     __shared__ unsigned s_hist[kMaxItemEnt], s_roff[kMaxItemEnt];
+    if (S.ctl->drain) return;  // the tail went to the per-lane finish
     const int n = S.ntiles;
     const unsigned ie = (unsigned)S.item_ent;
     const int per = (n + (int)blockDim.x - 1) / (int)blockDim.x;
@@ -753,9 +754,21 @@ __global__ void __launch_bounds__(1024) k_sweep_scan(SweepParams S, int b) {
         S.ent_off[n] = s_a[threadIdx.x];
         c->n_items = s_roff[0];
         c->item_next = 0u;
+        const bool emitted_all = c->emitted >= S.n_packets;
+        if (emitted_all && recs != 0u && recs <= S.drain_below) {
+            // few records left and nothing more to emit: the per-lane finish
+            // takes buffer b's entries as they are, and no sweep walks them
+            c->drain = 1u;
+            c->drain_buf = (unsigned)b;
+            c->drain_next = 0u;
+            c->drain_recs = recs;
+            c->n_items = 0u;
+            c->done = 1u;
+            return;
+        }
         c->visits += recs;
         if (recs) c->sweeps += 1u;
-        c->done = (recs == 0u && c->emitted >= S.n_packets) ? 1u : 0u;
+        c->done = (recs == 0u && emitted_all) ? 1u : 0u;
         c->rec_alloc[b ^ 1] = 0u;
         c->n_ent[b ^ 1] = 0u;
     }
@@ -773,6 +786,7 @@ constexpr int kGroupTiles = 4096;
 
 __global__ void __launch_bounds__(256) k_sweep_group(SweepParams S, int b) {
     __shared__ unsigned s_rank[kGroupTiles];
+    if (S.ctl->drain) return;
     const unsigned n = S.ctl->n_ent[b] < S.max_ent ? S.ctl->n_ent[b] : S.max_ent;
     if (S.ntiles > kGroupTiles) {
         for (unsigned e = blockIdx.x * blockDim.x + threadIdx.x; e < n; e += gridDim.x * blockDim.x) {
@@ -916,6 +930,7 @@ __global__ void __launch_bounds__(sizeof(R) == 4 ? (FULL ? 512 : 768) : 256) k_s
     __shared__ unsigned s_tc[14];          // records, entries registered per destination slot
     __shared__ unsigned long long s_cnt[C_COUNT];
     __shared__ double s_energy[2];
+    if (S.ctl->drain) return;  // the tail went to the per-lane finish
     const int bo = b ^ 1;  // the buffer this sweep writes
     const int txy = S.txy;
     const int tcells = txy * txy * S.tz;
@@ -1101,6 +1116,75 @@ __global__ void __launch_bounds__(sizeof(R) == 4 ? (FULL ? 512 : 768) : 256) k_s
     wave_out_release(S, bo, wo, lane);
     flush_block_counters(P, cnt, e_escaped, e_killed, s_cnt, s_energy);
 }
+
+// The tail of a pass.  Once every packet is emitted and at most drain_below
+// records remain, each further sweep would cost a kernel's start and end for
+// a few records of long-lived packets; instead the records of buffer b are
+// finished by the per-lane walk over the whole grid (global density and FP64
+// tally, the arithmetic of the tiled walk segment by segment), as in the
+// per-lane transport.  A wave takes one entry at a time and finishes its
+// records 64 at a time.
+template <typename R>
+__global__ void __launch_bounds__(256) k_sweep_drain(TransportParams<R> P, SweepParams S, int b) {
+    __shared__ unsigned long long s_cnt[C_COUNT];
+    __shared__ double s_energy[2];
+    if (threadIdx.x < C_COUNT) s_cnt[threadIdx.x] = 0ull;
+    if (threadIdx.x < 2) s_energy[threadIdx.x] = 0.0;
+    __syncthreads();
+    const Tables<R> tb = global_tables(P);
+    uint32_t cnt[C_COUNT];
+#pragma unroll
+    for (int c = 0; c < C_COUNT; ++c) cnt[c] = 0u;
+    double e_escaped = 0.0, e_killed = 0.0;
+    const int lane = __lane_id();
+    const unsigned n = S.ctl->n_ent[b] < S.max_ent ? S.ctl->n_ent[b] : S.max_ent;
+    for (;;) {
+        unsigned e = 0u;
+        if (lane == 0) e = atomicAdd(&S.ctl->drain_next, 1u);
+        e = __shfl(e, 0);
+        if (e >= n) break;
+        // (first record, count); count 0: an unused slot; a chunk holds at
+        // most 64 records, an emission run up to a block's step
+        const uint2 en = S.ent[b][e];
+        for (unsigned o = 0u; o < en.y; o += 64u) {
+            Packet<R> s;
+            s.st = ST_EMPTY;
+            Stream<R> rs;
+            rs.k0 = P.key0;
+            rs.k1 = P.key1;
+            rs.n = 0;
+            rs.p0 = rs.p1 = rs.s0 = rs.s1 = 0;
+            if (o + (unsigned)lane < en.y) {
+                Raw<R> r;
+                load_raw<R>(S, S.recs[b], en.x + o + (unsigned)lane, r);
+                unpack_rec(s, rs, P, r, tb.chi, tb.kap);
+            }
+            while (s.st == ST_WALK || s.st == ST_EVENT || s.st == ST_ESC) {
+                if (s.st == ST_WALK) walk<R, 4, 0>(s, P, P.acc, cnt);
+                if (s.st == ST_EVENT) interact(s, rs, P, tb, cnt, e_killed, global_deposit<0>(P, P.acc));
+                if (s.st == ST_ESC) escape(s, P, cnt, e_escaped);
+            }
+        }
+    }
+#pragma unroll
+    for (int c = 0; c < C_COUNT; ++c) atomicAdd(&s_cnt[c], (unsigned long long)cnt[c]);
+    atomicAdd(&s_energy[0], e_escaped);
+    atomicAdd(&s_energy[1], e_killed);
+    __syncthreads();
+    if (threadIdx.x < C_COUNT) atomicAdd(P.counters + threadIdx.x, s_cnt[threadIdx.x]);
+    if (threadIdx.x < 2) unsafeAtomicAdd(P.energies + threadIdx.x, s_energy[threadIdx.x]);
+}
+
+template <typename R>
+hipError_t launch_sweep_drain(const TransportParams<R>& P, const SweepParams& S, int b, int blocks,
+                              hipStream_t st) {
+    hipLaunchKernelGGL(k_sweep_drain<R>, dim3(blocks), dim3(256), 0, st, P, S, b);
+    return hipGetLastError();
+}
+template hipError_t launch_sweep_drain<float>(const TransportParams<float>&, const SweepParams&, int, int,
+                                              hipStream_t);
+template hipError_t launch_sweep_drain<double>(const TransportParams<double>&, const SweepParams&, int, int,
+                                               hipStream_t);
 
 __global__ void k_fill_u32(unsigned* p, int n, unsigned v) {
     for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) p[i] = v;

@@ -41,6 +41,7 @@ class RunCfg(C.Structure):
         ("grid_layout", C.c_int32), ("tally_copies", C.c_int32),
         ("transport_mode", C.c_int32), ("tile_z", C.c_int32), ("visit_events", C.c_int32),
         ("tile_xy", C.c_int32), ("mrw_gamma", C.c_double), ("sweep_batch", C.c_int64),
+        ("sweep_drain", C.c_int64),
     ]
 
 
@@ -55,7 +56,7 @@ class IterStats(C.Structure):
         ("n_killed", C.c_int64), ("e_escaped", C.c_double), ("e_killed", C.c_double),
         ("ms_transport", C.c_double), ("ms_update", C.c_double), ("ms_total", C.c_double),
         ("n_sweeps", C.c_int64), ("n_visits", C.c_int64), ("n_mrw", C.c_int64),
-        ("ms_dominant", C.c_double),
+        ("ms_dominant", C.c_double), ("n_drained", C.c_int64),
     ]
 
     def as_dict(self) -> dict:

@@ -1,4 +1,4 @@
-"""The tiled transport's pool refill (Sec. 2.2 packets, Eq. 2 tallies), driven
+"""The tiled transport's pool refill and tail (Sec. 2.2 packets, Eq. 2 tallies), driven
 with a small emission batch so that one pass refills the pool many times: the
 path the 1e8-packet benchmark pass takes with its 2^25-packet batches.
 
@@ -107,6 +107,46 @@ def test_fp32_tiled_refills_equal_the_per_lane_walk(M):
     a = M.Model(cfg, precision=M.MCRT_FP32_TRANSPORT, transport_mode=0)
     b = M.Model(cfg, precision=M.MCRT_FP32_TRANSPORT, transport_mode=1, sweep_batch=3000)
     sa, sb = a.iterate(), b.iterate()
+    for k in COUNTERS:
+        assert sa[k] == sb[k], (k, sa[k], sb[k])
+    aa, ab = a.specific_energy(), b.specific_energy()
+    nz = aa > 0
+    assert np.array_equal(nz, ab > 0)
+    np.testing.assert_allclose(ab[nz], aa[nz], rtol=1e-9)
+    a.close()
+    b.close()
+
+
+@pytest.mark.parametrize("drain", [-1, 1000, 1 << 30])
+def test_fp64_tail_finish_matches_oracle(M, sphere_oracle, drain):
+    # once every packet is emitted and at most `drain` records remain, the
+    # per-lane walk finishes them (-1: never; 2^30: everything left after the
+    # emission): the same histories as the oracle's either way
+    cfg, run, so, (eo, co), ao = sphere_oracle
+    g = M.Model(cfg, precision=M.MCRT_FP64, transport_mode=1, sweep_batch=9999, sweep_drain=drain, **run)
+    sg = g.iterate()
+    for k in COUNTERS:
+        assert sg[k] == so[k], (drain, k, sg[k], so[k])
+    eg, cg = g.event_log()
+    _logs_equal(eo, co, eg, cg)
+    ag = g.specific_energy()
+    nz = ao > 0
+    assert np.array_equal(nz, ag > 0)
+    np.testing.assert_allclose(ag[nz], ao[nz], rtol=1e-9)
+    if drain < 0:
+        assert sg["n_drained"] == 0
+    else:
+        assert sg["n_drained"] > 0
+    g.close()
+
+
+def test_fp32_tail_finish_equals_sweeps(M):
+    # the benchmark's FP32 launch shape with and without the per-lane finish
+    cfg = synth.config2(n=64, n_packets=200_000, n_iter=1)
+    a = M.Model(cfg, precision=M.MCRT_FP32_TRANSPORT, transport_mode=1, sweep_drain=-1)
+    b = M.Model(cfg, precision=M.MCRT_FP32_TRANSPORT, transport_mode=1, sweep_drain=1 << 30)
+    sa, sb = a.iterate(), b.iterate()
+    assert sa["n_drained"] == 0 and sb["n_drained"] > 0
     for k in COUNTERS:
         assert sa[k] == sb[k], (k, sa[k], sb[k])
     aa, ab = a.specific_energy(), b.specific_energy()
