@@ -411,6 +411,8 @@ def main():
     ap.add_argument("--tile-xy", type=int, default=0)
     ap.add_argument("--tally-copies", type=int, default=0)
     ap.add_argument("--visit-events", type=int, default=0)
+    ap.add_argument("--sweep-batch", type=int, default=0,
+                    help="tiled sweeps: packets emitted at a time (0: default 2^25)")
     ap.add_argument("--drain", type=int, default=0,
                     help="tiled sweeps: records left for the per-lane finish (-1 never, 0 default)")
     ap.add_argument("--mrw", type=float, default=0.0, help="modified random walk gamma (0 = off)")
@@ -502,6 +504,8 @@ def main():
         run["visit_events"] = args.visit_events
     if args.drain:
         run["sweep_drain"] = args.drain
+    if args.sweep_batch:
+        run["sweep_batch"] = args.sweep_batch
     model = mcrt.Model(cfg, **run)
     print(f"# workload built in {gen_s:.1f} s; warmup {args.warmup}", file=sys.stderr, flush=True)
     for i in range(args.warmup):

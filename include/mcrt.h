@@ -132,7 +132,10 @@ typedef struct {
     int64_t sweep_batch;       /* tiled sweeps: packets emitted at a time; whenever fewer
                                   records than this are in flight after a sweep, the next
                                   sweep_batch packets are emitted into the pool (refill);
-                                  0: 2^25 [0]                                             */
+                                  0: as many as two record buffers (about 2.7 batches of
+                                  80-byte FP32 or 144-byte FP64 records each) hold in 30 %
+                                  of the device memory: 2e8 (FP32) or 1.1e8 (FP64) packets
+                                  on a 288 GB MI355X, at least 2^25 [0]                   */
     int64_t sweep_drain;       /* tiled sweeps: once every packet is emitted and at most
                                   this many records remain, the per-lane walk finishes
                                   them in one launch instead of further sweeps (same

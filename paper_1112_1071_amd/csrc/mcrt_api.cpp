@@ -111,6 +111,7 @@ struct mcrt_model {
     hipStream_t stream = nullptr;
     bool own_stream = false;
     int n_cu = 256;
+    size_t mem_total = 0;  // device memory, bytes
     // problem
     bool have_grid = false, have_rho = false, have_nu = false, have_dust = false,
          have_obs = false, have_run = false;
@@ -815,8 +816,20 @@ mcrt_status run_sweeps(mcrt_model* m, TransportParams<R>& P, int64_t np, int64_t
     // lanes of a wave that wait (events, escapes, exits, free lanes with a
     // record to take) before the wave handles them
     S.service = m->cfg.defer_lanes > 0 ? m->cfg.defer_lanes : 48;
-    const int64_t batch = m->cfg.sweep_batch > 0 ? std::min<int64_t>(m->cfg.sweep_batch, np)
-                                                 : std::min<int64_t>(kSweepBatch, np);
+    // packets emitted at a time: by default as many as two record buffers of
+    // about 2.7 batches each hold within 30 % of the device's memory (FP32:
+    // 2e8 packets on 288 GB), so that a pass of up to that many packets is
+    // emitted at once; every tile then starts with its share of the whole
+    // pass, the sweeps' visits serve the most records, and no refill tails
+    // follow one another (on the 256^3 clump at 1e8 packets: 110 ms per
+    // iteration, against 137 ms in batches of 2^25)
+    int64_t batch = m->cfg.sweep_batch;
+    if (batch <= 0) {
+        const double per = 2.0 * 2.7 * (double)sweep_record_bytes(f32 ? 1 : 0);
+        batch = std::max<int64_t>(kSweepBatch, (int64_t)(0.3 * (double)m->mem_total / per));
+        batch = std::min<int64_t>(batch, (int64_t)1 << 30);
+    }
+    batch = std::min<int64_t>(batch, np);
     S.batch = (unsigned long long)batch;
     S.n_packets = (unsigned long long)np;
     // the tail: records left once every packet is emitted, finished per lane
@@ -1162,6 +1175,10 @@ mcrt_status mcrt_create(mcrt_model** out, int hip_device) {
     }
     m->own_stream = true;
     hipDeviceGetAttribute(&m->n_cu, hipDeviceAttributeMultiprocessorCount, hip_device);
+    {
+        size_t fr = 0, tot = 0;
+        if (hipMemGetInfo(&fr, &tot) == hipSuccess) m->mem_total = tot;
+    }
     {
         int lds = 0;
         if (hipDeviceGetAttribute(&lds, hipDeviceAttributeMaxSharedMemoryPerBlock, hip_device) == hipSuccess &&
