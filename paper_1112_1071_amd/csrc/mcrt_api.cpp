@@ -91,6 +91,87 @@ template <typename T> struct DBuf {
     }
 };
 
+// Device memory of the tiled sweeps' record and entry buffers (tens of GB for
+// a pass of 1e8 packets).  Blocks a model lets go of stay with the process,
+// per device, and serve the next model that needs at most their size, so a
+// series of models (a warm-start comparison, a test suite) does not map and
+// unmap that memory once per model.  When the device runs out of memory the
+// device's idle blocks are freed and the allocation is tried again.
+struct PoolBlock {
+    int device;
+    void* p;
+    size_t bytes;
+};
+std::mutex g_pool_mu;
+std::vector<PoolBlock> g_pool;
+
+hipError_t pool_get(int device, size_t bytes, void** out, size_t* got) {
+    {
+        std::lock_guard<std::mutex> lk(g_pool_mu);
+        size_t best = g_pool.size();
+        for (size_t i = 0; i < g_pool.size(); ++i)
+            if (g_pool[i].device == device && g_pool[i].bytes >= bytes &&
+                (best == g_pool.size() || g_pool[i].bytes < g_pool[best].bytes))
+                best = i;
+        if (best < g_pool.size()) {
+            *out = g_pool[best].p;
+            *got = g_pool[best].bytes;
+            g_pool.erase(g_pool.begin() + (std::ptrdiff_t)best);
+            return hipSuccess;
+        }
+    }
+    hipError_t e = hipMalloc(out, bytes);
+    if (e == hipErrorOutOfMemory) {
+        (void)hipGetLastError();
+        {
+            std::lock_guard<std::mutex> lk(g_pool_mu);
+            for (size_t i = 0; i < g_pool.size();) {
+                if (g_pool[i].device == device) {
+                    hipFree(g_pool[i].p);
+                    g_pool.erase(g_pool.begin() + (std::ptrdiff_t)i);
+                } else {
+                    ++i;
+                }
+            }
+        }
+        e = hipMalloc(out, bytes);
+    }
+    *got = e == hipSuccess ? bytes : 0;
+    return e;
+}
+
+void pool_put(int device, void* p, size_t bytes) {
+    std::lock_guard<std::mutex> lk(g_pool_mu);
+    g_pool.push_back(PoolBlock{device, p, bytes});
+}
+
+template <typename T> struct PoolBuf {
+    T* p = nullptr;
+    size_t n = 0;
+    size_t bytes = 0;
+    int device = 0;
+    hipError_t ensure(int dev, size_t count) {
+        if (count <= n && p) return hipSuccess;
+        release();
+        void* q = nullptr;
+        size_t got = 0;
+        const hipError_t e = pool_get(dev, (count ? count : 1) * sizeof(T), &q, &got);
+        if (e == hipSuccess) {
+            p = static_cast<T*>(q);
+            n = got / sizeof(T);
+            bytes = got;
+            device = dev;
+        }
+        return e;
+    }
+    void release() {
+        if (p) pool_put(device, p, bytes);
+        p = nullptr;
+        n = 0;
+        bytes = 0;
+    }
+};
+
 struct Source {
     double pos[3];
     double lum;
@@ -178,9 +259,9 @@ struct mcrt_model {
     // lists), entries grouped by tile, per-tile counts, offsets and cursors,
     // control words; pinned host copies of the termination flag and events
     // for the lagged check of the host loop
-    DBuf<uint4> sw_rec[2];
-    DBuf<unsigned> sw_ent_tile[2];
-    DBuf<uint2> sw_ent[2], sw_sent;
+    PoolBuf<uint4> sw_rec[2];
+    PoolBuf<unsigned> sw_ent_tile[2];
+    PoolBuf<uint2> sw_ent[2], sw_sent;
     DBuf<unsigned> sw_tile_rec, sw_tile_ent, sw_ent_off, sw_cursor;
     DBuf<uint4> sw_item_desc;
     DBuf<SweepCtl> sw_ctl;
@@ -859,14 +940,14 @@ mcrt_status run_sweeps(mcrt_model* m, TransportParams<R>& P, int64_t np, int64_t
     S.max_ent = (unsigned)std::min<int64_t>(cap / 4 + 65536 + 32 * waves, 0xffff0000ll);
     const size_t rq = sweep_record_bytes(f32 ? 1 : 0) / 16;
     for (int b = 0; b < 2; ++b) {
-        HIPCHK(m->sw_rec[b].ensure((size_t)cap * rq));
-        HIPCHK(m->sw_ent_tile[b].ensure(S.max_ent));
-        HIPCHK(m->sw_ent[b].ensure(S.max_ent));
+        HIPCHK(m->sw_rec[b].ensure(m->device, (size_t)cap * rq));
+        HIPCHK(m->sw_ent_tile[b].ensure(m->device, S.max_ent));
+        HIPCHK(m->sw_ent[b].ensure(m->device, S.max_ent));
         S.recs[b] = m->sw_rec[b].p;
         S.ent_tile[b] = m->sw_ent_tile[b].p;
         S.ent[b] = m->sw_ent[b].p;
     }
-    HIPCHK(m->sw_sent.ensure(S.max_ent));
+    HIPCHK(m->sw_sent.ensure(m->device, S.max_ent));
     HIPCHK(m->sw_tile_rec.ensure((size_t)S.ntiles));
     HIPCHK(m->sw_tile_ent.ensure((size_t)S.ntiles));
     HIPCHK(m->sw_ent_off.ensure((size_t)S.ntiles + 1));
