@@ -36,10 +36,11 @@ def algorithmic_bytes(st: dict, precision: int) -> float:
 
 
 def measured_traffic(precision: int, mode: int, workload: str = "clump256"):
-    """HBM bytes per launch of the dominant transport kernel, and per pass of
-    every transport kernel, from the committed rocprofv3 FETCH_SIZE /
-    WRITE_SIZE summary, if it was taken on the current transport source, in the
-    same precision and transport mode."""
+    """HBM bytes per pass of the dominant transport kernel (the sweeps and the
+    tail's finish, or the per-lane walk), and per pass of every transport
+    kernel, from the committed rocprofv3 FETCH_SIZE / WRITE_SIZE summary, if it
+    was taken on the current transport source, in the same precision and
+    transport mode."""
     from paper_1112_1071_amd.profiling import transport_source_hash
 
     p = os.path.join(ROOT, "profiles", "transport_clump256_pmc.json")
@@ -52,7 +53,7 @@ def measured_traffic(precision: int, mode: int, workload: str = "clump256"):
     if (d.get("source_hash") != transport_source_hash() or d.get("precision") != precision
             or d.get("mode") != mode or d.get("workload", "clump256") != workload):
         return None, None
-    return d.get("hbm_bytes_per_launch"), d.get("hbm_bytes_per_pass")
+    return d.get("dominant_bytes_per_pass"), d.get("hbm_bytes_per_pass")
 
 
 def cpu_baseline(cfg: dict, n_packets: int, what: str, one_thread_packets: int = 0) -> dict:
@@ -545,7 +546,10 @@ def main():
                 if model.run["transport_mode"] == 1 else 1.0)
     abytes = float(np.mean([algorithmic_bytes(s, prec) for s in stats]))
     achieved = abytes / (ms_dom * 1e-3) / 1e9
-    traffic, traffic_pass = measured_traffic(prec, int(model.run["transport_mode"]), args.workload)
+    traffic_dom, traffic_pass = measured_traffic(prec, int(model.run["transport_mode"]), args.workload)
+    # counter bytes of the dominant kernel per pass over the launches timed
+    # here, the same division as the algorithmic bytes
+    traffic = traffic_dom / launches if traffic_dom else None
     last = stats[-1]
     out = {
         "metric": f"packets/s at {int(cfg['grid']['n'][0])}^3 (Lucy iterations)",

@@ -96,7 +96,7 @@ typedef struct {
     int32_t blocks_per_cu;     /* persistent blocks per compute unit [0 = occupancy]      */
     int32_t defer_lanes;       /* lanes of a wave that wait before events run (tiled
                                   sweeps: interactions, escapes, exits and free lanes with
-                                  a record to take); 0: 16 for the per-lane walk, 48 for
+                                  a record to take); 0: 16 for the per-lane walk, 40 for
                                   tiled sweeps [0]                                        */
     int32_t walk_batch;        /* grid segments a lane gathers per walk step of the
                                   per-lane walk: 1,2,4,8 [4]; tiled sweeps walk 4         */

@@ -895,8 +895,9 @@ mcrt_status run_sweeps(mcrt_model* m, TransportParams<R>& P, int64_t np, int64_t
     // a work item: entries of one tile, about 16 records per thread when full
     S.item_ent = std::max(1, std::min(threads * 16 / 64, 256));
     // lanes of a wave that wait (events, escapes, exits, free lanes with a
-    // record to take) before the wave handles them
-    S.service = m->cfg.defer_lanes > 0 ? m->cfg.defer_lanes : 48;
+    // record to take) before the wave handles them (40 on the 256^3 clump:
+    // 0.6 % faster than 48, 2 % faster than 32)
+    S.service = m->cfg.defer_lanes > 0 ? m->cfg.defer_lanes : 40;
     // packets emitted at a time: by default as many as two record buffers of
     // about 2.7 batches each hold within 30 % of the device's memory (FP32:
     // 2e8 packets on 288 GB), so that a pass of up to that many packets is

@@ -35,17 +35,27 @@ def transport_source_hash() -> str:
     return h.hexdigest()[:16]
 
 
-def _rows(d: str):
+def _rows(d: str, skip: int = 0, iterations: int = 0):
+    """counter rows in dispatch order; with `iterations` > 0, only those of the
+    Lucy iterations skip .. skip + iterations - 1 (an iteration ends with its
+    cell update, k_update)"""
     files = glob.glob(os.path.join(d, "**", "*counter_collection.csv"), recursive=True)
     if not files:
         raise FileNotFoundError(f"no counter_collection.csv under {d}")
-    for f in files:
-        yield from csv.DictReader(open(f))
+    rows = [r for f in files for r in csv.DictReader(open(f))]
+    if "Dispatch_Id" in (rows[0] if rows else {}):
+        rows.sort(key=lambda r: int(r["Dispatch_Id"]))
+    it = 0
+    for r in rows:
+        if iterations <= 0 or skip <= it < skip + iterations:
+            yield r
+        if "k_update" in r["Kernel_Name"]:
+            it += 1
 
 
-def _sum(d: str, counter: str, kernels=TRANSPORT_KERNELS) -> float:
+def _sum(d: str, counter: str, kernels=TRANSPORT_KERNELS, skip: int = 0, iterations: int = 0) -> float:
     tot = 0.0
-    for r in _rows(d):
+    for r in _rows(d, skip, iterations):
         if r["Counter_Name"] == counter and any(k in r["Kernel_Name"] for k in kernels):
             tot += float(r["Counter_Value"])
     return tot
@@ -61,38 +71,49 @@ def _copy_factor(d: str, counter: str) -> float:
     return (1 << 30) / (sum(vals) / len(vals))
 
 
-def _sweep_dispatches(d: str, counter: str, dominant: str):
+def _dispatches(d: str, counter: str, names, skip: int = 0, iterations: int = 0):
     """(summed counter, number of dispatches) over the dispatches of the
-    dominant kernel (names starting with `dominant` followed by '<')"""
+    kernels named in `names` (each name followed by '<' in the kernel's name)"""
     per = defaultdict(float)
-    pat = re.compile(r"(^|[\s:])" + re.escape(dominant) + "<")
-    for r in _rows(d):
+    pat = re.compile(r"(^|[\s:])(" + "|".join(re.escape(n) for n in names) + ")<")
+    for r in _rows(d, skip, iterations):
         if r["Counter_Name"] == counter and pat.search(r["Kernel_Name"]):
             per[r.get("Dispatch_Id") or r.get("Correlation_Id")] += float(r["Counter_Value"])
     return sum(per.values()), len(per)
 
 
 def traffic(a) -> dict:
+    """HBM bytes per Lucy iteration of the dominant transport kernel (the
+    sweeps and the per-lane finish of their tail, or the per-lane walk) and of
+    every transport kernel.  The dominant kernel's bytes are given per pass:
+    the device-driven sweep loop also launches a few sweeps that find no work,
+    so a mean over dispatches would not be a mean over the launches that
+    transport packets; the benchmark divides the per-pass figure by the
+    launches it times (the sweeps that ran, plus the tail's finish)."""
     ff = _copy_factor(a.copy_fetch, "FETCH_SIZE")
     fw = _copy_factor(a.copy_write, "WRITE_SIZE")
-    fetch = _sum(a.fetch, "FETCH_SIZE") * ff / a.iterations
-    write = _sum(a.write, "WRITE_SIZE") * fw / a.iterations
-    dom = "k_sweep" if a.mode == 1 else "k_transport"
-    df, nf = _sweep_dispatches(a.fetch, "FETCH_SIZE", dom)
-    dw, nw = _sweep_dispatches(a.write, "WRITE_SIZE", dom)
+    # the iterations skip .. skip + iterations - 1 of the run (skip 1 leaves
+    # out the first pass, which starts from the initial temperature)
+    sk = getattr(a, "skip", 0)
+    fetch = _sum(a.fetch, "FETCH_SIZE", skip=sk, iterations=a.iterations) * ff / a.iterations
+    write = _sum(a.write, "WRITE_SIZE", skip=sk, iterations=a.iterations) * fw / a.iterations
+    dom = ("k_sweep", "k_sweep_drain") if a.mode == 1 else ("k_transport",)
+    df, nf = _dispatches(a.fetch, "FETCH_SIZE", dom, sk, a.iterations)
+    dw, nw = _dispatches(a.write, "WRITE_SIZE", dom, sk, a.iterations)
     if nf == 0 or nw == 0:
-        raise ValueError(f"no {dom} dispatch in the counter runs")
+        raise ValueError(f"no {' / '.join(dom)} dispatch in the counter runs")
     return {"source_hash": transport_source_hash(), "precision": a.precision, "mode": a.mode,
-            "workload": a.workload, "kernel": dom,
-            "hbm_bytes_per_launch": df * ff / nf + dw * fw / nw,
-            "fetch_bytes_per_launch": df * ff / nf, "write_bytes_per_launch": dw * fw / nw,
-            "launches": nf,
+            "workload": a.workload, "kernel": " + ".join(dom),
+            "dominant_fetch_bytes_per_pass": df * ff / a.iterations,
+            "dominant_write_bytes_per_pass": dw * fw / a.iterations,
+            "dominant_bytes_per_pass": (df * ff + dw * fw) / a.iterations,
+            "dispatches_per_pass": nf / a.iterations,
             "fetch_bytes_per_pass": fetch, "write_bytes_per_pass": write,
             "hbm_bytes_per_pass": fetch + write,
             "fetch_scale": ff, "write_scale": fw,
-            "note": f"rocprofv3 FETCH_SIZE and WRITE_SIZE per {dom} dispatch (averaged over the "
-                    f"dispatches of {a.iterations} Lucy iterations), and summed over every transport "
-                    "kernel per iteration, scaled by a 1 GiB copy"}
+            "note": f"rocprofv3 FETCH_SIZE and WRITE_SIZE summed over the dispatches of "
+                    f"{' and '.join(dom)} and over every transport kernel, per Lucy iteration "
+                    f"(mean of {a.iterations} after skipping {sk}), scaled by a 1 GiB copy"}
 
 
 def kernels(a) -> str:
@@ -164,6 +185,7 @@ def main():
     t.add_argument("--copy-fetch", required=True)
     t.add_argument("--copy-write", required=True)
     t.add_argument("--iterations", type=int, default=2)
+    t.add_argument("--skip", type=int, default=0, help="Lucy iterations to leave out at the start")
     t.add_argument("--precision", type=int, default=1)
     t.add_argument("--mode", type=int, default=1)
     t.add_argument("--workload", default="clump256")

@@ -20,28 +20,39 @@ def _write(d, rows):
             w.writerow(dict(zip(FIELDS, r)))
 
 
-def test_traffic_per_sweep_launch_and_per_pass(tmp_path):
+def test_traffic_of_sweeps_and_tail_finish_per_pass(tmp_path):
     sweep = "void mcrt::k_sweep<float, false, false>(mcrt::SweepParams)"
+    drain = "void mcrt::k_sweep_drain<float>(mcrt::SweepParams)"
     emit = "void mcrt::k_sweep_emit<float, false>(mcrt::SweepParams)"
-    other = "void (anonymous namespace)::k_update(Foo)"
-    # two sweeps (100 and 300 KiB read), one emission (50), one unrelated kernel
-    _write(tmp_path / "f", [(1, sweep, "FETCH_SIZE", 100), (2, sweep, "FETCH_SIZE", 300),
-                            (3, emit, "FETCH_SIZE", 50), (4, other, "FETCH_SIZE", 1e6)])
-    _write(tmp_path / "w", [(1, sweep, "WRITE_SIZE", 10), (2, sweep, "WRITE_SIZE", 30),
-                            (3, emit, "WRITE_SIZE", 5), (4, other, "WRITE_SIZE", 1e6)])
+    upd = "void (anonymous namespace)::k_update(Foo)"
+    # two passes, each ended by its cell update (1e6 KiB, not transport):
+    # pass 0: one sweep (500 KiB read), the emission (60); pass 1: two sweeps
+    # (100, 300), the tail's finish (20), the emission (50)
+    fr = [(1, emit, 60), (2, sweep, 500), (3, upd, 1e6),
+          (4, emit, 50), (5, sweep, 100), (6, sweep, 300), (7, drain, 20), (8, upd, 1e6)]
+    # listed out of dispatch order: the passes follow the dispatch ids
+    _write(tmp_path / "f", [(i, k, "FETCH_SIZE", v) for i, k, v in reversed(fr)])
+    _write(tmp_path / "w", [(i, k, "WRITE_SIZE", v / 10) for i, k, v in fr])
     # the copy moves 1 GiB: FETCH reads half of it, WRITE all of it
     copy = "void copyBuffer(...)"
     _write(tmp_path / "cf", [(1, copy, "FETCH_SIZE", (1 << 30) / 2)])
     _write(tmp_path / "cw", [(1, copy, "WRITE_SIZE", 1 << 30)])
     a = SimpleNamespace(fetch=str(tmp_path / "f"), write=str(tmp_path / "w"),
                         copy_fetch=str(tmp_path / "cf"), copy_write=str(tmp_path / "cw"),
-                        iterations=1, precision=1, mode=1, workload="clump256")
+                        iterations=1, skip=1, precision=1, mode=1, workload="clump256")
     r = profiling.traffic(a)
     assert r["fetch_scale"] == pytest.approx(2.0) and r["write_scale"] == pytest.approx(1.0)
-    assert r["launches"] == 2
-    assert r["fetch_bytes_per_launch"] == pytest.approx(2.0 * 200)
-    assert r["write_bytes_per_launch"] == pytest.approx(20)
-    assert r["hbm_bytes_per_launch"] == pytest.approx(420)
-    # the pass sums every transport kernel (sweeps and emission), not k_update
-    assert r["fetch_bytes_per_pass"] == pytest.approx(2.0 * 450)
-    assert r["write_bytes_per_pass"] == pytest.approx(45)
+    # the second pass alone: sweeps and the tail's finish, not the emission
+    assert r["dispatches_per_pass"] == 3
+    assert r["dominant_fetch_bytes_per_pass"] == pytest.approx(2.0 * 420)
+    assert r["dominant_write_bytes_per_pass"] == pytest.approx(42)
+    assert r["dominant_bytes_per_pass"] == pytest.approx(882)
+    # every transport kernel of the pass (sweeps, finish, emission), not k_update
+    assert r["fetch_bytes_per_pass"] == pytest.approx(2.0 * 470)
+    assert r["write_bytes_per_pass"] == pytest.approx(47)
+    # both passes, averaged
+    a.skip, a.iterations = 0, 2
+    r = profiling.traffic(a)
+    assert r["dispatches_per_pass"] == 2
+    assert r["dominant_fetch_bytes_per_pass"] == pytest.approx(2.0 * 920 / 2)
+    assert r["fetch_bytes_per_pass"] == pytest.approx(2.0 * 1030 / 2)
