@@ -241,13 +241,13 @@ __device__ __forceinline__ void walk_tile(Packet<R>& s, const TransportParams<R>
     const int r0i = px ? h0 - 1 - s.c0 : s.c0 - o0;
     const int r1i = py ? h1 - 1 - s.c1 : s.c1 - o1;
     const int r2i = pz ? h2 - 1 - s.c2 : s.c2 - o2;
-    int r0 = r0i, r1 = r1i, r2 = r2i;  // moves left inside the tile per axis
+    // moves left inside the tile per axis, ten bits each (a tile spans at
+    // most 1023 cells per axis)
+    uint32_t rp = (uint32_t)r0i | ((uint32_t)r1i << 10) | ((uint32_t)r2i << 20);
     bool act = true;    // still walking in this call
     bool hit = false;   // the last segment ends in an interaction
     bool left = false;  // the last segment crosses the tile's (or grid's) wall
     int lax = 0;        // and on which axis
-    R rc_h = (R)1, ts_h = (R)0;
-    int jl_h = jl;
     uint32_t nd = 0, ne = 0;
     const R wk = s.wgt * s.kap;  // tally weight per unit path length
 #pragma unroll
@@ -256,13 +256,12 @@ __device__ __forceinline__ void walk_tile(Packet<R>& s, const TransportParams<R>
         R tm = ax1 ? s.ty : s.tx;
         const bool ax2 = s.tz < tm;
         tm = ax2 ? s.tz : tm;
-        const int r = ax2 ? r2 : (ax1 ? r1 : r0);
-        const bool edge = r == 0;  // the next cell is outside the tile or the grid
+        const uint32_t sh = ax2 ? 20u : (ax1 ? 10u : 0u);
+        const bool edge = ((rp >> sh) & 1023u) == 0u;  // the next cell is outside the tile or the grid
         const int dj = ax2 ? djz : (ax1 ? djy : sx);
         const int jn = edge ? jl : jl + dj;
         const R rho_n = rho_t[jn];
         // this segment
-        const R ts = s.t;
         const R l = fmax(tm - s.t, (R)0);
         const bool dust = rho > (R)0;
         const R rc = rho * s.chi;
@@ -271,12 +270,9 @@ __device__ __forceinline__ void walk_tile(Packet<R>& s, const TransportParams<R>
         const bool cross = act && !h;  // the segment reaches the cell wall
         nd += (act && dust) ? 1u : 0u;
         ne += (act && !dust) ? 1u : 0u;
-        if (h) {
-            hit = true;
-            rc_h = rc;
-            ts_h = ts;
-            jl_h = jl;
-        }
+        // after an interaction nothing moves: the ray parameter, the cell and
+        // its density stay those of the interaction's segment
+        hit = hit || h;
         if (cross && dust) {
             s.tau_acc += dtau;
             const R w = wk * l;
@@ -288,9 +284,7 @@ __device__ __forceinline__ void walk_tile(Packet<R>& s, const TransportParams<R>
         s.t = (cross && tm > s.t) ? tm : s.t;
         const bool mv = cross && !edge;
         const bool m0 = mv && !ax1 && !ax2, m1 = mv && ax1 && !ax2, m2 = mv && ax2;
-        r0 -= m0 ? 1 : 0;
-        r1 -= m1 ? 1 : 0;
-        r2 -= m2 ? 1 : 0;
+        rp -= mv ? (1u << sh) : 0u;
         s.tx += m0 ? s.dtx : (R)0;
         s.ty += m1 ? s.dty : (R)0;
         s.tz += m2 ? s.dtz : (R)0;
@@ -301,16 +295,16 @@ __device__ __forceinline__ void walk_tile(Packet<R>& s, const TransportParams<R>
         jl = mv ? jn : jl;
         rho = mv ? rho_n : rho;
     }
-    s.c0 += sx * (r0i - r0);
-    s.c1 += sy * (r1i - r1);
-    s.c2 += sz * (r2i - r2);
+    s.c0 += sx * (r0i - (int)(rp & 1023u));
+    s.c1 += sy * (r1i - (int)((rp >> 10) & 1023u));
+    s.c2 += sz * (r2i - (int)(rp >> 20));
     int st = ST_WALK;
     if (hit) {
-        const R l = (s.tau - s.tau_acc) / rc_h;
+        const R l = (s.tau - s.tau_acc) / (rho * s.chi);
         const R w = wk * l;
-        atomicAdd(acc_t + jl_h, (double)w);
-        if (NOISE) atomicAdd(acc2_t + jl_h, (double)w * (double)w);
-        s.t = ts_h + l;
+        atomicAdd(acc_t + jl, (double)w);
+        if (NOISE) atomicAdd(acc2_t + jl, (double)w * (double)w);
+        s.t = s.t + l;
         st = ST_EVENT;
         // the cell's emission row, loaded now for the interaction (an
         // absorption re-emits from it) while the wave walks on
