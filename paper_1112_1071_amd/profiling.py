@@ -45,12 +45,17 @@ def _rows(d: str, skip: int = 0, iterations: int = 0):
     rows = [r for f in files for r in csv.DictReader(open(f))]
     if "Dispatch_Id" in (rows[0] if rows else {}):
         rows.sort(key=lambda r: int(r["Dispatch_Id"]))
-    it = 0
+    # a dispatch has one row per counter: an iteration ends after the last
+    # row of its k_update dispatch
+    it, upd = 0, None
     for r in rows:
+        did = r.get("Dispatch_Id")
+        if upd is not None and did != upd:
+            it, upd = it + 1, None
         if iterations <= 0 or skip <= it < skip + iterations:
             yield r
         if "k_update" in r["Kernel_Name"]:
-            it += 1
+            upd = did
 
 
 def _sum(d: str, counter: str, kernels=TRANSPORT_KERNELS, skip: int = 0, iterations: int = 0) -> float:

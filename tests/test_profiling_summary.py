@@ -56,3 +56,16 @@ def test_traffic_of_sweeps_and_tail_finish_per_pass(tmp_path):
     assert r["dispatches_per_pass"] == 2
     assert r["dominant_fetch_bytes_per_pass"] == pytest.approx(2.0 * 920 / 2)
     assert r["fetch_bytes_per_pass"] == pytest.approx(2.0 * 1030 / 2)
+
+
+def test_iterations_split_with_several_counters_per_dispatch(tmp_path):
+    # a run with two counters writes two rows per dispatch; the iteration ends
+    # after both rows of its cell update
+    sweep = "void mcrt::k_sweep<float, false, false>(mcrt::SweepParams)"
+    upd = "void (anonymous namespace)::k_update(Foo)"
+    fr = [(1, sweep, 5), (2, upd, 0), (3, sweep, 7), (4, upd, 0)]
+    rows = [(i, k, c, v * (1 if c == "A" else 100)) for i, k, v in fr for c in ("A", "B")]
+    _write(tmp_path / "p", rows)
+    got = [(r["Dispatch_Id"], r["Counter_Name"]) for r in profiling._rows(str(tmp_path / "p"), 1, 1)]
+    assert got == [("3", "A"), ("3", "B"), ("4", "A"), ("4", "B")]
+    assert profiling._sum(str(tmp_path / "p"), "B", kernels=("k_sweep",), skip=0, iterations=1) == 500
