@@ -45,18 +45,25 @@ template <> __device__ __forceinline__ float make_uniform<float>(uint32_t hi, ui
     return (float)(((hi >> 9) << 1) | 1u) * 0x1p-24f;
 }
 
+// Uniform n of a packet's stream is half of Philox block n / 2: the first
+// pair of words for even n, the second for odd n.  The second pair is kept
+// from the block's call; s0 = s1 = 0 marks it as not kept (a stream restored
+// from a stored position), and the block is then computed again when the
+// pair is drawn: the same block gives the same words, so a pair that is
+// really zero costs one recomputation and nothing else.
 template <typename R> struct Stream {
     uint32_t k0, k1, p0, p1;
     uint32_t n;
     uint32_t s0, s1;
     __device__ __forceinline__ R next() {
-        if ((n & 1u) == 0u) {
+        const bool first = (n & 1u) == 0u;
+        if (first || (s0 | s1) == 0u) {
             uint32_t c0 = n >> 1, c1 = 0u, c2 = p0, c3 = p1;
             philox4x32_10(c0, c1, c2, c3, k0, k1);
             s0 = c2;
             s1 = c3;
             ++n;
-            return make_uniform<R>(c0, c1);
+            return first ? make_uniform<R>(c0, c1) : make_uniform<R>(c2, c3);
         }
         ++n;
         return make_uniform<R>(s0, s1);

@@ -145,7 +145,7 @@ __device__ __forceinline__ void load_raw(const SweepParams& S, const uint4* recs
 
 // The packet of a record: the state fields, then what begin_flight derived
 // from them (wall spacings along the ray, the bin's opacities) and the random
-// stream (the second uniform of the last Philox call when the position is odd).
+// stream's position.
 template <typename R>
 __device__ __forceinline__ void unpack_rec(Packet<R>& s, Stream<R>& rs, const TransportParams<R>& P,
                                            const Raw<R>& r, const R* chi_t, const R* kap_t) {
@@ -169,12 +169,9 @@ __device__ __forceinline__ void unpack_rec(Packet<R>& s, Stream<R>& rs, const Tr
     rs.p0 = (uint32_t)gid;
     rs.p1 = (uint32_t)(gid >> 32);
     rs.n = n;
-    if (rs.n & 1u) {
-        uint32_t c0 = rs.n >> 1, c1 = 0u, c2 = rs.p0, c3 = rs.p1;
-        philox4x32_10(c0, c1, c2, c3, rs.k0, rs.k1);
-        rs.s0 = c2;
-        rs.s1 = c3;
-    }
+    // the second words of the last block are recomputed when drawn (most
+    // visits draw nothing)
+    rs.s0 = rs.s1 = 0u;
     s.st = state == RS_WALK ? ST_WALK : ST_EVENT;
 }
 
