@@ -193,16 +193,6 @@ __device__ __forceinline__ int slot_tile(const SweepParams& S, int t, int d) {
         default: return t;
     }
 }
-__device__ __forceinline__ int slot_of(const SweepParams& S, int t, int dest) {
-    const int dt = dest - t, nxy = S.ntx * S.nty;
-    if (dt == 0) return 0;
-    if (dt == -1) return 1;
-    if (dt == 1) return 2;
-    if (dt == -S.ntx) return 3;
-    if (dt == S.ntx) return 4;
-    if (dt == -nxy) return 5;
-    return 6;  // dt == nxy: a packet moves at most one cell per crossing
-}
 
 // Local LDS index of the packet's cell in the tile with origin (o0, o1, o2).
 __device__ __forceinline__ int tile_index(int c0, int c1, int c2, int o0, int o1, int o2, int txy) {
@@ -469,13 +459,23 @@ __device__ __forceinline__ void flush_tile_counts(const SweepParams& S, int t, u
 // (state MOVE / YIELD) into the open chunks of their destination tiles, and
 // free those lanes.  Per destination: the wave's lanes take consecutive slots
 // (their rank among the lanes of that destination); a chunk that fills is
-// registered and the rest goes to a new chunk.
+// registered and the rest goes to a new chunk.  A packet that leaves has
+// crossed one wall of the tile (origin o0, o1, o2) by one cell, so its
+// destination slot follows from comparisons with the tile's bounds.
 template <typename R>
-__device__ __forceinline__ void write_exits(const SweepParams& S, int b, int tile, Packet<R>& s,
-                                            const Stream<R>& rs, WaveOut& w, unsigned* s_tc, int lane) {
+__device__ __forceinline__ void write_exits(const SweepParams& S, int b, int tile, int o0, int o1, int o2,
+                                            Packet<R>& s, const Stream<R>& rs, WaveOut& w, unsigned* s_tc,
+                                            int lane) {
     const bool out = s.st == ST_MOVE || s.st == ST_YIELD;
     if (__ballot(out) == 0ull) return;
-    const int slot = out ? slot_of(S, tile, tile_of(S, s.c0, s.c1, s.c2)) : -1;
+    const int slot = !out                    ? -1
+                     : s.c0 < o0             ? 1
+                     : s.c0 >= o0 + S.txy    ? 2
+                     : s.c1 < o1             ? 3
+                     : s.c1 >= o1 + S.txy    ? 4
+                     : s.c2 < o2             ? 5
+                     : s.c2 >= o2 + S.tz     ? 6
+                                             : 0;
     unsigned idx = kNone;
 #pragma unroll
     for (int d = 0; d < 7; ++d) {
@@ -1033,7 +1033,7 @@ __global__ void __launch_bounds__(sizeof(R) == 4 ? (FULL ? 512 : 768) : 256) k_s
                 }
             }
             if (s.st == ST_ESC) escape<R, FULL>(s, P, cnt, e_escaped);
-            write_exits(S, bo, tile, s, rs, wo, s_tc, lane);
+            write_exits(S, bo, tile, o0, o1, o2, s, rs, wo, s_tc, lane);
             // free lanes take their next record
             if (s.st == ST_EMPTY && hn) {
                 unpack_rec(s, rs, P, nx, tb.chi, tb.kap);
