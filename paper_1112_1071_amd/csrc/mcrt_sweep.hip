@@ -194,6 +194,14 @@ __device__ __forceinline__ int slot_tile(const SweepParams& S, int t, int d) {
     }
 }
 
+// Global index of cell (c0, c1, c2).  Tiled sweeps hold at most 1024 cells
+// per axis, so every factor fits 24 bits and the index 30.
+template <typename R>
+__device__ __forceinline__ unsigned grid_index(const TransportParams<R>& P, int c0, int c1, int c2) {
+    return (unsigned)c0 +
+           __umul24((unsigned)P.n[0], (unsigned)c1 + __umul24((unsigned)P.n[1], (unsigned)c2));
+}
+
 // Local LDS index of the packet's cell in the tile with origin (o0, o1, o2).
 __device__ __forceinline__ int tile_index(int c0, int c1, int c2, int o0, int o1, int o2, int txy) {
     return (c0 - o0) + txy * ((c1 - o1) + txy * (c2 - o2));
@@ -295,7 +303,7 @@ __device__ __forceinline__ void walk_tile(Packet<R>& s, const TransportParams<R>
         st = ST_EVENT;
         // the cell's emission row, loaded now for the interaction (an
         // absorption re-emits from it) while the wave walks on
-        s.rowp = P.rowpos[s.c0 + (int64_t)P.n[0] * (s.c1 + (int64_t)P.n[1] * s.c2)];
+        s.rowp = P.rowpos[grid_index(P, s.c0, s.c1, s.c2)];
     } else if (left) {
         // past the tile's wall on axis lax: the neighbour tile's cell, or out
         // of the grid if that wall is the grid's
@@ -1050,7 +1058,7 @@ __global__ void __launch_bounds__(sizeof(R) == 4 ? (FULL ? 512 : 768) : 256) k_s
                         rho = rho_t[jl];
                         visit = 0;
                         if (s.st == ST_EVENT)
-                            s.rowp = P.rowpos[s.c0 + (int64_t)P.n[0] * (s.c1 + (int64_t)P.n[1] * s.c2)];
+                            s.rowp = P.rowpos[grid_index(P, s.c0, s.c1, s.c2)];
                     }
                 }
             }
