@@ -879,6 +879,10 @@ mcrt_status run_sweeps(mcrt_model* m, TransportParams<R>& P, int64_t np, int64_t
                4 * m->kap.size() * sizeof(R) + tab_lds;
     };
     while (tile_bytes(S.tz) > m->lds_max && S.tz > 1) S.tz /= 2;
+    if (S.txy < 1 || S.txy > 64 || S.tz < 1 || S.tz > 64)
+        return fail(m, MCRT_E_ARG, "tile extents must be in [1, 64] cells");
+    S.mxy = (65536u + (unsigned)S.txy - 1u) / (unsigned)S.txy;
+    S.mz = (65536u + (unsigned)S.tz - 1u) / (unsigned)S.tz;
     S.ntx = (m->n[0] + S.txy - 1) / S.txy;
     S.nty = (m->n[1] + S.txy - 1) / S.txy;
     S.ntz = (m->n[2] + S.tz - 1) / S.tz;

@@ -189,6 +189,9 @@ struct SweepParams {
     int txy;                    // tile extent in x and y (cells): 16 or 32
     int tz;                     // tile extent in z (cells)
     int ntx, nty, ntz, ntiles;  // tiles per axis, total
+    // ceil(2^16 / txy), ceil(2^16 / tz): c / t = (c * m) >> 16 exactly for
+    // cell coordinates c < 1024 and tile extents t <= 64
+    unsigned mxy, mz;
     int visit_events;           // interactions per visit before a packet yields
     int item_ent;               // entries per work item
     int service;                // lanes of a wave that wait before its events and exits run

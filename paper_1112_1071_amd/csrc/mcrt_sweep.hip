@@ -176,8 +176,14 @@ __device__ __forceinline__ void unpack_rec(Packet<R>& s, Stream<R>& rs, const Tr
 }
 
 // ---- tiles --------------------------------------------------------------------
+// The tile of cell (c0, c1, c2); the quotients by the tile extents as
+// multiplications by their rounded-up 2^16 reciprocals (exact for the
+// extents and coordinates tiled sweeps allow).
 __device__ __forceinline__ int tile_of(const SweepParams& S, int c0, int c1, int c2) {
-    return (c0 / S.txy) + S.ntx * ((c1 / S.txy) + S.nty * (c2 / S.tz));
+    const int q0 = (int)(__umul24((unsigned)c0, S.mxy) >> 16);
+    const int q1 = (int)(__umul24((unsigned)c1, S.mxy) >> 16);
+    const int q2 = (int)(__umul24((unsigned)c2, S.mz) >> 16);
+    return q0 + S.ntx * (q1 + S.nty * q2);
 }
 
 // the tile of destination slot d of tile t: itself, then -x, +x, -y, +y, -z, +z
