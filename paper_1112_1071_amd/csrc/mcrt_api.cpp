@@ -213,6 +213,7 @@ struct mcrt_model {
     DBuf<double> chi64, kap64, alb64, g64, lcdf64, scdf64, ecdf64;
     DBuf<float> chi32, kap32, alb32, g32, lcdf32, scdf32, ecdf32;
     DBuf<double> spos, sweight, lnA, slope;
+    DBuf<int4> scell;
     DBuf<double> ecoarse64, scoarse64;
     DBuf<float> ecoarse32, scoarse32;
     int npad = 0, ngroup = 0;
@@ -480,6 +481,18 @@ mcrt_status build_tables(mcrt_model* m) {
         lcdf[i] = acc / m->ltot;
         for (int a = 0; a < 3; ++a) spos[3 * i + a] = m->src[i].pos[a];
     }
+    // each source's cell, from the same FP64 arithmetic as the emission's
+    std::vector<int4> scell(ns);
+    for (size_t i = 0; i < ns; ++i) {
+        int c[3], w = 0;
+        for (int a = 0; a < 3; ++a) {
+            const double fp = (m->src[i].pos[a] - m->lo[a]) / m->dx[a];
+            const double fl = std::floor(fp);
+            c[a] = (int)fl;
+            if (fp == fl) w |= 1 << a;
+        }
+        scell[i] = make_int4(c[0], c[1], c[2], w);
+    }
     lcdf.back() = 1.0;
     std::vector<double> ecdf, lnA, slope;
     dust_tables(m->nu, m->kap, ecdf, lnA, slope, &m->dy);
@@ -521,6 +534,7 @@ mcrt_status build_tables(mcrt_model* m) {
     HIPCHK(upload(m->scoarse32, scoarse32, st));
     HIPCHK(upload(m->ecoarse32, ecoarse32, st));
     HIPCHK(upload(m->spos, spos, st));
+    HIPCHK(upload(m->scell, scell, st));
     HIPCHK(upload(m->lnA, lnA, st));
     HIPCHK(upload(m->slope, slope, st));
     HIPCHK(upload(m->img_of_bin, iob, st));
@@ -781,6 +795,7 @@ void make_params(mcrt_model* m, int64_t np, uint32_t key1, int binning, Transpor
         P.nsrc = (int)m->src.size();
         P.sampling = m->cfg.source_sampling;
         P.spos = m->spos.p;
+        P.scell = m->scell.p;
         P.lcdf = lcdf;
         P.scdf = scdf;
         P.sweight = m->sweight.p;
@@ -1293,7 +1308,7 @@ void mcrt_destroy(mcrt_model* m) {
     m->lcdf64.release(); m->scdf64.release(); m->ecdf64.release();
     m->chi32.release(); m->kap32.release(); m->alb32.release(); m->g32.release();
     m->lcdf32.release(); m->scdf32.release(); m->ecdf32.release();
-    m->spos.release(); m->sweight.release(); m->lnA.release(); m->slope.release();
+    m->spos.release(); m->scell.release(); m->sweight.release(); m->lnA.release(); m->slope.release();
     m->img_of_bin.release();
     m->acc.release(); m->acc2.release(); m->adot.release(); m->adot_prev.release();
     m->adot_sig.release(); m->T.release(); m->T_prev.release(); m->sig_rel.release();

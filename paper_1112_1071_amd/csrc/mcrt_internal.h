@@ -55,6 +55,8 @@ struct TransportParams {
     int nsrc;
     int sampling;           // 0 luminosity-proportional, 1 equal numbers
     const double* spos;     // [3*nsrc]
+    const int4* scell;      // [nsrc] a source's cell (x, y, z) and w: bit a set when it lies
+                            // on a cell wall of axis a (the direction's sign picks the cell)
     const R* lcdf;          // [nsrc] luminosity CDF
     const R* scdf;          // [nsrc*npad] spectral CDFs
     const double* sweight;  // [nsrc] packet weight relative to eps0 (equal sampling)

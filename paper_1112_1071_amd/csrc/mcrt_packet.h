@@ -622,6 +622,34 @@ __device__ __forceinline__ int emit_start(Packet<R>& s, Stream<R>& rs, const Tra
     return src;
 }
 
+// The start cell of packet id, as emit_start finds it, from the source's
+// tabulated cell: one random block for the source, and the direction only for
+// a source on a cell wall, where its sign picks the cell.
+template <typename R>
+__device__ __forceinline__ void emit_start_cell(Stream<R>& rs, const TransportParams<R>& P,
+                                                const Tables<R>& tb, uint64_t id, int& c0, int& c1,
+                                                int& c2) {
+    const uint64_t gid = P.packet_base + id;
+    rs.p0 = (uint32_t)gid;
+    rs.p1 = (uint32_t)(gid >> 32);
+    rs.n = 0;
+    const R u_src = rs.next();
+    const int src = P.sampling == 0 ? cdf_search(tb.lcdf, P.nsrc, u_src) : (int)(gid % (uint64_t)P.nsrc);
+    const int4 sc = P.scell[src];
+    c0 = sc.x;
+    c1 = sc.y;
+    c2 = sc.z;
+    if (sc.w) {
+        rs.next();  // the frequency's uniform
+        const R u_mu = rs.next(), u_phi = rs.next();
+        Packet<R> s;
+        isotropic(s, u_mu, u_phi);
+        if ((sc.w & 1) && s.d0 < (R)0) c0 -= 1;
+        if ((sc.w & 2) && s.d1 < (R)0) c1 -= 1;
+        if ((sc.w & 4) && s.d2 < (R)0) c2 -= 1;
+    }
+}
+
 template <typename R>
 __device__ __forceinline__ bool in_grid(const TransportParams<R>& P, int c0, int c1, int c2) {
     return (unsigned)c0 < (unsigned)P.n[0] && (unsigned)c1 < (unsigned)P.n[1] &&

@@ -606,11 +606,10 @@ __global__ void __launch_bounds__(kEmitThreads) k_sweep_emit(TransportParams<R> 
             int& slot = s_slot[j * kEmitThreads + threadIdx.x];
             slot = -2;  // no packet, or it starts outside the grid
             if (i < count) {
-                Packet<R> s;
-                R u_nu, f[3];
-                emit_start(s, rs, P, tb, first + i, u_nu, f);
-                if (in_grid(P, s.c0, s.c1, s.c2)) {
-                    const unsigned t = (unsigned)tile_of(S, s.c0, s.c1, s.c2);
+                int e0, e1, e2;
+                emit_start_cell(rs, P, tb, first + i, e0, e1, e2);
+                if (in_grid(P, e0, e1, e2)) {
+                    const unsigned t = (unsigned)tile_of(S, e0, e1, e2);
                     unsigned h = (t * 2654435761u) >> 22;
                     slot = -1;  // no hash slot: one entry of its own
                     for (int probe = 0; probe < kEmitHash; ++probe) {

@@ -391,3 +391,49 @@ def test_peeloff_same_stream(M, mode):
     # a point projected exactly onto a pixel edge may land on either side
     close = np.isclose(ig, io, rtol=1e-9, atol=0)
     assert close.mean() > 0.999
+
+
+@pytest.mark.parametrize("sampling", [0, 1])
+def test_sources_on_tile_walls_same_stream(M, sampling):
+    # Sources exactly on cell walls that are also tile walls (FP64 tiles are
+    # 16 cells wide): a packet whose direction points to the lower side starts
+    # in the lower cell (Sec. 2.2 emission; reading of a position on a wall),
+    # which lies in the neighbouring tile.  The tiled emission registers every
+    # packet with the tile of that cell, so the FP64 tiled pass equals the
+    # oracle's event by event, and the FP32 tiled pass equals the FP32 per-lane
+    # walk.  Cell size 2^43 cm keeps every wall position exact.
+    base = synth.config0(n=32, n_packets=20000, n_iter=1, n_bins=20)
+    dx = 2.0 ** 43
+    cfg = dict(base)
+    cfg["grid"] = {"n": [32, 32, 32], "lo": [0.0, 0.0, 0.0], "hi": [32 * dx] * 3}
+    cfg["sources"] = [{"pos": [16 * dx, 16 * dx, 16.5 * dx], "lum": synth.L_SUN, "teff": 6000.0},
+                      {"pos": [8 * dx, 16 * dx, 16 * dx], "lum": 0.5 * synth.L_SUN, "teff": 4000.0},
+                      {"pos": [0.0, 20.25 * dx, 32 * dx - dx / 4], "lum": 0.25 * synth.L_SUN, "teff": 3000.0}]
+    run = dict(event_log_packets=2000, event_log_cap=16, source_sampling=sampling)
+    o = oracle.OracleModel(cfg, **run)
+    g = M.Model(cfg, precision=M.MCRT_FP64, **run)
+    assert g.run["transport_mode"] == 1
+    so, sg = o.iterate(), g.iterate()
+    for k in ["n_cross_dust", "n_cross_empty", "n_scatter", "n_absorb", "n_escape", "n_killed"]:
+        assert so[k] == sg[k], k
+    assert sg["n_escape"] + sg["n_killed"] == 20000
+    eo, co = o.event_log()
+    eg, cg = g.event_log()
+    compare_logs(eo, co, eg, cg)
+    ao, ag = o.specific_energy(), g.specific_energy()
+    o.close()
+    g.close()
+    nz = ao > 0
+    assert np.array_equal(nz, ag > 0)
+    assert np.max(np.abs(ag[nz] / ao[nz] - 1)) < 1e-9
+    a = M.Model(cfg, precision=M.MCRT_FP32_TRANSPORT, transport_mode=0, source_sampling=sampling)
+    b = M.Model(cfg, precision=M.MCRT_FP32_TRANSPORT, transport_mode=1, source_sampling=sampling)
+    sa, sb = a.iterate(), b.iterate()
+    for k in ["n_cross_dust", "n_cross_empty", "n_scatter", "n_absorb", "n_escape", "n_killed"]:
+        assert sa[k] == sb[k], k
+    aa, ab = a.specific_energy(), b.specific_energy()
+    a.close()
+    b.close()
+    nz = aa > 0
+    assert np.array_equal(nz, ab > 0)
+    assert np.max(np.abs(ab[nz] / aa[nz] - 1)) < 1e-9
