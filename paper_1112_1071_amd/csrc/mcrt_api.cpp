@@ -214,6 +214,7 @@ struct mcrt_model {
     DBuf<float> chi32, kap32, alb32, g32, lcdf32, scdf32, ecdf32;
     DBuf<double> spos, sweight, lnA, slope;
     DBuf<int4> scell;
+    DBuf<double> sfrac;
     DBuf<double> ecoarse64, scoarse64;
     DBuf<float> ecoarse32, scoarse32;
     int npad = 0, ngroup = 0;
@@ -483,12 +484,14 @@ mcrt_status build_tables(mcrt_model* m) {
     }
     // each source's cell, from the same FP64 arithmetic as the emission's
     std::vector<int4> scell(ns);
+    std::vector<double> sfrac(3 * ns);
     for (size_t i = 0; i < ns; ++i) {
         int c[3], w = 0;
         for (int a = 0; a < 3; ++a) {
             const double fp = (m->src[i].pos[a] - m->lo[a]) / m->dx[a];
             const double fl = std::floor(fp);
             c[a] = (int)fl;
+            sfrac[3 * i + a] = fp - fl;
             if (fp == fl) w |= 1 << a;
         }
         scell[i] = make_int4(c[0], c[1], c[2], w);
@@ -535,6 +538,7 @@ mcrt_status build_tables(mcrt_model* m) {
     HIPCHK(upload(m->ecoarse32, ecoarse32, st));
     HIPCHK(upload(m->spos, spos, st));
     HIPCHK(upload(m->scell, scell, st));
+    HIPCHK(upload(m->sfrac, sfrac, st));
     HIPCHK(upload(m->lnA, lnA, st));
     HIPCHK(upload(m->slope, slope, st));
     HIPCHK(upload(m->img_of_bin, iob, st));
@@ -796,6 +800,7 @@ void make_params(mcrt_model* m, int64_t np, uint32_t key1, int binning, Transpor
         P.sampling = m->cfg.source_sampling;
         P.spos = m->spos.p;
         P.scell = m->scell.p;
+        P.sfrac = m->sfrac.p;
         P.lcdf = lcdf;
         P.scdf = scdf;
         P.sweight = m->sweight.p;
@@ -1308,7 +1313,7 @@ void mcrt_destroy(mcrt_model* m) {
     m->lcdf64.release(); m->scdf64.release(); m->ecdf64.release();
     m->chi32.release(); m->kap32.release(); m->alb32.release(); m->g32.release();
     m->lcdf32.release(); m->scdf32.release(); m->ecdf32.release();
-    m->spos.release(); m->scell.release(); m->sweight.release(); m->lnA.release(); m->slope.release();
+    m->spos.release(); m->scell.release(); m->sfrac.release(); m->sweight.release(); m->lnA.release(); m->slope.release();
     m->img_of_bin.release();
     m->acc.release(); m->acc2.release(); m->adot.release(); m->adot_prev.release();
     m->adot_sig.release(); m->T.release(); m->T_prev.release(); m->sig_rel.release();

@@ -57,6 +57,7 @@ struct TransportParams {
     const double* spos;     // [3*nsrc]
     const int4* scell;      // [nsrc] a source's cell (x, y, z) and w: bit a set when it lies
                             // on a cell wall of axis a (the direction's sign picks the cell)
+    const double* sfrac;    // [3*nsrc] its offsets in that cell, in cells
     const R* lcdf;          // [nsrc] luminosity CDF
     const R* scdf;          // [nsrc*npad] spectral CDFs
     const double* sweight;  // [nsrc] packet weight relative to eps0 (equal sampling)

@@ -602,16 +602,16 @@ __device__ __forceinline__ int emit_start(Packet<R>& s, Stream<R>& rs, const Tra
         s.wgt = (R)P.sweight[src];
     }
     isotropic(s, u_mu, u_phi);
-    const double* x = P.spos + 3 * src;
-    int c[3];
+    // the source's cell and offsets, (x - lo) / dx split into its floor and
+    // the rest, tabulated per source in FP64
+    const int4 sc = P.scell[src];
+    const double* fr = P.sfrac + 3 * src;
+    int c[3] = {sc.x, sc.y, sc.z};
     const R dd[3] = {s.d0, s.d1, s.d2};
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
-        const double fp = (x[a] - P.lo[a]) / P.dx[a];
-        const double fl = floor(fp);
-        c[a] = (int)fl;
-        f[a] = (R)(fp - fl);
-        if (fp == fl && dd[a] < (R)0) {
+        f[a] = (R)fr[a];
+        if (((sc.w >> a) & 1) && dd[a] < (R)0) {
             c[a] -= 1;
             f[a] = (R)1;
         }
