@@ -68,47 +68,56 @@ struct ConvArgs {
 
 // source voxel of GEMM row r (a voxel of the row grid) and tap t; -1 if padding.
 // Rows: CONV3/DOWN -> output voxels (grid Dout); UP -> input voxels (grid Din).
+// The row's decomposition runs in the index type I: 32-bit whenever the
+// launch's rows and voxels fit (every network size here), 64-bit otherwise.
+template <typename I>
 __device__ __forceinline__ int64_t src_voxel(const ConvArgs& A, int64_t r, int t) {
     if (A.mode == UP) return r;
-    const int Dg = A.Dout;
-    const int64_t per = (int64_t)Dg * Dg * Dg;
-    const int n = (int)(r / per);
-    int64_t q = r - (int64_t)n * per;
-    const int z = (int)(q / (Dg * Dg));
-    q -= (int64_t)z * Dg * Dg;
-    const int y = (int)(q / Dg), x = (int)(q - (int64_t)y * Dg);
+    const I Dg = (I)A.Dout;
+    const I per = Dg * Dg * Dg;
+    const I rr = (I)r;
+    const I n = rr / per;
+    I q = rr - n * per;
+    const I z = q / (Dg * Dg);
+    q -= z * Dg * Dg;
+    const I y = q / Dg, x = q - y * Dg;
     int sz, sy, sx;
     if (A.mode == CONV3) {
-        sz = z + t / 9 - 1;
-        sy = y + (t / 3) % 3 - 1;
-        sx = x + t % 3 - 1;
+        sz = (int)z + t / 9 - 1;
+        sy = (int)y + (t / 3) % 3 - 1;
+        sx = (int)x + t % 3 - 1;
         if ((unsigned)sz >= (unsigned)A.Din || (unsigned)sy >= (unsigned)A.Din ||
             (unsigned)sx >= (unsigned)A.Din)
             return -1;
     } else {
-        sz = 2 * z + (t >> 2);
-        sy = 2 * y + ((t >> 1) & 1);
-        sx = 2 * x + (t & 1);
+        sz = 2 * (int)z + (t >> 2);
+        sy = 2 * (int)y + ((t >> 1) & 1);
+        sx = 2 * (int)x + (t & 1);
     }
-    return (((int64_t)n * A.Din + sz) * A.Din + sy) * A.Din + sx;
+    const I Di = (I)A.Din;
+    return (int64_t)(((n * Di + (I)sz) * Di + (I)sy) * Di + (I)sx);
 }
 
 // output voxel of GEMM row r (parity class p for UP)
+template <typename I>
 __device__ __forceinline__ int64_t dst_voxel(const ConvArgs& A, int64_t r, int p) {
     if (A.mode != UP) return r;
-    const int Dg = A.Din;
-    const int64_t per = (int64_t)Dg * Dg * Dg;
-    const int n = (int)(r / per);
-    int64_t q = r - (int64_t)n * per;
-    const int z = (int)(q / (Dg * Dg));
-    q -= (int64_t)z * Dg * Dg;
-    const int y = (int)(q / Dg), x = (int)(q - (int64_t)y * Dg);
-    const int Do = A.Dout;
-    return (((int64_t)n * Do + 2 * z + (p >> 2)) * Do + 2 * y + ((p >> 1) & 1)) * Do + 2 * x + (p & 1);
+    const I Dg = (I)A.Din;
+    const I per = Dg * Dg * Dg;
+    const I rr = (I)r;
+    const I n = rr / per;
+    I q = rr - n * per;
+    const I z = q / (Dg * Dg);
+    q -= z * Dg * Dg;
+    const I y = q / Dg, x = q - y * Dg;
+    const I Do = (I)A.Dout;
+    return (int64_t)(((n * Do + 2 * z + (I)(p >> 2)) * Do + 2 * y + (I)((p >> 1) & 1)) * Do + 2 * x +
+                     (I)(p & 1));
 }
 
 // Implicit-GEMM convolution.  A workgroup of 4 waves covers 64 rows; each wave
 // 16 rows x 64 output channels (4 MFMA tiles) of blockIdx.y's channel block.
+template <typename I>
 __global__ void __launch_bounds__(256) k_conv(ConvArgs A, int64_t rows) {
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int64_t r0 = ((int64_t)blockIdx.x * 4 + wave) * 16;
@@ -125,7 +134,7 @@ __global__ void __launch_bounds__(256) k_conv(ConvArgs A, int64_t rows) {
     for (int t = 0; t < 4; ++t) acc[t] = (f32x4){0.f, 0.f, 0.f, 0.f};
     const int t_lo = A.mode == UP ? p : 0, t_hi = A.mode == UP ? p + 1 : taps;
     for (int t = t_lo; t < t_hi; ++t) {
-        const int64_t sv = row_ok ? src_voxel(A, row, t) : -1;
+        const int64_t sv = row_ok ? src_voxel<I>(A, row, t) : -1;
         const uint16_t* wt = A.w + (size_t)t * A.Cout * Cin;
         for (int c0 = 0; c0 < Cin; c0 += 16) {
             bf16x4 a = {0, 0, 0, 0};
@@ -155,7 +164,7 @@ __global__ void __launch_bounds__(256) k_conv(ConvArgs A, int64_t rows) {
         for (int i = 0; i < 4; ++i) {
             const int64_t r = r0 + 4 * kq + i;
             if (r >= rows) continue;
-            const int64_t dv = dst_voxel(A, r, p);
+            const int64_t dv = dst_voxel<I>(A, r, p);
             float v = acc[tt][i] + b;
             if (A.out_bf) {
                 if (A.act) v = v > 0.f ? v : A.slope * v;
@@ -285,6 +294,7 @@ struct WgradArgs {
 // MFMA with M = output channels, N = input channels, K = rows.  Each wave
 // reduces `chunk` rows for one (tap, 16x16 channel tile) and adds its tile to
 // dW with FP32 atomics.
+template <typename I>
 __global__ void __launch_bounds__(256) k_wgrad(WgradArgs W, int64_t rows, int chunk) {
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int Cin = W.C1 + W.C2;
@@ -318,10 +328,10 @@ __global__ void __launch_bounds__(256) k_wgrad(WgradArgs W, int64_t rows, int ch
                 int64_t dv, sv;
                 if (W.mode == UP) {  // row = input voxel u, tap t = parity of the output voxel
                     sv = r;
-                    dv = dst_voxel(G, r, t);
+                    dv = dst_voxel<I>(G, r, t);
                 } else {
                     dv = r;
-                    sv = src_voxel(G, r, t);
+                    sv = src_voxel<I>(G, r, t);
                 }
                 av = W.dz[dv * W.Cout + co];
                 if (sv >= 0)
@@ -663,6 +673,12 @@ __global__ void k_exp10(int64_t n, const float* __restrict__ y, double* __restri
 }
 
 // ---------------------------------------------------------------------------
+// whether every voxel index of a layer (N samples, grids Din and Dout) fits 32 bits
+static bool index32(int N, int Din, int Dout) {
+    const int64_t d = Din > Dout ? Din : Dout;
+    return (int64_t)N * d * d * d < ((int64_t)1 << 32);
+}
+
 static int blocks_for(int64_t n) {
     int64_t b = (n + 255) / 256;
     return (int)(b > 4096 ? 4096 : (b < 1 ? 1 : b));
@@ -688,7 +704,10 @@ hipError_t launch_conv(const ConvArgs& A, hipStream_t st) {
     const int Dg = A.mode == UP ? A.Din : A.Dout;
     const int64_t rows = (int64_t)A.N * Dg * Dg * Dg;
     dim3 grid((unsigned)((rows + 63) / 64), (unsigned)((A.Cout + 63) / 64), A.mode == UP ? 8 : 1);
-    hipLaunchKernelGGL(k_conv, grid, dim3(256), 0, st, A, rows);
+    if (index32(A.N, A.Din, A.Dout))
+        hipLaunchKernelGGL(k_conv<uint32_t>, grid, dim3(256), 0, st, A, rows);
+    else
+        hipLaunchKernelGGL(k_conv<int64_t>, grid, dim3(256), 0, st, A, rows);
     return hipGetLastError();
 }
 
@@ -717,7 +736,10 @@ hipError_t launch_wgrad(const WgradArgs& W, hipStream_t st) {
     if (c > (1 << 20)) c = 1 << 20;
     const int chunk = (int)c;
     dim3 grid((unsigned)((rows + chunk - 1) / chunk), (unsigned)((tasks + 3) / 4));
-    hipLaunchKernelGGL(k_wgrad, grid, dim3(256), 0, st, W, rows, chunk);
+    if (index32(W.N, W.Din, W.Dout))
+        hipLaunchKernelGGL(k_wgrad<uint32_t>, grid, dim3(256), 0, st, W, rows, chunk);
+    else
+        hipLaunchKernelGGL(k_wgrad<int64_t>, grid, dim3(256), 0, st, W, rows, chunk);
     return hipGetLastError();
 }
 
